@@ -1,0 +1,106 @@
+"""Pins of the oracle's domain selection (paper Sec. III-B and Sec. IV-B)."""
+import numpy as np
+import pytest
+import torch
+
+import instances as I
+import oracle
+
+
+def test_vertex_identity():
+    # at theta in {+-pi/2}^n, L = 1^T s ((J - mu I) s + h) = E(s) - mu n
+    inst = I.random_integer_field(I.sk_pm1(30, 1), 1, 4)
+    rng = np.random.default_rng(0)
+    for mu in (0.0, 0.5, 3.0):
+        s = rng.choice([-1, 1], size=(30, 5))
+        theta = s * np.pi / 2
+        L = oracle.ds_loss(inst, theta, np.where(np.sin(theta) >= 0, 1, -1), mu)
+        E = oracle.energies(inst, s)
+        assert np.allclose(L, E - mu * 30, rtol=0, atol=1e-9)
+
+
+def test_gradient_matches_finite_difference():
+    inst = I.sk_gauss(25, 3)
+    inst.h[:] = np.random.default_rng(1).normal(size=25)
+    rng = np.random.default_rng(2)
+    theta = rng.uniform(-np.pi, np.pi, size=(25, 3))
+    mu = 0.7
+    s_fixed = np.where(np.sin(theta) >= 0, 1, -1)
+    g = oracle.ds_grad(inst, theta, mu)
+    d = 1e-6
+    for i in range(25):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += d
+        tm[i] -= d
+        fd = (oracle.ds_loss(inst, tp, s_fixed, mu) - oracle.ds_loss(inst, tm, s_fixed, mu)) / (2 * d)
+        assert np.allclose(fd, g[i], rtol=1e-6, atol=1e-7)
+
+
+def _torch_reference(inst, U, steps, opt, lr, mu):
+    """Autograd + torch.optim on L(theta) with s~ = sign(sin theta) (torch.sign has zero gradient)."""
+    J = torch.tensor(inst.dense().astype(np.float64))
+    h = torch.tensor(inst.h.astype(np.float64))
+    theta = torch.tensor(np.arcsin(U).T.copy(), requires_grad=True)
+    optim = (torch.optim.Adam([theta], lr=lr, betas=(0.9, 0.999), eps=1e-8) if opt == "adam"
+             else torch.optim.SGD([theta], lr=lr))
+    sins = []
+    for _ in range(steps):
+        optim.zero_grad()
+        x = torch.sin(theta)
+        s = torch.where(x >= 0, 1.0, -1.0).to(torch.float64).detach()
+        loss = (x * (J @ s - mu * s + h[:, None])).sum()
+        loss.backward()
+        optim.step()
+        sins.append(torch.sin(theta).detach().numpy().T.copy())
+    return np.array(sins)
+
+
+@pytest.mark.parametrize("opt,lr", [("adam", 0.05), ("gd", 0.01)])
+def test_optimizer_matches_torch(opt, lr):
+    inst = I.random_integer_field(I.sk_pm1(20, 4), 4, 2)
+    U = I.uniform_draws(11, 6, 20)
+    res = oracle.ds_run(inst, U, 25, opt=opt, lr=lr, mu=0.5, record_sin=True)
+    ref = _torch_reference(inst, U, 25, opt, lr, 0.5)
+    assert np.max(np.abs(res.sin_trace - ref)) < 1e-9
+
+
+def test_large_mu_freezes_spins():
+    inst = I.sk_pm1(40, 2)
+    U = I.uniform_draws(3, 8, 40)
+    res = oracle.ds_run(inst, U, 200, opt="gd", lr=1e-4, mu=1000.0, record=True, record_sin=True)
+    s0 = np.where(U >= 0, 1, -1)
+    assert np.all(res.spin_trace == s0[None])
+
+
+def test_l1_equivalence_large_mu():
+    # L1-norm equations: for large enough mu, max_s ||(J - mu I)s + h||_1 = mu n - min_s E(s)
+    inst = I.random_integer_field(I.sk_pm1(10, 6), 6, 3)
+    mu = float(np.max(np.abs(inst.J).sum(1) + np.abs(inst.h))) + 1.0
+    e_min, _, _ = oracle.brute_force_min(inst)
+    codes = np.arange(1 << 10)
+    S = 1 - 2 * ((codes[:, None] >> np.arange(10)[None]) & 1)
+    l1 = np.abs(S @ (inst.J - mu * np.eye(10)) + inst.h).sum(1)
+    assert np.isclose(l1.max(), mu * 10 - e_min)
+
+
+def test_best_tracking_and_energy_trace_consistent():
+    inst = I.erdos_renyi(60, 0.1, 1, "pm1")
+    U = I.uniform_draws(5, 7, 60)
+    res = oracle.ds_run(inst, U, 50, opt="adam", lr=6.0, mu=0.5, record=True, record_sin=True)
+    for t in range(50):
+        assert np.array_equal(res.energy_trace[t], oracle.energies(inst, res.spin_trace[t].T))
+    assert np.array_equal(res.e_best, res.energy_trace.min(0))
+    assert np.array_equal(res.best_step, res.energy_trace.argmin(0) + 1)
+    assert np.array_equal(res.e_best, oracle.energies(inst, res.s_best.T))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_reaches_brute_force_optimum_n20(seed):
+    # quality sanity (guards a flipped gradient sign): 32 replicas x 1000 steps on an
+    # N = 20 SK instance reach the exhaustive minimum
+    inst = I.sk_pm1(20, seed)
+    e_min, _, _ = oracle.brute_force_min(inst)
+    U = I.uniform_draws(seed, 32, 20)
+    res = oracle.ds_run(inst, U, 1000, opt="adam", lr=6.0, mu=0.5)
+    assert res.e_best.min() == e_min
+    assert np.all(res.e_best >= e_min)
