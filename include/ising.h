@@ -1,0 +1,244 @@
+/*
+ * ising.h -- C ABI of the MI355X (gfx950) pruning + domain-selection Ising solver.
+ *
+ * Problem (paper, Sec. II, scalar energy form and primal problem):
+ *     minimise E(s) = s^T J s + h^T s   over s in {-1,+1}^n,
+ * with J real symmetric, J_ii = 0.  J is the matrix of that form (each pair is
+ * counted twice); a Hamiltonian given with J-hat (sum over i > j) is passed as
+ * J = J-hat / 2.
+ *
+ * Pipeline (paper, Fig. 1): pruning (Sec. III-A, Algorithm 1) -> domain
+ * selection (Sec. III-B, loss-function equation, optimised by GD or ADAM as in
+ * Sec. IV-B) over many independent replicas -> selection of the best replica
+ * -> retrieval of the full spin vector from the pruning record (Fig. 1c).
+ *
+ * Conventions for every entry point:
+ *  - Return value: ISING_OK or an error code; no exception crosses the ABI.
+ *    A one-line message for the last failure of a context is available from
+ *    ising_last_error().  A context is used by one host thread at a time,
+ *    except ising_submit / ising_wait / ising_cancel, which are thread-safe.
+ *  - Ownership: the caller owns every buffer it passes.  Host inputs are
+ *    read (and copied) before the call returns.  Outputs go to caller-
+ *    allocated buffers.  The library owns the memory behind handles it
+ *    returns (ising_ctx, ising_pruned) until the matching destroy/free call.
+ *  - "_dev" entry points take device pointers (memory on the context's
+ *    device) and a hipStream_t passed as void*; they enqueue work on that
+ *    stream, borrow the buffers only for the duration of the call, and return
+ *    after the work is enqueued unless stated otherwise.  NULL stream = the
+ *    legacy default stream.
+ *  - Layouts: dense J is row-major n x n (row stride n).  CSR holds both
+ *    directions of every coupling, column indices strictly ascending within a
+ *    row, no diagonal entries, int32 row_ptr[n+1] and col[nnz].  Spin arrays
+ *    are int8 values -1/+1; a block of R spin vectors is replica-major
+ *    (vector r occupies [r*n, (r+1)*n)).
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ising_status {
+    ISING_OK = 0,
+    ISING_EINVAL = 1,     /* malformed problem or parameters (asymmetric J, diagonal, bad CSR, n <= 0 ...) */
+    ISING_ENOMEM = 2,     /* device or host allocation failed, or over the serving memory budget */
+    ISING_EDEVICE = 3,    /* a HIP runtime call failed */
+    ISING_EBUSY = 4,      /* request not finished yet / queue full */
+    ISING_ETIMEDOUT = 5,  /* ising_wait timed out */
+    ISING_ECANCELED = 6,  /* request was cancelled */
+    ISING_ENOTSUP = 7     /* combination of format / value type / precision not supported */
+} ising_status;
+
+enum { ISING_DENSE = 0, ISING_CSR = 1 };
+
+/* Value type of J (dense entries or CSR values) and of h. */
+enum { ISING_I32 = 0, ISING_F32 = 1, ISING_F64 = 2 };
+
+enum { ISING_OPT_GD = 0, ISING_OPT_ADAM = 1 };
+
+/* Arithmetic of the domain-selection iterates (angles, moments, gradient):
+ * FP64 or FP32.  The coupling product follows it, except for the dense
+ * reduced-precision forms of the coupling product (see ising_ds_dense_dev). */
+enum { ISING_PREC_FP64 = 0, ISING_PREC_FP32 = 1 };
+
+typedef struct ising_problem {
+    int32_t n;           /* spin count, > 0 */
+    int32_t format;      /* ISING_DENSE or ISING_CSR */
+    int32_t value_type;  /* ISING_I32, ISING_F32 or ISING_F64: type of J values and of h */
+    int32_t reserved0;
+    int64_t nnz;         /* CSR: number of stored couplings (both directions) */
+    const void *J;       /* DENSE: n*n values, row-major */
+    const int32_t *row_ptr; /* CSR: n+1 offsets */
+    const int32_t *col;  /* CSR: nnz column indices */
+    const void *val;     /* CSR: nnz values */
+    const void *h;       /* n values, or NULL for h = 0 */
+} ising_problem;
+
+typedef struct ising_params {
+    int32_t replicas;    /* R >= 1 independent trajectories */
+    int32_t steps;       /* T >= 0 iterations */
+    int32_t optimizer;   /* ISING_OPT_GD or ISING_OPT_ADAM */
+    int32_t precision;   /* ISING_PREC_FP64 or ISING_PREC_FP32 */
+    double lr;           /* learning rate (the paper uses 6.0 with ADAM) */
+    double mu;           /* augmented-Lagrangian weight mu > 0 of the L1-norm form */
+    double beta1, beta2, eps;  /* ADAM constants (Kingma-Ba defaults 0.9, 0.999, 1e-8) */
+    uint64_t seed;       /* key of the counter-based initial draws */
+    int32_t prune;       /* nonzero: run Algorithm 1 before domain selection */
+    int32_t reserved0;
+} ising_params;
+
+typedef struct ising_stats {
+    int32_t n;               /* original spin count */
+    int32_t n_G;             /* spins left after pruning */
+    int32_t rounds;          /* pruning rounds executed */
+    int32_t best_replica;    /* replica whose vertex was returned */
+    int64_t steps;           /* domain-selection steps per replica */
+    int32_t best_step;       /* step at which the returned vertex was first seen */
+    int32_t reserved0;
+    double eta;              /* pruning rate 1 - n_G / n */
+    double constant_C;       /* constant of the reduced problem */
+    double t_upload_ms, t_prune_ms, t_ds_ms, t_finish_ms, t_total_ms;
+    double replica_spin_updates_per_s;  /* n_G * R * T / t_ds */
+    double t_ds_kernel_ms;   /* the domain-selection kernel alone (HIP events around its launch) */
+} ising_stats;
+
+typedef struct ising_ctx ising_ctx;
+typedef struct ising_pruned ising_pruned;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+ising_status ising_create(int device, ising_ctx **out);
+/* Destroy a context; waits for its outstanding work.  NULL is allowed. */
+ising_status ising_destroy(ising_ctx *ctx);
+/* Message of the last failed call on ctx ("" if none).  Valid until the next call. */
+const char *ising_last_error(const ising_ctx *ctx);
+
+/* ---- whole solve (host buffers) ---------------------------------------- */
+
+/* Solve the problem of Sec. II with the pipeline of Fig. 1.
+ * problem: host buffers.  spins_out: n int8 (host).  energy_out: E(s) of the
+ * returned vector on the full instance, recomputed exactly on the device
+ * (FP64 for real J, exact integer for ISING_I32).  energy_int_out (nullable):
+ * the same as int64 for ISING_I32 problems.  stats_out nullable.
+ * Blocking.  Errors: EINVAL for a malformed problem or parameters, ENOTSUP,
+ * ENOMEM, EDEVICE. */
+ising_status ising_solve(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
+                         int8_t *spins_out, double *energy_out, int64_t *energy_int_out,
+                         ising_stats *stats_out);
+
+/* The same pipeline on device buffers: problem, spins_out (n int8),
+ * energy_out (1 double, nullable) and energy_int_out (1 int64, nullable) are
+ * device pointers; stats_out is host memory (nullable).  Work is enqueued on
+ * `stream`; the call returns after it has completed (pruning reads a counter
+ * per round and the stats need the event timings). */
+ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
+                             int8_t *spins_out, double *energy_out, int64_t *energy_int_out,
+                             ising_stats *stats_out, void *stream);
+
+/* ---- exact energy (scalar energy form, Sec. II) ------------------------- */
+
+/* E(s_r) = s_r^T J s_r + h^T s_r for `count` spin vectors (replica-major).
+ * problem and spins are device pointers.  E_out (nullable): count doubles.
+ * E_int_out (nullable, ISING_I32 problems only): count int64, exact.
+ * Real J: each row's sum is FP64 in ascending column order; rows are combined
+ * in a fixed tree order, so results are reproducible run to run. */
+ising_status ising_energy_dev(ising_ctx *ctx, const ising_problem *problem, const int8_t *spins,
+                              int32_t count, double *E_out, int64_t *E_int_out, void *stream);
+
+/* ---- pruning (Sec. III-A, Algorithm 1) and retrieval (Fig. 1c) --------- */
+
+/* Run Algorithm 1 on the device.  problem: device pointers.  Each round takes
+ * the determined spins D (|h_i| > 2 sum_{j active}|J_ij|, strict), folds them
+ * into h and C, then the semi-determined spins S (exactly one active
+ * neighbour k, 2|J_ik| >= |h_i|; of a mutual pair only the larger index),
+ * folds them, and repeats until a round removes nothing.  Row sums of real J
+ * use 64 strided partials combined by an xor butterfly (32,16,8,4,2,1); the
+ * folds add their terms in ascending index.  Synchronises the stream once per
+ * round.  *out receives a handle owning the device-resident reduced problem
+ * and record; free it with ising_pruned_free. */
+ising_status ising_prune_dev(ising_ctx *ctx, const ising_problem *problem, ising_pruned **out,
+                             void *stream);
+void ising_pruned_free(ising_pruned *pruned);
+
+/* Sizes of a pruning result: n, n_G, rounds, nnz of the reduced CSR (0 for
+ * dense) and the constant C of the reduced problem. */
+ising_status ising_pruned_info(const ising_pruned *pruned, int32_t *n, int32_t *n_G,
+                               int32_t *rounds, int64_t *nnz_G, double *C);
+/* Copy the record to device buffers (each nullable; n entries unless noted):
+ * kind (int8: 0 kept, 1 determined, 2 semi-determined), round_of (int32, -1
+ * for kept), fixed (int8 value of determined spins), partner (int32 n(k) of
+ * semi-determined spins, -1 otherwise), sigma (int8 sgn J_k,n(k)), G (int32,
+ * n_G original indices ascending), h_G (n_G values of the reduced problem's
+ * value type, see ising_pruned_problem). */
+ising_status ising_pruned_record_dev(ising_ctx *ctx, const ising_pruned *pruned, int8_t *kind,
+                                     int32_t *round_of, int8_t *fixed, int32_t *partner,
+                                     int8_t *sigma, int32_t *G, void *h_G, void *stream);
+/* The reduced problem (device pointers owned by the handle, valid until
+ * ising_pruned_free).  When nothing was pruned it aliases the input problem
+ * (same pointers and value type); otherwise its value type is ISING_I32 for
+ * integer problems and ISING_F64 otherwise. */
+ising_status ising_pruned_problem(const ising_pruned *pruned, ising_problem *reduced);
+/* Copy the reduced problem into caller device buffers (each nullable): dense
+ * J_G (n_G*n_G) or CSR values, row_ptr (n_G+1), col (nnz_G), and h (n_G; left
+ * untouched when the reduced problem has no field).  Value type as reported
+ * by ising_pruned_problem. */
+ising_status ising_pruned_copy_dev(ising_ctx *ctx, const ising_pruned *pruned, void *J_or_val,
+                                   int32_t *row_ptr, int32_t *col, void *h, void *stream);
+/* Retrieval: s[G] = s_G, then rounds in reverse: s_k = -sigma s_n(k) for
+ * semi-determined spins, the recorded value for determined ones.  s_G: n_G
+ * int8 (device), s_out: n int8 (device). */
+ising_status ising_unprune_dev(ising_ctx *ctx, const ising_pruned *pruned, const int8_t *s_G,
+                               int8_t *s_out, void *stream);
+
+/* ---- domain selection (Sec. III-B), persistent replica-parallel engine -- */
+
+/* Device-resident state of R replicas of an n-spin problem.  Angles and
+ * moments are replica-major (element (r,i) at r*n+i) in the precision chosen
+ * by params->precision (double for FP64, float for FP32). */
+typedef struct ising_ds_state {
+    void *theta;          /* R*n angles */
+    void *m;              /* R*n ADAM first moments (may be NULL for GD) */
+    void *v;              /* R*n ADAM second moments (may be NULL for GD) */
+    int8_t *s_best;       /* R*n vertex with the lowest energy seen */
+    double *e_best;       /* R lowest energy seen (+inf before the first step) */
+    int32_t *best_step;   /* R step index (1-based) of e_best */
+    double *energy_trace; /* nullable: steps*R energies E_t, row t-1-t0 holds step t */
+    double *loss_trace;   /* nullable: steps*R losses L_t */
+} ising_ds_state;
+
+/* Run steps t0+1 .. t0+steps of domain selection on the problem (device
+ * pointers) for params->replicas replicas.  Each step, per replica:
+ * x = sin theta, s = sgn x (sgn 0 = +1), y = J s, E = s^T (y + h),
+ * L = x^T (y - mu s + h), best-vertex update if E < e_best (strict),
+ * g = cos theta (y - mu s + h), GD or ADAM update (bias corrections use the
+ * global step index), theta <- theta - 2 pi rint(theta / 2 pi).
+ * If t0 == 0 the state is initialised first: theta = asin(U) with U from
+ * `uniform` (R*n values of the state precision, nullable) or, when NULL, from
+ * the counter-based SplitMix64 draws U = 2 (top24(splitmix64(seed,
+ * (r << 32) | i)) / 2^24) - 1; m = v = 0; e_best = +inf.  If t0 > 0 the
+ * state is read from `state` and continued.
+ * Energies of integer problems are exact.  One kernel launch per call; every
+ * replica is handled by one workgroup, whose angles and moments stay in
+ * registers across all steps.  ENOTSUP if n is beyond the on-chip limit
+ * (ising_ds_max_n). */
+ising_status ising_ds_dev(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
+                          const void *uniform, int32_t t0, int32_t steps, ising_ds_state *state,
+                          void *stream);
+/* Largest n the persistent engine accepts for a given precision. */
+int32_t ising_ds_max_n(int32_t precision);
+
+/* ---- best replica (argmin) ---------------------------------------------- */
+
+/* *best = argmin_r e_best[r] (lowest index on ties), written to device memory. */
+ising_status ising_select_dev(ising_ctx *ctx, const double *e_best, int32_t replicas, int32_t *best,
+                              void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISING_H */

@@ -1,0 +1,365 @@
+"""Python binding of libising.so (include/ising.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Device
+buffers are torch tensors on the GPU (torch supplies memory and the current
+stream); all work runs in the library's HIP kernels.  Importing this package
+fails loudly when the built library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libising.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_05837_amd.build` "
+                      "(or __graft_entry__.build()); there is no CPU fallback")
+_lib = C.CDLL(LIB_PATH)
+
+ISING_OK, ISING_EINVAL, ISING_ENOMEM, ISING_EDEVICE, ISING_EBUSY, ISING_ETIMEDOUT, ISING_ECANCELED, \
+    ISING_ENOTSUP = range(8)
+ISING_DENSE, ISING_CSR = 0, 1
+ISING_I32, ISING_F32, ISING_F64 = 0, 1, 2
+ISING_OPT_GD, ISING_OPT_ADAM = 0, 1
+ISING_PREC_FP64, ISING_PREC_FP32 = 0, 1
+
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EBUSY", 5: "ETIMEDOUT",
+                6: "ECANCELED", 7: "ENOTSUP"}
+
+
+class IsingError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ising_problem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("format", C.c_int32), ("value_type", C.c_int32), ("reserved0", C.c_int32),
+                ("nnz", C.c_int64), ("J", C.c_void_p), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
+                ("val", C.c_void_p), ("h", C.c_void_p)]
+
+
+class ising_params(C.Structure):
+    _fields_ = [("replicas", C.c_int32), ("steps", C.c_int32), ("optimizer", C.c_int32),
+                ("precision", C.c_int32), ("lr", C.c_double), ("mu", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64), ("prune", C.c_int32),
+                ("reserved0", C.c_int32)]
+
+
+class ising_stats(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_G", C.c_int32), ("rounds", C.c_int32), ("best_replica", C.c_int32),
+                ("steps", C.c_int64), ("best_step", C.c_int32), ("reserved0", C.c_int32), ("eta", C.c_double),
+                ("constant_C", C.c_double), ("t_upload_ms", C.c_double), ("t_prune_ms", C.c_double),
+                ("t_ds_ms", C.c_double), ("t_finish_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("replica_spin_updates_per_s", C.c_double), ("t_ds_kernel_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
+
+
+class ising_ds_state(C.Structure):
+    _fields_ = [("theta", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("s_best", C.c_void_p),
+                ("e_best", C.c_void_p), ("best_step", C.c_void_p), ("energy_trace", C.c_void_p),
+                ("loss_trace", C.c_void_p)]
+
+
+_P = C.c_void_p
+_sigs = {
+    "ising_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
+    "ising_destroy": (C.c_int, [_P]),
+    "ising_last_error": (C.c_char_p, [_P]),
+    "ising_solve": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(ising_params), _P, C.POINTER(C.c_double),
+                              C.POINTER(C.c_int64), C.POINTER(ising_stats)]),
+    "ising_solve_dev": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(ising_params), _P, _P, _P,
+                                  C.POINTER(ising_stats), _P]),
+    "ising_energy_dev": (C.c_int, [_P, C.POINTER(ising_problem), _P, C.c_int32, _P, _P, _P]),
+    "ising_prune_dev": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(C.c_void_p), _P]),
+    "ising_pruned_free": (None, [_P]),
+    "ising_pruned_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "ising_pruned_record_dev": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ising_pruned_problem": (C.c_int, [_P, C.POINTER(ising_problem)]),
+    "ising_pruned_copy_dev": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "ising_unprune_dev": (C.c_int, [_P, _P, _P, _P, _P]),
+    "ising_ds_dev": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(ising_params), _P, C.c_int32, C.c_int32,
+                               C.POINTER(ising_ds_state), _P]),
+    "ising_ds_max_n": (C.c_int32, [C.c_int32]),
+    "ising_select_dev": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
+}
+for _name, (_res, _args) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols():
+    return list(_sigs)
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _check(ctx, status):
+    if status != ISING_OK:
+        msg = _lib.ising_last_error(ctx).decode() if ctx else ""
+        raise IsingError(status, msg)
+
+
+def _vtype(dtype):
+    import torch
+    return {torch.int32: ISING_I32, torch.float32: ISING_F32, torch.float64: ISING_F64}[dtype]
+
+
+def _dtype(vtype):
+    import torch
+    return {ISING_I32: torch.int32, ISING_F32: torch.float32, ISING_F64: torch.float64}[vtype]
+
+
+@dataclass
+class Problem:
+    """An ising_problem plus the tensors that back it (kept alive here)."""
+    n: int
+    format: int
+    value_type: int
+    J: object = None
+    row_ptr: object = None
+    col: object = None
+    val: object = None
+    h: object = None
+    nnz: int = 0
+    keep: list = field(default_factory=list)
+
+    def struct(self) -> ising_problem:
+        return ising_problem(self.n, self.format, self.value_type, 0, self.nnz, _ptr(self.J), _ptr(self.row_ptr),
+                             _ptr(self.col), _ptr(self.val), _ptr(self.h))
+
+
+def dense_problem(J, h=None) -> Problem:
+    """Problem from a dense (n, n) tensor J (int32/float32/float64) and optional h of the same dtype."""
+    n = J.shape[0]
+    return Problem(n, ISING_DENSE, _vtype(J.dtype), J=J.contiguous(), h=None if h is None else h.contiguous())
+
+
+def csr_problem(row_ptr, col, val, h=None) -> Problem:
+    n = row_ptr.shape[0] - 1
+    return Problem(n, ISING_CSR, _vtype(val.dtype), row_ptr=row_ptr.contiguous(), col=col.contiguous(),
+                   val=val.contiguous(), h=None if h is None else h.contiguous(), nnz=int(col.shape[0]))
+
+
+def params(replicas=32, steps=100, optimizer="adam", precision="fp32", lr=6.0, mu=0.5, beta1=0.9,
+           beta2=0.999, eps=1e-8, seed=0, prune=True) -> ising_params:
+    opt = {"gd": ISING_OPT_GD, "adam": ISING_OPT_ADAM}[optimizer] if isinstance(optimizer, str) else optimizer
+    prec = {"fp64": ISING_PREC_FP64, "fp32": ISING_PREC_FP32}[precision] if isinstance(precision, str) \
+        else precision
+    return ising_params(replicas, steps, opt, prec, lr, mu, beta1, beta2, eps, seed, 1 if prune else 0, 0)
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def ising_create(device: int = 0):
+    h = C.c_void_p()
+    _check(None, _lib.ising_create(device, C.byref(h)))
+    return h
+
+
+def ising_destroy(ctx):
+    _check(None, _lib.ising_destroy(ctx))
+
+
+def ising_last_error(ctx) -> str:
+    return _lib.ising_last_error(ctx).decode()
+
+
+def ising_solve(ctx, problem_host: ising_problem, prm: ising_params):
+    """Host-buffer solve.  problem_host points at host memory (numpy arrays kept alive by the caller)."""
+    import numpy as np
+    n = problem_host.n
+    spins = np.zeros(n, dtype=np.int8)
+    e = C.c_double()
+    ei = C.c_int64()
+    st = ising_stats()
+    _check(ctx, _lib.ising_solve(ctx, C.byref(problem_host), C.byref(prm), spins.ctypes.data_as(C.c_void_p),
+                                 C.byref(e), C.byref(ei), C.byref(st)))
+    return spins, e.value, ei.value, st.as_dict()
+
+
+def ising_solve_dev(ctx, problem: Problem, prm: ising_params, spins_out=None, energy_out=None,
+                    energy_int_out=None, stream=None):
+    import torch
+    dev = torch.device("cuda")
+    if spins_out is None:
+        spins_out = torch.empty(problem.n, dtype=torch.int8, device=dev)
+    if energy_out is None:
+        energy_out = torch.empty(1, dtype=torch.float64, device=dev)
+    if energy_int_out is None and problem.value_type == ISING_I32:
+        energy_int_out = torch.empty(1, dtype=torch.int64, device=dev)
+    st = ising_stats()
+    ps = problem.struct()
+    _check(ctx, _lib.ising_solve_dev(ctx, C.byref(ps), C.byref(prm), _ptr(spins_out), _ptr(energy_out),
+                                     _ptr(energy_int_out), C.byref(st), _stream(stream)))
+    return spins_out, energy_out, energy_int_out, st.as_dict()
+
+
+def ising_energy_dev(ctx, problem: Problem, spins, E_out=None, E_int_out=None, stream=None):
+    import torch
+    spins = spins.contiguous()
+    count = spins.shape[0] if spins.dim() == 2 else 1
+    if E_out is None:
+        E_out = torch.empty(count, dtype=torch.float64, device=spins.device)
+    if E_int_out is None and problem.value_type == ISING_I32:
+        E_int_out = torch.empty(count, dtype=torch.int64, device=spins.device)
+    ps = problem.struct()
+    _check(ctx, _lib.ising_energy_dev(ctx, C.byref(ps), _ptr(spins), count, _ptr(E_out), _ptr(E_int_out),
+                                      _stream(stream)))
+    return E_out, E_int_out
+
+
+class Pruned:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.ising_pruned_free(self.handle)
+            self.handle = None
+
+
+def ising_prune_dev(ctx, problem: Problem, stream=None) -> Pruned:
+    h = C.c_void_p()
+    ps = problem.struct()
+    _check(ctx, _lib.ising_prune_dev(ctx, C.byref(ps), C.byref(h), _stream(stream)))
+    return Pruned(h)
+
+
+def ising_pruned_free(pr: Pruned):
+    if pr.handle:
+        _lib.ising_pruned_free(pr.handle)
+        pr.handle = None
+
+
+def ising_pruned_info(pr: Pruned) -> dict:
+    n, nG, rounds, nnz = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+    c = C.c_double()
+    _check(None, _lib.ising_pruned_info(pr.handle, C.byref(n), C.byref(nG), C.byref(rounds), C.byref(nnz),
+                                        C.byref(c)))
+    return dict(n=n.value, n_G=nG.value, rounds=rounds.value, nnz_G=nnz.value, C=c.value)
+
+
+def ising_pruned_problem(pr: Pruned) -> ising_problem:
+    p = ising_problem()
+    _check(None, _lib.ising_pruned_problem(pr.handle, C.byref(p)))
+    return p
+
+
+def ising_pruned_record_dev(ctx, pr: Pruned, stream=None) -> dict:
+    import torch
+    info = ising_pruned_info(pr)
+    n, nG = info["n"], info["n_G"]
+    red = ising_pruned_problem(pr)
+    dev = torch.device("cuda")
+    out = dict(kind=torch.empty(n, dtype=torch.int8, device=dev),
+               round_of=torch.empty(n, dtype=torch.int32, device=dev),
+               fixed=torch.empty(n, dtype=torch.int8, device=dev),
+               partner=torch.empty(n, dtype=torch.int32, device=dev),
+               sigma=torch.empty(n, dtype=torch.int8, device=dev),
+               G=torch.empty(max(nG, 1), dtype=torch.int32, device=dev),
+               h_G=torch.zeros(max(nG, 1), dtype=_dtype(red.value_type), device=dev))
+    _check(ctx, _lib.ising_pruned_record_dev(ctx, pr.handle, _ptr(out["kind"]), _ptr(out["round_of"]),
+                                             _ptr(out["fixed"]), _ptr(out["partner"]), _ptr(out["sigma"]),
+                                             _ptr(out["G"]), _ptr(out["h_G"]), _stream(stream)))
+    out["G"] = out["G"][:nG]
+    out["h_G"] = out["h_G"][:nG]
+    return out
+
+
+def ising_pruned_copy_dev(ctx, pr: Pruned, stream=None) -> Problem:
+    """The reduced problem copied into fresh tensors."""
+    import torch
+    red = ising_pruned_problem(pr)
+    dev = torch.device("cuda")
+    dt = _dtype(red.value_type)
+    nG = red.n
+    if red.format == ISING_DENSE:
+        J = torch.zeros((nG, nG), dtype=dt, device=dev)
+        h = torch.zeros(nG, dtype=dt, device=dev)
+        _check(ctx, _lib.ising_pruned_copy_dev(ctx, pr.handle, _ptr(J), None, None, _ptr(h), _stream(stream)))
+        return Problem(nG, ISING_DENSE, red.value_type, J=J, h=h)
+    rp = torch.zeros(nG + 1, dtype=torch.int32, device=dev)
+    col = torch.zeros(max(red.nnz, 1), dtype=torch.int32, device=dev)
+    val = torch.zeros(max(red.nnz, 1), dtype=dt, device=dev)
+    h = torch.zeros(max(nG, 1), dtype=dt, device=dev)
+    _check(ctx, _lib.ising_pruned_copy_dev(ctx, pr.handle, _ptr(val), _ptr(rp), _ptr(col), _ptr(h),
+                                           _stream(stream)))
+    return Problem(nG, ISING_CSR, red.value_type, row_ptr=rp, col=col[:red.nnz], val=val[:red.nnz],
+                   h=h[:nG], nnz=int(red.nnz))
+
+
+def ising_unprune_dev(ctx, pr: Pruned, s_G, s_out=None, stream=None):
+    import torch
+    n = ising_pruned_info(pr)["n"]
+    if s_out is None:
+        s_out = torch.empty(n, dtype=torch.int8, device=torch.device("cuda"))
+    _check(ctx, _lib.ising_unprune_dev(ctx, pr.handle, _ptr(s_G), _ptr(s_out), _stream(stream)))
+    return s_out
+
+
+def ising_ds_max_n(precision=ISING_PREC_FP32) -> int:
+    return _lib.ising_ds_max_n(precision)
+
+
+def ds_state(n: int, replicas: int, precision="fp32", optimizer="adam", steps_trace: int = 0):
+    """Allocate an ising_ds_state's tensors (dict) on the current device."""
+    import torch
+    dev = torch.device("cuda")
+    dt = torch.float64 if precision in ("fp64", ISING_PREC_FP64) else torch.float32
+    st = dict(theta=torch.zeros((replicas, n), dtype=dt, device=dev),
+              m=torch.zeros((replicas, n), dtype=dt, device=dev),
+              v=torch.zeros((replicas, n), dtype=dt, device=dev),
+              s_best=torch.zeros((replicas, n), dtype=torch.int8, device=dev),
+              e_best=torch.zeros(replicas, dtype=torch.float64, device=dev),
+              best_step=torch.zeros(replicas, dtype=torch.int32, device=dev))
+    if steps_trace:
+        st["energy_trace"] = torch.zeros((steps_trace, replicas), dtype=torch.float64, device=dev)
+        st["loss_trace"] = torch.zeros((steps_trace, replicas), dtype=torch.float64, device=dev)
+    return st
+
+
+def ising_ds_dev(ctx, problem, prm: ising_params, state: dict, t0: int = 0, steps: Optional[int] = None,
+                 uniform=None, stream=None):
+    """Run domain selection steps t0+1..t0+steps on `state` (tensors from ds_state)."""
+    ps = problem.struct() if isinstance(problem, Problem) else problem
+    steps = prm.steps if steps is None else steps
+    st = ising_ds_state(_ptr(state["theta"]), _ptr(state.get("m")), _ptr(state.get("v")), _ptr(state["s_best"]),
+                        _ptr(state["e_best"]), _ptr(state["best_step"]), _ptr(state.get("energy_trace")),
+                        _ptr(state.get("loss_trace")))
+    _check(ctx, _lib.ising_ds_dev(ctx, C.byref(ps), C.byref(prm), _ptr(uniform), t0, steps, C.byref(st),
+                                  _stream(stream)))
+    return state
+
+
+def ising_select_dev(ctx, e_best, best=None, stream=None):
+    import torch
+    if best is None:
+        best = torch.empty(1, dtype=torch.int32, device=e_best.device)
+    _check(ctx, _lib.ising_select_dev(ctx, _ptr(e_best), int(e_best.shape[0]), _ptr(best), _stream(stream)))
+    return best

@@ -1,0 +1,710 @@
+// Host runtime behind include/ising.h: contexts, device buffers, ingest checks,
+// the pruning round loop, the domain-selection launch and the whole-solve
+// pipeline.  All arithmetic of the method runs in the kernels; this file only
+// allocates, launches, synchronises and copies.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace ising;
+
+namespace {
+
+struct Pool {
+    struct Entry {
+        void *p = nullptr;
+        size_t bytes = 0;
+    };
+    std::map<std::string, Entry> m;
+    hipError_t get(const std::string &key, size_t bytes, void **out) {
+        Entry &e = m[key];
+        if (bytes == 0) bytes = 8;
+        if (e.bytes < bytes) {
+            if (e.p) {
+                hipError_t er = hipFree(e.p);
+                if (er != hipSuccess) return er;
+            }
+            e.p = nullptr;
+            e.bytes = 0;
+            hipError_t er = hipMalloc(&e.p, bytes);
+            if (er != hipSuccess) return er;
+            e.bytes = bytes;
+        }
+        *out = e.p;
+        return hipSuccess;
+    }
+    void release() {
+        for (auto &kv : m)
+            if (kv.second.p) (void)hipFree(kv.second.p);
+        m.clear();
+    }
+    ~Pool() { release(); }
+};
+
+}  // namespace
+
+struct ising_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    Pool pool;
+    std::mutex mu;
+};
+
+struct ising_pruned {
+    int device = 0;
+    int32_t n = 0, nG = 0, rounds = 0;
+    int64_t nnzG = 0;
+    int32_t vtype = ISING_I32;  // input value type
+    int32_t format = ISING_DENSE;
+    bool identity = true;
+    double C = 0.0;
+    PruneWork w{};
+    ising_problem reduced{};
+    Pool own;        // buffers when the handle owns them
+    Pool *pool = nullptr;
+};
+
+namespace {
+
+ising_status fail(ising_ctx *ctx, ising_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                     \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess)                                                                  \
+            return fail((ctx), _e == hipErrorOutOfMemory ? ISING_ENOMEM : ISING_EDEVICE,        \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));                    \
+    } while (0)
+
+#define ST_TRY(expr)                          \
+    do {                                      \
+        ising_status _s = (expr);             \
+        if (_s != ISING_OK) return _s;        \
+    } while (0)
+
+ising_status check_problem_shape(ising_ctx *ctx, const ising_problem *p) {
+    if (!p) return fail(ctx, ISING_EINVAL, "problem is NULL");
+    if (p->n <= 0) return fail(ctx, ISING_EINVAL, "n must be positive");
+    if (p->value_type < ISING_I32 || p->value_type > ISING_F64)
+        return fail(ctx, ISING_EINVAL, "unknown value_type");
+    if (p->format == ISING_DENSE) {
+        if (!p->J) return fail(ctx, ISING_EINVAL, "dense problem without J");
+    } else if (p->format == ISING_CSR) {
+        if (!p->row_ptr || (p->nnz > 0 && (!p->col || !p->val)) || p->nnz < 0 || p->nnz > INT32_MAX)
+            return fail(ctx, ISING_EINVAL, "malformed CSR pointers or nnz");
+    } else {
+        return fail(ctx, ISING_EINVAL, "unknown format");
+    }
+    return ISING_OK;
+}
+
+struct Ingest {
+    int32_t flags[4] = {0, 0, 1, 1};
+    bool integer() const { return flags[3] != 0; }
+    bool uniform_mag() const { return flags[2] != 0; }
+    int maxdeg() const { return flags[1]; }
+    double w = 1.0;
+};
+
+ising_status ingest(ising_ctx *ctx, const DevProblem &p, Pool &pool, Ingest &out, hipStream_t s) {
+    void *flags = nullptr, *wdev = nullptr;
+    HIP_TRY(ctx, pool.get("ingest.flags", 16, &flags));
+    HIP_TRY(ctx, pool.get("ingest.w", 8, &wdev));
+    HIP_TRY(ctx, launch_validate(p, (int32_t *)flags, (double *)wdev, s));
+    HIP_TRY(ctx, hipMemcpyAsync(out.flags, flags, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(&out.w, wdev, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const int bits = out.flags[0];
+    if (bits & 1) return fail(ctx, ISING_EINVAL, "J is not symmetric");
+    if (bits & 2) return fail(ctx, ISING_EINVAL, "J has a nonzero diagonal entry");
+    if (bits & 4) return fail(ctx, ISING_EINVAL, "bad CSR structure (row_ptr, range or unsorted/duplicate columns)");
+    if (bits & 8) return fail(ctx, ISING_EINVAL, "non-finite value in J or h");
+    return ISING_OK;
+}
+
+// ---- pruning core ---------------------------------------------------------
+
+ising_status prune_core(ising_ctx *ctx, const DevProblem &p, ising_pruned &pr, hipStream_t s) {
+    Pool &pool = *pr.pool;
+    const int n = p.n;
+    const bool integer = p.vtype == ISING_I32;
+    PruneWork &w = pr.w;
+    auto g8 = [&](const char *k, int8_t **o) { return pool.get(std::string("pr.") + k, n, (void **)o); };
+    auto g32 = [&](const char *k, int32_t **o) { return pool.get(std::string("pr.") + k, (size_t)n * 4, (void **)o); };
+    HIP_TRY(ctx, g8("active", &w.active));
+    HIP_TRY(ctx, g8("isD", &w.isD));
+    HIP_TRY(ctx, g8("isS", &w.isS));
+    HIP_TRY(ctx, g8("cand", &w.cand));
+    HIP_TRY(ctx, g8("kind", &w.kind));
+    HIP_TRY(ctx, g8("fixed", &w.fixed));
+    HIP_TRY(ctx, g8("sigma", &w.sigma));
+    HIP_TRY(ctx, g32("round", &w.round_of));
+    HIP_TRY(ctx, g32("partner", &w.partner));
+    HIP_TRY(ctx, g32("nb", &w.nb));
+    HIP_TRY(ctx, g32("map", &w.map));
+    HIP_TRY(ctx, g32("G", &w.G));
+    HIP_TRY(ctx, pool.get("pr.h", (size_t)n * 8, &w.h));
+    HIP_TRY(ctx, pool.get("pr.jv", (size_t)n * 8, &w.jv));
+    HIP_TRY(ctx, pool.get("pr.cpart", (size_t)n * 8, &w.cpart));
+    HIP_TRY(ctx, pool.get("pr.C", 8, &w.C));
+    HIP_TRY(ctx, pool.get("pr.counts", 16, (void **)&w.counts));
+
+    pr.n = n;
+    pr.vtype = p.vtype;
+    pr.format = p.format;
+    HIP_TRY(ctx, launch_prune_init(p, w, s));
+    int32_t counts[4] = {0, 0, 0, 0};
+    int round = 0;
+    for (;;) {
+        HIP_TRY(ctx, launch_prune_round(p, w, round, s));
+        HIP_TRY(ctx, hipMemcpyAsync(counts, w.counts, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        ++round;
+        if (counts[0] == 0 && counts[1] == 0) break;
+        if (round > n + 1) return fail(ctx, ISING_EDEVICE, "pruning did not terminate");
+    }
+    pr.rounds = round;
+    if (integer) {
+        int64_t c = 0;
+        HIP_TRY(ctx, hipMemcpyAsync(&c, w.C, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        pr.C = (double)c;
+    } else {
+        HIP_TRY(ctx, hipMemcpyAsync(&pr.C, w.C, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+    }
+    HIP_TRY(ctx, launch_prune_compact_scan(p, w, s));
+    HIP_TRY(ctx, hipMemcpyAsync(counts, w.counts, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const int nG = counts[2];
+    pr.nG = nG;
+    pr.identity = (nG == n);
+    ising_problem &r = pr.reduced;
+    std::memset(&r, 0, sizeof(r));
+    if (pr.identity) {
+        r.n = n;
+        r.format = p.format;
+        r.value_type = p.vtype;
+        r.nnz = p.nnz;
+        r.J = p.J;
+        r.row_ptr = p.row_ptr;
+        r.col = p.col;
+        r.val = p.val;
+        r.h = p.h;
+        pr.nnzG = p.format == ISING_CSR ? p.nnz : 0;
+        return ISING_OK;
+    }
+    const int ovt = integer ? ISING_I32 : ISING_F64;
+    const size_t osz = integer ? 4 : 8;
+    r.n = nG;
+    r.format = p.format;
+    r.value_type = ovt;
+    if (nG == 0) {
+        pr.nnzG = 0;
+        return ISING_OK;
+    }
+    void *hG = nullptr;
+    HIP_TRY(ctx, pool.get("pr.hG", (size_t)nG * osz, &hG));
+    r.h = hG;
+    if (p.format == ISING_DENSE) {
+        void *JG = nullptr;
+        HIP_TRY(ctx, pool.get("pr.JG", (size_t)nG * nG * osz, &JG));
+        HIP_TRY(ctx, launch_prune_gather_dense(p, w, nG, JG, hG, s));
+        r.J = JG;
+        pr.nnzG = 0;
+    } else {
+        int32_t *rp = nullptr;
+        HIP_TRY(ctx, pool.get("pr.rpG", (size_t)(nG + 1) * 4, (void **)&rp));
+        HIP_TRY(ctx, launch_prune_csr_count(p, w, nG, rp, s));
+        HIP_TRY(ctx, hipMemcpyAsync(counts, w.counts, 16, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        const int64_t nnzG = counts[3];
+        int32_t *cG = nullptr;
+        void *vG = nullptr;
+        HIP_TRY(ctx, pool.get("pr.colG", (size_t)std::max<int64_t>(nnzG, 1) * 4, (void **)&cG));
+        HIP_TRY(ctx, pool.get("pr.valG", (size_t)std::max<int64_t>(nnzG, 1) * osz, &vG));
+        HIP_TRY(ctx, launch_prune_csr_fill(p, w, nG, rp, cG, vG, hG, s));
+        r.row_ptr = rp;
+        r.col = cG;
+        r.val = vG;
+        r.nnz = nnzG;
+        pr.nnzG = nnzG;
+    }
+    return ISING_OK;
+}
+
+// ---- domain-selection launch planning -------------------------------------
+
+struct DSPlan {
+    DSLaunch l;
+    bool packed = false;
+};
+
+ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
+                     DSPlan &plan) {
+    const bool fp64 = prm.precision == ISING_PREC_FP64;
+    if (prm.precision != ISING_PREC_FP64 && prm.precision != ISING_PREC_FP32)
+        return fail(ctx, ISING_ENOTSUP, "precision not supported by the persistent engine");
+    const int n = p.n, R = prm.replicas;
+    if (n > ds_max_n(fp64)) return fail(ctx, ISING_ENOTSUP, "n exceeds the on-chip vertex-buffer limit");
+    DSLaunch &l = plan.l;
+    l.fp64 = fp64;
+    plan.packed = p.format == ISING_CSR && ing.uniform_mag();
+    l.coupling = p.format == ISING_DENSE ? CK_DENSE : (plan.packed ? CK_PM : CK_CSRV);
+    // register-resident engine while at most 4 (spin, replica) elements per thread
+    // fit, else the streaming engine; replicas per workgroup chosen so that there
+    // are at least as many workgroups as compute units where R allows it
+    int rg = 1;
+    if (!fp64) {
+        for (int cand : {4, 2}) {
+            if (R % cand) continue;
+            if (R / cand < 256) continue;
+            if (plan.packed && cand == 4 && ing.maxdeg() > 255) continue;
+            rg = cand;
+            break;
+        }
+    }
+    int ept = 0;
+    const int maxept = fp64 ? 2 : (rg == 4 ? 2 : 4);
+    for (int e = 1; e <= maxept; e *= 2) {
+        if ((int64_t)e * 1024 >= n) {
+            ept = e;
+            break;
+        }
+    }
+    if (ept == 0) {
+        // streaming: spins triple-buffered in LDS
+        const size_t sw = rg == 1 ? 1 : 4;
+        while (rg > 1 && (size_t)3 * n * sw > 120 * 1024) {
+            rg /= 2;
+            if (R % rg) rg = 1;
+        }
+        if ((size_t)3 * n * (rg == 1 ? 1 : 4) > 150 * 1024)
+            return fail(ctx, ISING_ENOTSUP, "n too large for the on-chip vertex buffers");
+        l.rg = rg;
+        l.ept = 0;
+        l.block = 1024;
+        return ISING_OK;
+    }
+    l.rg = rg;
+    l.ept = ept;
+    const int per = (n + ept - 1) / ept;
+    l.block = std::max(64, (per + 63) / 64 * 64);
+    return ISING_OK;
+}
+
+ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
+                    const void *uniform, int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool,
+                    hipStream_t s, hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr) {
+    if (prm.replicas <= 0 || steps < 0 || t0 < 0) return fail(ctx, ISING_EINVAL, "bad replicas/steps/t0");
+    if (prm.optimizer != ISING_OPT_GD && prm.optimizer != ISING_OPT_ADAM)
+        return fail(ctx, ISING_EINVAL, "unknown optimizer");
+    if (!st || !st->theta || !st->s_best || !st->e_best || !st->best_step)
+        return fail(ctx, ISING_EINVAL, "state buffers missing");
+    if (prm.optimizer == ISING_OPT_ADAM && (!st->m || !st->v))
+        return fail(ctx, ISING_EINVAL, "ADAM needs m and v buffers");
+    DSPlan plan;
+    ST_TRY(plan_ds(ctx, p, prm, ing, plan));
+    const bool fp64 = plan.l.fp64;
+    const size_t real = fp64 ? 8 : 4;
+    const DevProblem dp = to_dev(p);
+    DSArgs a;
+    a.n = p.n;
+    a.R = prm.replicas;
+    a.t0 = t0;
+    a.steps = steps;
+    a.opt = prm.optimizer;
+    a.init_mode = t0 > 0 ? 0 : (uniform ? 1 : 2);
+    a.seed = prm.seed;
+    a.lr = prm.lr;
+    a.mu = prm.mu;
+    a.b1 = prm.beta1;
+    a.b2 = prm.beta2;
+    a.eps = prm.eps;
+    a.w = ing.w;
+    const int64_t total = p.format == ISING_DENSE ? (int64_t)p.n * p.n : p.nnz;
+    void *fmt = nullptr, *hbuf = nullptr;
+    HIP_TRY(ctx, pool.get("ds.fmt", (size_t)std::max<int64_t>(total, 1) * (plan.packed ? 4 : real), &fmt));
+    if (p.h) HIP_TRY(ctx, pool.get("ds.h", (size_t)p.n * real, &hbuf));
+    HIP_TRY(ctx, launch_ds_format(dp, fp64, plan.packed, (uint32_t *)fmt, fmt, p.h ? hbuf : nullptr, s));
+    a.row_ptr = p.row_ptr;
+    a.col = p.col;
+    if (plan.packed) a.pm = (const uint32_t *)fmt;
+    else if (p.format == ISING_CSR) a.val = fmt;
+    else a.J = fmt;
+    a.h = p.h ? hbuf : nullptr;
+    a.theta = st->theta;
+    a.m = prm.optimizer == ISING_OPT_ADAM ? st->m : nullptr;
+    a.v = prm.optimizer == ISING_OPT_ADAM ? st->v : nullptr;
+    a.uniform = uniform;
+    a.s_best = st->s_best;
+    a.e_best = st->e_best;
+    a.best_step = st->best_step;
+    a.etrace = st->energy_trace;
+    a.ltrace = st->loss_trace;
+    if (prm.optimizer == ISING_OPT_ADAM && steps > 0) {
+        void *bias = nullptr;
+        HIP_TRY(ctx, pool.get("ds.bias", (size_t)2 * steps * real, &bias));
+        HIP_TRY(ctx, launch_bias_table(prm.beta1, prm.beta2, t0, steps, fp64, bias, s));
+        a.bias = bias;
+    }
+    if (kbeg) HIP_TRY(ctx, hipEventRecord(kbeg, s));
+    hipError_t e = launch_ds(a, plan.l, s);
+    if (kend && e == hipSuccess) HIP_TRY(ctx, hipEventRecord(kend, s));
+    if (e != hipSuccess)
+        return fail(ctx, e == hipErrorInvalidValue ? ISING_ENOTSUP : ISING_EDEVICE,
+                    std::string("domain-selection launch: ") + hipGetErrorString(e));
+    return ISING_OK;
+}
+
+double ms_between(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+ising_status ising_create(int device, ising_ctx **out) {
+    if (!out) return ISING_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return ISING_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return ISING_EDEVICE;
+    auto *c = new (std::nothrow) ising_ctx();
+    if (!c) return ISING_ENOMEM;
+    c->device = device;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return ISING_EDEVICE;
+    }
+    *out = c;
+    return ISING_OK;
+}
+
+ising_status ising_destroy(ising_ctx *ctx) {
+    if (!ctx) return ISING_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipDeviceSynchronize();
+    ctx->pool.release();
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return ISING_OK;
+}
+
+const char *ising_last_error(const ising_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+ising_status ising_energy_dev(ising_ctx *ctx, const ising_problem *problem, const int8_t *spins, int32_t count,
+                              double *E_out, int64_t *E_int_out, void *stream) {
+    if (!ctx) return ISING_EINVAL;
+    ST_TRY(check_problem_shape(ctx, problem));
+    if (count < 0 || (count > 0 && !spins)) return fail(ctx, ISING_EINVAL, "bad spins/count");
+    if (E_int_out && problem->value_type != ISING_I32)
+        return fail(ctx, ISING_EINVAL, "integer energies need an ISING_I32 problem");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    void *partial = nullptr;
+    HIP_TRY(ctx, ctx->pool.get("energy.partial", energy_partial_bytes(problem->n, count), &partial));
+    HIP_TRY(ctx, launch_energy(to_dev(*problem), spins, count, partial, E_out, E_int_out, s));
+    return ISING_OK;
+}
+
+ising_status ising_prune_dev(ising_ctx *ctx, const ising_problem *problem, ising_pruned **out, void *stream) {
+    if (!ctx || !out) return ISING_EINVAL;
+    *out = nullptr;
+    ST_TRY(check_problem_shape(ctx, problem));
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Ingest ing;
+    ST_TRY(ingest(ctx, to_dev(*problem), ctx->pool, ing, s));
+    auto pr = std::make_unique<ising_pruned>();
+    pr->device = ctx->device;
+    pr->pool = &pr->own;
+    ST_TRY(prune_core(ctx, to_dev(*problem), *pr, s));
+    *out = pr.release();
+    return ISING_OK;
+}
+
+void ising_pruned_free(ising_pruned *pruned) {
+    if (!pruned) return;
+    (void)hipSetDevice(pruned->device);
+    (void)hipDeviceSynchronize();
+    delete pruned;
+}
+
+ising_status ising_pruned_info(const ising_pruned *pr, int32_t *n, int32_t *n_G, int32_t *rounds, int64_t *nnz_G,
+                               double *C) {
+    if (!pr) return ISING_EINVAL;
+    if (n) *n = pr->n;
+    if (n_G) *n_G = pr->nG;
+    if (rounds) *rounds = pr->rounds;
+    if (nnz_G) *nnz_G = pr->nnzG;
+    if (C) *C = pr->C;
+    return ISING_OK;
+}
+
+ising_status ising_pruned_record_dev(ising_ctx *ctx, const ising_pruned *pr, int8_t *kind, int32_t *round_of,
+                                     int8_t *fixed, int32_t *partner, int8_t *sigma, int32_t *G, void *h_G,
+                                     void *stream) {
+    if (!ctx || !pr) return ISING_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, launch_copy_record(pr->w, pr->n, kind, round_of, fixed, partner, sigma, s));
+    if (G && pr->nG > 0) {
+        if (pr->identity) {
+            std::vector<int32_t> idx(pr->n);
+            for (int i = 0; i < pr->n; ++i) idx[i] = i;
+            HIP_TRY(ctx, hipMemcpyAsync(G, idx.data(), (size_t)pr->n * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(ctx, hipStreamSynchronize(s));
+        } else {
+            HIP_TRY(ctx, hipMemcpyAsync(G, pr->w.G, (size_t)pr->nG * 4, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    if (h_G && pr->nG > 0 && pr->reduced.h) {
+        const size_t sz = pr->identity ? vsize(pr->vtype) : (pr->vtype == ISING_I32 ? 4 : 8);
+        HIP_TRY(ctx, hipMemcpyAsync(h_G, pr->reduced.h, (size_t)pr->nG * sz, hipMemcpyDeviceToDevice, s));
+    }
+    return ISING_OK;
+}
+
+ising_status ising_pruned_problem(const ising_pruned *pr, ising_problem *reduced) {
+    if (!pr || !reduced) return ISING_EINVAL;
+    *reduced = pr->reduced;
+    return ISING_OK;
+}
+
+ising_status ising_pruned_copy_dev(ising_ctx *ctx, const ising_pruned *pr, void *J_or_val, int32_t *row_ptr,
+                                   int32_t *col, void *h, void *stream) {
+    if (!ctx || !pr) return ISING_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const ising_problem &r = pr->reduced;
+    if (r.n == 0) return ISING_OK;
+    const size_t vs = vsize(r.value_type);
+    if (r.format == ISING_DENSE) {
+        if (J_or_val) HIP_TRY(ctx, hipMemcpyAsync(J_or_val, r.J, (size_t)r.n * r.n * vs, hipMemcpyDeviceToDevice, s));
+    } else {
+        if (row_ptr) HIP_TRY(ctx, hipMemcpyAsync(row_ptr, r.row_ptr, (size_t)(r.n + 1) * 4, hipMemcpyDeviceToDevice, s));
+        if (col && r.nnz) HIP_TRY(ctx, hipMemcpyAsync(col, r.col, (size_t)r.nnz * 4, hipMemcpyDeviceToDevice, s));
+        if (J_or_val && r.nnz) HIP_TRY(ctx, hipMemcpyAsync(J_or_val, r.val, (size_t)r.nnz * vs, hipMemcpyDeviceToDevice, s));
+    }
+    if (h && r.h) HIP_TRY(ctx, hipMemcpyAsync(h, r.h, (size_t)r.n * vs, hipMemcpyDeviceToDevice, s));
+    return ISING_OK;
+}
+
+ising_status ising_unprune_dev(ising_ctx *ctx, const ising_pruned *pr, const int8_t *s_G, int8_t *s_out,
+                               void *stream) {
+    if (!ctx || !pr || !s_out || (pr->nG > 0 && !s_G)) return ISING_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (pr->identity) {
+        HIP_TRY(ctx, hipMemcpyAsync(s_out, s_G, pr->n, hipMemcpyDeviceToDevice, s));
+        return ISING_OK;
+    }
+    HIP_TRY(ctx, launch_unprune(pr->w, pr->n, pr->rounds, s_G, s_out, s));
+    return ISING_OK;
+}
+
+int32_t ising_ds_max_n(int32_t precision) { return ds_max_n(precision == ISING_PREC_FP64); }
+
+ising_status ising_ds_dev(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
+                          const void *uniform, int32_t t0, int32_t steps, ising_ds_state *state, void *stream) {
+    if (!ctx || !params) return ISING_EINVAL;
+    ST_TRY(check_problem_shape(ctx, problem));
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Ingest ing;
+    ST_TRY(ingest(ctx, to_dev(*problem), ctx->pool, ing, s));
+    return run_ds(ctx, *problem, *params, ing, uniform, t0, steps, state, ctx->pool, s);
+}
+
+ising_status ising_select_dev(ising_ctx *ctx, const double *e_best, int32_t replicas, int32_t *best,
+                              void *stream) {
+    if (!ctx || !e_best || !best || replicas <= 0) return ISING_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_select(e_best, replicas, best, (hipStream_t)stream));
+    return ISING_OK;
+}
+
+// Whole solve on device buffers.  Blocking (pruning reads a counter per round).
+ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
+                             int8_t *spins_out, double *energy_out, int64_t *energy_int_out,
+                             ising_stats *stats_out, void *stream) {
+    if (!ctx || !params || !spins_out) return ISING_EINVAL;
+    ST_TRY(check_problem_shape(ctx, problem));
+    if (params->replicas <= 0 || params->steps < 0) return fail(ctx, ISING_EINVAL, "bad replicas/steps");
+    if (energy_int_out && problem->value_type != ISING_I32)
+        return fail(ctx, ISING_EINVAL, "integer energies need an ISING_I32 problem");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Pool &pool = ctx->pool;
+    hipEvent_t ev[7];
+    for (auto &e : ev) HIP_TRY(ctx, hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int k = 0; k < 7; ++k) (void)hipEventDestroy(e[k]);
+        }
+    } guard{ev};
+    const auto t_host0 = std::chrono::steady_clock::now();
+    HIP_TRY(ctx, hipEventRecord(ev[0], s));
+    const DevProblem dp = to_dev(*problem);
+    Ingest ing;
+    ST_TRY(ingest(ctx, dp, pool, ing, s));
+    HIP_TRY(ctx, hipEventRecord(ev[1], s));
+
+    ising_pruned pr;
+    pr.device = ctx->device;
+    pr.pool = &pool;
+    const ising_problem *red = problem;
+    if (params->prune) {
+        ST_TRY(prune_core(ctx, dp, pr, s));
+        red = &pr.reduced;
+    } else {
+        pr.n = pr.nG = problem->n;
+        pr.identity = true;
+        pr.rounds = 0;
+    }
+    HIP_TRY(ctx, hipEventRecord(ev[2], s));
+    const int nG = red->n;
+    const int R = params->replicas;
+    const size_t real = params->precision == ISING_PREC_FP64 ? 8 : 4;
+    int32_t *bestdev = nullptr;
+    int8_t *sG = nullptr;
+    HIP_TRY(ctx, pool.get("solve.best", 8, (void **)&bestdev));
+    HIP_TRY(ctx, pool.get("solve.sG", std::max(nG, 1), (void **)&sG));
+    int32_t best_replica = -1, best_step = 0;
+    if (nG > 0) {
+        ising_ds_state st{};
+        HIP_TRY(ctx, pool.get("solve.theta", (size_t)nG * R * real, &st.theta));
+        if (params->optimizer == ISING_OPT_ADAM) {
+            HIP_TRY(ctx, pool.get("solve.m", (size_t)nG * R * real, &st.m));
+            HIP_TRY(ctx, pool.get("solve.v", (size_t)nG * R * real, &st.v));
+        }
+        HIP_TRY(ctx, pool.get("solve.sbest", (size_t)nG * R, (void **)&st.s_best));
+        HIP_TRY(ctx, pool.get("solve.ebest", (size_t)R * 8, (void **)&st.e_best));
+        HIP_TRY(ctx, pool.get("solve.bstep", (size_t)R * 4, (void **)&st.best_step));
+        ST_TRY(run_ds(ctx, *red, *params, ing, nullptr, 0, params->steps, &st, pool, s, ev[5], ev[6]));
+        HIP_TRY(ctx, hipEventRecord(ev[3], s));
+        HIP_TRY(ctx, launch_select(st.e_best, R, bestdev, s));
+        HIP_TRY(ctx, launch_gather_row(st.s_best, nG, bestdev, sG, s));
+        HIP_TRY(ctx, hipMemcpyAsync(&best_replica, bestdev, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        if (best_replica >= 0 && best_replica < R)
+            HIP_TRY(ctx, hipMemcpyAsync(&best_step, st.best_step + best_replica, 4, hipMemcpyDeviceToHost, s));
+    } else {
+        HIP_TRY(ctx, hipEventRecord(ev[3], s));
+    }
+    if (pr.identity) {
+        HIP_TRY(ctx, hipMemcpyAsync(spins_out, sG, problem->n, hipMemcpyDeviceToDevice, s));
+    } else {
+        HIP_TRY(ctx, launch_unprune(pr.w, pr.n, pr.rounds, sG, spins_out, s));
+    }
+    if (energy_out || energy_int_out) {
+        void *partial = nullptr;
+        HIP_TRY(ctx, pool.get("energy.partial", energy_partial_bytes(problem->n, 1), &partial));
+        HIP_TRY(ctx, launch_energy(dp, spins_out, 1, partial, energy_out, energy_int_out, s));
+    }
+    HIP_TRY(ctx, hipEventRecord(ev[4], s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const double host_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host0).count();
+    if (stats_out) {
+        ising_stats &o = *stats_out;
+        std::memset(&o, 0, sizeof(o));
+        o.n = problem->n;
+        o.n_G = nG;
+        o.rounds = pr.rounds;
+        o.best_replica = best_replica;
+        o.steps = params->steps;
+        o.best_step = best_step;
+        o.eta = 1.0 - (double)nG / problem->n;
+        o.constant_C = params->prune ? pr.C : 0.0;
+        o.t_upload_ms = ms_between(ev[0], ev[1]);
+        o.t_prune_ms = ms_between(ev[1], ev[2]);
+        o.t_ds_ms = ms_between(ev[2], ev[3]);
+        o.t_finish_ms = ms_between(ev[3], ev[4]);
+        o.t_total_ms = host_ms;
+        o.t_ds_kernel_ms = nG > 0 ? ms_between(ev[5], ev[6]) : 0.0;
+        o.replica_spin_updates_per_s =
+            o.t_ds_ms > 0 ? (double)nG * R * params->steps / (o.t_ds_ms * 1e-3) : 0.0;
+    }
+    return ISING_OK;
+}
+
+ising_status ising_solve(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
+                         int8_t *spins_out, double *energy_out, int64_t *energy_int_out, ising_stats *stats_out) {
+    if (!ctx || !params || !spins_out) return ISING_EINVAL;
+    ST_TRY(check_problem_shape(ctx, problem));
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    Pool &pool = ctx->pool;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int n = problem->n;
+    const size_t vs = vsize(problem->value_type);
+    ising_problem d = *problem;
+    void *buf = nullptr;
+    if (problem->format == ISING_DENSE) {
+        HIP_TRY(ctx, pool.get("in.J", (size_t)n * n * vs, &buf));
+        HIP_TRY(ctx, hipMemcpyAsync(buf, problem->J, (size_t)n * n * vs, hipMemcpyHostToDevice, s));
+        d.J = buf;
+    } else {
+        void *rp = nullptr, *c = nullptr, *v = nullptr;
+        HIP_TRY(ctx, pool.get("in.rp", (size_t)(n + 1) * 4, &rp));
+        HIP_TRY(ctx, pool.get("in.col", (size_t)std::max<int64_t>(problem->nnz, 1) * 4, &c));
+        HIP_TRY(ctx, pool.get("in.val", (size_t)std::max<int64_t>(problem->nnz, 1) * vs, &v));
+        HIP_TRY(ctx, hipMemcpyAsync(rp, problem->row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, s));
+        if (problem->nnz > 0) {
+            HIP_TRY(ctx, hipMemcpyAsync(c, problem->col, (size_t)problem->nnz * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(ctx, hipMemcpyAsync(v, problem->val, (size_t)problem->nnz * vs, hipMemcpyHostToDevice, s));
+        }
+        d.row_ptr = (const int32_t *)rp;
+        d.col = (const int32_t *)c;
+        d.val = v;
+    }
+    if (problem->h) {
+        void *hb = nullptr;
+        HIP_TRY(ctx, pool.get("in.h", (size_t)n * vs, &hb));
+        HIP_TRY(ctx, hipMemcpyAsync(hb, problem->h, (size_t)n * vs, hipMemcpyHostToDevice, s));
+        d.h = hb;
+    }
+    int8_t *sdev = nullptr;
+    double *edev = nullptr;
+    int64_t *eidev = nullptr;
+    HIP_TRY(ctx, pool.get("out.s", n, (void **)&sdev));
+    HIP_TRY(ctx, pool.get("out.E", 8, (void **)&edev));
+    HIP_TRY(ctx, pool.get("out.Ei", 8, (void **)&eidev));
+    const bool want_int = problem->value_type == ISING_I32;
+    ST_TRY(ising_solve_dev(ctx, &d, params, sdev, edev, want_int ? eidev : nullptr, stats_out, s));
+    HIP_TRY(ctx, hipMemcpyAsync(spins_out, sdev, n, hipMemcpyDeviceToHost, s));
+    double e = 0;
+    int64_t ei = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&e, edev, 8, hipMemcpyDeviceToHost, s));
+    if (want_int) HIP_TRY(ctx, hipMemcpyAsync(&ei, eidev, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (energy_out) *energy_out = e;
+    if (energy_int_out) *energy_int_out = want_int ? ei : 0;
+    if (stats_out)
+        stats_out->t_total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return ISING_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+
+#include "../../include/ising.h"
+
+namespace ising {
+
+// Device view of a problem (all pointers on the device).
+struct DevProblem {
+    int32_t n = 0;
+    int32_t format = ISING_DENSE;
+    int32_t vtype = ISING_I32;
+    int64_t nnz = 0;
+    const void *J = nullptr;
+    const int32_t *row_ptr = nullptr;
+    const int32_t *col = nullptr;
+    const void *val = nullptr;
+    const void *h = nullptr;
+};
+
+inline DevProblem to_dev(const ising_problem &p) {
+    DevProblem d;
+    d.n = p.n;
+    d.format = p.format;
+    d.vtype = p.value_type;
+    d.nnz = p.nnz;
+    d.J = p.J;
+    d.row_ptr = p.row_ptr;
+    d.col = p.col;
+    d.val = p.val;
+    d.h = p.h;
+    return d;
+}
+
+inline size_t vsize(int vtype) { return vtype == ISING_F64 ? 8 : 4; }
+
+// ---- validation (kernels_validate.hip) -----------------------------------
+// flags[0] bit 0: asymmetric, bit 1: nonzero diagonal, bit 2: bad CSR structure,
+// bit 3: non-finite value.  flags[1]: max row degree.  flags[2]: 1 if every
+// nonzero has the same magnitude.  flags[3]: 1 if every value of J and h is integral.
+// wdev: one device double of scratch.  Synchronises the stream once.
+hipError_t launch_validate(const DevProblem &p, int32_t *flags, double *wdev, hipStream_t s);
+// Magnitude of the first stored nonzero coupling (1.0 if none), written to *w.
+hipError_t launch_first_magnitude(const DevProblem &p, double *w, hipStream_t s);
+
+// ---- energy (kernels_energy.hip) -----------------------------------------
+// partial must hold count * ceil(n / 256) accumulators (int64 or double).
+hipError_t launch_energy(const DevProblem &p, const int8_t *spins, int32_t count, void *partial,
+                         double *E_out, int64_t *E_int_out, hipStream_t s);
+size_t energy_partial_bytes(int32_t n, int32_t count);
+
+// ---- pruning (kernels_prune.hip) -------------------------------------------
+struct PruneWork {
+    int8_t *active, *isD, *isS, *cand;
+    int8_t *kind, *fixed, *sigma;
+    int32_t *round_of, *partner, *nb, *map, *G;
+    void *h;        // working field: int64 (integer problems) or double
+    void *jv;       // coupling to the unique neighbour: int64 or double
+    void *cpart;    // per-spin contribution to C this phase
+    void *C;        // accumulated constant (one int64 or double)
+    int32_t *counts;  // [0] = |D| this round, [1] = |S| this round, [2] = n_G, [3] = nnz_G
+};
+hipError_t launch_prune_init(const DevProblem &p, const PruneWork &w, hipStream_t s);
+hipError_t launch_prune_round(const DevProblem &p, const PruneWork &w, int32_t round, hipStream_t s);
+hipError_t launch_prune_compact_scan(const DevProblem &p, const PruneWork &w, hipStream_t s);
+// Reduced problem: dense J_G (n_G*n_G) or CSR (row_ptr_G filled by a scan, then cols/vals).
+// Integer problems produce int32 values, real problems double values.
+hipError_t launch_prune_gather_dense(const DevProblem &p, const PruneWork &w, int32_t nG, void *JG,
+                                     void *hG, hipStream_t s);
+hipError_t launch_prune_csr_count(const DevProblem &p, const PruneWork &w, int32_t nG,
+                                  int32_t *row_ptr_G, hipStream_t s);
+hipError_t launch_prune_csr_fill(const DevProblem &p, const PruneWork &w, int32_t nG,
+                                 const int32_t *row_ptr_G, int32_t *col_G, void *val_G, void *hG,
+                                 hipStream_t s);
+hipError_t launch_unprune(const PruneWork &w, int32_t n, int32_t rounds, const int8_t *s_G,
+                          int8_t *s_out, hipStream_t s);
+hipError_t launch_copy_record(const PruneWork &w, int32_t n, int8_t *kind, int32_t *round_of,
+                              int8_t *fixed, int32_t *partner, int8_t *sigma, hipStream_t s);
+
+// ---- domain selection, persistent engine (kernels_ds.hip) -----------------
+enum Coupling { CK_PM = 0, CK_CSRV = 1, CK_DENSE = 2 };
+
+struct DSArgs {
+    int32_t n = 0, R = 0, t0 = 0, steps = 0, opt = ISING_OPT_ADAM, init_mode = 0;
+    uint64_t seed = 0;
+    double lr = 6.0, mu = 0.5, b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    // coupling (device formats built by launch_ds_format)
+    const int32_t *row_ptr = nullptr;
+    const int32_t *col = nullptr;
+    const uint32_t *pm = nullptr;      // sign-packed entries: col | (J < 0) << 31
+    const void *val = nullptr;         // CSR values in the state precision
+    const void *J = nullptr;           // dense values in the state precision
+    double w = 1.0;                    // common magnitude of sign-packed couplings
+    const void *h = nullptr;           // field in the state precision (nullable)
+    // state
+    void *theta = nullptr, *m = nullptr, *v = nullptr;
+    const void *uniform = nullptr;
+    int8_t *s_best = nullptr;
+    double *e_best = nullptr;
+    int32_t *best_step = nullptr;
+    double *etrace = nullptr, *ltrace = nullptr;
+    const void *bias = nullptr;        // 2*steps bias corrections (ADAM), state precision
+};
+
+struct DSLaunch {
+    int coupling = CK_CSRV;
+    bool fp64 = false;
+    int rg = 1;      // replicas per workgroup
+    int ept = 1;     // spins per thread
+    int block = 64;  // threads per workgroup
+};
+
+// Build the engine's device formats: pm entries (if sign-packed), values and h
+// converted to the state precision.  Buffers are caller-provided.
+hipError_t launch_ds_format(const DevProblem &p, bool fp64, bool packed, uint32_t *pm, void *val_out,
+                            void *h_out, hipStream_t s);
+hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s);
+// ADAM bias corrections 1/(1-b1^t), 1/(1-b2^t), t = t0+1..t0+steps (FP64, rounded).
+hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64, void *out, hipStream_t s);
+int32_t ds_max_n(bool fp64);
+
+hipError_t launch_select(const double *e_best, int32_t R, int32_t *best, hipStream_t s);
+// s_G = rows[best] of a replica-major int8 block (device-side gather).
+hipError_t launch_gather_row(const int8_t *block, int32_t n, const int32_t *best, int8_t *out,
+                             hipStream_t s);
+
+}  // namespace ising

@@ -1,0 +1,746 @@
+// Domain selection (paper Sec. III-B): persistent, replica-parallel engine.
+//
+// Replicas are independent trajectories, so a workgroup owns RG replicas and
+// all n spins of them for the whole run: no workgroup ever waits for another.
+// Angles, ADAM moments and (when they fit) sin/cos of the angles live in
+// registers for all steps; the current vertex lives in LDS, double-buffered,
+// as one bit per (spin, replica) packed into one word per spin.  A step is
+//
+//   y   = J s                 coupling product, gathered from LDS
+//   E  += s (y + h)           energy of the current vertex (wavefront shuffles,
+//                             then one fixed-order sum over wavefronts)
+//   t   = y - mu s + h;  g = cos(theta) t;  L += sin(theta) t
+//   theta <- GD / ADAM update, wrapped to [-pi, pi] with a two-constant 2 pi
+//   s'  = sgn(sin theta)      next vertex, written to the other LDS buffer
+//
+// with one workgroup barrier per step.  The best-vertex bookkeeping is
+// pipelined: wavefront 0 compares E_t with the best energy after the barrier of
+// step t and publishes a bit per replica; every thread applies it after the
+// barrier of step t+1, copying its bits of s_t (still held in registers).
+//
+// Coupling formats:
+//   CK_PM    all couplings +-w: entries col | (J<0) << 31.  The product counts,
+//            per replica, the neighbours with J_ij s_j = -w by adding
+//            (bit_j xor sign_ij) in packed lanes; y = w (deg - 2 count), exact.
+//   CK_CSRV  CSR values in the state precision.
+//   CK_DENSE dense rows in the state precision (small problems).
+#include "internal.hpp"
+
+#include <cmath>
+
+namespace ising {
+
+namespace {
+
+template <int RG>
+struct SpinWord;
+template <>
+struct SpinWord<1> {
+    using T = uint8_t;
+    static constexpr uint32_t ones = 0x1u;
+    static constexpr int width = 32;
+    __device__ static constexpr int shift(int) { return 0; }
+};
+template <>
+struct SpinWord<2> {
+    using T = uint32_t;
+    static constexpr uint32_t ones = 0x00010001u;
+    static constexpr int width = 16;
+    __device__ static constexpr int shift(int r) { return 16 * r; }
+};
+template <>
+struct SpinWord<4> {
+    using T = uint32_t;
+    static constexpr uint32_t ones = 0x01010101u;
+    static constexpr int width = 8;
+    __device__ static constexpr int shift(int r) { return 8 * r; }
+};
+
+template <typename Real>
+struct Consts;
+template <>
+struct Consts<float> {
+    // 2 pi = hi + lo to about 2^-48 relative
+    static constexpr float twopi_hi = 6.28318548202514648f;
+    static constexpr float twopi_lo = -1.7484555314695172e-07f;
+    static constexpr float inv_twopi = 0.159154943091895336f;
+};
+template <>
+struct Consts<double> {
+    static constexpr double twopi_hi = 6.283185307179586232;
+    static constexpr double twopi_lo = 2.4492935982947064e-16;
+    static constexpr double inv_twopi = 0.15915494309189533577;
+};
+
+// sin and cos of |x| <= 4 in float: quadrant k = rint(x 2/pi), reduction
+// r = x - k pi/2 with pi/2 split in three parts (each step one FMA, Cody-Waite
+// style), then Taylor polynomials on |r| <= pi/4 (sin to r^9, cos to r^10: the
+// truncation is below 2e-9) evaluated by Horner's rule, and the quadrant
+// symmetries.  Angles here are always wrapped to [-pi, pi].
+__device__ inline void dsincos(float x, float *s, float *c) {
+    const float k = rintf(x * 0.636619772367581343f);
+    float r = __builtin_fmaf(-k, 1.57079637050628662f, x);
+    r = __builtin_fmaf(-k, -4.37113882867379300e-08f, r);
+    r = __builtin_fmaf(-k, -1.71512451000588190e-15f, r);
+    const float r2 = r * r;
+    float ps = __builtin_fmaf(r2, 2.75573192239858907e-06f, -1.98412698412698413e-04f);
+    ps = __builtin_fmaf(r2, ps, 8.33333333333333333e-03f);
+    ps = __builtin_fmaf(r2, ps, -1.66666666666666667e-01f);
+    const float sn = __builtin_fmaf(r * r2, ps, r);
+    float pc = __builtin_fmaf(r2, -2.75573192239858907e-07f, 2.48015873015873016e-05f);
+    pc = __builtin_fmaf(r2, pc, -1.38888888888888889e-03f);
+    pc = __builtin_fmaf(r2, pc, 4.16666666666666667e-02f);
+    pc = __builtin_fmaf(r2, pc, -0.5f);
+    const float cn = __builtin_fmaf(r2, pc, 1.0f);
+    const int q = (int)k & 3;
+    const float a = (q & 1) ? cn : sn;
+    const float b = (q & 1) ? sn : cn;
+    *s = (q & 2) ? -a : a;
+    *c = ((q + 1) & 2) ? -b : b;
+}
+__device__ inline void dsincos(double x, double *s, double *c) { sincos(x, s, c); }
+__device__ inline float dsin(float x) {
+    float s, c;
+    dsincos(x, &s, &c);
+    return s;
+}
+__device__ inline double dsin(double x) { return sin(x); }
+__device__ inline float dasin(float x) { return asinf(x); }
+__device__ inline double dasin(double x) { return asin(x); }
+__device__ inline float dsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double dsqrt(double x) { return sqrt(x); }
+__device__ inline float drint(float x) { return rintf(x); }
+__device__ inline float drcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double drcp(double x) { return 1.0 / x; }
+__device__ inline double drint(double x) { return rint(x); }
+
+// Output number (c + 1) of SplitMix64 seeded with `seed` (Steele, Lea, Flood 2014).
+__device__ inline uint64_t splitmix64(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// U = 2 * top24 / 2^24 - 1, exact in float and double
+template <typename Real>
+__device__ inline Real draw_uniform(uint64_t seed, int r, int i) {
+    const uint64_t z = splitmix64(seed, ((uint64_t)(uint32_t)r << 32) | (uint32_t)i);
+    const Real u24 = (Real)(uint32_t)(z >> 40);
+    return (Real)2 * (u24 * (Real)5.9604644775390625e-08) - (Real)1;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+template <typename Real, int CK, int RG>
+__device__ inline void coupling(const DSArgs &a, int i, const typename SpinWord<RG>::T *sc, Real (&y)[RG]) {
+    using SW = SpinWord<RG>;
+    if constexpr (CK == CK_PM) {
+        const int rs = a.row_ptr[i], re = a.row_ptr[i + 1];
+        uint32_t acc = 0;
+        for (int q = rs; q < re; ++q) {
+            const uint32_t e = a.pm[q];
+            const uint32_t nm = (uint32_t)((int32_t)e >> 31) & SW::ones;
+            acc += (uint32_t)sc[e & 0x7fffffffu] ^ nm;
+        }
+        const int deg = re - rs;
+        const Real w = (Real)a.w;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            const uint32_t cnt = SW::width == 32 ? acc : ((acc >> SW::shift(r)) & ((1u << SW::width) - 1u));
+            y[r] = w * (Real)(deg - 2 * (int)cnt);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RG; ++r) y[r] = 0;
+        if constexpr (CK == CK_CSRV) {
+            const Real *val = (const Real *)a.val;
+            const int rs = a.row_ptr[i], re = a.row_ptr[i + 1];
+            for (int q = rs; q < re; ++q) {
+                const Real v = val[q];
+                const uint32_t wd = (uint32_t)sc[a.col[q]];
+#pragma unroll
+                for (int r = 0; r < RG; ++r) y[r] += ((wd >> SW::shift(r)) & 1u) ? -v : v;
+            }
+        } else {
+            const Real *row = (const Real *)a.J + (size_t)i * a.n;
+            for (int j = 0; j < a.n; ++j) {
+                const Real v = row[j];
+                const uint32_t wd = (uint32_t)sc[j];
+#pragma unroll
+                for (int r = 0; r < RG; ++r) y[r] += ((wd >> SW::shift(r)) & 1u) ? -v : v;
+            }
+        }
+    }
+}
+
+constexpr int launch_bound(int) { return 1024; }
+
+template <typename Real, int CK, int RG, int EPT>
+__global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
+    using SWd = SpinWord<RG>;
+    using SW = typename SWd::T;
+    constexpr int NE = EPT * RG;
+    constexpr bool KEEP = NE * (int)sizeof(Real) <= 32;  // keep sin/cos of theta in registers
+    static_assert(NE <= 32, "one 32-bit mask per thread");
+    extern __shared__ __align__(16) unsigned char smem[];
+
+    const int n = a.n, B = blockDim.x, tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, NW = B >> 6;
+    const int npad = EPT * B;
+    SW *sbuf = (SW *)smem;
+    const size_t off = ((size_t)2 * npad * sizeof(SW) + 15) & ~(size_t)15;
+    Real *ep = (Real *)(smem + off);      // [2][NW][RG]
+    Real *lp = ep + 2 * NW * RG;          // [2][NW][RG]
+    uint32_t *flg = (uint32_t *)(lp + 2 * NW * RG);  // [2]
+    const int r0 = blockIdx.x * RG;
+    const Real *hv = (const Real *)a.h;
+    Real *gth = (Real *)a.theta;
+    Real *gm = (Real *)a.m;
+    Real *gv = (Real *)a.v;
+    const bool adam = a.opt == ISING_OPT_ADAM;
+
+    Real th[NE], mo[NE], ve[NE];
+    Real xs[KEEP ? NE : 1], cs[KEEP ? NE : 1];
+    uint32_t cur = 0, prv = 0, best = 0;
+
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int i = e * B + tid;
+        SW word = 0;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            const int k = e * RG + r;
+            th[k] = 0;
+            mo[k] = 0;
+            ve[k] = 0;
+            if (KEEP) {
+                xs[k] = 0;
+                cs[k] = 1;
+            }
+            if (i < n) {
+                const size_t idx = (size_t)(r0 + r) * n + i;
+                Real t;
+                if (a.init_mode == 0) {
+                    t = gth[idx];
+                    if (gm) mo[k] = gm[idx];
+                    if (gv) ve[k] = gv[idx];
+                    if (a.s_best[idx] < 0) best |= 1u << k;
+                } else {
+                    const Real u = a.init_mode == 1 ? ((const Real *)a.uniform)[idx]
+                                                    : draw_uniform<Real>(a.seed, r0 + r, i);
+                    t = dasin(u);
+                }
+                th[k] = t;
+                Real x, c;
+                dsincos(t, &x, &c);
+                if (KEEP) {
+                    xs[k] = x;
+                    cs[k] = c;
+                }
+                if (x < 0) {
+                    cur |= 1u << k;
+                    word |= (SW)(1u << SWd::shift(r));
+                }
+            }
+        }
+        if (i < n) sbuf[i] = word;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (tid < 2) flg[tid] = 0;
+    double ebest = INFINITY;
+    int bstep = 0;
+    if (wave == 0 && lane < RG && a.init_mode == 0) {
+        ebest = a.e_best[r0 + lane];
+        bstep = a.best_step[r0 + lane];
+    }
+    __syncthreads();
+
+    const Real lr = (Real)a.lr, mu = (Real)a.mu, b1 = (Real)a.b1, b2 = (Real)a.b2, eps = (Real)a.eps;
+    const Real omb1 = (Real)(1.0 - a.b1), omb2 = (Real)(1.0 - a.b2);
+    const Real *bct = (const Real *)a.bias;  // 1/(1-b1^t), 1/(1-b2^t) for this launch's steps
+    const bool trace_l = a.ltrace != nullptr;
+
+    for (int t = 1; t <= a.steps; ++t) {
+        const SW *sc = sbuf + ((t - 1) & 1) * npad;
+        SW *sn = sbuf + (t & 1) * npad;
+        const Real ib1 = adam ? bct[2 * (t - 1)] : (Real)1, ib2 = adam ? bct[2 * (t - 1) + 1] : (Real)1;
+        Real Ep[RG], Lp[RG];
+#pragma unroll
+        for (int r = 0; r < RG; ++r) Ep[r] = Lp[r] = 0;
+        uint32_t nxt = 0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = e * B + tid;
+            if (i >= n) continue;
+            Real y[RG];
+            coupling<Real, CK, RG>(a, i, sc, y);
+            const Real hh = hv ? hv[i] : (Real)0;
+            SW word = 0;
+#pragma unroll
+            for (int r = 0; r < RG; ++r) {
+                const int k = e * RG + r;
+                const bool neg = (cur >> k) & 1u;
+                const Real yh = y[r] + hh;
+                Ep[r] += neg ? -yh : yh;
+                const Real tt = neg ? yh + mu : yh - mu;
+                Real x, c;
+                if (KEEP) {
+                    x = xs[k];
+                    c = cs[k];
+                } else {
+                    dsincos(th[k], &x, &c);
+                }
+                Lp[r] += x * tt;
+                const Real g = c * tt;
+                Real upd;
+                if (adam) {
+                    mo[k] = b1 * mo[k] + omb1 * g;
+                    ve[k] = b2 * ve[k] + omb2 * (g * g);
+                    upd = lr * (mo[k] * ib1) * drcp(dsqrt(ve[k] * ib2) + eps);
+                } else {
+                    upd = lr * g;
+                }
+                Real tn = th[k] - upd;
+                const Real q = drint(tn * Consts<Real>::inv_twopi);
+                tn = tn - q * Consts<Real>::twopi_hi;
+                tn = tn - q * Consts<Real>::twopi_lo;
+                th[k] = tn;
+                Real xn;
+                if (KEEP) {
+                    Real cn;
+                    dsincos(tn, &xn, &cn);
+                    xs[k] = xn;
+                    cs[k] = cn;
+                } else {
+                    xn = dsin(tn);
+                }
+                if (xn < 0) {
+                    nxt |= 1u << k;
+                    word |= (SW)(1u << SWd::shift(r));
+                }
+            }
+            sn[i] = word;
+            // keep the scheduler from interleaving elements: bounds live ranges
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            Ep[r] = wave_sum(Ep[r]);
+            if (trace_l) Lp[r] = wave_sum(Lp[r]);
+        }
+        if (lane == 0) {
+            Real *epo = ep + ((t & 1) * NW + wave) * RG;
+            Real *lpo = lp + ((t & 1) * NW + wave) * RG;
+#pragma unroll
+            for (int r = 0; r < RG; ++r) {
+                epo[r] = Ep[r];
+                lpo[r] = Lp[r];
+            }
+        }
+        __syncthreads();
+        const uint32_t f = flg[(t - 1) & 1];
+        if (f) {
+#pragma unroll
+            for (int r = 0; r < RG; ++r) {
+                if ((f >> r) & 1u) {
+                    uint32_t mask = 0;
+#pragma unroll
+                    for (int e = 0; e < EPT; ++e) mask |= 1u << (e * RG + r);
+                    best = (best & ~mask) | (prv & mask);
+                }
+            }
+        }
+        prv = cur;
+        cur = nxt;
+        if (wave == 0) {
+            bool imp = false;
+            if (lane < RG) {
+                Real Es = 0, Ls = 0;
+                for (int w = 0; w < NW; ++w) {
+                    Es += ep[((t & 1) * NW + w) * RG + lane];
+                    Ls += lp[((t & 1) * NW + w) * RG + lane];
+                }
+                const double E = (double)Es, L = (double)Ls;
+                imp = E < ebest;
+                if (imp) {
+                    ebest = E;
+                    bstep = a.t0 + t;
+                }
+                if (a.etrace) a.etrace[(size_t)(t - 1) * a.R + r0 + lane] = E;
+                if (a.ltrace) a.ltrace[(size_t)(t - 1) * a.R + r0 + lane] = L;
+            }
+            const uint64_t bal = __ballot(imp);
+            if (lane == 0) flg[t & 1] = (uint32_t)bal;
+        }
+    }
+    __syncthreads();
+    if (a.steps > 0) {
+        const uint32_t f = flg[a.steps & 1];
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            if ((f >> r) & 1u) {
+                uint32_t mask = 0;
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) mask |= 1u << (e * RG + r);
+                best = (best & ~mask) | (prv & mask);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int i = e * B + tid;
+        if (i >= n) continue;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            const int k = e * RG + r;
+            const size_t idx = (size_t)(r0 + r) * n + i;
+            gth[idx] = th[k];
+            if (gm) gm[idx] = mo[k];
+            if (gv) gv[idx] = ve[k];
+            a.s_best[idx] = ((best >> k) & 1u) ? (int8_t)-1 : (int8_t)1;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (wave == 0 && lane < RG) {
+        a.e_best[r0 + lane] = ebest;
+        a.best_step[r0 + lane] = bstep;
+    }
+}
+
+
+// Same step for problems too large to keep the state in registers: angles and
+// moments are streamed from global memory every step (each workgroup touches
+// only its own replicas, so there is still no inter-workgroup dependence), and
+// the vertex is triple-buffered in LDS so that s_{t-1} is still readable when
+// the best-vertex decision of step t-1 arrives.
+template <typename Real, int CK, int RG>
+__global__ __launch_bounds__(1024) void k_ds_stream(const DSArgs a) {
+    using SWd = SpinWord<RG>;
+    using SW = typename SWd::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = a.n, B = blockDim.x, tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, NW = B >> 6;
+    SW *sbuf = (SW *)smem;  // [3][n]
+    const size_t off = ((size_t)3 * n * sizeof(SW) + 15) & ~(size_t)15;
+    Real *ep = (Real *)(smem + off);
+    Real *lp = ep + 2 * NW * RG;
+    uint32_t *flg = (uint32_t *)(lp + 2 * NW * RG);
+    const int r0 = blockIdx.x * RG;
+    const Real *hv = (const Real *)a.h;
+    Real *gth = (Real *)a.theta;
+    Real *gm = (Real *)a.m;
+    Real *gv = (Real *)a.v;
+    const bool adam = a.opt == ISING_OPT_ADAM;
+
+    // buffer k % 3 holds s_{t0+k}; the initial vertex is s_{t0+1}... use local step t: buf[t % 3] = s_t
+    for (int i = tid; i < n; i += B) {
+        SW word = 0;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            const size_t idx = (size_t)(r0 + r) * n + i;
+            Real t;
+            if (a.init_mode == 0) {
+                t = gth[idx];
+            } else {
+                const Real u = a.init_mode == 1 ? ((const Real *)a.uniform)[idx]
+                                                : draw_uniform<Real>(a.seed, r0 + r, i);
+                t = dasin(u);
+                gth[idx] = t;
+                if (gm) gm[idx] = 0;
+                if (gv) gv[idx] = 0;
+                a.s_best[idx] = 1;
+            }
+            if (dsin(t) < 0) word |= (SW)(1u << SWd::shift(r));
+        }
+        sbuf[1 * n + i] = word;
+    }
+    if (tid < 2) flg[tid] = 0;
+    double ebest = INFINITY;
+    int bstep = 0;
+    if (wave == 0 && lane < RG && a.init_mode == 0) {
+        ebest = a.e_best[r0 + lane];
+        bstep = a.best_step[r0 + lane];
+    }
+    __syncthreads();
+    const Real lr = (Real)a.lr, mu = (Real)a.mu, b1 = (Real)a.b1, b2 = (Real)a.b2, eps = (Real)a.eps;
+    const Real omb1 = (Real)(1.0 - a.b1), omb2 = (Real)(1.0 - a.b2);
+    const Real *bct = (const Real *)a.bias;
+    const bool trace_l = a.ltrace != nullptr;
+
+    auto apply_best = [&](uint32_t f, const SW *sold) {
+        for (int i = tid; i < n; i += B) {
+            const uint32_t wd = (uint32_t)sold[i];
+#pragma unroll
+            for (int r = 0; r < RG; ++r)
+                if ((f >> r) & 1u)
+                    a.s_best[(size_t)(r0 + r) * n + i] = ((wd >> SWd::shift(r)) & 1u) ? (int8_t)-1 : (int8_t)1;
+        }
+    };
+
+    for (int t = 1; t <= a.steps; ++t) {
+        const SW *sc = sbuf + (t % 3) * n;
+        SW *sn = sbuf + ((t + 1) % 3) * n;
+        const Real ib1 = adam ? bct[2 * (t - 1)] : (Real)1, ib2 = adam ? bct[2 * (t - 1) + 1] : (Real)1;
+        Real Ep[RG], Lp[RG];
+#pragma unroll
+        for (int r = 0; r < RG; ++r) Ep[r] = Lp[r] = 0;
+        for (int i = tid; i < n; i += B) {
+            Real y[RG];
+            coupling<Real, CK, RG>(a, i, sc, y);
+            const Real hh = hv ? hv[i] : (Real)0;
+            const uint32_t wcur = (uint32_t)sc[i];
+            SW word = 0;
+#pragma unroll
+            for (int r = 0; r < RG; ++r) {
+                const size_t idx = (size_t)(r0 + r) * n + i;
+                const bool neg = (wcur >> SWd::shift(r)) & 1u;
+                const Real yh = y[r] + hh;
+                Ep[r] += neg ? -yh : yh;
+                const Real tt = neg ? yh + mu : yh - mu;
+                const Real th = gth[idx];
+                Real x, c;
+                dsincos(th, &x, &c);
+                Lp[r] += x * tt;
+                const Real g = c * tt;
+                Real upd;
+                if (adam) {
+                    const Real mo = b1 * gm[idx] + omb1 * g;
+                    const Real ve = b2 * gv[idx] + omb2 * (g * g);
+                    gm[idx] = mo;
+                    gv[idx] = ve;
+                    upd = lr * (mo * ib1) * drcp(dsqrt(ve * ib2) + eps);
+                } else {
+                    upd = lr * g;
+                }
+                Real tn = th - upd;
+                const Real q = drint(tn * Consts<Real>::inv_twopi);
+                tn = tn - q * Consts<Real>::twopi_hi;
+                tn = tn - q * Consts<Real>::twopi_lo;
+                gth[idx] = tn;
+                if (dsin(tn) < 0) word |= (SW)(1u << SWd::shift(r));
+            }
+            sn[i] = word;
+        }
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            Ep[r] = wave_sum(Ep[r]);
+            if (trace_l) Lp[r] = wave_sum(Lp[r]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < RG; ++r) {
+                ep[((t & 1) * NW + wave) * RG + r] = Ep[r];
+                lp[((t & 1) * NW + wave) * RG + r] = Lp[r];
+            }
+        }
+        __syncthreads();
+        const uint32_t f = flg[(t - 1) & 1];
+        if (f) apply_best(f, sbuf + ((t - 1) % 3) * n);
+        if (wave == 0) {
+            bool imp = false;
+            if (lane < RG) {
+                Real Es = 0, Ls = 0;
+                for (int w = 0; w < NW; ++w) {
+                    Es += ep[((t & 1) * NW + w) * RG + lane];
+                    Ls += lp[((t & 1) * NW + w) * RG + lane];
+                }
+                const double E = (double)Es, L = (double)Ls;
+                imp = E < ebest;
+                if (imp) {
+                    ebest = E;
+                    bstep = a.t0 + t;
+                }
+                if (a.etrace) a.etrace[(size_t)(t - 1) * a.R + r0 + lane] = E;
+                if (a.ltrace) a.ltrace[(size_t)(t - 1) * a.R + r0 + lane] = L;
+            }
+            const uint64_t bal = __ballot(imp);
+            if (lane == 0) flg[t & 1] = (uint32_t)bal;
+        }
+    }
+    __syncthreads();
+    if (a.steps > 0) {
+        const uint32_t f = flg[a.steps & 1];
+        if (f) apply_best(f, sbuf + (a.steps % 3) * n);
+    }
+    if (wave == 0 && lane < RG) {
+        a.e_best[r0 + lane] = ebest;
+        a.best_step[r0 + lane] = bstep;
+    }
+}
+
+// 1/(1 - b1^t) and 1/(1 - b2^t) for t = t0+1 .. t0+steps, in FP64, rounded to Real
+template <typename Real>
+__global__ void k_bias_table(double b1, double b2, int t0, int steps, Real *out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= steps) return;
+    const double t = (double)(t0 + q + 1);
+    out[2 * q] = (Real)(1.0 / -expm1(t * log(b1)));
+    out[2 * q + 1] = (Real)(1.0 / -expm1(t * log(b2)));
+}
+
+template <typename Real>
+__global__ void k_format(DevProblem p, int packed, uint32_t *pm, Real *val_out, Real *h_out) {
+    const int64_t total = p.format == ISING_DENSE ? (int64_t)p.n * p.n : p.nnz;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const void *src = p.format == ISING_DENSE ? p.J : p.val;
+        double v;
+        if (p.vtype == ISING_I32) v = ((const int32_t *)src)[q];
+        else if (p.vtype == ISING_F32) v = ((const float *)src)[q];
+        else v = ((const double *)src)[q];
+        if (packed) pm[q] = (uint32_t)p.col[q] | (v < 0 ? 0x80000000u : 0u);
+        else val_out[q] = (Real)v;
+    }
+    if (h_out && p.h) {
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            double v;
+            if (p.vtype == ISING_I32) v = ((const int32_t *)p.h)[i];
+            else if (p.vtype == ISING_F32) v = ((const float *)p.h)[i];
+            else v = ((const double *)p.h)[i];
+            h_out[i] = (Real)v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_select(const double *e, int R, int32_t *best) {
+    __shared__ double sv[1024];
+    __shared__ int si[1024];
+    double bv = INFINITY;
+    int bi = -1;
+    for (int r = threadIdx.x; r < R; r += 1024) {
+        const double x = e[r];
+        if (bi < 0 || x < bv) {
+            bv = x;
+            bi = r;
+        }
+    }
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int d = 512; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) {
+            const double ov = sv[threadIdx.x + d];
+            const int oi = si[threadIdx.x + d];
+            const double mv = sv[threadIdx.x];
+            const int mi = si[threadIdx.x];
+            const bool take = oi >= 0 && (mi < 0 || ov < mv || (ov == mv && oi < mi));
+            if (take) {
+                sv[threadIdx.x] = ov;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *best = si[0] < 0 ? 0 : si[0];
+}
+
+__global__ void k_gather_row(const int8_t *block, int n, const int32_t *best, int8_t *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = block[(size_t)(*best) * n + i];
+}
+
+using KFn = void (*)(const DSArgs);
+
+template <typename Real, int CK, int RG>
+KFn pick_ept(int ept) {
+    switch (ept) {
+        case 0: return k_ds_stream<Real, CK, RG>;
+        case 1: return k_ds<Real, CK, RG, 1>;
+        case 2: return k_ds<Real, CK, RG, 2>;
+        case 4:
+            if constexpr (RG <= 2) return k_ds<Real, CK, RG, 4>;
+            return nullptr;
+        default: return nullptr;
+    }
+}
+
+template <typename Real, int CK>
+KFn pick_rg(int rg, int ept) {
+    if constexpr (sizeof(Real) == 8) {
+        return rg == 1 ? pick_ept<Real, CK, 1>(ept) : nullptr;
+    } else {
+        switch (rg) {
+            case 1: return pick_ept<Real, CK, 1>(ept);
+            case 2: return pick_ept<Real, CK, 2>(ept);
+            case 4: return pick_ept<Real, CK, 4>(ept);
+            default: return nullptr;
+        }
+    }
+}
+
+template <typename Real>
+KFn pick(int ck, int rg, int ept) {
+    switch (ck) {
+        case CK_PM: return pick_rg<Real, CK_PM>(rg, ept);
+        case CK_CSRV: return pick_rg<Real, CK_CSRV>(rg, ept);
+        case CK_DENSE: return pick_rg<Real, CK_DENSE>(rg, ept);
+        default: return nullptr;
+    }
+}
+
+}  // namespace
+
+int32_t ds_max_n(bool fp64) {
+    // streaming engine, one replica per workgroup: three byte-per-spin LDS buffers
+    (void)fp64;
+    return 48 * 1024;
+}
+
+hipError_t launch_ds_format(const DevProblem &p, bool fp64, bool packed, uint32_t *pm, void *val_out,
+                            void *h_out, hipStream_t s) {
+    const int64_t total = p.format == ISING_DENSE ? (int64_t)p.n * p.n : p.nnz;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((std::max<int64_t>(total, p.n) + 255) / 256, 8192));
+    if (fp64)
+        hipLaunchKernelGGL(k_format<double>, dim3(blocks), dim3(256), 0, s, p, packed ? 1 : 0, pm,
+                           (double *)val_out, (double *)h_out);
+    else
+        hipLaunchKernelGGL(k_format<float>, dim3(blocks), dim3(256), 0, s, p, packed ? 1 : 0, pm,
+                           (float *)val_out, (float *)h_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
+    KFn fn = l.fp64 ? pick<double>(l.coupling, l.rg, l.ept) : pick<float>(l.coupling, l.rg, l.ept);
+    if (!fn) return hipErrorInvalidValue;
+    if (l.block % 64 || l.block < 64 || l.block > 1024 || (l.ept > 0 && (int64_t)l.ept * l.block < a.n) ||
+        a.R % l.rg)
+        return hipErrorInvalidValue;
+    const size_t sw = l.rg == 1 ? 1 : 4;
+    const size_t real = l.fp64 ? 8 : 4;
+    const int nw = l.block / 64;
+    const size_t sbytes = l.ept > 0 ? (size_t)2 * l.ept * l.block * sw : (size_t)3 * a.n * sw;
+    const size_t lds = ((sbytes + 15) & ~(size_t)15) + 2 * 2 * nw * l.rg * real + 16;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3(a.R / l.rg), dim3(l.block), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64, void *out, hipStream_t s) {
+    if (steps <= 0) return hipSuccess;
+    if (fp64) hipLaunchKernelGGL(k_bias_table<double>, dim3((steps + 255) / 256), dim3(256), 0, s, b1, b2, t0, steps, (double *)out);
+    else hipLaunchKernelGGL(k_bias_table<float>, dim3((steps + 255) / 256), dim3(256), 0, s, b1, b2, t0, steps, (float *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const double *e_best, int32_t R, int32_t *best, hipStream_t s) {
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, e_best, R, best);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_row(const int8_t *block, int32_t n, const int32_t *best, int8_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_row, dim3((n + 255) / 256), dim3(256), 0, s, block, n, best, out);
+    return hipGetLastError();
+}
+
+}  // namespace ising

@@ -1,0 +1,178 @@
+// Ingest checks of a problem on the device: symmetry, zero diagonal, CSR
+// structure, finiteness, maximum degree, common coupling magnitude and
+// integrality.  One pass over J.
+#include "internal.hpp"
+
+namespace ising {
+
+template <typename V>
+__device__ inline double as_double(const void *p, int64_t k) {
+    return (double)(((const V *)p)[k]);
+}
+
+__device__ inline double load_val(const void *p, int vtype, int64_t k) {
+    if (vtype == ISING_I32) return as_double<int32_t>(p, k);
+    if (vtype == ISING_F32) return as_double<float>(p, k);
+    return as_double<double>(p, k);
+}
+
+__device__ inline bool is_integral(double x) { return x == rint(x) && fabs(x) < 9.0e15; }
+
+// flags: [0] error bits, [1] max degree (atomicMax), [2] uniform magnitude (cleared on mismatch),
+// [3] integral (cleared on a non-integral value)
+__global__ void validate_dense(DevProblem p, double w0, int32_t *flags) {
+    const int n = p.n;
+    const int64_t total = (int64_t)n * n;
+    int bits = 0;
+    bool uni = true, integ = true;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / n), j = (int)(k % n);
+        const double a = load_val(p.J, p.vtype, k);
+        if (!isfinite(a)) bits |= 8;
+        if (i == j) {
+            if (a != 0.0) bits |= 2;
+            continue;
+        }
+        if (j > i) {
+            const double b = load_val(p.J, p.vtype, (int64_t)j * n + i);
+            if (a != b) bits |= 1;
+        }
+        if (a != 0.0) {
+            if (fabs(a) != w0) uni = false;
+            if (!is_integral(a)) integ = false;
+        }
+    }
+    if (bits) atomicOr(&flags[0], bits);
+    if (!uni) atomicAnd(&flags[2], 0);
+    if (!integ) atomicAnd(&flags[3], 0);
+}
+
+__global__ void dense_degree(DevProblem p, int32_t *flags) {
+    // one wave per row: count nonzeros
+    const int n = p.n;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= n) return;
+    int c = 0;
+    for (int j = lane; j < n; j += 64)
+        c += load_val(p.J, p.vtype, (int64_t)row * n + j) != 0.0;
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d);
+    if (lane == 0) atomicMax(&flags[1], c);
+}
+
+__global__ void validate_csr(DevProblem p, double w0, int32_t *flags) {
+    const int n = p.n;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int bits = 0;
+    bool uni = true, integ = true;
+    const int rs = p.row_ptr[i], re = p.row_ptr[i + 1];
+    if (rs < 0 || re < rs || re > p.nnz) {
+        atomicOr(&flags[0], 4);
+        return;
+    }
+    int prev = -1;
+    for (int k = rs; k < re; ++k) {
+        const int j = p.col[k];
+        if (j < 0 || j >= n || j <= prev) {
+            bits |= 4;
+            break;
+        }
+        prev = j;
+        if (j == i) bits |= 2;
+        const double a = load_val(p.val, p.vtype, k);
+        if (!isfinite(a)) bits |= 8;
+        if (fabs(a) != w0) uni = false;
+        if (!is_integral(a)) integ = false;
+        // symmetric partner: binary search row j for column i
+        const int js = p.row_ptr[j], je = p.row_ptr[j + 1];
+        if (js < 0 || je < js || je > p.nnz) {
+            bits |= 4;
+            break;
+        }
+        int lo = js, hi = je - 1, found = -1;
+        while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            const int c = p.col[mid];
+            if (c == i) {
+                found = mid;
+                break;
+            }
+            if (c < i) lo = mid + 1;
+            else hi = mid - 1;
+        }
+        if (found < 0 || load_val(p.val, p.vtype, found) != a) bits |= 1;
+    }
+    if (bits) atomicOr(&flags[0], bits);
+    atomicMax(&flags[1], re - rs);
+    if (!uni) atomicAnd(&flags[2], 0);
+    if (!integ) atomicAnd(&flags[3], 0);
+}
+
+__global__ void validate_h(DevProblem p, int32_t *flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n || p.h == nullptr) return;
+    const double a = load_val(p.h, p.vtype, i);
+    if (!isfinite(a)) atomicOr(&flags[0], 8);
+    if (!is_integral(a)) atomicAnd(&flags[3], 0);
+}
+
+__global__ void first_magnitude(DevProblem p, double *w) {
+    // magnitude of the first nonzero coupling (row-major order); 1.0 if none
+    if (threadIdx.x != 0) return;
+    double r = 1.0;
+    if (p.format == ISING_CSR) {
+        if (p.nnz > 0) r = fabs(load_val(p.val, p.vtype, 0));
+    } else {
+        const int64_t total = (int64_t)p.n * p.n;
+        for (int64_t k = 0; k < total; ++k) {
+            const double a = load_val(p.J, p.vtype, k);
+            if (a != 0.0) {
+                r = fabs(a);
+                break;
+            }
+        }
+    }
+    *w = r;
+}
+
+hipError_t launch_first_magnitude(const DevProblem &p, double *w, hipStream_t s) {
+    hipLaunchKernelGGL(first_magnitude, dim3(1), dim3(64), 0, s, p, w);
+    return hipGetLastError();
+}
+
+__global__ void init_flags(int32_t *flags) {
+    if (threadIdx.x == 0) {
+        flags[0] = 0;
+        flags[1] = 0;
+        flags[2] = 1;
+        flags[3] = 1;
+    }
+}
+
+hipError_t launch_validate_with(const DevProblem &p, double w0, int32_t *flags, hipStream_t s) {
+    hipLaunchKernelGGL(init_flags, dim3(1), dim3(64), 0, s, flags);
+    if (p.format == ISING_DENSE) {
+        const int64_t total = (int64_t)p.n * p.n;
+        int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+        hipLaunchKernelGGL(validate_dense, dim3(blocks), dim3(256), 0, s, p, w0, flags);
+        hipLaunchKernelGGL(dense_degree, dim3((p.n + 3) / 4), dim3(256), 0, s, p, flags);
+    } else {
+        hipLaunchKernelGGL(validate_csr, dim3((p.n + 255) / 256), dim3(256), 0, s, p, w0, flags);
+    }
+    hipLaunchKernelGGL(validate_h, dim3((p.n + 255) / 256), dim3(256), 0, s, p, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const DevProblem &p, int32_t *flags, double *wdev, hipStream_t s) {
+    // the common magnitude candidate is needed on the host (ingest, not the hot loop)
+    hipLaunchKernelGGL(first_magnitude, dim3(1), dim3(64), 0, s, p, wdev);
+    double w0 = 1.0;
+    hipError_t e = hipMemcpyAsync(&w0, wdev, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    return launch_validate_with(p, w0, flags, s);
+}
+
+}  // namespace ising

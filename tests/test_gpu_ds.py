@@ -1,0 +1,242 @@
+"""GPU parity of domain selection (Sec. III-B) against the FP64 oracle.
+
+Tolerance: per replica, max_i |sin theta_gpu - sin theta_oracle| / max_i |sin theta_oracle|
+<= 1e-5.  With gradient descent this holds for the FP32 engine over the first
+100 steps (GD lr 0.01) and for the FP64 engine at GD lr 0.05.  ADAM normalises
+the gradient by its running RMS, which amplifies rounding differences
+exponentially once moments are small: a float32 emulation of these same
+formulas on the host departs from the FP64 oracle by 4e-5 (SK n = 64) to 6e-5
+(ER n = 800) at step 100 even at lr 0.02, exactly as the GPU does, and two FP64
+runs one ulp apart separate by up to 1e-1 at the paper's lr 6.0.  ADAM is
+therefore compared over the horizon where that growth stays 5-10x under the
+tolerance: 30 steps at lr 0.02 in FP32 and 20 steps at lr 6.0 in FP64; its long
+runs are checked through exact properties and the energy statistics.  Energies
+of integer instances are exact on both sides and compared bit for bit.  A
+replica is excluded from later steps only if a vertex sign differs where the
+oracle's |sin theta| < 1e-5 (a legitimate discontinuity); exclusions are counted.
+"""
+import numpy as np
+import pytest
+
+import instances as I
+import oracle
+from gpu_util import to_problem, iterate_error
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2312_05837_amd as P
+    c = P.ising_create(0)
+    yield c
+    P.ising_destroy(c)
+
+
+def _run_gpu(ctx, inst, R, steps, opt, lr, prec, chunks=1, uniform=None, seed=0, mu=0.5, real_dtype=None):
+    import torch
+    import paper_2312_05837_amd as P
+    prob = to_problem(inst, real_dtype=real_dtype)
+    state = P.ds_state(inst.n, R, prec, steps_trace=steps)
+    prm = P.params(replicas=R, steps=steps, optimizer=opt, precision=prec, lr=lr, mu=mu, seed=seed)
+    per = steps // chunks
+    trace_e = []
+    trace_l = []
+    thetas = []
+    for c in range(chunks):
+        st2 = dict(state)
+        st2["energy_trace"] = torch.zeros((per, R), dtype=torch.float64, device="cuda")
+        st2["loss_trace"] = torch.zeros((per, R), dtype=torch.float64, device="cuda")
+        P.ising_ds_dev(ctx, prob, prm, st2, t0=c * per, steps=per, uniform=uniform if c == 0 else None)
+        torch.cuda.synchronize()
+        trace_e.append(st2["energy_trace"].cpu().numpy())
+        trace_l.append(st2["loss_trace"].cpu().numpy())
+        thetas.append(state["theta"].cpu().numpy().astype(np.float64))
+    out = {k: v.cpu().numpy() for k, v in state.items() if k not in ("energy_trace", "loss_trace")}
+    out["energy_trace"] = np.concatenate(trace_e)
+    out["loss_trace"] = np.concatenate(trace_l)
+    out["thetas"] = thetas
+    return out
+
+
+CASES = [
+    # name, maker, replicas
+    ("sk64_dense", lambda: I.sk_pm1(64, 0), 32),
+    ("er800_pm1_packed", lambda: I.erdos_renyi(800, 0.06, 1, "pm1"), 64),
+    ("er800_one_packed_rg4", lambda: I.erdos_renyi(800, 0.06, 2, "one"), 1024),
+    ("torus20x40", lambda: I.torus(20, 40, 3, "pm1"), 48),
+    ("er_field_csrv", lambda: I.random_integer_field(I.erdos_renyi(300, 0.05, 4, "pm1"), 4, 3), 16),
+    ("gauss_dense257", lambda: I.sk_gauss(257, 5), 8),
+    ("t1_uniform_real_csr", lambda: I.table1_regular(500, 6, "uniform", 6), 8),
+    ("torus50x100_stream", lambda: I.torus(50, 100, 7, "pm1"), 8),
+    ("ragged_n65_r6", lambda: I.random_integer_field(I.erdos_renyi(65, 0.2, 8, "pm1"), 8, 2), 6),
+]
+
+
+def _subset(got, sel):
+    out = dict(got)
+    for k in ("theta", "m", "v", "s_best", "e_best", "best_step"):
+        out[k] = got[k][sel]
+    out["energy_trace"] = got["energy_trace"][:, sel]
+    out["loss_trace"] = got["loss_trace"][:, sel]
+    out["thetas"] = [t[sel] for t in got["thetas"]]
+    return out
+
+
+def _compare(inst, got, U, steps, opt, lr, chunks):
+    R = U.shape[0]
+    if R > 128:  # the oracle checks the first and last 64 replicas (trajectories are independent)
+        sel = np.r_[0:64, R - 64:R]
+        got = _subset(got, sel)
+        U = U[sel]
+        R = U.shape[0]
+    ref = oracle.ds_run(inst, U, steps, opt=opt, lr=lr, mu=0.5, record=True, record_sin=True)
+    excluded = np.zeros(R, dtype=bool)
+    # sign discrepancies only at legitimate discontinuities
+    per = steps // chunks
+    worst = 0.0
+    for c, th in enumerate(got["thetas"]):
+        t = (c + 1) * per
+        s_ref = ref.sin_trace[t - 1]
+        s_gpu = np.sin(th)
+        flip = (np.sign(s_ref) != np.sign(s_gpu)) & (s_ref != 0)
+        legit = flip & (np.abs(s_ref) < TOL)
+        assert not np.any(flip & ~legit & ~excluded[:, None]), f"vertex differs away from a discontinuity at step {t}"
+        excluded |= legit.any(axis=1)
+        err = iterate_error(s_gpu, s_ref)
+        err[excluded] = 0
+        worst = max(worst, err.max())
+    assert worst <= TOL, worst
+    keep = ~excluded
+    assert excluded.sum() <= max(1, R // 16), excluded.sum()
+    if inst.integer:
+        assert np.array_equal(got["energy_trace"][:, keep], ref.energy_trace[:, keep].astype(np.float64))
+        assert np.array_equal(got["e_best"][keep], ref.e_best[keep].astype(np.float64))
+        assert np.array_equal(got["best_step"][keep], ref.best_step[keep])
+        assert np.array_equal(got["s_best"][keep], ref.s_best[keep])
+    else:
+        scale = np.abs(ref.energy_trace).max() + 1.0
+        assert np.abs(got["energy_trace"][:, keep] - ref.energy_trace[:, keep]).max() <= 1e-4 * scale
+    scale_l = np.abs(ref.loss_trace).max() + 1.0
+    assert np.abs(got["loss_trace"][:, keep] - ref.loss_trace[:, keep]).max() <= 1e-4 * scale_l
+    return worst, int(excluded.sum())
+
+
+@pytest.mark.parametrize("opt,lr,steps", [("gd", 0.01, 100), ("adam", 0.02, 30)])
+@pytest.mark.parametrize("name,mk,R", CASES, ids=[c[0] for c in CASES])
+def test_fp32_iterates(ctx, name, mk, R, opt, lr, steps):
+    import torch
+    inst = mk()
+    U = I.uniform_draws(11, R, inst.n)
+    chunks = 10 if steps == 100 else 3
+    got = _run_gpu(ctx, inst, R, steps, opt, lr, "fp32", chunks=chunks,
+                   uniform=torch.tensor(U, dtype=torch.float32, device="cuda"))
+    worst, excl = _compare(inst, got, U, steps, opt, lr, chunks)
+    print(f"{name} {opt} lr={lr}: worst iterate error {worst:.2e}, excluded {excl}/{R}")
+
+
+@pytest.mark.parametrize("opt,lr,steps", [("adam", 6.0, 20), ("gd", 0.05, 100)])
+@pytest.mark.parametrize("name,mk,R", [CASES[0], CASES[1], CASES[3], CASES[4], CASES[5], CASES[6], CASES[8]],
+                         ids=[c[0] for c in [CASES[0], CASES[1], CASES[3], CASES[4], CASES[5], CASES[6], CASES[8]]])
+def test_fp64_iterates_paper_lr(ctx, name, mk, R, opt, lr, steps):
+    import torch
+    inst = mk()
+    U = I.uniform_draws(12, R, inst.n)
+    chunks = 10 if steps == 100 else 2
+    got = _run_gpu(ctx, inst, R, steps, opt, lr, "fp64", chunks=chunks,
+                   uniform=torch.tensor(U, dtype=torch.float64, device="cuda"))
+    worst, excl = _compare(inst, got, U, steps, opt, lr, chunks)
+    print(f"{name} {opt} lr={lr} fp64: worst iterate error {worst:.2e}, excluded {excl}/{R}")
+
+
+def test_fp64_streaming_engine_paper_lr(ctx):
+    import torch
+    inst = I.torus(50, 100, 13, "pm1")   # n = 5000 > register-resident limit
+    U = I.uniform_draws(14, 4, inst.n)
+    got = _run_gpu(ctx, inst, 4, 20, "adam", 6.0, "fp64", chunks=2,
+                   uniform=torch.tensor(U, dtype=torch.float64, device="cuda"))
+    _compare(inst, got, U, 20, "adam", 6.0, 2)
+    got = _run_gpu(ctx, inst, 4, 100, "gd", 0.05, "fp64", chunks=5,
+                   uniform=torch.tensor(U, dtype=torch.float64, device="cuda"))
+    _compare(inst, got, U, 100, "gd", 0.05, 5)
+
+
+@pytest.mark.parametrize("name,mk", [("er800", lambda: I.erdos_renyi(800, 0.06, 21, "pm1")),
+                                     ("torus20x40", lambda: I.torus(20, 40, 22, "pm1"))])
+def test_adam_long_run_energy_statistics(ctx, name, mk):
+    # beyond the trajectory horizon, FP32 GPU and FP64 oracle runs at the paper's lr 6.0
+    # are samples of the same best-energy distribution (same draws, same instance)
+    import torch
+    inst = mk()
+    R, T = 64, 1000
+    U = I.uniform_draws(23, R, inst.n)
+    got = _run_gpu(ctx, inst, R, T, "adam", 6.0, "fp32", uniform=torch.tensor(U, dtype=torch.float32, device="cuda"))
+    ref = oracle.ds_run(inst, U, T, opt="adam", lr=6.0, mu=0.5)
+    a = got["e_best"]
+    b = ref.e_best.astype(np.float64)
+    se = np.sqrt(a.var() / R + b.var() / R) + 1e-9
+    assert abs(a.mean() - b.mean()) <= 4 * se, (a.mean(), b.mean(), se)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_device_draws_equal_shared_generator(ctx, prec):
+    import torch
+    inst = I.erdos_renyi(300, 0.03, 3, "pm1")
+    R = 12
+    U = I.uniform_draws(77, R, inst.n)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    a = _run_gpu(ctx, inst, R, 0, "adam", 6.0, prec, uniform=torch.tensor(U, dtype=dt, device="cuda"))
+    b = _run_gpu(ctx, inst, R, 0, "adam", 6.0, prec, seed=77)
+    assert np.array_equal(a["theta"], b["theta"])
+    assert np.all(np.sign(np.sin(a["theta"].astype(np.float64))) * np.sign(U) >= 0)
+    ref = np.arcsin(U)
+    assert np.abs(a["theta"] - ref).max() < (2e-6 if prec == "fp32" else 1e-14)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_chunked_equals_single_launch(ctx, prec):
+    inst = I.erdos_renyi(200, 0.05, 5, "pm1")
+    one = _run_gpu(ctx, inst, 8, 60, "adam", 6.0, prec, chunks=1, seed=3)
+    six = _run_gpu(ctx, inst, 8, 60, "adam", 6.0, prec, chunks=6, seed=3)
+    for k in ("theta", "m", "v", "s_best", "e_best", "best_step", "energy_trace"):
+        assert np.array_equal(one[k], six[k]), k
+
+
+def test_best_vertex_consistency_long_run(ctx):
+    import torch
+    import paper_2312_05837_amd as P
+    inst = I.random_integer_field(I.erdos_renyi(800, 0.06, 9, "pm1"), 9, 2)
+    R, T = 64, 1000
+    got = _run_gpu(ctx, inst, R, T, "adam", 6.0, "fp32", seed=4)
+    tr = got["energy_trace"]
+    assert np.array_equal(got["e_best"], tr.min(axis=0))
+    assert np.array_equal(got["best_step"], tr.argmin(axis=0) + 1)
+    # recompute the energy of every returned vertex: on the GPU and with numpy
+    E, Ei = P.ising_energy_dev(ctx, to_problem(inst), torch.tensor(got["s_best"], device="cuda"))
+    torch.cuda.synchronize()
+    assert np.array_equal(Ei.cpu().numpy().astype(np.float64), got["e_best"])
+    Jd = inst.dense()
+    S = got["s_best"].astype(np.int64)
+    assert np.array_equal(((S @ Jd) * S).sum(1) + S @ inst.h, got["e_best"].astype(np.int64))
+
+
+def test_select_lowest_index_on_ties(ctx):
+    import torch
+    import paper_2312_05837_amd as P
+    e = torch.tensor([3.0, -1.0, 5.0, -1.0, 0.0], dtype=torch.float64, device="cuda")
+    assert int(P.ising_select_dev(ctx, e).item()) == 1
+    e = torch.full((3000,), 7.0, dtype=torch.float64, device="cuda")
+    e[2999] = -2.0
+    e[1500] = -2.0
+    assert int(P.ising_select_dev(ctx, e).item()) == 1500
+
+
+def test_single_spin_and_empty_graph(ctx):
+    import torch
+    inst = I.from_edges(3, [], np.array([2, -1, 0]))
+    U = I.uniform_draws(1, 4, 3)
+    got = _run_gpu(ctx, inst, 4, 50, "gd", 0.01, "fp32", uniform=torch.tensor(U, dtype=torch.float32, device="cuda"))
+    ref = oracle.ds_run(inst, U, 50, opt="gd", lr=0.01, mu=0.5, record=True)
+    assert np.array_equal(got["energy_trace"], ref.energy_trace.astype(np.float64))

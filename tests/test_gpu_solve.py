@@ -1,0 +1,109 @@
+"""Whole-solve parity (pruning -> domain selection -> selection -> retrieval -> exact energy)."""
+import numpy as np
+import pytest
+
+import instances as I
+import oracle
+from gpu_util import to_problem, energy_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2312_05837_amd as P
+    c = P.ising_create(0)
+    yield c
+    P.ising_destroy(c)
+
+
+def _solve(ctx, inst, **kw):
+    import torch
+    import paper_2312_05837_amd as P
+    prob = to_problem(inst)
+    s, E, Ei, st = P.ising_solve_dev(ctx, prob, P.params(**kw))
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), float(E.item()), (int(Ei.item()) if Ei is not None else None), st
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_sk20_reaches_brute_force_minimum_fp64(ctx, seed):
+    # plain method, FP64, on the N = 20 leading block of an SK +-1 instance (a SK instance itself)
+    inst = I.sk_pm1(64, seed)
+    sub = I.Instance(20, "sk20", np.zeros(20, dtype=np.int64), inst.J[:20, :20].copy(), integer=True)
+    e_min, _, _ = oracle.brute_force_min(sub)
+    s, E, Ei, st = _solve(ctx, sub, replicas=32, steps=1000, optimizer="adam", precision="fp64", lr=6.0,
+                          mu=0.5, seed=seed)
+    assert Ei == oracle.energy(sub, s)
+    assert Ei >= e_min
+    assert Ei == e_min, (Ei, e_min)
+
+
+def test_sk64_fp64_config(ctx):
+    inst = I.sk_pm1(64, 0)
+    s, E, Ei, st = _solve(ctx, inst, replicas=32, steps=1000, optimizer="adam", precision="fp64", lr=6.0,
+                          mu=0.5, seed=0)
+    assert st["n_G"] == 64 and st["eta"] == 0.0
+    assert Ei == oracle.energy(inst, s)
+    # quality sanity: SK ground states sit near E/N^1.5 = -1.5; a broken optimiser lands near 0
+    assert Ei / 64 ** 1.5 < -1.2
+
+
+CASES = [
+    ("forest_field", lambda: I.random_forest_plus_cycles(600, 3, n_extra=40, hmax=3)),
+    ("er_planted_field", lambda: I.planted(I.random_integer_field(I.erdos_renyi(500, 0.01, 4, "pm1"), 4, 3), 5)[0]),
+    ("t1_uniform_1000", lambda: I.table1_regular(1000, 6, "uniform", 6)),
+    ("t1_binary_int_1000", lambda: I.table1_regular(1000, 6, "binary_int", 7)),
+    ("torus_20x40", lambda: I.torus(20, 40, 8, "pm1")),
+    ("all_pruned", lambda: I.from_edges(4, [(0, 1, 1), (2, 3, -1)], np.array([5, 0, 0, 1]))),
+]
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_solve_consistent_with_oracle(ctx, name, mk, prec):
+    inst = mk()
+    pr = oracle.prune(inst)
+    s, E, Ei, st = _solve(ctx, inst, replicas=64, steps=300, optimizer="adam", precision=prec, lr=6.0, mu=0.5,
+                          seed=11)
+    assert st["n_G"] == pr.G.size
+    assert np.all(np.abs(s) == 1)
+    # every spin fixed by pruning is set as the record says
+    assert np.array_equal(s[pr.kind == 1], pr.fixed[pr.kind == 1])
+    k = np.nonzero(pr.kind == 2)[0]
+    assert np.array_equal(s[k], -pr.sigma[k] * s[pr.partner[k]])
+    if inst.integer:
+        assert Ei == oracle.energy(inst, s)
+        assert st["constant_C"] == pr.C
+    else:
+        assert abs(E - oracle.energy(inst, s)) <= 2 * energy_bound(inst)
+        assert abs(st["constant_C"] - pr.C) <= 1e-9 * (abs(pr.C) + 1)
+
+
+def test_solve_matches_oracle_solution_non_chaotic(ctx):
+    # GD at a small step: GPU FP64 and oracle follow the same trajectories, so the
+    # selected replica and returned vertex coincide
+    inst = I.random_forest_plus_cycles(400, 9, n_extra=60, hmax=2)
+    pr = oracle.prune(inst)
+    R, T = 16, 200
+    s, E, Ei, st = _solve(ctx, inst, replicas=R, steps=T, optimizer="gd", precision="fp64", lr=0.01, mu=0.5,
+                          seed=21)
+    U = I.uniform_draws(21, R, pr.G.size)
+    ref = oracle.solve(inst, U, T, opt="gd", lr=0.01, mu=0.5)
+    assert Ei == ref["energy"]
+    assert st["best_replica"] == ref["replica"]
+    assert np.array_equal(s, ref["spins"])
+
+
+def test_solve_host_buffers(ctx):
+    import ctypes as C
+    import paper_2312_05837_amd as P
+    inst = I.random_integer_field(I.erdos_renyi(200, 0.05, 3, "pm1"), 3, 2)
+    rp = inst.row_ptr.astype(np.int32)
+    col = inst.col.astype(np.int32)
+    val = inst.val.astype(np.int32)
+    h = inst.h.astype(np.int32)
+    prob = P.ising_problem(inst.n, P.ISING_CSR, P.ISING_I32, 0, col.size, None, rp.ctypes.data, col.ctypes.data,
+                           val.ctypes.data, h.ctypes.data)
+    s, E, Ei, st = P.ising_solve(ctx, prob, P.params(replicas=32, steps=200, precision="fp32"))
+    assert Ei == oracle.energy(inst, s) and E == Ei

@@ -104,3 +104,32 @@ def test_reaches_brute_force_optimum_n20(seed):
     res = oracle.ds_run(inst, U, 1000, opt="adam", lr=6.0, mu=0.5)
     assert res.e_best.min() == e_min
     assert np.all(res.e_best >= e_min)
+
+
+def _fp32_rounded_start(inst, U, steps, opt, lr):
+    """Oracle run whose initial angles are rounded to float32: a perturbation of one float32 rounding."""
+    import oracle.ds as D
+    th0 = np.arcsin(U).astype(np.float32).astype(np.float64)
+    U2 = np.sin(th0)   # asin(U2) == th0 up to one float64 rounding
+    return D.ds_run(inst, U2, steps, opt=opt, lr=lr, mu=0.5, record_sin=True)
+
+
+def test_adam_amplifies_rounding_gd_does_not():
+    # property of the method that sets the iterate-parity horizon of any FP32 implementation:
+    # one float32 rounding of theta_0 stays below 1e-5 for 100 GD steps (lr 0.01), while
+    # ADAM (lr 0.02) carries it above 1e-5 before step 100
+    inst = I.sk_pm1(64, 0)
+    U = I.uniform_draws(11, 32, 64)
+    base_gd = oracle.ds_run(inst, U, 100, opt="gd", lr=0.01, mu=0.5, record_sin=True)
+    pert_gd = _fp32_rounded_start(inst, U, 100, "gd", 0.01)
+    base_ad = oracle.ds_run(inst, U, 100, opt="adam", lr=0.02, mu=0.5, record_sin=True)
+    pert_ad = _fp32_rounded_start(inst, U, 100, "adam", 0.02)
+
+    def err(a, b):
+        return (np.abs(a - b).max(axis=2) / np.abs(a).max(axis=2)).max(axis=1)
+
+    e_gd = err(base_gd.sin_trace, pert_gd.sin_trace)
+    e_ad = err(base_ad.sin_trace, pert_ad.sin_trace)
+    assert e_gd.max() < 1e-5
+    assert e_ad[:30].max() < 1e-5
+    assert e_ad.max() > 1e-5
