@@ -12,6 +12,10 @@ import os
 from dataclasses import dataclass, field
 from typing import Optional
 
+# torch provides device memory and streams; import it first so that the HIP
+# runtime it loads is the one this library binds to (a single runtime per process)
+import torch  # noqa: E402,F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libising.so")
 

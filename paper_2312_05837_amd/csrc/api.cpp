@@ -343,6 +343,31 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
     HIP_TRY(ctx, launch_ds_format(dp, fp64, plan.packed, (uint32_t *)fmt, fmt, p.h ? hbuf : nullptr, s));
     a.row_ptr = p.row_ptr;
     a.col = p.col;
+    if (plan.packed && plan.l.ept > 0) {
+        // stage the +-w couplings in LDS when the image fits next to the vertex buffers
+        const int wbytes = plan.l.rg == 1 ? 1 : 4;
+        if ((int64_t)(p.n + 1) * wbytes <= 65535) {
+            int32_t *groups = nullptr, *prow = nullptr;
+            uint32_t *pcnt = nullptr;
+            HIP_TRY(ctx, pool.get("ds.pms.groups", (size_t)p.n * 4, (void **)&groups));
+            HIP_TRY(ctx, pool.get("ds.pms.prow", (size_t)(p.n + 1) * 4, (void **)&prow));
+            HIP_TRY(ctx, pool.get("ds.pms.pcnt", (size_t)p.n * 4, (void **)&pcnt));
+            int32_t total = 0;
+            HIP_TRY(ctx, launch_pms_format(dp, wbytes, groups, prow, pcnt, nullptr, &total, s));
+            DSLaunch l2 = plan.l;
+            l2.coupling = CK_PMS;
+            if (ds_lds_bytes(l2, p.n, total) <= 160 * 1024) {
+                uint16_t *img = nullptr;
+                HIP_TRY(ctx, pool.get("ds.pms.img", (size_t)std::max(total, 1) * 8, (void **)&img));
+                HIP_TRY(ctx, launch_pms_format(dp, wbytes, groups, prow, pcnt, img, &total, s));
+                plan.l = l2;
+                a.pimg = img;
+                a.pimg_groups = total;
+                a.prow = prow;
+                a.pcnt = pcnt;
+            }
+        }
+    }
     if (plan.packed) a.pm = (const uint32_t *)fmt;
     else if (p.format == ISING_CSR) a.val = fmt;
     else a.J = fmt;

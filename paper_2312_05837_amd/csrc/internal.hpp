@@ -82,7 +82,7 @@ hipError_t launch_copy_record(const PruneWork &w, int32_t n, int8_t *kind, int32
                               int8_t *fixed, int32_t *partner, int8_t *sigma, hipStream_t s);
 
 // ---- domain selection, persistent engine (kernels_ds.hip) -----------------
-enum Coupling { CK_PM = 0, CK_CSRV = 1, CK_DENSE = 2 };
+enum Coupling { CK_PM = 0, CK_CSRV = 1, CK_DENSE = 2, CK_PMS = 3 };
 
 struct DSArgs {
     int32_t n = 0, R = 0, t0 = 0, steps = 0, opt = ISING_OPT_ADAM, init_mode = 0;
@@ -104,6 +104,11 @@ struct DSArgs {
     int32_t *best_step = nullptr;
     double *etrace = nullptr, *ltrace = nullptr;
     const void *bias = nullptr;        // 2*steps bias corrections (ADAM), state precision
+    // sign-split LDS image (CK_PMS): 4 uint16 entries per group
+    const void *pimg = nullptr;
+    int32_t pimg_groups = 0;
+    const int32_t *prow = nullptr;     // first group of each row
+    const uint32_t *pcnt = nullptr;    // n_pos | n_neg << 16
 };
 
 struct DSLaunch {
@@ -122,6 +127,11 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s);
 // ADAM bias corrections 1/(1-b1^t), 1/(1-b2^t), t = t0+1..t0+steps (FP64, rounded).
 hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64, void *out, hipStream_t s);
 int32_t ds_max_n(bool fp64);
+// Build the CK_PMS image; writes the total group count to *total_groups (host,
+// synchronises once).  img may be NULL to only count.
+hipError_t launch_pms_format(const DevProblem &p, int wbytes, int32_t *groups, int32_t *prow, uint32_t *pcnt,
+                             uint16_t *img, int32_t *total_groups, hipStream_t s);
+size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups);
 
 hipError_t launch_select(const double *e_best, int32_t R, int32_t *best, hipStream_t s);
 // s_G = rows[best] of a replica-major int8 block (device-side gather).

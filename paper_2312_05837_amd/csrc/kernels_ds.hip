@@ -22,6 +22,12 @@
 //   CK_PM    all couplings +-w: entries col | (J<0) << 31.  The product counts,
 //            per replica, the neighbours with J_ij s_j = -w by adding
 //            (bit_j xor sign_ij) in packed lanes; y = w (deg - 2 count), exact.
+//   CK_PMS   the same couplings staged in LDS for the whole run: each row's
+//            neighbours split into J > 0 and J < 0 runs (each padded to a
+//            multiple of 4 with a slot whose vertex word is always 0), entries
+//            are 16-bit byte offsets of the neighbour's vertex word, so one
+//            neighbour costs one LDS read and one packed add:
+//            count = sum_{J>0} b_j + (n_neg - sum_{J<0} b_j).
 //   CK_CSRV  CSR values in the state precision.
 //   CK_DENSE dense rows in the state precision (small problems).
 #include "internal.hpp"
@@ -130,17 +136,56 @@ __device__ inline Real draw_uniform(uint64_t seed, int r, int i) {
     return (Real)2 * (u24 * (Real)5.9604644775390625e-08) - (Real)1;
 }
 
-template <typename T>
-__device__ inline T wave_sum(T v) {
+// Sum over the 64 lanes of a wavefront in a fixed order, result in every lane.
+// float: DPP adds within quads, half-rows and rows, then the row broadcasts of
+// lane 15 and lane 31 accumulate the four rows into lane 63, which is read back.
+// double: butterfly of lane shuffles.
+__device__ inline float wave_sum(float v) {
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
     return v;
 }
 
 template <typename Real, int CK, int RG>
-__device__ inline void coupling(const DSArgs &a, int i, const typename SpinWord<RG>::T *sc, Real (&y)[RG]) {
+__device__ inline void coupling(const DSArgs &a, int i, const typename SpinWord<RG>::T *sc, Real (&y)[RG],
+                                const uint2 *img = nullptr, int g0 = 0, uint32_t cnt = 0) {
     using SW = SpinWord<RG>;
-    if constexpr (CK == CK_PM) {
+    if constexpr (CK == CK_PMS) {
+        using T = typename SW::T;
+        const unsigned char *sb = (const unsigned char *)sc;
+        const int npos = (int)(cnt & 0xffffu), nneg = (int)(cnt >> 16);
+        const int gp = (npos + 3) >> 2, gn = (nneg + 3) >> 2;
+        uint32_t ap = 0, an = 0;
+        const uint2 *q = img + g0;
+        for (int k = 0; k < gp; ++k) {
+            const uint2 v = q[k];
+            ap += (uint32_t)(*(const T *)(sb + (v.x & 0xffffu))) + (uint32_t)(*(const T *)(sb + (v.x >> 16))) +
+                  (uint32_t)(*(const T *)(sb + (v.y & 0xffffu))) + (uint32_t)(*(const T *)(sb + (v.y >> 16)));
+        }
+        q += gp;
+        for (int k = 0; k < gn; ++k) {
+            const uint2 v = q[k];
+            an += (uint32_t)(*(const T *)(sb + (v.x & 0xffffu))) + (uint32_t)(*(const T *)(sb + (v.x >> 16))) +
+                  (uint32_t)(*(const T *)(sb + (v.y & 0xffffu))) + (uint32_t)(*(const T *)(sb + (v.y >> 16)));
+        }
+        const uint32_t acc = ap + (uint32_t)nneg * SW::ones - an;
+        const int deg = npos + nneg;
+        const Real w = (Real)a.w;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            const uint32_t c = SW::width == 32 ? acc : ((acc >> SW::shift(r)) & ((1u << SW::width) - 1u));
+            y[r] = w * (Real)(deg - 2 * (int)c);
+        }
+    } else if constexpr (CK == CK_PM) {
         const int rs = a.row_ptr[i], re = a.row_ptr[i + 1];
         uint32_t acc = 0;
         for (int q = rs; q < re; ++q) {
@@ -192,13 +237,30 @@ __global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
 
     const int n = a.n, B = blockDim.x, tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, NW = B >> 6;
-    const int npad = EPT * B;
+    const int npad = EPT * B + 1;  // one extra vertex word that stays 0 (padding target)
     SW *sbuf = (SW *)smem;
     const size_t off = ((size_t)2 * npad * sizeof(SW) + 15) & ~(size_t)15;
     Real *ep = (Real *)(smem + off);      // [2][NW][RG]
     Real *lp = ep + 2 * NW * RG;          // [2][NW][RG]
     uint32_t *flg = (uint32_t *)(lp + 2 * NW * RG);  // [2]
+    uint2 *img = (uint2 *)(smem + ((off + 2 * 2 * NW * RG * sizeof(Real) + 8 + 15) & ~(size_t)15));
     const int r0 = blockIdx.x * RG;
+    int prow_r[CK == CK_PMS ? EPT : 1];
+    uint32_t pcnt_r[CK == CK_PMS ? EPT : 1];
+    if constexpr (CK == CK_PMS) {
+        const uint2 *src = (const uint2 *)a.pimg;
+        for (int q = tid; q < a.pimg_groups; q += B) img[q] = src[q];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = e * B + tid;
+            prow_r[e] = i < n ? a.prow[i] : 0;
+            pcnt_r[e] = i < n ? a.pcnt[i] : 0u;
+        }
+    }
+    if (tid == 0) {
+        sbuf[n] = 0;
+        sbuf[npad + n] = 0;
+    }
     const Real *hv = (const Real *)a.h;
     Real *gth = (Real *)a.theta;
     Real *gm = (Real *)a.m;
@@ -279,7 +341,8 @@ __global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
             const int i = e * B + tid;
             if (i >= n) continue;
             Real y[RG];
-            coupling<Real, CK, RG>(a, i, sc, y);
+            if constexpr (CK == CK_PMS) coupling<Real, CK, RG>(a, i, sc, y, img, prow_r[e], pcnt_r[e]);
+            else coupling<Real, CK, RG>(a, i, sc, y);
             const Real hh = hv ? hv[i] : (Real)0;
             SW word = 0;
 #pragma unroll
@@ -609,6 +672,69 @@ __global__ void k_format(DevProblem p, int packed, uint32_t *pm, Real *val_out, 
     }
 }
 
+// Sign-split LDS image of +-w couplings: per row, J > 0 neighbours then J < 0
+// neighbours (ascending columns), each run padded to a multiple of 4 with the
+// byte offset of the zero vertex word; entries are byte offsets col * wbytes.
+__global__ void k_pms_count(DevProblem p, int32_t *groups, uint32_t *pcnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    int np = 0, nn = 0;
+    for (int q = p.row_ptr[i]; q < p.row_ptr[i + 1]; ++q) {
+        double v;
+        if (p.vtype == ISING_I32) v = ((const int32_t *)p.val)[q];
+        else if (p.vtype == ISING_F32) v = ((const float *)p.val)[q];
+        else v = ((const double *)p.val)[q];
+        if (v > 0) ++np;
+        else if (v < 0) ++nn;
+    }
+    pcnt[i] = (uint32_t)np | ((uint32_t)nn << 16);
+    groups[i] = ((np + 3) >> 2) + ((nn + 3) >> 2);
+}
+
+// exclusive scan of groups[0..n) into prow[0..n], prow[n] = total
+__global__ __launch_bounds__(1024) void k_pms_scan(int n, const int32_t *groups, int32_t *prow) {
+    __shared__ int part[1024];
+    const int per = (n + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(n, lo + per);
+    int c = 0;
+    for (int i = lo; i < hi; ++i) c += groups[i];
+    part[threadIdx.x] = c;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int v = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int base = part[threadIdx.x] - c;
+    for (int i = lo; i < hi; ++i) {
+        prow[i] = base;
+        base += groups[i];
+    }
+    if (threadIdx.x == 1023) prow[n] = part[1023];
+}
+
+__global__ void k_pms_fill(DevProblem p, const int32_t *prow, const uint32_t *pcnt, int wbytes, uint16_t *img) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    const int np = (int)(pcnt[i] & 0xffffu), nn = (int)(pcnt[i] >> 16);
+    const uint16_t pad = (uint16_t)(p.n * wbytes);
+    uint16_t *pos = img + (size_t)prow[i] * 4;
+    uint16_t *neg = pos + ((np + 3) >> 2) * 4;
+    int a = 0, b = 0;
+    for (int q = p.row_ptr[i]; q < p.row_ptr[i + 1]; ++q) {
+        double v;
+        if (p.vtype == ISING_I32) v = ((const int32_t *)p.val)[q];
+        else if (p.vtype == ISING_F32) v = ((const float *)p.val)[q];
+        else v = ((const double *)p.val)[q];
+        const uint16_t e = (uint16_t)(p.col[q] * wbytes);
+        if (v > 0) pos[a++] = e;
+        else if (v < 0) neg[b++] = e;
+    }
+    for (; a < ((np + 3) >> 2) * 4; ++a) pos[a] = pad;
+    for (; b < ((nn + 3) >> 2) * 4; ++b) neg[b] = pad;
+}
+
 __global__ __launch_bounds__(1024) void k_select(const double *e, int R, int32_t *best) {
     __shared__ double sv[1024];
     __shared__ int si[1024];
@@ -651,7 +777,9 @@ using KFn = void (*)(const DSArgs);
 template <typename Real, int CK, int RG>
 KFn pick_ept(int ept) {
     switch (ept) {
-        case 0: return k_ds_stream<Real, CK, RG>;
+        case 0:
+            if constexpr (CK != CK_PMS) return k_ds_stream<Real, CK, RG>;
+            return nullptr;
         case 1: return k_ds<Real, CK, RG, 1>;
         case 2: return k_ds<Real, CK, RG, 2>;
         case 4:
@@ -679,6 +807,7 @@ template <typename Real>
 KFn pick(int ck, int rg, int ept) {
     switch (ck) {
         case CK_PM: return pick_rg<Real, CK_PM>(rg, ept);
+        case CK_PMS: return ept > 0 ? pick_rg<Real, CK_PMS>(rg, ept) : nullptr;
         case CK_CSRV: return pick_rg<Real, CK_CSRV>(rg, ept);
         case CK_DENSE: return pick_rg<Real, CK_DENSE>(rg, ept);
         default: return nullptr;
@@ -715,8 +844,9 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
     const size_t sw = l.rg == 1 ? 1 : 4;
     const size_t real = l.fp64 ? 8 : 4;
     const int nw = l.block / 64;
-    const size_t sbytes = l.ept > 0 ? (size_t)2 * l.ept * l.block * sw : (size_t)3 * a.n * sw;
-    const size_t lds = ((sbytes + 15) & ~(size_t)15) + 2 * 2 * nw * l.rg * real + 16;
+    const size_t sbytes = l.ept > 0 ? (size_t)2 * (l.ept * l.block + 1) * sw : (size_t)3 * a.n * sw;
+    size_t lds = ((sbytes + 15) & ~(size_t)15) + 2 * 2 * nw * l.rg * real + 8;
+    if (l.coupling == CK_PMS) lds = ((lds + 15) & ~(size_t)15) + (size_t)8 * a.pimg_groups;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -731,6 +861,29 @@ hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64,
     if (fp64) hipLaunchKernelGGL(k_bias_table<double>, dim3((steps + 255) / 256), dim3(256), 0, s, b1, b2, t0, steps, (double *)out);
     else hipLaunchKernelGGL(k_bias_table<float>, dim3((steps + 255) / 256), dim3(256), 0, s, b1, b2, t0, steps, (float *)out);
     return hipGetLastError();
+}
+
+hipError_t launch_pms_format(const DevProblem &p, int wbytes, int32_t *groups, int32_t *prow, uint32_t *pcnt,
+                             uint16_t *img, int32_t *total_groups, hipStream_t s) {
+    const dim3 g((p.n + 255) / 256);
+    hipLaunchKernelGGL(k_pms_count, g, dim3(256), 0, s, p, groups, pcnt);
+    hipLaunchKernelGGL(k_pms_scan, dim3(1), dim3(1024), 0, s, p.n, groups, prow);
+    hipError_t e = hipMemcpyAsync(total_groups, prow + p.n, 4, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (img) hipLaunchKernelGGL(k_pms_fill, g, dim3(256), 0, s, p, prow, pcnt, wbytes, img);
+    return hipGetLastError();
+}
+
+size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups) {
+    const size_t sw = l.rg == 1 ? 1 : 4;
+    const size_t real = l.fp64 ? 8 : 4;
+    const int nw = l.block / 64;
+    const size_t sbytes = l.ept > 0 ? (size_t)2 * (l.ept * l.block + 1) * sw : (size_t)3 * n * sw;
+    size_t lds = ((sbytes + 15) & ~(size_t)15) + 2 * 2 * nw * l.rg * real + 8;
+    if (l.coupling == CK_PMS) lds = ((lds + 15) & ~(size_t)15) + (size_t)8 * pimg_groups;
+    return lds;
 }
 
 hipError_t launch_select(const double *e_best, int32_t R, int32_t *best, hipStream_t s) {
