@@ -41,7 +41,12 @@ WORKLOADS = {
     "sk64_fp64": ("dense SK N=64 +-1, FP64", "sk64", 32, 1000, "fp64"),
     "torus20000": ("2D torus 100x200 +-1 weights, CSR", "torus20000", 256, 10000, "fp32"),
     "reg3_20000": ("random 3-regular N=20000 +-1 weights, CSR", "reg3", 256, 10000, "fp32"),
+    "sk2000_bf16x2": ("dense SK N=2000 J~N(0,1/N), J split hi/lo BF16 on MFMA", "sk2000g", 4096, 2000, "bf16x2"),
+    "sk2000_bf16": ("dense SK N=2000 J~N(0,1/N), J in BF16 on MFMA", "sk2000g", 4096, 2000, "bf16"),
+    "sk2000_fp32": ("dense SK N=2000 J~N(0,1/N), FP32 MFMA", "sk2000g", 4096, 2000, "fp32"),
 }
+# peak rates of the matrix cores (dense, no sparsity), per precision of the coupling product
+MFMA_PEAK = {"bf16x2": 2.5e15, "bf16": 2.5e15, "fp32": 157.3e12}
 
 
 def make_instance(kind):
@@ -56,6 +61,8 @@ def make_instance(kind):
         return I.torus(100, 200, 0, "pm1")
     if kind == "reg3":
         return I.random_regular(20000, 3, 0, "pm1")
+    if kind == "sk2000g":
+        return I.sk_gauss(2000, 0)
     raise ValueError(kind)
 
 
@@ -150,8 +157,21 @@ def main():
     if nnzG is None:
         import oracle
         nnzG = int(oracle.prune(inst).reduced.nnz)
-    ops = float(T) * R * (nnzG + EPI_OPS[args.optimizer] * nG)
-    achieved = ops / (k_ms * 1e-3)
+    dense_mfma = inst.is_dense and (prec in ("bf16x2", "bf16") or (prec == "fp32" and nG > 256))
+    if dense_mfma:
+        # the coupling product J S~ on the matrix cores: 2 n_G^2 R flops per step
+        ops = 2.0 * nG * nG * R * T
+        achieved = ops / (k_ms * 1e-3)
+        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_PEAK[prec] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / MFMA_PEAK[prec], "traffic": None,
+                "kernel": "k_dense_step (MFMA product + fused update) and k_dense_best, all steps", "kernel_ms": k_ms,
+                "flops_per_launch_sequence": ops}
+    else:
+        ops = float(T) * R * (nnzG + EPI_OPS[args.optimizer] * nG)
+        achieved = ops / (k_ms * 1e-3)
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+                "frac": achieved / ALU_PEAK_OPS, "traffic": None,
+                "kernel": "k_ds (persistent domain-selection engine)", "kernel_ms": k_ms, "ops_per_launch": ops}
     e_final = float(E.item())
     best_step = stats[-1]["best_step"]
     t_ds = float(np.mean([s["t_ds_ms"] for s in stats]))
@@ -167,15 +187,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x2": "bf16x2/f32", "bf16": "bf16/f32"}[prec],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n": inst.n, "n_G": nG, "nnz": int(inst.nnz),
                    "replicas": R, "ds_steps": T, "optimizer": args.optimizer, "lr": lr, "mu": mu,
                    "precision": prec, "prune": True},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                     "frac": achieved / ALU_PEAK_OPS, "traffic": None,
-                     "kernel": "k_ds (persistent domain-selection engine)", "kernel_ms": k_ms,
-                     "ops_per_launch": ops},
+        "roofline": roof,
         "time_to_target_s": (t_pre + t_ds * best_step / T) * 1e-3,
         "best_energy": e_final,
         "stage_ms": {"ingest": float(np.mean([s["t_upload_ms"] for s in stats])),

@@ -60,10 +60,13 @@ enum { ISING_I32 = 0, ISING_F32 = 1, ISING_F64 = 2 };
 
 enum { ISING_OPT_GD = 0, ISING_OPT_ADAM = 1 };
 
-/* Arithmetic of the domain-selection iterates (angles, moments, gradient):
- * FP64 or FP32.  The coupling product follows it, except for the dense
- * reduced-precision forms of the coupling product (see ising_ds_dense_dev). */
-enum { ISING_PREC_FP64 = 0, ISING_PREC_FP32 = 1 };
+/* Arithmetic of domain selection.  FP64 and FP32: iterates (angles, moments,
+ * gradient) and coupling product in that precision.  BF16X2 and BF16 (dense
+ * couplings on the matrix cores only): FP32 iterates, coupling product with J
+ * split into two BF16 parts (J = J_hi + J_lo) or rounded to one BF16, the
+ * vertex (+-1) exact in BF16, FP32 accumulation; the energy of the returned
+ * vector is always recomputed in FP64 (or exactly for integer J). */
+enum { ISING_PREC_FP64 = 0, ISING_PREC_FP32 = 1, ISING_PREC_BF16X2 = 2, ISING_PREC_BF16 = 3 };
 
 typedef struct ising_problem {
     int32_t n;           /* spin count, > 0 */
@@ -231,6 +234,18 @@ ising_status ising_ds_dev(ising_ctx *ctx, const ising_problem *problem, const is
                           void *stream);
 /* Largest n the persistent engine accepts for a given precision. */
 int32_t ising_ds_max_n(int32_t precision);
+
+/* The same steps for a dense problem on the matrix cores: each step is one
+ * launch computing Y = J S~ for a 128-spin x 128-replica tile with MFMA
+ * (precision FP32: v_mfma_f32_32x32x2_f32; BF16X2 / BF16: v_mfma_f32_32x32x16_bf16
+ * on J_hi (+ J_lo)), with the elementwise update fused into the tile epilogue,
+ * plus a small launch that keeps each replica's best energy.  State arrays are
+ * float (theta, m, v), traces and e_best double; energies tracked during the
+ * run are those of the chosen form (FP32 accumulation).  Any R >= 1; n up to
+ * the device memory.  Errors: ENOTSUP for FP64 precision or a CSR problem. */
+ising_status ising_ds_dense_dev(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
+                                const void *uniform, int32_t t0, int32_t steps, ising_ds_state *state,
+                                void *stream);
 
 /* ---- best replica (argmin) ---------------------------------------------- */
 

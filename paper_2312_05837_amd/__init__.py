@@ -29,7 +29,7 @@ ISING_OK, ISING_EINVAL, ISING_ENOMEM, ISING_EDEVICE, ISING_EBUSY, ISING_ETIMEDOU
 ISING_DENSE, ISING_CSR = 0, 1
 ISING_I32, ISING_F32, ISING_F64 = 0, 1, 2
 ISING_OPT_GD, ISING_OPT_ADAM = 0, 1
-ISING_PREC_FP64, ISING_PREC_FP32 = 0, 1
+ISING_PREC_FP64, ISING_PREC_FP32, ISING_PREC_BF16X2, ISING_PREC_BF16 = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EBUSY", 5: "ETIMEDOUT",
                 6: "ECANCELED", 7: "ENOTSUP"}
@@ -92,6 +92,8 @@ _sigs = {
     "ising_ds_dev": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(ising_params), _P, C.c_int32, C.c_int32,
                                C.POINTER(ising_ds_state), _P]),
     "ising_ds_max_n": (C.c_int32, [C.c_int32]),
+    "ising_ds_dense_dev": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(ising_params), _P, C.c_int32,
+                                     C.c_int32, C.POINTER(ising_ds_state), _P]),
     "ising_select_dev": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
 }
 for _name, (_res, _args) in _sigs.items():
@@ -171,7 +173,8 @@ def csr_problem(row_ptr, col, val, h=None) -> Problem:
 def params(replicas=32, steps=100, optimizer="adam", precision="fp32", lr=6.0, mu=0.5, beta1=0.9,
            beta2=0.999, eps=1e-8, seed=0, prune=True) -> ising_params:
     opt = {"gd": ISING_OPT_GD, "adam": ISING_OPT_ADAM}[optimizer] if isinstance(optimizer, str) else optimizer
-    prec = {"fp64": ISING_PREC_FP64, "fp32": ISING_PREC_FP32}[precision] if isinstance(precision, str) \
+    prec = {"fp64": ISING_PREC_FP64, "fp32": ISING_PREC_FP32, "bf16x2": ISING_PREC_BF16X2,
+            "bf16": ISING_PREC_BF16}[precision] if isinstance(precision, str) \
         else precision
     return ising_params(replicas, steps, opt, prec, lr, mu, beta1, beta2, eps, seed, 1 if prune else 0, 0)
 
@@ -367,3 +370,16 @@ def ising_select_dev(ctx, e_best, best=None, stream=None):
         best = torch.empty(1, dtype=torch.int32, device=e_best.device)
     _check(ctx, _lib.ising_select_dev(ctx, _ptr(e_best), int(e_best.shape[0]), _ptr(best), _stream(stream)))
     return best
+
+
+def ising_ds_dense_dev(ctx, problem, prm: ising_params, state: dict, t0: int = 0, steps: Optional[int] = None,
+                       uniform=None, stream=None):
+    """Matrix-core domain selection on a dense problem (state tensors from ds_state(..., "fp32"))."""
+    ps = problem.struct() if isinstance(problem, Problem) else problem
+    steps = prm.steps if steps is None else steps
+    st = ising_ds_state(_ptr(state["theta"]), _ptr(state.get("m")), _ptr(state.get("v")), _ptr(state["s_best"]),
+                        _ptr(state["e_best"]), _ptr(state["best_step"]), _ptr(state.get("energy_trace")),
+                        _ptr(state.get("loss_trace")))
+    _check(ctx, _lib.ising_ds_dense_dev(ctx, C.byref(ps), C.byref(prm), _ptr(uniform), t0, steps, C.byref(st),
+                                        _stream(stream)))
+    return state

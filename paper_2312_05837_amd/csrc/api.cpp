@@ -396,6 +396,83 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
     return ISING_OK;
 }
 
+ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const void *uniform,
+                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s,
+                       hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr) {
+    if (p.format != ISING_DENSE) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine needs dense couplings");
+    int form;
+    if (prm.precision == ISING_PREC_FP32) form = DF_FP32;
+    else if (prm.precision == ISING_PREC_BF16X2) form = DF_BF16X2;
+    else if (prm.precision == ISING_PREC_BF16) form = DF_BF16;
+    else return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs FP32, BF16X2 or BF16");
+    if (prm.replicas <= 0 || steps < 0 || t0 < 0) return fail(ctx, ISING_EINVAL, "bad replicas/steps/t0");
+    if (!st || !st->theta || !st->s_best || !st->e_best || !st->best_step)
+        return fail(ctx, ISING_EINVAL, "state buffers missing");
+    if (prm.optimizer == ISING_OPT_ADAM && (!st->m || !st->v)) return fail(ctx, ISING_EINVAL, "ADAM needs m and v");
+    const int n = p.n, R = prm.replicas;
+    DenseRun d;
+    d.n = n;
+    d.R = R;
+    d.Mp = (n + 127) / 128 * 128;
+    d.Kp = (n + 31) / 32 * 32;
+    d.form = form;
+    d.opt = prm.optimizer;
+    d.t0 = t0;
+    d.steps = steps;
+    d.init_mode = t0 > 0 ? 0 : (uniform ? 1 : 2);
+    d.seed = prm.seed;
+    d.lr = prm.lr;
+    d.mu = prm.mu;
+    d.b1 = prm.beta1;
+    d.b2 = prm.beta2;
+    d.eps = prm.eps;
+    void *Jhi = nullptr, *Jlo = nullptr, *Jf = nullptr, *hf = nullptr, *S = nullptr, *Ep = nullptr, *Lp = nullptr;
+    const size_t mk = (size_t)d.Mp * d.Kp;
+    if (form == DF_FP32) {
+        HIP_TRY(ctx, pool.get("dn.Jf", mk * 4, &Jf));
+    } else {
+        HIP_TRY(ctx, pool.get("dn.Jhi", mk * 2, &Jhi));
+        if (form == DF_BF16X2) HIP_TRY(ctx, pool.get("dn.Jlo", mk * 2, &Jlo));
+    }
+    if (p.h) HIP_TRY(ctx, pool.get("dn.h", (size_t)n * 4, &hf));
+    HIP_TRY(ctx, pool.get("dn.S", (size_t)2 * R * d.Kp * (form == DF_FP32 ? 4 : 2), &S));
+    HIP_TRY(ctx, pool.get("dn.Ep", (size_t)(d.Mp / 128) * R * 4, &Ep));
+    HIP_TRY(ctx, pool.get("dn.Lp", (size_t)(d.Mp / 128) * R * 4, &Lp));
+    HIP_TRY(ctx, launch_dense_prepare(to_dev(p), form, d.Mp, d.Kp, Jhi, Jlo, Jf, (float *)hf, s));
+    d.Jhi = Jhi;
+    d.Jlo = Jlo;
+    d.Jf = Jf;
+    d.h = p.h ? (const float *)hf : nullptr;
+    d.uniform = uniform;
+    d.S = S;
+    d.theta = (float *)st->theta;
+    d.m = prm.optimizer == ISING_OPT_ADAM ? (float *)st->m : nullptr;
+    d.v = prm.optimizer == ISING_OPT_ADAM ? (float *)st->v : nullptr;
+    d.Epart = (float *)Ep;
+    d.Lpart = (float *)Lp;
+    d.e_best = st->e_best;
+    d.best_step = st->best_step;
+    d.s_best = st->s_best;
+    d.etrace = st->energy_trace;
+    d.ltrace = st->loss_trace;
+    if (kbeg) HIP_TRY(ctx, hipEventRecord(kbeg, s));
+    hipError_t e = launch_dense_run(d, s);
+    if (e != hipSuccess)
+        return fail(ctx, e == hipErrorInvalidValue ? ISING_ENOTSUP : ISING_EDEVICE,
+                    std::string("matrix-core domain selection: ") + hipGetErrorString(e));
+    if (kend) HIP_TRY(ctx, hipEventRecord(kend, s));
+    return ISING_OK;
+}
+
+// dense problems with more than this many spins use the matrix-core engine in FP32
+constexpr int kDenseMfmaMinN = 256;
+
+bool use_dense_engine(const ising_problem &p, const ising_params &prm) {
+    if (p.format != ISING_DENSE) return false;
+    if (prm.precision == ISING_PREC_BF16X2 || prm.precision == ISING_PREC_BF16) return true;
+    return prm.precision == ISING_PREC_FP32 && p.n > kDenseMfmaMinN;
+}
+
 double ms_between(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
@@ -560,6 +637,17 @@ ising_status ising_ds_dev(ising_ctx *ctx, const ising_problem *problem, const is
     return run_ds(ctx, *problem, *params, ing, uniform, t0, steps, state, ctx->pool, s);
 }
 
+ising_status ising_ds_dense_dev(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
+                                const void *uniform, int32_t t0, int32_t steps, ising_ds_state *state, void *stream) {
+    if (!ctx || !params) return ISING_EINVAL;
+    ST_TRY(check_problem_shape(ctx, problem));
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Ingest ing;
+    ST_TRY(ingest(ctx, to_dev(*problem), ctx->pool, ing, s));
+    return run_dense(ctx, *problem, *params, uniform, t0, steps, state, ctx->pool, s);
+}
+
 ising_status ising_select_dev(ising_ctx *ctx, const double *e_best, int32_t replicas, int32_t *best,
                               void *stream) {
     if (!ctx || !e_best || !best || replicas <= 0) return ISING_EINVAL;
@@ -610,6 +698,9 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
     HIP_TRY(ctx, hipEventRecord(ev[2], s));
     const int nG = red->n;
     const int R = params->replicas;
+    const bool dense_engine = use_dense_engine(*red, *params);
+    if (!dense_engine && (params->precision == ISING_PREC_BF16X2 || params->precision == ISING_PREC_BF16))
+        return fail(ctx, ISING_ENOTSUP, "BF16 forms need dense couplings");
     const size_t real = params->precision == ISING_PREC_FP64 ? 8 : 4;
     int32_t *bestdev = nullptr;
     int8_t *sG = nullptr;
@@ -626,7 +717,8 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
         HIP_TRY(ctx, pool.get("solve.sbest", (size_t)nG * R, (void **)&st.s_best));
         HIP_TRY(ctx, pool.get("solve.ebest", (size_t)R * 8, (void **)&st.e_best));
         HIP_TRY(ctx, pool.get("solve.bstep", (size_t)R * 4, (void **)&st.best_step));
-        ST_TRY(run_ds(ctx, *red, *params, ing, nullptr, 0, params->steps, &st, pool, s, ev[5], ev[6]));
+        if (dense_engine) ST_TRY(run_dense(ctx, *red, *params, nullptr, 0, params->steps, &st, pool, s, ev[5], ev[6]));
+        else ST_TRY(run_ds(ctx, *red, *params, ing, nullptr, 0, params->steps, &st, pool, s, ev[5], ev[6]));
         HIP_TRY(ctx, hipEventRecord(ev[3], s));
         HIP_TRY(ctx, launch_select(st.e_best, R, bestdev, s));
         HIP_TRY(ctx, launch_gather_row(st.s_best, nG, bestdev, sG, s));

@@ -138,4 +138,28 @@ hipError_t launch_select(const double *e_best, int32_t R, int32_t *best, hipStre
 hipError_t launch_gather_row(const int8_t *block, int32_t n, const int32_t *best, int8_t *out,
                              hipStream_t s);
 
+// ---- domain selection for dense couplings on MFMA (kernels_dense.hip) --------
+enum DenseForm { DF_FP32 = 0, DF_BF16X2 = 1, DF_BF16 = 2 };
+
+struct DenseRun {
+    int n = 0, R = 0, Mp = 0, Kp = 0, form = DF_BF16X2, opt = ISING_OPT_ADAM, t0 = 0, steps = 0, init_mode = 2;
+    int reinit = 1;
+    uint64_t seed = 0;
+    double lr = 6.0, mu = 0.5, b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    const void *Jhi = nullptr, *Jlo = nullptr, *Jf = nullptr;
+    const float *h = nullptr;
+    const void *uniform = nullptr;
+    void *S = nullptr;  // two vertex buffers [R][Kp] (BF16 bits or FP32)
+    float *theta = nullptr, *m = nullptr, *v = nullptr;
+    float *Epart = nullptr, *Lpart = nullptr;  // [Mp / 128][R]
+    double *e_best = nullptr;
+    int32_t *best_step = nullptr;
+    int8_t *s_best = nullptr;
+    double *etrace = nullptr, *ltrace = nullptr;
+};
+// Pad and split J (and convert h to float into hf when both are non-null).
+hipError_t launch_dense_prepare(const DevProblem &p, int form, int Mp, int Kp, void *Jhi, void *Jlo, void *Jf,
+                                float *hf, hipStream_t s);
+hipError_t launch_dense_run(const DenseRun &d, hipStream_t s);
+
 }  // namespace ising

@@ -75,53 +75,7 @@ CASES = [
 ]
 
 
-def _subset(got, sel):
-    out = dict(got)
-    for k in ("theta", "m", "v", "s_best", "e_best", "best_step"):
-        out[k] = got[k][sel]
-    out["energy_trace"] = got["energy_trace"][:, sel]
-    out["loss_trace"] = got["loss_trace"][:, sel]
-    out["thetas"] = [t[sel] for t in got["thetas"]]
-    return out
-
-
-def _compare(inst, got, U, steps, opt, lr, chunks):
-    R = U.shape[0]
-    if R > 128:  # the oracle checks the first and last 64 replicas (trajectories are independent)
-        sel = np.r_[0:64, R - 64:R]
-        got = _subset(got, sel)
-        U = U[sel]
-        R = U.shape[0]
-    ref = oracle.ds_run(inst, U, steps, opt=opt, lr=lr, mu=0.5, record=True, record_sin=True)
-    excluded = np.zeros(R, dtype=bool)
-    # sign discrepancies only at legitimate discontinuities
-    per = steps // chunks
-    worst = 0.0
-    for c, th in enumerate(got["thetas"]):
-        t = (c + 1) * per
-        s_ref = ref.sin_trace[t - 1]
-        s_gpu = np.sin(th)
-        flip = (np.sign(s_ref) != np.sign(s_gpu)) & (s_ref != 0)
-        legit = flip & (np.abs(s_ref) < TOL)
-        assert not np.any(flip & ~legit & ~excluded[:, None]), f"vertex differs away from a discontinuity at step {t}"
-        excluded |= legit.any(axis=1)
-        err = iterate_error(s_gpu, s_ref)
-        err[excluded] = 0
-        worst = max(worst, err.max())
-    assert worst <= TOL, worst
-    keep = ~excluded
-    assert excluded.sum() <= max(1, R // 16), excluded.sum()
-    if inst.integer:
-        assert np.array_equal(got["energy_trace"][:, keep], ref.energy_trace[:, keep].astype(np.float64))
-        assert np.array_equal(got["e_best"][keep], ref.e_best[keep].astype(np.float64))
-        assert np.array_equal(got["best_step"][keep], ref.best_step[keep])
-        assert np.array_equal(got["s_best"][keep], ref.s_best[keep])
-    else:
-        scale = np.abs(ref.energy_trace).max() + 1.0
-        assert np.abs(got["energy_trace"][:, keep] - ref.energy_trace[:, keep]).max() <= 1e-4 * scale
-    scale_l = np.abs(ref.loss_trace).max() + 1.0
-    assert np.abs(got["loss_trace"][:, keep] - ref.loss_trace[:, keep]).max() <= 1e-4 * scale_l
-    return worst, int(excluded.sum())
+from gpu_util import compare_trajectories as _compare  # noqa: E402
 
 
 @pytest.mark.parametrize("opt,lr,steps", [("gd", 0.01, 100), ("adam", 0.02, 30)])
