@@ -148,8 +148,9 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
 /* E(s_r) = s_r^T J s_r + h^T s_r for `count` spin vectors (replica-major).
  * problem and spins are device pointers.  E_out (nullable): count doubles.
  * E_int_out (nullable, ISING_I32 problems only): count int64, exact.
- * Real J: each row's sum is FP64 in ascending column order; rows are combined
- * in a fixed tree order, so results are reproducible run to run. */
+ * Real J: FP64, each row summed as 64 strided partials combined by an xor
+ * butterfly, rows and blocks combined in a fixed order, so results are
+ * reproducible run to run. */
 ising_status ising_energy_dev(ising_ctx *ctx, const ising_problem *problem, const int8_t *spins,
                               int32_t count, double *E_out, int64_t *E_int_out, void *stream);
 

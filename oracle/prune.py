@@ -7,15 +7,14 @@ Each round, on the set A of still-active spins:
   1. a_i = sum_{j in A} |J_ij|; D = {i in A : |h_i| > 2 a_i}  (strict, the
      determined-spin rule); s_i = -sgn(h_i) for i in D.
   2. C += sum_{i in D} h_i s_i + sum_{i,j in D} J_ij s_i s_j (ordered pairs);
-     for j in A \\ D: h_j += 2 sum_{i in D} J_ji s_i, the terms added in
-     ascending i;  A <- A \\ D.
+     for j in A \\ D: h_j += 2 sum_{i in D} J_ji s_i;  A <- A \\ D.
   3. deg_k = #{j in A : J_kj != 0}.  K = {k : deg_k = 1 and 2|J_k,n(k)| >= |h_k|}
      (the semi-determined-spin rule, non-strict) with n(k) the unique active
      neighbour.  If k and n(k) are both in K and are each other's neighbour
      they would fix each other, so only the larger index of the pair is taken:
      S = K minus those smaller partners.
-  4. For k in S ascending, with i = n(k) and sigma = sgn(J_ki): record
-     (k, i, sigma); h_i -= sigma h_k; C -= 2 |J_ki|;  A <- A \\ S.
+  4. For k in S, with i = n(k) and sigma = sgn(J_ki): record (k, i, sigma);
+     h_i -= sum over those k of sigma h_k; C -= 2 |J_ki|;  A <- A \\ S.
   5. Stop when D and S are both empty.  G = A (ascending original index),
      J_G = J[G, G], h_G = h[G].
 
@@ -26,14 +25,19 @@ Retrieval: s[G] = s_G, then rounds in reverse: s_k = -sigma s_i for S records
 (n(k) survives its round, so it is already resolved) and the recorded value for
 D records.
 
-Rounding convention for real couplings (a reading; the paper is silent): the
-row sums a_i are formed in one fixed order so that an FP64 threshold decision
-is reproducible by any implementation that follows it.  The stored entries of
-row i (all n columns for a dense matrix, the stored nonzeros in ascending
-column order for CSR) are numbered p = 0, 1, ...; partial sum l (0 <= l < 64)
-adds |J_ip| (0 for inactive j) for p = l, l + 64, l + 128, ... in ascending p;
-then the 64 partials are combined pairwise by index xor 32, 16, 8, 4, 2, 1.
-Integer couplings are summed exactly in int64, where order is irrelevant.
+Rounding convention for real couplings (a reading; the paper is silent): every
+per-row sum of the algorithm -- the row sums a_i, the fold of the determined
+spins into h_j (sum over i in D of 2 J_ji s_i, then added to h_j once), the
+fold of the semi-determined spins into h_i (sum over k in S with n(k) = i of
+sgn(J_ik) h_k, then subtracted once) and the D-D couplings of C -- is formed in
+one fixed order, so that FP64 decisions and h_G are reproducible by any
+implementation that follows it.  The stored entries of row i (all n columns
+for a dense matrix, the stored nonzeros in ascending column order for CSR) are
+numbered p = 0, 1, ...; partial sum l (0 <= l < 64) adds the terms of
+p = l, l + 64, l + 128, ... in ascending p (0 for entries that do not take
+part); then the 64 partials are combined pairwise by index xor 32, 16, 8, 4,
+2, 1.  Integer couplings are summed exactly in int64, where order is
+irrelevant.
 """
 from __future__ import annotations
 
@@ -82,22 +86,26 @@ def _entries(inst):
     return rows, cols, vals, pos
 
 
-def fixed_order_abs_rowsum(n, rows, cols, vals, pos, active, integer):
-    """a_i = sum_{j active} |J_ij| in the fixed 64-partial order described above."""
-    mag = np.abs(vals) * active[cols] * active[rows]
+def fixed_order_rowsum(n, rows, pos, terms, integer):
+    """Per-row sums of per-entry terms in the fixed 64-partial order described above."""
     if integer:
-        return _exact_int_rowsum(n, rows, mag)
+        return _exact_int_rowsum(n, rows, terms)
     acc = np.zeros((n, LANES), dtype=np.float64)
     chunk = pos // LANES
     lane = pos % LANES
-    mag = mag.astype(np.float64)
+    terms = terms.astype(np.float64)
     for k in range(int(chunk.max()) + 1 if chunk.size else 0):
         sel = chunk == k
-        acc[rows[sel], lane[sel]] = acc[rows[sel], lane[sel]] + mag[sel]
+        acc[rows[sel], lane[sel]] = acc[rows[sel], lane[sel]] + terms[sel]
     idx = np.arange(LANES)
     for d in (32, 16, 8, 4, 2, 1):
         acc = acc + acc[:, idx ^ d]
     return acc[:, 0]
+
+
+def fixed_order_abs_rowsum(n, rows, cols, vals, pos, active, integer):
+    """a_i = sum_{j active} |J_ij| in the fixed 64-partial order described above."""
+    return fixed_order_rowsum(n, rows, pos, np.abs(vals) * active[cols] * active[rows], integer)
 
 
 def _exact_int_rowsum(n, rows, mag):
@@ -144,16 +152,11 @@ def prune(inst) -> PruneResult:
         s_full[Didx] = sD
         # 2. fold D into C and into the fields of the remaining active spins
         if Didx.size:
-            C = C + (h[Didx] * sD).sum()
-            inD = D[rows] & D[cols]
-            C = C + (vals[inD] * s_full[rows[inD]] * s_full[cols[inD]]).sum()
+            dd = fixed_order_rowsum(n, rows, pos, vals * s_full[rows] * s_full[cols], integer)
+            C = C + (h[Didx] * sD + dd[Didx]).sum()
             keep = active & ~D
-            for i in Didx:  # ascending i: each h_j receives its terms in ascending i
-                sl = slice(starts[i], ends[i])
-                j = cols[sl]
-                w = vals[sl]
-                m = keep[j] & (w != 0)
-                h[j[m]] = h[j[m]] + 2 * w[m] * s_full[i]
+            F = fixed_order_rowsum(n, rows, pos, 2 * vals * s_full[cols], integer)
+            h[keep] = h[keep] + F[keep]
             kind[Didx] = 1
             round_of[Didx] = rnd
             fixed[Didx] = sD
@@ -172,12 +175,12 @@ def prune(inst) -> PruneResult:
         mutual = cand & (nb >= 0) & cand[nbc] & (nb[nbc] == ar)
         S = cand & ~(mutual & (ar < nb))
         Sidx = np.nonzero(S)[0]
-        # 4. fold S
-        for k in Sidx:  # ascending k
-            i = nb[k]
-            sg = _sgn(jv[k])
-            h[i] = h[i] - sg * h[k]
+        # 4. fold S: h_i -= sum over k in S with n(k) = i of sgn(J_ik) h_k
         if Sidx.size:
+            to_me = S[cols] & (nb[cols] == rows)
+            G_ = fixed_order_rowsum(n, rows, pos, np.where(to_me, _sgn(vals) * h[cols], 0), integer)
+            rest = active & ~S
+            h[rest] = h[rest] - G_[rest]
             C = C - 2 * np.abs(jv[Sidx]).sum()
             kind[Sidx] = 2
             round_of[Sidx] = rnd

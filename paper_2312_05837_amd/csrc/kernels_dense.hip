@@ -34,6 +34,20 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 constexpr int BM = 128, BN = 128, KC = 32;
 constexpr int AST = KC + 8;   // LDS row stride (bf16 elements) of the A and B chunks
 constexpr int FST = KC + 1;   // LDS row stride (floats) for the FP32 form
+constexpr int TST = BM + 4;   // LDS row stride (floats) of the transposed accumulator tile
+constexpr int GEMM_LDS_BF16 = (2 * BM + BN) * AST * 2;
+constexpr int GEMM_LDS_FP32 = (BM + BN) * FST * 4;
+constexpr int EPI_LDS = 64 * TST * 4;
+constexpr int cmax(int x, int y) { return x > y ? x : y; }
+
+// sum of each 16-lane row of a wavefront (quads, then half rows, then rows), result in every lane
+__device__ inline float row_sum16(float v) {
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false));
+    return v;
+}
 
 __device__ inline unsigned short bf16_bits(float x) {
     // round to nearest even
@@ -161,8 +175,8 @@ struct DenseStepArgs {
 
 template <int FORM>
 __global__ __launch_bounds__(256) void k_dense_step(const DenseStepArgs a) {
-    __shared__ __align__(16) unsigned char lds[FORM == DF_FP32 ? (BM + BN) * FST * 4 : (2 * BM + BN) * AST * 2];
-    __shared__ float red_e[2][BN], red_l[2][BN];
+    __shared__ __align__(16) unsigned char lds[cmax(2 * (FORM == DF_FP32 ? GEMM_LDS_FP32 : GEMM_LDS_BF16), EPI_LDS)];
+    __shared__ float red_e[1][BN], red_l[1][BN];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int mt = blockIdx.x, nt = blockIdx.y;
@@ -173,23 +187,36 @@ __global__ __launch_bounds__(256) void k_dense_step(const DenseStepArgs a) {
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x16{};
 
-    for (int k0 = 0; k0 < a.Kp; k0 += KC) {
-        if constexpr (FORM == DF_FP32) {
-            float *As = (float *)lds;
-            float *Bs = As + BM * FST;
-            // A: 128 rows x 32 floats; each thread loads 16 floats (4 x float4)
-            for (int q = tid; q < BM * KC / 4; q += 256) {
+    // K loop: the next chunk's global loads are issued into registers before the
+    // current chunk's MFMAs, and LDS is double-buffered, so one barrier per chunk.
+    const int nchunks = a.Kp / KC;
+    if constexpr (FORM == DF_FP32) {
+        float4 pa[4], pb[4];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = tid + 256 * u;
                 const int r = q / (KC / 4), c4 = (q % (KC / 4)) * 4;
-                const float4 x = *(const float4 *)(a.Jf + (size_t)(row0 + r) * a.Kp + k0 + c4);
-                As[r * FST + c4] = x.x; As[r * FST + c4 + 1] = x.y; As[r * FST + c4 + 2] = x.z; As[r * FST + c4 + 3] = x.w;
+                pa[u] = *(const float4 *)(a.Jf + (size_t)(row0 + r) * a.Kp + k0 + c4);
+                pb[u] = (col0 + r < a.R) ? *(const float4 *)((const float *)a.S_in + (size_t)(col0 + r) * a.Kp + k0 + c4)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            for (int q = tid; q < BN * KC / 4; q += 256) {
+        };
+        gload(0);
+        for (int c = 0; c < nchunks; ++c) {
+            float *As = (float *)lds + (c & 1) * (BM + BN) * FST;
+            float *Bs = As + BM * FST;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = tid + 256 * u;
                 const int r = q / (KC / 4), c4 = (q % (KC / 4)) * 4;
-                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (col0 + r < a.R) x = *(const float4 *)((const float *)a.S_in + (size_t)(col0 + r) * a.Kp + k0 + c4);
-                Bs[r * FST + c4] = x.x; Bs[r * FST + c4 + 1] = x.y; Bs[r * FST + c4 + 2] = x.z; Bs[r * FST + c4 + 3] = x.w;
+                As[r * FST + c4] = pa[u].x; As[r * FST + c4 + 1] = pa[u].y;
+                As[r * FST + c4 + 2] = pa[u].z; As[r * FST + c4 + 3] = pa[u].w;
+                Bs[r * FST + c4] = pb[u].x; Bs[r * FST + c4 + 1] = pb[u].y;
+                Bs[r * FST + c4 + 2] = pb[u].z; Bs[r * FST + c4 + 3] = pb[u].w;
             }
             __syncthreads();
+            if (c + 1 < nchunks) gload((c + 1) * KC);
 #pragma unroll
             for (int ks = 0; ks < KC; ks += 2) {
                 const int kk = ks + (lane >> 5);
@@ -204,26 +231,36 @@ __global__ __launch_bounds__(256) void k_dense_step(const DenseStepArgs a) {
                     for (int bj = 0; bj < 2; ++bj)
                         acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
             }
-            __syncthreads();
-        } else {
-            unsigned short *Ah = (unsigned short *)lds;
+        }
+    } else {
+        u16x8 pah[2], pal[2], pb[2];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int q = tid + 256 * u;
+                const int r = q >> 2, c8 = (q & 3) * 8;
+                pah[u] = *(const u16x8 *)(a.Jhi + (size_t)(row0 + r) * a.Kp + k0 + c8);
+                if (FORM == DF_BF16X2) pal[u] = *(const u16x8 *)(a.Jlo + (size_t)(row0 + r) * a.Kp + k0 + c8);
+                pb[u] = (col0 + r < a.R)
+                            ? *(const u16x8 *)((const unsigned short *)a.S_in + (size_t)(col0 + r) * a.Kp + k0 + c8)
+                            : u16x8{};
+            }
+        };
+        gload(0);
+        for (int c = 0; c < nchunks; ++c) {
+            unsigned short *Ah = (unsigned short *)lds + (c & 1) * (2 * BM + BN) * AST;
             unsigned short *Al = Ah + BM * AST;
             unsigned short *Bs = Al + BM * AST;
-            // A chunk: 128 rows x 32 bf16 = 4 x 16 B per row; 512 vectors per operand
-            for (int q = tid; q < BM * 4; q += 256) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int q = tid + 256 * u;
                 const int r = q >> 2, c8 = (q & 3) * 8;
-                *(u16x8 *)(Ah + r * AST + c8) = *(const u16x8 *)(a.Jhi + (size_t)(row0 + r) * a.Kp + k0 + c8);
-                if (FORM == DF_BF16X2)
-                    *(u16x8 *)(Al + r * AST + c8) = *(const u16x8 *)(a.Jlo + (size_t)(row0 + r) * a.Kp + k0 + c8);
-            }
-            for (int q = tid; q < BN * 4; q += 256) {
-                const int r = q >> 2, c8 = (q & 3) * 8;
-                u16x8 x = u16x8{};
-                if (col0 + r < a.R)
-                    x = *(const u16x8 *)((const unsigned short *)a.S_in + (size_t)(col0 + r) * a.Kp + k0 + c8);
-                *(u16x8 *)(Bs + r * AST + c8) = x;
+                *(u16x8 *)(Ah + r * AST + c8) = pah[u];
+                if (FORM == DF_BF16X2) *(u16x8 *)(Al + r * AST + c8) = pal[u];
+                *(u16x8 *)(Bs + r * AST + c8) = pb[u];
             }
             __syncthreads();
+            if (c + 1 < nchunks) gload((c + 1) * KC);
 #pragma unroll
             for (int ks = 0; ks < KC; ks += 16) {
                 const int kk = ks + 8 * (lane >> 5);
@@ -236,8 +273,8 @@ __global__ __launch_bounds__(256) void k_dense_step(const DenseStepArgs a) {
                 }
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj) {
-                    const int c = wn * 64 + bj * 32 + (lane & 31);
-                    bv[bj] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Bs + c * AST + kk));
+                    const int cc = wn * 64 + bj * 32 + (lane & 31);
+                    bv[bj] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Bs + cc * AST + kk));
                 }
 #pragma unroll
                 for (int bi = 0; bi < 2; ++bi)
@@ -248,75 +285,148 @@ __global__ __launch_bounds__(256) void k_dense_step(const DenseStepArgs a) {
                         acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bv[bj], acc[bi][bj], 0, 0, 0);
                     }
             }
-            __syncthreads();
         }
     }
+    __syncthreads();  // the epilogue reuses LDS
 
-    // ---- fused epilogue: C block (bi, bj), lane l, element q ->
-    //      row 64 wm + 32 bi + 8 (q / 4) + 4 (l / 32) + q % 4, column 64 wn + 32 bj + l % 32
+    // ---- fused epilogue.  The accumulators (C block (bi, bj), lane l, element q hold
+    // row 64 wm + 32 bi + 8 (q / 4) + 4 (l / 32) + q % 4, column 64 wn + 32 bj + l % 32) are
+    // transposed through LDS, one half of the replica columns at a time, so that each
+    // thread then owns 4 consecutive spins of a replica: the state streams as float4
+    // with 32 lanes covering 128 consecutive spins of one replica.
     const bool adam = a.opt == ISING_OPT_ADAM;
-    float Ecol[2] = {0.f, 0.f}, Lcol[2] = {0.f, 0.f};
+    float *T = (float *)lds;  // [64 replicas][TST]
+    const int g = tid & 31;   // spin group: rows 4g .. 4g+3 of the tile
+    const int i0 = row0 + 4 * g;
+    const bool vec = (a.n & 3) == 0 && i0 + 3 < a.n;
+    float h4[4];
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        const int r = col0 + wn * 64 + bj * 32 + (lane & 31);
-        if (r >= a.R) continue;
+    for (int u = 0; u < 4; ++u) h4[u] = (a.h && i0 + u < a.n) ? a.h[i0 + u] : 0.f;
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi) {
+    for (int half = 0; half < 2; ++half) {
+        if (wn == half) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int i = row0 + wm * 64 + bi * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                if (i >= a.n) continue;
-                const size_t idx = (size_t)r * a.n + i;
-                const float y = acc[bi][bj][q];
-                const float th = a.theta[idx];
-                float x, c;
-                fsincos(th, &x, &c);
-                const bool neg = x < 0.f;
-                const float yh = y + (a.h ? a.h[i] : 0.f);
-                Ecol[bj] += neg ? -yh : yh;
-                const float tt = neg ? yh + a.mu : yh - a.mu;
-                Lcol[bj] += x * tt;
-                const float g = c * tt;
-                float upd;
-                if (adam) {
-                    const float mo = a.b1 * a.m[idx] + a.omb1 * g;
-                    const float ve = a.b2 * a.v[idx] + a.omb2 * (g * g);
-                    a.m[idx] = mo;
-                    a.v[idx] = ve;
-                    upd = a.lr * (mo * a.ib1) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(ve * a.ib2) + a.eps);
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int m = wm * 64 + bi * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                        const int nl = bj * 32 + (lane & 31);
+                        T[nl * TST + m] = acc[bi][bj][q];
+                    }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int rl = (tid >> 5) + 8 * k;        // replica within this half
+            const int r = col0 + half * 64 + rl;
+            float Ep = 0.f, Lp = 0.f;
+            if (r < a.R && i0 < a.n) {
+                const float4 y4 = *(const float4 *)(T + rl * TST + 4 * g);
+                const float yv[4] = {y4.x, y4.y, y4.z, y4.w};
+                const size_t base = (size_t)r * a.n + i0;
+                float th[4], mo[4], ve[4];
+                if (vec) {
+                    const float4 t4 = *(const float4 *)(a.theta + base);
+                    th[0] = t4.x; th[1] = t4.y; th[2] = t4.z; th[3] = t4.w;
+                    if (adam) {
+                        const float4 m4 = *(const float4 *)(a.m + base);
+                        const float4 v4 = *(const float4 *)(a.v + base);
+                        mo[0] = m4.x; mo[1] = m4.y; mo[2] = m4.z; mo[3] = m4.w;
+                        ve[0] = v4.x; ve[1] = v4.y; ve[2] = v4.z; ve[3] = v4.w;
+                    }
                 } else {
-                    upd = a.lr * g;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const bool ok = i0 + u < a.n;
+                        th[u] = ok ? a.theta[base + u] : 0.f;
+                        mo[u] = (ok && adam) ? a.m[base + u] : 0.f;
+                        ve[u] = (ok && adam) ? a.v[base + u] : 0.f;
+                    }
                 }
-                float tn = th - upd;
-                const float kq = rintf(tn * 0.159154943091895336f);
-                tn = tn - kq * 6.28318548202514648f;
-                tn = tn - kq * -1.7484555314695172e-07f;
-                a.theta[idx] = tn;
-                float xn, cn;
-                fsincos(tn, &xn, &cn);
-                const float sn = xn < 0.f ? -1.f : 1.f;
-                if (FORM == DF_FP32) ((float *)a.S_out)[(size_t)r * a.Kp + i] = sn;
-                else ((unsigned short *)a.S_out)[(size_t)r * a.Kp + i] = bf16_bits(sn);
+                unsigned short sb[4];
+                float sf[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    float x, c;
+                    fsincos(th[u], &x, &c);
+                    const bool neg = x < 0.f;
+                    const float yh = yv[u] + h4[u];
+                    const bool live = i0 + u < a.n;
+                    Ep += live ? (neg ? -yh : yh) : 0.f;
+                    const float tt = neg ? yh + a.mu : yh - a.mu;
+                    Lp += live ? x * tt : 0.f;
+                    const float gr = c * tt;
+                    float upd;
+                    if (adam) {
+                        mo[u] = a.b1 * mo[u] + a.omb1 * gr;
+                        ve[u] = a.b2 * ve[u] + a.omb2 * (gr * gr);
+                        upd = a.lr * (mo[u] * a.ib1) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(ve[u] * a.ib2) + a.eps);
+                    } else {
+                        upd = a.lr * gr;
+                    }
+                    float tn = th[u] - upd;
+                    const float kq = rintf(tn * 0.159154943091895336f);
+                    tn = tn - kq * 6.28318548202514648f;
+                    tn = tn - kq * -1.7484555314695172e-07f;
+                    th[u] = tn;
+                    float xn, cn;
+                    fsincos(tn, &xn, &cn);
+                    sf[u] = live ? (xn < 0.f ? -1.f : 1.f) : 0.f;
+                    sb[u] = bf16_bits(sf[u]);
+                }
+                if (vec) {
+                    *(float4 *)(a.theta + base) = make_float4(th[0], th[1], th[2], th[3]);
+                    if (adam) {
+                        *(float4 *)(a.m + base) = make_float4(mo[0], mo[1], mo[2], mo[3]);
+                        *(float4 *)(a.v + base) = make_float4(ve[0], ve[1], ve[2], ve[3]);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (i0 + u < a.n) {
+                            a.theta[base + u] = th[u];
+                            if (adam) {
+                                a.m[base + u] = mo[u];
+                                a.v[base + u] = ve[u];
+                            }
+                        }
+                }
+                const size_t sbase = (size_t)r * a.Kp + i0;  // Kp % 32 == 0, i0 % 4 == 0: aligned
+                if (FORM == DF_FP32) {
+                    *(float4 *)((float *)a.S_out + sbase) = make_float4(sf[0], sf[1], sf[2], sf[3]);
+                } else {
+                    const uint2 w = make_uint2((uint32_t)sb[0] | ((uint32_t)sb[1] << 16),
+                                               (uint32_t)sb[2] | ((uint32_t)sb[3] << 16));
+                    *(uint2 *)((unsigned short *)a.S_out + sbase) = w;
+                }
+            }
+            // sum over the 32 spin groups of this replica (lanes 0-31 and 32-63 hold two replicas):
+            // quad, half-row and row sums by DPP, then the two rows of each half-wavefront
+            Ep = row_sum16(Ep);
+            Lp = row_sum16(Lp);
+            const float e_lo = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Ep), 15)) +
+                               __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Ep), 31));
+            const float e_hi = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Ep), 47)) +
+                               __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Ep), 63));
+            const float l_lo = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Lp), 15)) +
+                               __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Lp), 31));
+            const float l_hi = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Lp), 47)) +
+                               __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Lp), 63));
+            if (lane == 0) {
+                const int rw = half * 64 + (wave * 2) + 8 * k;  // replica of lanes 0-31 (tid >> 5 = 2 wave)
+                red_e[0][rw] = e_lo;
+                red_e[0][rw + 1] = e_hi;
+                red_l[0][rw] = l_lo;
+                red_l[0][rw + 1] = l_hi;
             }
         }
+        __syncthreads();
     }
-    // combine the two lane halves (rows +4) of each column, then the two row-waves
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        Ecol[bj] += __shfl_xor(Ecol[bj], 32);
-        Lcol[bj] += __shfl_xor(Lcol[bj], 32);
-    }
-    if (lane < 32) {
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-            red_e[wm][wn * 64 + bj * 32 + lane] = Ecol[bj];
-            red_l[wm][wn * 64 + bj * 32 + lane] = Lcol[bj];
-        }
-    }
-    __syncthreads();
     if (tid < BN && col0 + tid < a.R) {
-        a.Epart[(size_t)mt * a.R + col0 + tid] = red_e[0][tid] + red_e[1][tid];
-        if (a.Lpart) a.Lpart[(size_t)mt * a.R + col0 + tid] = red_l[0][tid] + red_l[1][tid];
+        a.Epart[(size_t)mt * a.R + col0 + tid] = red_e[0][tid];
+        if (a.Lpart) a.Lpart[(size_t)mt * a.R + col0 + tid] = red_l[0][tid];
     }
 }
 

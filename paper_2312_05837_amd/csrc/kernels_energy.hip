@@ -1,43 +1,47 @@
 // Exact energy E(s) = s^T J s + h^T s (paper, Sec. II, scalar energy form) for a
 // block of spin vectors.  Integer problems accumulate in int64 (exact, order
-// free); real problems accumulate each row in FP64 in ascending column order,
-// then combine rows by a fixed shared-memory tree and blocks in ascending
-// order, so results are reproducible.
+// free).  Real problems accumulate in FP64: one wavefront per row (64 strided
+// partials over the row's stored positions, xor butterfly), the four rows of a
+// block in index order, blocks in ascending order -- reproducible run to run.
 #include "internal.hpp"
 
 namespace ising {
 
 namespace {
 
-constexpr int EB = 256;  // rows per block
+constexpr int EB = 4;  // rows per block (one wavefront each)
 
 template <typename V, typename Acc>
-__global__ __launch_bounds__(EB) void energy_rows(DevProblem p, const int8_t *spins, Acc *partial) {
-    __shared__ Acc red[EB];
+__global__ __launch_bounds__(256) void energy_rows(DevProblem p, const int8_t *spins, Acc *partial) {
+    __shared__ Acc red[4];
     const int n = p.n;
     const int r = blockIdx.y;
-    const int i = blockIdx.x * EB + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * EB + wv;
     const int8_t *s = spins + (size_t)r * n;
-    Acc term = 0;
+    Acc y = 0;
     if (i < n) {
-        Acc y = 0;
         if (p.format == ISING_DENSE) {
             const V *row = (const V *)p.J + (size_t)i * n;
-            for (int j = 0; j < n; ++j) y += (Acc)row[j] * (Acc)s[j];
+            for (int j = lane; j < n; j += 64) y += (Acc)row[j] * (Acc)s[j];
         } else {
-            const V *val = (const V *)p.val;
-            for (int k = p.row_ptr[i]; k < p.row_ptr[i + 1]; ++k) y += (Acc)val[k] * (Acc)s[p.col[k]];
+            const int rs = p.row_ptr[i], len = p.row_ptr[i + 1] - rs;
+            const V *val = (const V *)p.val + rs;
+            const int32_t *col = p.col + rs;
+            for (int q = lane; q < len; q += 64) y += (Acc)val[q] * (Acc)s[col[q]];
         }
-        const Acc hi = p.h ? (Acc)((const V *)p.h)[i] : (Acc)0;
-        term = (Acc)s[i] * (y + hi);
     }
-    red[threadIdx.x] = term;
+    for (int d = 32; d >= 1; d >>= 1) y += __shfl_xor(y, d);
+    if (lane == 0) {
+        Acc term = 0;
+        if (i < n) {
+            const Acc hi = p.h ? (Acc)((const V *)p.h)[i] : (Acc)0;
+            term = (Acc)s[i] * (y + hi);
+        }
+        red[wv] = term;
+    }
     __syncthreads();
-    for (int w = EB / 2; w >= 1; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(size_t)r * gridDim.x + blockIdx.x] = red[0];
+    if (threadIdx.x == 0) partial[(size_t)r * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 template <typename Acc>
@@ -64,17 +68,17 @@ hipError_t launch_energy(const DevProblem &p, const int8_t *spins, int32_t count
     dim3 grid(nb, count);
     const int fb = (count + 63) / 64;
     if (p.vtype == ISING_I32) {
-        hipLaunchKernelGGL((energy_rows<int32_t, int64_t>), grid, dim3(EB), 0, s, p, spins,
+        hipLaunchKernelGGL((energy_rows<int32_t, int64_t>), grid, dim3(256), 0, s, p, spins,
                            (int64_t *)partial);
         hipLaunchKernelGGL((energy_finish<int64_t>), dim3(fb), dim3(64), 0, s, (const int64_t *)partial,
                            nb, count, E_out, E_int_out);
     } else if (p.vtype == ISING_F32) {
-        hipLaunchKernelGGL((energy_rows<float, double>), grid, dim3(EB), 0, s, p, spins,
+        hipLaunchKernelGGL((energy_rows<float, double>), grid, dim3(256), 0, s, p, spins,
                            (double *)partial);
         hipLaunchKernelGGL((energy_finish<double>), dim3(fb), dim3(64), 0, s, (const double *)partial,
                            nb, count, E_out, (int64_t *)nullptr);
     } else {
-        hipLaunchKernelGGL((energy_rows<double, double>), grid, dim3(EB), 0, s, p, spins,
+        hipLaunchKernelGGL((energy_rows<double, double>), grid, dim3(256), 0, s, p, spins,
                            (double *)partial);
         hipLaunchKernelGGL((energy_finish<double>), dim3(fb), dim3(64), 0, s, (const double *)partial,
                            nb, count, E_out, (int64_t *)nullptr);

@@ -5,12 +5,14 @@
 //              strided partials over the row's stored positions, combined by an
 //              xor butterfly 32,16,8,4,2,1); D = {i in A : |h_i| > 2 a_i};
 //              s_i = -sgn(h_i)  (determined-spin rule).
-//   fold_D   : h_j += 2 J_ji s_i for i in D, j in A \ D, terms in ascending i;
+//   fold_D   : h_j += sum_{i in D} 2 J_ji s_i for j in A \ D;
 //              C gets h_i s_i + sum_{j in D} J_ij s_i s_j per i in D.
 //   degree   : deg_k over A \ D; candidate if deg_k = 1 and 2|J_k,n(k)| >= |h_k|.
 //   select_S : of a mutual candidate pair only the larger index is taken.
-//   fold_S   : h_i -= sgn(J_ik) h_k for k in S with n(k) = i, ascending k;
+//   fold_S   : h_i -= sum_{k in S, n(k) = i} sgn(J_ik) h_k;
 //              C gets -2|J_k,n(k)| per k in S  (semi-determined-spin rule).
+// Every per-row sum runs on one wavefront in the same fixed order as the row
+// sums (64 strided partials, xor butterfly), with coalesced reads of the row.
 // Integer problems work in int64 (exact); real problems in FP64.
 #include "internal.hpp"
 
@@ -83,70 +85,94 @@ __global__ __launch_bounds__(256) void k_rowsum_D(DevProblem p, PruneWork w) {
     }
 }
 
+// visit the entries of row i assigned to this lane (positions lane, lane + 64, ...)
+template <typename V, typename F>
+__device__ inline void lane_entries(const DevProblem &p, int i, int lane, F &&f) {
+    if (p.format == ISING_DENSE) {
+        const V *row = (const V *)p.J + (size_t)i * p.n;
+        for (int j = lane; j < p.n; j += 64) f(j, row[j]);
+    } else {
+        const int rs = p.row_ptr[i], len = p.row_ptr[i + 1] - rs;
+        const V *val = (const V *)p.val + rs;
+        const int32_t *col = p.col + rs;
+        for (int q = lane; q < len; q += 64) f(col[q], val[q]);
+    }
+}
+
+template <typename W>
+__device__ inline W wave_sum_fixed(W acc) {
+    for (int d = 32; d >= 1; d >>= 1) acc = acc + __shfl_xor(acc, d);
+    return acc;
+}
+
+// one wavefront per row j
 template <typename V, typename W>
-__global__ void k_fold_D(DevProblem p, PruneWork w, int round) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_fold_D(DevProblem p, PruneWork w, int round) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= p.n) return;
     W *h = (W *)w.h;
     W *cp = (W *)w.cpart;
     if (!w.active[j]) {
-        cp[j] = 0;
+        if (lane == 0) cp[j] = 0;
         return;
     }
     const bool dj = w.isD[j];
     const W sj = dj ? (W)w.fixed[j] : (W)0;
-    W acc = dj ? h[j] * sj : (W)0;
-    W hj = h[j];
-    auto visit = [&](int i, W v) {
-        if (v == 0 || !w.isD[i]) return;
-        const W si = (W)w.fixed[i];
-        if (dj) acc = acc + v * sj * si;
-        else hj = hj + 2 * v * si;
-    };
-    if (p.format == ISING_DENSE) {
-        const V *row = (const V *)p.J + (size_t)j * p.n;
-        for (int i = 0; i < p.n; ++i) visit(i, (W)row[i]);
-    } else {
-        const V *val = (const V *)p.val;
-        for (int k = p.row_ptr[j]; k < p.row_ptr[j + 1]; ++k) visit(p.col[k], (W)val[k]);
-    }
-    if (dj) {
-        cp[j] = acc;
-        w.kind[j] = 1;
-        w.round_of[j] = round;
-        w.active[j] = 0;
-    } else {
-        cp[j] = 0;
-        h[j] = hj;
+    W acc = 0;
+    lane_entries<V>(p, j, lane, [&](int i, V v) {
+        if (w.isD[i]) {
+            const W si = (W)w.fixed[i];
+            acc = acc + (dj ? (W)v * sj * si : 2 * (W)v * si);
+        }
+    });
+    acc = wave_sum_fixed(acc);
+    if (lane == 0) {
+        if (dj) {
+            cp[j] = h[j] * sj + acc;
+            w.kind[j] = 1;
+            w.round_of[j] = round;
+            w.active[j] = 0;
+        } else {
+            cp[j] = 0;
+            h[j] = h[j] + acc;
+        }
     }
 }
 
+// one wavefront per row k: active degree and the unique neighbour
 template <typename V, typename W>
-__global__ void k_degree(DevProblem p, PruneWork w) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_degree(DevProblem p, PruneWork w) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (k >= p.n) return;
-    w.cand[k] = 0;
-    if (!w.active[k]) return;
+    if (!w.active[k]) {
+        if (lane == 0) w.cand[k] = 0;
+        return;
+    }
     int deg = 0, nbj = -1;
     W jvv = 0;
-    auto visit = [&](int j, W v) {
+    lane_entries<V>(p, k, lane, [&](int j, V v) {
         if (v != 0 && w.active[j]) {
             ++deg;
             nbj = j;
-            jvv = v;
+            jvv = (W)v;
         }
-    };
-    if (p.format == ISING_DENSE) {
-        const V *row = (const V *)p.J + (size_t)k * p.n;
-        for (int j = 0; j < p.n; ++j) visit(j, (W)row[j]);
-    } else {
-        const V *val = (const V *)p.val;
-        for (int q = p.row_ptr[k]; q < p.row_ptr[k + 1]; ++q) visit(p.col[q], (W)val[q]);
+    });
+    for (int d = 32; d >= 1; d >>= 1) deg += __shfl_xor(deg, d);
+    if (deg == 1) {
+        const uint64_t m = __ballot(nbj >= 0);
+        const int src = __builtin_ctzll(m);
+        nbj = __shfl(nbj, src);
+        jvv = __shfl(jvv, src);
     }
-    if (deg == 1 && 2 * wabs(jvv) >= wabs(((const W *)w.h)[k])) {
-        w.cand[k] = 1;
-        w.nb[k] = nbj;
-        ((W *)w.jv)[k] = jvv;
+    if (lane == 0) {
+        w.cand[k] = 0;
+        if (deg == 1 && 2 * wabs(jvv) >= wabs(((const W *)w.h)[k])) {
+            w.cand[k] = 1;
+            w.nb[k] = nbj;
+            ((W *)w.jv)[k] = jvv;
+        }
     }
 }
 
@@ -162,37 +188,40 @@ __global__ void k_select_S(int n, PruneWork w) {
     w.isS[k] = s;
 }
 
+// one wavefront per row i
 template <typename V, typename W>
-__global__ void k_fold_S(DevProblem p, PruneWork w, int round) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_fold_S(DevProblem p, PruneWork w, int round) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= p.n) return;
     W *h = (W *)w.h;
     W *cp = (W *)w.cpart;
     if (w.isS[i]) {
-        const W jvi = ((const W *)w.jv)[i];
-        cp[i] = -2 * wabs(jvi);
-        w.kind[i] = 2;
-        w.round_of[i] = round;
-        w.partner[i] = w.nb[i];
-        w.sigma[i] = (int8_t)wsgn(jvi);
-        w.active[i] = 0;
-        atomicAdd(&w.counts[1], 1);
+        if (lane == 0) {
+            const W jvi = ((const W *)w.jv)[i];
+            cp[i] = -2 * wabs(jvi);
+            w.kind[i] = 2;
+            w.round_of[i] = round;
+            w.partner[i] = w.nb[i];
+            w.sigma[i] = (int8_t)wsgn(jvi);
+            w.active[i] = 0;
+            atomicAdd(&w.counts[1], 1);
+        }
         return;
     }
-    cp[i] = 0;
-    if (!w.active[i]) return;
-    W hi = h[i];
-    auto visit = [&](int k, W v) {
-        if (v != 0 && w.isS[k] && w.nb[k] == i) hi = hi - (W)wsgn(v) * h[k];
-    };
-    if (p.format == ISING_DENSE) {
-        const V *row = (const V *)p.J + (size_t)i * p.n;
-        for (int k = 0; k < p.n; ++k) visit(k, (W)row[k]);
-    } else {
-        const V *val = (const V *)p.val;
-        for (int q = p.row_ptr[i]; q < p.row_ptr[i + 1]; ++q) visit(p.col[q], (W)val[q]);
+    if (!w.active[i]) {
+        if (lane == 0) cp[i] = 0;
+        return;
     }
-    h[i] = hi;
+    W acc = 0;
+    lane_entries<V>(p, i, lane, [&](int k, V v) {
+        if (v != 0 && w.isS[k] && w.nb[k] == i) acc = acc + (W)wsgn((W)v) * h[k];
+    });
+    acc = wave_sum_fixed(acc);
+    if (lane == 0) {
+        cp[i] = 0;
+        h[i] = h[i] - acc;
+    }
 }
 
 // C += sum_i cpart[i]: each of 1024 threads sums i = tid, tid + 1024, ... in
@@ -341,11 +370,11 @@ template <typename V, typename W>
 hipError_t round_impl(const DevProblem &p, const PruneWork &w, int32_t round, hipStream_t s) {
     hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, s, w.counts);
     hipLaunchKernelGGL((k_rowsum_D<V, W>), dim3((p.n + 3) / 4), dim3(256), 0, s, p, w);
-    hipLaunchKernelGGL((k_fold_D<V, W>), g1(p.n), dim3(256), 0, s, p, w, round);
+    hipLaunchKernelGGL((k_fold_D<V, W>), dim3((p.n + 3) / 4), dim3(256), 0, s, p, w, round);
     hipLaunchKernelGGL((k_accumulate_C<W>), dim3(1), dim3(1024), 0, s, p.n, w);
-    hipLaunchKernelGGL((k_degree<V, W>), g1(p.n), dim3(256), 0, s, p, w);
+    hipLaunchKernelGGL((k_degree<V, W>), dim3((p.n + 3) / 4), dim3(256), 0, s, p, w);
     hipLaunchKernelGGL(k_select_S, g1(p.n), dim3(256), 0, s, p.n, w);
-    hipLaunchKernelGGL((k_fold_S<V, W>), g1(p.n), dim3(256), 0, s, p, w, round);
+    hipLaunchKernelGGL((k_fold_S<V, W>), dim3((p.n + 3) / 4), dim3(256), 0, s, p, w, round);
     hipLaunchKernelGGL((k_accumulate_C<W>), dim3(1), dim3(1024), 0, s, p.n, w);
     return hipGetLastError();
 }

@@ -20,27 +20,50 @@ __device__ inline bool is_integral(double x) { return x == rint(x) && fabs(x) < 
 
 // flags: [0] error bits, [1] max degree (atomicMax), [2] uniform magnitude (cleared on mismatch),
 // [3] integral (cleared on a non-integral value)
-__global__ void validate_dense(DevProblem p, double w0, int32_t *flags) {
+// One 32 x 32 tile (bi, bj) with bi <= bj per workgroup: the tile and its mirror
+// are read coalesced into LDS and compared element by element.
+__global__ __launch_bounds__(256) void validate_dense(DevProblem p, double w0, int32_t *flags) {
+    __shared__ double A[32][33], Bt[32][33];
+    const int nt = (p.n + 31) / 32;
+    // map the linear block index to an upper-triangular tile (bi <= bj)
+    int b = blockIdx.x, bi = 0;
+    while (b >= nt - bi) {
+        b -= nt - bi;
+        ++bi;
+    }
+    const int bj = bi + b;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const int n = p.n;
-    const int64_t total = (int64_t)n * n;
+    for (int yy = ty; yy < 32; yy += 8) {
+        const int i = bi * 32 + yy, j = bj * 32 + tx;
+        A[yy][tx] = (i < n && j < n) ? load_val(p.J, p.vtype, (int64_t)i * n + j) : 0.0;
+        const int i2 = bj * 32 + yy, j2 = bi * 32 + tx;
+        Bt[yy][tx] = (i2 < n && j2 < n) ? load_val(p.J, p.vtype, (int64_t)i2 * n + j2) : 0.0;
+    }
+    __syncthreads();
     int bits = 0;
     bool uni = true, integ = true;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(k / n), j = (int)(k % n);
-        const double a = load_val(p.J, p.vtype, k);
+    for (int yy = ty; yy < 32; yy += 8) {
+        const int i = bi * 32 + yy, j = bj * 32 + tx;
+        if (i >= n || j >= n) continue;
+        const double a = A[yy][tx];
+        const double m = Bt[tx][yy];  // J[j][i]
         if (!isfinite(a)) bits |= 8;
         if (i == j) {
             if (a != 0.0) bits |= 2;
-            continue;
-        }
-        if (j > i) {
-            const double b = load_val(p.J, p.vtype, (int64_t)j * n + i);
-            if (a != b) bits |= 1;
-        }
-        if (a != 0.0) {
-            if (fabs(a) != w0) uni = false;
-            if (!is_integral(a)) integ = false;
+        } else {
+            if (a != m) bits |= 1;
+            if (a != 0.0) {
+                if (fabs(a) != w0) uni = false;
+                if (!is_integral(a)) integ = false;
+            }
+            if (bi != bj) {  // the mirror tile's element is checked here too
+                if (!isfinite(m)) bits |= 8;
+                if (m != 0.0) {
+                    if (fabs(m) != w0) uni = false;
+                    if (!is_integral(m)) integ = false;
+                }
+            }
         }
     }
     if (bits) atomicOr(&flags[0], bits);
@@ -154,9 +177,8 @@ __global__ void init_flags(int32_t *flags) {
 hipError_t launch_validate_with(const DevProblem &p, double w0, int32_t *flags, hipStream_t s) {
     hipLaunchKernelGGL(init_flags, dim3(1), dim3(64), 0, s, flags);
     if (p.format == ISING_DENSE) {
-        const int64_t total = (int64_t)p.n * p.n;
-        int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-        hipLaunchKernelGGL(validate_dense, dim3(blocks), dim3(256), 0, s, p, w0, flags);
+        const int64_t nt = (p.n + 31) / 32;
+        hipLaunchKernelGGL(validate_dense, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, s, p, w0, flags);
         hipLaunchKernelGGL(dense_degree, dim3((p.n + 3) / 4), dim3(256), 0, s, p, flags);
     } else {
         hipLaunchKernelGGL(validate_csr, dim3((p.n + 255) / 256), dim3(256), 0, s, p, w0, flags);
