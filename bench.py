@@ -104,15 +104,109 @@ def cpu_baseline(inst, replicas, steps, opt, lr, mu, budget_s=15.0):
             "best_energy_sample": float(res["energy"])}
 
 
+def serve_bench(args):
+    """Continuous-batching server vs plain per-instance solves on a Poisson request stream."""
+    import numpy as np
+    import torch
+    import instances as I
+    import paper_2312_05837_amd as P
+
+    count, T = args.requests, 1000
+    descs = I.serving_stream(count, 2024, rate=1.0)
+    insts = [I.make_request_instance(d) for d in descs]
+    prm = [P.params(replicas=d["replicas"], steps=T, optimizer="adam", lr=6.0, mu=0.5, seed=d["seed"],
+                    precision="fp32") for d in descs]
+    host = [P.host_problem(i.n, J=i.J.astype(np.int32)) if i.is_dense else
+            P.host_problem(i.n, row_ptr=i.row_ptr, col=i.col, val=i.val.astype(np.int32)) for i in insts]
+    work = float(sum(i.n * d["replicas"] * T for i, d in zip(insts, descs)))
+    ctx = P.ising_create(0)
+    # warm-up: one request of each kind through both paths
+    for k in range(min(4, count)):
+        P.ising_solve(ctx, host[k][0], prm[k])
+
+    # plain per-instance solves, one after another (inputs uploaded per solve, as a server would)
+    service = []
+    t0 = time.perf_counter()
+    for k in range(count):
+        a = time.perf_counter()
+        P.ising_solve(ctx, host[k][0], prm[k])
+        service.append(time.perf_counter() - a)
+    plain_span = time.perf_counter() - t0
+    plain_rate = count / plain_span
+
+    failures = []
+
+    def run_server(rate):
+        P.ising_serve_start(ctx, hbm_budget_bytes=64 << 30, max_resident=args.max_resident,
+                            chunk_steps=args.chunk_steps)
+        gaps = np.random.default_rng(7).exponential(1.0 / rate, size=count) if rate else np.zeros(count)
+        arrive = np.cumsum(gaps)
+        t_start = time.perf_counter()
+        tickets = []
+        for k in range(count):
+            while time.perf_counter() - t_start < arrive[k]:
+                time.sleep(min(0.0005, arrive[k] - (time.perf_counter() - t_start)))
+            tickets.append(P.ising_submit(ctx, host[k][0], prm[k]))
+        lat, ok = [], 0
+        for k, t in enumerate(tickets):
+            st, _, _, stats = P.ising_wait(ctx, t, insts[k].n)
+            ok += st == P.ISING_OK
+            if st != P.ISING_OK:
+                failures.append((k, insts[k].name, descs[k]["replicas"], P.STATUS_NAMES.get(st, st),
+                                 P.ising_last_error(ctx)))
+            lat.append(stats["t_total_ms"])
+        span = time.perf_counter() - t_start
+        info = P.ising_serve_query(ctx)
+        P.ising_serve_stop(ctx)
+        return span, np.array(lat), ok, info
+
+    burst_span, burst_lat, ok1, info1 = run_server(0.0)
+    sat_rate = count / burst_span
+    pois_span, pois_lat, ok2, info2 = run_server(0.8 * sat_rate)
+    # the plain path at the same Poisson arrivals: FIFO single server, latency = wait + service
+    gaps = np.random.default_rng(7).exponential(1.0 / (0.8 * sat_rate), size=count)
+    arrive = np.cumsum(gaps)
+    free, plat = 0.0, []
+    for k in range(count):
+        start = max(arrive[k], free)
+        free = start + service[k]
+        plat.append((free - arrive[k]) * 1e3)
+    plat = np.array(plat)
+    P.ising_destroy(ctx)
+    out = {
+        "metric": "replica-spin updates/s",
+        "value": work / burst_span,
+        "unit": "replica-spin updates/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": burst_span * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serve: Poisson stream of {count} requests, N log-uniform [64, 4096], half dense SK "
+                               "+-1 / half ER mean degree 8 +-1, 64-1024 replicas, 1000 ADAM steps each",
+                   "requests": count, "chunk_steps": args.chunk_steps, "max_resident": args.max_resident},
+        "serving": {"saturation_requests_per_s": sat_rate, "plain_requests_per_s": plain_rate,
+                    "speedup_vs_plain": sat_rate / plain_rate,
+                    "poisson_rate_requests_per_s": 0.8 * sat_rate,
+                    "p50_latency_ms": float(np.percentile(pois_lat, 50)),
+                    "p99_latency_ms": float(np.percentile(pois_lat, 99)),
+                    "plain_p50_latency_ms_same_arrivals": float(np.percentile(plat, 50)),
+                    "plain_p99_latency_ms_same_arrivals": float(np.percentile(plat, 99)),
+                    "completed": int(ok1 + ok2), "failures": failures[:10], "chunks": int(info1["chunks"]),
+                    "launches": int(info1["launches"])},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed solves")
     ap.add_argument("--warmup", type=int, default=2, help="untimed solves")
-    ap.add_argument("--workload", default="er800", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="er800", choices=sorted(WORKLOADS) + ["serve"])
     ap.add_argument("--optimizer", default="adam", choices=["adam", "gd"])
     ap.add_argument("--lr", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=200, help="serving workload: stream length")
+    ap.add_argument("--chunk-steps", type=int, default=100, help="serving workload: steps per scheduling round")
+    ap.add_argument("--max-resident", type=int, default=64, help="serving workload: resident requests")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -125,6 +219,9 @@ def main():
     import torch
     import paper_2312_05837_amd as P
 
+    if args.workload == "serve":
+        serve_bench(args)
+        return
     desc, kind, R, T, prec = WORKLOADS[args.workload]
     lr = args.lr if args.lr is not None else (6.0 if args.optimizer == "adam" else 0.01)
     mu = 0.5

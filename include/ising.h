@@ -254,6 +254,59 @@ ising_status ising_ds_dense_dev(ising_ctx *ctx, const ising_problem *problem, co
 ising_status ising_select_dev(ising_ctx *ctx, const double *e_best, int32_t replicas, int32_t *best,
                               void *stream);
 
+/* ---- serving: continuous batching of many solves --------------------------
+ * Callers: request loops that submit independent problems over time.  A
+ * scheduler thread admits queued requests in arrival order while their device
+ * footprint fits `hbm_budget_bytes` and fewer than `max_resident` are resident,
+ * keeps their state on the device, and advances all resident requests by
+ * `chunk_steps` steps per iteration: sparse requests with the same launch shape
+ * share one launch of the persistent engine (one workgroup per request x
+ * replica group), dense requests run the matrix-core engine on `dense_streams`
+ * streams.  Finished requests are harvested (best replica, retrieval, exact
+ * energy) and their memory is freed, so newly arrived requests are admitted
+ * while others run.  A request's result depends only on its own problem and
+ * parameters: it is bit-identical alone and in any mix. */
+typedef struct ising_serve_config {
+    size_t hbm_budget_bytes;  /* device memory resident requests may hold (0: 16 GiB) */
+    int32_t max_resident;     /* requests resident at once (0: 64) */
+    int32_t chunk_steps;      /* steps per scheduling iteration (0: 100) */
+    int32_t dense_streams;    /* streams for dense requests (0: 4) */
+    int32_t reserved0;
+} ising_serve_config;
+
+typedef struct ising_serve_info {
+    uint64_t submitted, admitted, completed, canceled, failed;
+    uint64_t chunks;          /* scheduling iterations with device work */
+    uint64_t launches;        /* kernel launches issued by those iterations */
+    int32_t resident, queued;
+    size_t bytes_in_use;      /* device memory held by resident requests */
+    double busy_ms;           /* wall time spent in device chunks */
+} ising_serve_info;
+
+/* Start the scheduler of ctx (one per context).  cfg nullable (defaults). */
+ising_status ising_serve_start(ising_ctx *ctx, const ising_serve_config *cfg);
+/* Finish every queued and resident request, then stop the scheduler. */
+ising_status ising_serve_stop(ising_ctx *ctx);
+/* Queue a solve.  problem: host buffers, copied before the call returns.
+ * params as for ising_solve; sparse requests run in FP32.  *ticket identifies
+ * the request.  Thread-safe.  Errors: EINVAL (no server, malformed shape). */
+ising_status ising_submit(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
+                          uint64_t *ticket);
+/* Wait up to timeout_ms (negative: forever) for a request and copy its result
+ * (spins_out: n int8, energy_out, stats_out; each nullable).  A wait that
+ * returns anything but ETIMEDOUT consumes the ticket.  For served requests the
+ * stats hold: t_upload_ms = time queued, t_prune_ms = admission (upload,
+ * checks, pruning, formats), t_ds_ms = time resident, t_total_ms = submit to
+ * completion.  Returns the request's status: OK, EINVAL / ENOTSUP (rejected at
+ * admission), ENOMEM (larger than the budget), ECANCELED, ETIMEDOUT. */
+ising_status ising_wait(ising_ctx *ctx, uint64_t ticket, int32_t timeout_ms, int8_t *spins_out,
+                        double *energy_out, ising_stats *stats_out);
+/* Cancel a request (queued: never admitted; resident: dropped at the next
+ * chunk boundary).  Its wait returns ECANCELED.  Thread-safe. */
+ising_status ising_cancel(ising_ctx *ctx, uint64_t ticket);
+/* Counters of the scheduler. */
+ising_status ising_serve_query(ising_ctx *ctx, ising_serve_info *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -71,6 +71,21 @@ class ising_ds_state(C.Structure):
                 ("loss_trace", C.c_void_p)]
 
 
+class ising_serve_config(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_resident", C.c_int32), ("chunk_steps", C.c_int32),
+                ("dense_streams", C.c_int32), ("reserved0", C.c_int32)]
+
+
+class ising_serve_info(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
+                ("canceled", C.c_uint64), ("failed", C.c_uint64), ("chunks", C.c_uint64), ("launches", C.c_uint64),
+                ("resident", C.c_int32), ("queued", C.c_int32), ("bytes_in_use", C.c_size_t),
+                ("busy_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _P = C.c_void_p
 _sigs = {
     "ising_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
@@ -95,6 +110,12 @@ _sigs = {
     "ising_ds_dense_dev": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(ising_params), _P, C.c_int32,
                                      C.c_int32, C.POINTER(ising_ds_state), _P]),
     "ising_select_dev": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
+    "ising_serve_start": (C.c_int, [_P, C.POINTER(ising_serve_config)]),
+    "ising_serve_stop": (C.c_int, [_P]),
+    "ising_submit": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(ising_params), C.POINTER(C.c_uint64)]),
+    "ising_wait": (C.c_int, [_P, C.c_uint64, C.c_int32, _P, C.POINTER(C.c_double), C.POINTER(ising_stats)]),
+    "ising_cancel": (C.c_int, [_P, C.c_uint64]),
+    "ising_serve_query": (C.c_int, [_P, C.POINTER(ising_serve_info)]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -383,3 +404,69 @@ def ising_ds_dense_dev(ctx, problem, prm: ising_params, state: dict, t0: int = 0
     _check(ctx, _lib.ising_ds_dense_dev(ctx, C.byref(ps), C.byref(prm), _ptr(uniform), t0, steps, C.byref(st),
                                         _stream(stream)))
     return state
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+def host_problem(n, J=None, row_ptr=None, col=None, val=None, h=None):
+    """ising_problem over host numpy arrays (int32 / float32 / float64 values).
+
+    Returns (struct, keep): keep holds the arrays, which must outlive the call
+    that reads the struct (ising_solve, ising_submit)."""
+    import numpy as np
+    vals = J if J is not None else val
+    vt = {np.dtype(np.int32): ISING_I32, np.dtype(np.float32): ISING_F32,
+          np.dtype(np.float64): ISING_F64}[np.asarray(vals).dtype]
+    keep = []
+
+    def ptr(a, dt=None):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    if J is not None:
+        st = ising_problem(n, ISING_DENSE, vt, 0, 0, ptr(J), None, None, None, ptr(h, np.asarray(J).dtype))
+    else:
+        st = ising_problem(n, ISING_CSR, vt, 0, int(len(col)), None, ptr(row_ptr, np.int32), ptr(col, np.int32),
+                           ptr(val), ptr(h, np.asarray(val).dtype))
+    return st, keep
+
+
+def ising_serve_start(ctx, hbm_budget_bytes=0, max_resident=0, chunk_steps=0, dense_streams=0):
+    cfg = ising_serve_config(hbm_budget_bytes, max_resident, chunk_steps, dense_streams, 0)
+    _check(ctx, _lib.ising_serve_start(ctx, C.byref(cfg)))
+
+
+def ising_serve_stop(ctx):
+    _check(ctx, _lib.ising_serve_stop(ctx))
+
+
+def ising_submit(ctx, problem: ising_problem, prm: ising_params) -> int:
+    t = C.c_uint64()
+    _check(ctx, _lib.ising_submit(ctx, C.byref(problem), C.byref(prm), C.byref(t)))
+    return t.value
+
+
+def ising_wait(ctx, ticket: int, n: int, timeout_ms: int = -1):
+    """(status, spins, energy, stats); status is an ISING_* code (the call does not raise)."""
+    import numpy as np
+    spins = np.zeros(n, dtype=np.int8)
+    e = C.c_double()
+    st = ising_stats()
+    status = _lib.ising_wait(ctx, C.c_uint64(ticket), timeout_ms, spins.ctypes.data_as(C.c_void_p), C.byref(e),
+                             C.byref(st))
+    return status, spins, e.value, st.as_dict()
+
+
+def ising_cancel(ctx, ticket: int):
+    _check(ctx, _lib.ising_cancel(ctx, C.c_uint64(ticket)))
+
+
+def ising_serve_query(ctx) -> dict:
+    info = ising_serve_info()
+    _check(ctx, _lib.ising_serve_query(ctx, C.byref(info)))
+    return info.as_dict()

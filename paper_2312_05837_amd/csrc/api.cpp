@@ -15,86 +15,18 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "runtime.hpp"
 
 using namespace ising;
+using namespace ising::rt;
 
-namespace {
-
-struct Pool {
-    struct Entry {
-        void *p = nullptr;
-        size_t bytes = 0;
-    };
-    std::map<std::string, Entry> m;
-    hipError_t get(const std::string &key, size_t bytes, void **out) {
-        Entry &e = m[key];
-        if (bytes == 0) bytes = 8;
-        if (e.bytes < bytes) {
-            if (e.p) {
-                hipError_t er = hipFree(e.p);
-                if (er != hipSuccess) return er;
-            }
-            e.p = nullptr;
-            e.bytes = 0;
-            hipError_t er = hipMalloc(&e.p, bytes);
-            if (er != hipSuccess) return er;
-            e.bytes = bytes;
-        }
-        *out = e.p;
-        return hipSuccess;
-    }
-    void release() {
-        for (auto &kv : m)
-            if (kv.second.p) (void)hipFree(kv.second.p);
-        m.clear();
-    }
-    ~Pool() { release(); }
-};
-
-}  // namespace
-
-struct ising_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string err;
-    Pool pool;
-    std::mutex mu;
-};
-
-struct ising_pruned {
-    int device = 0;
-    int32_t n = 0, nG = 0, rounds = 0;
-    int64_t nnzG = 0;
-    int32_t vtype = ISING_I32;  // input value type
-    int32_t format = ISING_DENSE;
-    bool identity = true;
-    double C = 0.0;
-    PruneWork w{};
-    ising_problem reduced{};
-    Pool own;        // buffers when the handle owns them
-    Pool *pool = nullptr;
-};
-
-namespace {
+namespace ising {
+namespace rt {
 
 ising_status fail(ising_ctx *ctx, ising_status st, const std::string &msg) {
     if (ctx) ctx->err = msg;
     return st;
 }
-
-#define HIP_TRY(ctx, expr)                                                                     \
-    do {                                                                                       \
-        hipError_t _e = (expr);                                                                \
-        if (_e != hipSuccess)                                                                  \
-            return fail((ctx), _e == hipErrorOutOfMemory ? ISING_ENOMEM : ISING_EDEVICE,        \
-                        std::string(#expr) + ": " + hipGetErrorString(_e));                    \
-    } while (0)
-
-#define ST_TRY(expr)                          \
-    do {                                      \
-        ising_status _s = (expr);             \
-        if (_s != ISING_OK) return _s;        \
-    } while (0)
 
 ising_status check_problem_shape(ising_ctx *ctx, const ising_problem *p) {
     if (!p) return fail(ctx, ISING_EINVAL, "problem is NULL");
@@ -111,14 +43,6 @@ ising_status check_problem_shape(ising_ctx *ctx, const ising_problem *p) {
     }
     return ISING_OK;
 }
-
-struct Ingest {
-    int32_t flags[4] = {0, 0, 1, 1};
-    bool integer() const { return flags[3] != 0; }
-    bool uniform_mag() const { return flags[2] != 0; }
-    int maxdeg() const { return flags[1]; }
-    double w = 1.0;
-};
 
 ising_status ingest(ising_ctx *ctx, const DevProblem &p, Pool &pool, Ingest &out, hipStream_t s) {
     void *flags = nullptr, *wdev = nullptr;
@@ -249,13 +173,8 @@ ising_status prune_core(ising_ctx *ctx, const DevProblem &p, ising_pruned &pr, h
 
 // ---- domain-selection launch planning -------------------------------------
 
-struct DSPlan {
-    DSLaunch l;
-    bool packed = false;
-};
-
 ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
-                     DSPlan &plan) {
+                     DSPlan &plan, bool register_only) {
     const bool fp64 = prm.precision == ISING_PREC_FP64;
     if (prm.precision != ISING_PREC_FP64 && prm.precision != ISING_PREC_FP32)
         return fail(ctx, ISING_ENOTSUP, "precision not supported by the persistent engine");
@@ -279,13 +198,19 @@ ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params 
         }
     }
     int ept = 0;
-    const int maxept = fp64 ? 2 : (rg == 4 ? 2 : 4);
-    for (int e = 1; e <= maxept; e *= 2) {
-        if ((int64_t)e * 1024 >= n) {
-            ept = e;
-            break;
+    for (;;) {
+        const int maxept = fp64 ? 2 : (rg == 4 ? 2 : 4);
+        for (int e = 1; e <= maxept; e *= 2) {
+            if ((int64_t)e * 1024 >= n) {
+                ept = e;
+                break;
+            }
         }
+        if (ept || !register_only || rg == 1) break;
+        rg = rg == 4 ? 2 : 1;  // fewer replicas per workgroup leave room for more spins per thread
     }
+    if (ept == 0 && register_only)
+        return fail(ctx, ISING_ENOTSUP, "n too large for the register-resident engine");
     if (ept == 0) {
         // streaming: spins triple-buffered in LDS
         const size_t sw = rg == 1 ? 1 : 4;
@@ -307,28 +232,19 @@ ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params 
     return ISING_OK;
 }
 
-ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
-                    const void *uniform, int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool,
-                    hipStream_t s, hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr) {
-    if (prm.replicas <= 0 || steps < 0 || t0 < 0) return fail(ctx, ISING_EINVAL, "bad replicas/steps/t0");
+ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
+                        Pool &pool, hipStream_t s, DSArgs &a, DSPlan &plan, bool register_only) {
+    if (prm.replicas <= 0) return fail(ctx, ISING_EINVAL, "bad replicas");
     if (prm.optimizer != ISING_OPT_GD && prm.optimizer != ISING_OPT_ADAM)
         return fail(ctx, ISING_EINVAL, "unknown optimizer");
-    if (!st || !st->theta || !st->s_best || !st->e_best || !st->best_step)
-        return fail(ctx, ISING_EINVAL, "state buffers missing");
-    if (prm.optimizer == ISING_OPT_ADAM && (!st->m || !st->v))
-        return fail(ctx, ISING_EINVAL, "ADAM needs m and v buffers");
-    DSPlan plan;
-    ST_TRY(plan_ds(ctx, p, prm, ing, plan));
+    ST_TRY(plan_ds(ctx, p, prm, ing, plan, register_only));
     const bool fp64 = plan.l.fp64;
     const size_t real = fp64 ? 8 : 4;
     const DevProblem dp = to_dev(p);
-    DSArgs a;
+    a = DSArgs();
     a.n = p.n;
     a.R = prm.replicas;
-    a.t0 = t0;
-    a.steps = steps;
     a.opt = prm.optimizer;
-    a.init_mode = t0 > 0 ? 0 : (uniform ? 1 : 2);
     a.seed = prm.seed;
     a.lr = prm.lr;
     a.mu = prm.mu;
@@ -372,6 +288,25 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
     else if (p.format == ISING_CSR) a.val = fmt;
     else a.J = fmt;
     a.h = p.h ? hbuf : nullptr;
+    return ISING_OK;
+}
+
+ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
+                    const void *uniform, int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool,
+                    hipStream_t s, hipEvent_t kbeg, hipEvent_t kend) {
+    if (steps < 0 || t0 < 0) return fail(ctx, ISING_EINVAL, "bad steps/t0");
+    if (!st || !st->theta || !st->s_best || !st->e_best || !st->best_step)
+        return fail(ctx, ISING_EINVAL, "state buffers missing");
+    if (prm.optimizer == ISING_OPT_ADAM && (!st->m || !st->v))
+        return fail(ctx, ISING_EINVAL, "ADAM needs m and v buffers");
+    DSArgs a;
+    DSPlan plan;
+    ST_TRY(prepare_ds(ctx, p, prm, ing, pool, s, a, plan));
+    const bool fp64 = plan.l.fp64;
+    const size_t real = fp64 ? 8 : 4;
+    a.t0 = t0;
+    a.steps = steps;
+    a.init_mode = t0 > 0 ? 0 : (uniform ? 1 : 2);
     a.theta = st->theta;
     a.m = prm.optimizer == ISING_OPT_ADAM ? st->m : nullptr;
     a.v = prm.optimizer == ISING_OPT_ADAM ? st->v : nullptr;
@@ -396,30 +331,25 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
     return ISING_OK;
 }
 
-ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const void *uniform,
-                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s,
-                       hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr) {
+ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, Pool &pool,
+                           hipStream_t s, DenseRun &d) {
     if (p.format != ISING_DENSE) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine needs dense couplings");
     int form;
     if (prm.precision == ISING_PREC_FP32) form = DF_FP32;
     else if (prm.precision == ISING_PREC_BF16X2) form = DF_BF16X2;
     else if (prm.precision == ISING_PREC_BF16) form = DF_BF16;
     else return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs FP32, BF16X2 or BF16");
-    if (prm.replicas <= 0 || steps < 0 || t0 < 0) return fail(ctx, ISING_EINVAL, "bad replicas/steps/t0");
-    if (!st || !st->theta || !st->s_best || !st->e_best || !st->best_step)
-        return fail(ctx, ISING_EINVAL, "state buffers missing");
-    if (prm.optimizer == ISING_OPT_ADAM && (!st->m || !st->v)) return fail(ctx, ISING_EINVAL, "ADAM needs m and v");
+    if (prm.replicas <= 0) return fail(ctx, ISING_EINVAL, "bad replicas");
+    if (prm.optimizer != ISING_OPT_GD && prm.optimizer != ISING_OPT_ADAM)
+        return fail(ctx, ISING_EINVAL, "unknown optimizer");
     const int n = p.n, R = prm.replicas;
-    DenseRun d;
+    d = DenseRun();
     d.n = n;
     d.R = R;
     d.Mp = (n + 127) / 128 * 128;
     d.Kp = (n + 31) / 32 * 32;
     d.form = form;
     d.opt = prm.optimizer;
-    d.t0 = t0;
-    d.steps = steps;
-    d.init_mode = t0 > 0 ? 0 : (uniform ? 1 : 2);
     d.seed = prm.seed;
     d.lr = prm.lr;
     d.mu = prm.mu;
@@ -443,13 +373,28 @@ ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_param
     d.Jlo = Jlo;
     d.Jf = Jf;
     d.h = p.h ? (const float *)hf : nullptr;
-    d.uniform = uniform;
     d.S = S;
+    d.Epart = (float *)Ep;
+    d.Lpart = (float *)Lp;
+    return ISING_OK;
+}
+
+ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const void *uniform,
+                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s,
+                       hipEvent_t kbeg, hipEvent_t kend) {
+    if (steps < 0 || t0 < 0) return fail(ctx, ISING_EINVAL, "bad steps/t0");
+    if (!st || !st->theta || !st->s_best || !st->e_best || !st->best_step)
+        return fail(ctx, ISING_EINVAL, "state buffers missing");
+    if (prm.optimizer == ISING_OPT_ADAM && (!st->m || !st->v)) return fail(ctx, ISING_EINVAL, "ADAM needs m and v");
+    DenseRun d;
+    ST_TRY(prepare_dense(ctx, p, prm, pool, s, d));
+    d.t0 = t0;
+    d.steps = steps;
+    d.init_mode = t0 > 0 ? 0 : (uniform ? 1 : 2);
+    d.uniform = uniform;
     d.theta = (float *)st->theta;
     d.m = prm.optimizer == ISING_OPT_ADAM ? (float *)st->m : nullptr;
     d.v = prm.optimizer == ISING_OPT_ADAM ? (float *)st->v : nullptr;
-    d.Epart = (float *)Ep;
-    d.Lpart = (float *)Lp;
     d.e_best = st->e_best;
     d.best_step = st->best_step;
     d.s_best = st->s_best;
@@ -465,7 +410,7 @@ ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_param
 }
 
 // dense problems with more than this many spins use the matrix-core engine in FP32
-constexpr int kDenseMfmaMinN = 256;
+constexpr int kDenseMfmaMinN = 256;  // n above which dense FP32 problems use MFMA
 
 bool use_dense_engine(const ising_problem &p, const ising_params &prm) {
     if (p.format != ISING_DENSE) return false;
@@ -479,7 +424,8 @@ double ms_between(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
-}  // namespace
+}  // namespace rt
+}  // namespace ising
 
 extern "C" {
 
@@ -502,6 +448,7 @@ ising_status ising_create(int device, ising_ctx **out) {
 
 ising_status ising_destroy(ising_ctx *ctx) {
     if (!ctx) return ISING_OK;
+    if (ctx->server) (void)ising_serve_stop(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipDeviceSynchronize();

@@ -132,6 +132,10 @@ int32_t ds_max_n(bool fp64);
 hipError_t launch_pms_format(const DevProblem &p, int wbytes, int32_t *groups, int32_t *prow, uint32_t *pcnt,
                              uint16_t *img, int32_t *total_groups, hipStream_t s);
 size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups);
+// Batched persistent engine (FP32): workgroup b runs replica group map[b].y of
+// descs[map[b].x]; all descriptors share the launch configuration l.
+hipError_t launch_ds_batch(const DSArgs *descs, const int2 *map, int nwg, const DSLaunch &l, size_t lds,
+                           hipStream_t s);
 
 hipError_t launch_select(const double *e_best, int32_t R, int32_t *best, hipStream_t s);
 // s_G = rows[best] of a replica-major int8 block (device-side gather).

@@ -227,7 +227,7 @@ __device__ inline void coupling(const DSArgs &a, int i, const typename SpinWord<
 constexpr int launch_bound(int) { return 1024; }
 
 template <typename Real, int CK, int RG, int EPT>
-__global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
+__device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     using SWd = SpinWord<RG>;
     using SW = typename SWd::T;
     constexpr int NE = EPT * RG;
@@ -244,7 +244,6 @@ __global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
     Real *lp = ep + 2 * NW * RG;          // [2][NW][RG]
     uint32_t *flg = (uint32_t *)(lp + 2 * NW * RG);  // [2]
     uint2 *img = (uint2 *)(smem + ((off + 2 * 2 * NW * RG * sizeof(Real) + 8 + 15) & ~(size_t)15));
-    const int r0 = blockIdx.x * RG;
     int prow_r[CK == CK_PMS ? EPT : 1];
     uint32_t pcnt_r[CK == CK_PMS ? EPT : 1];
     if constexpr (CK == CK_PMS) {
@@ -476,6 +475,19 @@ __global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
     }
 }
 
+
+template <typename Real, int CK, int RG, int EPT>
+__global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
+    ds_body<Real, CK, RG, EPT>(a, blockIdx.x * RG);
+}
+
+// Batched form for serving: workgroup b runs replica group map[b].y of problem
+// map[b].x; every problem's steps and state are independent of the others'.
+template <typename Real, int CK, int RG, int EPT>
+__global__ __launch_bounds__(launch_bound(EPT)) void k_ds_batch(const DSArgs *descs, const int2 *map) {
+    const int2 m = map[blockIdx.x];
+    ds_body<Real, CK, RG, EPT>(descs[m.x], m.y * RG);
+}
 
 // Same step for problems too large to keep the state in registers: angles and
 // moments are streamed from global memory every step (each workgroup touches
@@ -853,6 +865,41 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(fn, dim3(a.R / l.rg), dim3(l.block), lds, s, a);
+    return hipGetLastError();
+}
+
+using KBFn = void (*)(const DSArgs *, const int2 *);
+
+template <int CK>
+KBFn pick_batch(int rg, int ept) {
+    if (rg == 1) {
+        if (ept == 1) return k_ds_batch<float, CK, 1, 1>;
+        if (ept == 2) return k_ds_batch<float, CK, 1, 2>;
+        if (ept == 4) return k_ds_batch<float, CK, 1, 4>;
+    } else if (rg == 2) {
+        if (ept == 1) return k_ds_batch<float, CK, 2, 1>;
+        if (ept == 2) return k_ds_batch<float, CK, 2, 2>;
+    } else if (rg == 4) {
+        if (ept == 1) return k_ds_batch<float, CK, 4, 1>;
+        if (ept == 2) return k_ds_batch<float, CK, 4, 2>;
+    }
+    return nullptr;
+}
+
+hipError_t launch_ds_batch(const DSArgs *descs, const int2 *map, int nwg, const DSLaunch &l, size_t lds,
+                           hipStream_t s) {
+    if (l.fp64 || l.ept <= 0 || nwg <= 0) return hipErrorInvalidValue;
+    KBFn fn = l.coupling == CK_PMS ? pick_batch<CK_PMS>(l.rg, l.ept)
+            : l.coupling == CK_PM  ? pick_batch<CK_PM>(l.rg, l.ept)
+            : l.coupling == CK_CSRV ? pick_batch<CK_CSRV>(l.rg, l.ept)
+                                    : pick_batch<CK_DENSE>(l.rg, l.ept);
+    if (!fn) return hipErrorInvalidValue;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3(nwg), dim3(l.block), lds, s, descs, map);
     return hipGetLastError();
 }
 

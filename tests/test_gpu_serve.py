@@ -1,0 +1,139 @@
+"""Serving form: continuous batching of many solves on one GPU.
+
+Checks: every served result equals the same request solved alone (bit for bit:
+the mix never changes a request's arithmetic); served results equal the plain
+per-instance solve; requests arriving while others run are admitted and
+overlap; failure handling (rejected input, over-budget request, cancellation,
+timeout) is forced from the host.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import instances as I
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _host(inst):
+    import paper_2312_05837_amd as P
+    if inst.is_dense:
+        return P.host_problem(inst.n, J=inst.J.astype(np.int32),
+                              h=inst.h.astype(np.int32) if np.any(inst.h) else None)
+    return P.host_problem(inst.n, row_ptr=inst.row_ptr, col=inst.col, val=inst.val.astype(np.int32),
+                          h=inst.h.astype(np.int32) if np.any(inst.h) else None)
+
+
+def _requests(count, seed, steps=200):
+    descs = I.serving_stream(count, seed, rate=1000.0, nmin=64, nmax=1200, replica_choices=(64, 128, 256))
+    out = []
+    for k, d in enumerate(descs):
+        inst = I.make_request_instance(d)
+        if k % 5 == 0:  # some requests carry an integer field, so pruning has work to do
+            inst = I.random_integer_field(inst, d["seed"], 3)
+        out.append((inst, d["replicas"], d["seed"]))
+    return out
+
+
+@pytest.fixture()
+def ctx():
+    import paper_2312_05837_amd as P
+    c = P.ising_create(0)
+    yield c
+    P.ising_destroy(c)
+
+
+def _serve(ctx, reqs, steps=200, chunk=50, **cfg):
+    import paper_2312_05837_amd as P
+    P.ising_serve_start(ctx, chunk_steps=chunk, **cfg)
+    tickets = []
+    keep = []
+    for inst, R, seed in reqs:
+        st, k = _host(inst)
+        keep.append(k)
+        tickets.append(P.ising_submit(ctx, st, P.params(replicas=R, steps=steps, optimizer="adam", lr=6.0, mu=0.5,
+                                                         seed=seed, precision="fp32")))
+    res = [P.ising_wait(ctx, t, inst.n) for t, (inst, _, _) in zip(tickets, reqs)]
+    info = P.ising_serve_query(ctx)
+    P.ising_serve_stop(ctx)
+    return res, info
+
+
+def test_alone_equals_mix_and_plain_solve(ctx):
+    import torch
+    import paper_2312_05837_amd as P
+    from gpu_util import to_problem
+    reqs = _requests(24, 5)
+    mix, info = _serve(ctx, reqs, chunk=50, max_resident=16)
+    assert info["completed"] == len(reqs) and info["failed"] == 0
+    assert info["chunks"] < len(reqs) * 4  # requests shared chunks (4 chunks of 50 steps each if alone)
+    for k in (0, 3, 7, 11, 19):
+        inst, R, seed = reqs[k]
+        alone, _ = _serve(ctx, [reqs[k]], chunk=50)
+        assert alone[0][0] == P.ISING_OK and mix[k][0] == P.ISING_OK
+        assert np.array_equal(alone[0][1], mix[k][1]), k
+        assert alone[0][2] == mix[k][2]
+        # the same request through the plain per-instance solve
+        s, E, Ei, st = P.ising_solve_dev(ctx, to_problem(inst), P.params(replicas=R, steps=200, optimizer="adam",
+                                                                          lr=6.0, mu=0.5, seed=seed,
+                                                                          precision="fp32"))
+        torch.cuda.synchronize()
+        assert np.array_equal(s.cpu().numpy(), mix[k][1]), k
+        assert float(E.item()) == mix[k][2]
+    for (inst, _, _), (status, spins, energy, stats) in zip(reqs, mix):
+        assert status == P.ISING_OK
+        assert energy == oracle.energy(inst, spins)
+        assert stats["t_total_ms"] >= stats["t_ds_ms"] >= 0
+
+
+def test_requests_arriving_while_others_run_are_admitted(ctx):
+    import paper_2312_05837_amd as P
+    reqs = _requests(12, 7)
+    P.ising_serve_start(ctx, chunk_steps=20, max_resident=8)
+    keep, tickets = [], []
+    for k, (inst, R, seed) in enumerate(reqs):
+        st, kp = _host(inst)
+        keep.append(kp)
+        tickets.append(P.ising_submit(ctx, st, P.params(replicas=R, steps=400, seed=seed)))
+        if k == 5:
+            time.sleep(0.05)  # the first requests are already running when the rest arrive
+    res = [P.ising_wait(ctx, t, inst.n) for t, (inst, _, _) in zip(tickets, reqs)]
+    info = P.ising_serve_query(ctx)
+    P.ising_serve_stop(ctx)
+    assert all(r[0] == P.ISING_OK for r in res)
+    assert info["admitted"] == len(reqs) and info["completed"] == len(reqs)
+    # 12 requests x 20 chunks each would be 240 chunks one at a time
+    assert info["chunks"] < 120
+
+
+def test_failures_forced_from_the_host(ctx):
+    import paper_2312_05837_amd as P
+    P.ising_serve_start(ctx, hbm_budget_bytes=4 << 20, max_resident=4, chunk_steps=10)
+    # asymmetric J: rejected at admission
+    J = np.array([[0, 1], [2, 0]], dtype=np.int32)
+    st, keep1 = P.host_problem(2, J=J)
+    t_bad = P.ising_submit(ctx, st, P.params(replicas=8, steps=10))
+    assert P.ising_wait(ctx, t_bad, 2)[0] == P.ISING_EINVAL
+    # larger than the whole budget: refused with ENOMEM
+    big = I.sk_pm1(1200, 1)
+    st2, keep2 = _host(big)
+    t_big = P.ising_submit(ctx, st2, P.params(replicas=1024, steps=10))
+    assert P.ising_wait(ctx, t_big, big.n)[0] == P.ISING_ENOMEM
+    # timeout on a long request, then cancellation
+    inst = I.erdos_renyi(300, 0.03, 2, "pm1")
+    st3, keep3 = _host(inst)
+    t_long = P.ising_submit(ctx, st3, P.params(replicas=64, steps=200000))
+    assert P.ising_wait(ctx, t_long, inst.n, timeout_ms=0)[0] == P.ISING_ETIMEDOUT
+    P.ising_cancel(ctx, t_long)
+    assert P.ising_wait(ctx, t_long, inst.n)[0] == P.ISING_ECANCELED
+    # the server still works afterwards
+    small = I.erdos_renyi(100, 0.05, 3, "pm1")
+    st4, keep4 = _host(small)
+    t_ok = P.ising_submit(ctx, st4, P.params(replicas=32, steps=50))
+    status, spins, energy, _ = P.ising_wait(ctx, t_ok, small.n)
+    assert status == P.ISING_OK and energy == oracle.energy(small, spins)
+    info = P.ising_serve_query(ctx)
+    P.ising_serve_stop(ctx)
+    assert info["failed"] == 2 and info["canceled"] == 1 and info["completed"] == 1
