@@ -332,10 +332,13 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
 }
 
 ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, Pool &pool,
-                           hipStream_t s, DenseRun &d) {
+                           hipStream_t s, DenseRun &d, bool exact_bf16) {
     if (p.format != ISING_DENSE) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine needs dense couplings");
     int form;
-    if (prm.precision == ISING_PREC_FP32) form = DF_FP32;
+    // integer couplings of magnitude <= 256 are exact in BF16 and their products
+    // are summed exactly in FP32, so the BF16 form gives the FP32 form's results bit for bit
+    if (prm.precision == ISING_PREC_FP32 && exact_bf16) form = DF_BF16;
+    else if (prm.precision == ISING_PREC_FP32) form = DF_FP32;
     else if (prm.precision == ISING_PREC_BF16X2) form = DF_BF16X2;
     else if (prm.precision == ISING_PREC_BF16) form = DF_BF16;
     else return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs FP32, BF16X2 or BF16");
@@ -380,18 +383,24 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
 }
 
 ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const void *uniform,
-                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s,
+                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s, bool exact_bf16,
                        hipEvent_t kbeg, hipEvent_t kend) {
     if (steps < 0 || t0 < 0) return fail(ctx, ISING_EINVAL, "bad steps/t0");
     if (!st || !st->theta || !st->s_best || !st->e_best || !st->best_step)
         return fail(ctx, ISING_EINVAL, "state buffers missing");
     if (prm.optimizer == ISING_OPT_ADAM && (!st->m || !st->v)) return fail(ctx, ISING_EINVAL, "ADAM needs m and v");
     DenseRun d;
-    ST_TRY(prepare_dense(ctx, p, prm, pool, s, d));
+    ST_TRY(prepare_dense(ctx, p, prm, pool, s, d, exact_bf16));
     d.t0 = t0;
     d.steps = steps;
     d.init_mode = t0 > 0 ? 0 : (uniform ? 1 : 2);
     d.uniform = uniform;
+    if (prm.optimizer == ISING_OPT_ADAM && steps > 0) {
+        void *bias = nullptr;
+        HIP_TRY(ctx, pool.get("dn.bias", (size_t)2 * steps * 4, &bias));
+        HIP_TRY(ctx, launch_bias_table(prm.beta1, prm.beta2, t0, steps, false, bias, s));
+        d.bias = (const float *)bias;
+    }
     d.theta = (float *)st->theta;
     d.m = prm.optimizer == ISING_OPT_ADAM ? (float *)st->m : nullptr;
     d.v = prm.optimizer == ISING_OPT_ADAM ? (float *)st->v : nullptr;
@@ -400,8 +409,11 @@ ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_param
     d.s_best = st->s_best;
     d.etrace = st->energy_trace;
     d.ltrace = st->loss_trace;
+    void *scratch = nullptr;
+    const DenseRun *one = &d;
+    HIP_TRY(ctx, pool.get("dn.group", dense_group_scratch_bytes(&one, 1), &scratch));
     if (kbeg) HIP_TRY(ctx, hipEventRecord(kbeg, s));
-    hipError_t e = launch_dense_run(d, s);
+    hipError_t e = launch_dense_run(d, scratch, s);
     if (e != hipSuccess)
         return fail(ctx, e == hipErrorInvalidValue ? ISING_ENOTSUP : ISING_EDEVICE,
                     std::string("matrix-core domain selection: ") + hipGetErrorString(e));
@@ -416,6 +428,10 @@ bool use_dense_engine(const ising_problem &p, const ising_params &prm) {
     if (p.format != ISING_DENSE) return false;
     if (prm.precision == ISING_PREC_BF16X2 || prm.precision == ISING_PREC_BF16) return true;
     return prm.precision == ISING_PREC_FP32 && p.n > kDenseMfmaMinN;
+}
+
+bool exact_in_bf16(const Ingest &ing, int n) {
+    return ing.integer() && ing.uniform_mag() && ing.w <= 256.0 && (double)n * ing.w < 16777216.0;
 }
 
 double ms_between(hipEvent_t a, hipEvent_t b) {
@@ -592,7 +608,7 @@ ising_status ising_ds_dense_dev(ising_ctx *ctx, const ising_problem *problem, co
     hipStream_t s = (hipStream_t)stream;
     Ingest ing;
     ST_TRY(ingest(ctx, to_dev(*problem), ctx->pool, ing, s));
-    return run_dense(ctx, *problem, *params, uniform, t0, steps, state, ctx->pool, s);
+    return run_dense(ctx, *problem, *params, uniform, t0, steps, state, ctx->pool, s, exact_in_bf16(ing, problem->n));
 }
 
 ising_status ising_select_dev(ising_ctx *ctx, const double *e_best, int32_t replicas, int32_t *best,
@@ -664,7 +680,9 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
         HIP_TRY(ctx, pool.get("solve.sbest", (size_t)nG * R, (void **)&st.s_best));
         HIP_TRY(ctx, pool.get("solve.ebest", (size_t)R * 8, (void **)&st.e_best));
         HIP_TRY(ctx, pool.get("solve.bstep", (size_t)R * 4, (void **)&st.best_step));
-        if (dense_engine) ST_TRY(run_dense(ctx, *red, *params, nullptr, 0, params->steps, &st, pool, s, ev[5], ev[6]));
+        if (dense_engine)
+            ST_TRY(run_dense(ctx, *red, *params, nullptr, 0, params->steps, &st, pool, s, exact_in_bf16(ing, red->n),
+                             ev[5], ev[6]));
         else ST_TRY(run_ds(ctx, *red, *params, ing, nullptr, 0, params->steps, &st, pool, s, ev[5], ev[6]));
         HIP_TRY(ctx, hipEventRecord(ev[3], s));
         HIP_TRY(ctx, launch_select(st.e_best, R, bestdev, s));

@@ -160,10 +160,18 @@ struct DenseRun {
     int32_t *best_step = nullptr;
     int8_t *s_best = nullptr;
     double *etrace = nullptr, *ltrace = nullptr;
+    const float *bias = nullptr;  // ADAM bias corrections of steps t0+1.. (2 floats per step)
 };
 // Pad and split J (and convert h to float into hf when both are non-null).
 hipError_t launch_dense_prepare(const DevProblem &p, int form, int Mp, int Kp, void *Jhi, void *Jlo, void *Jf,
                                 float *hf, hipStream_t s);
-hipError_t launch_dense_run(const DenseRun &d, hipStream_t s);
+// State initialisation (t0 = 0) or vertex re-derivation (t0 > 0) before a chunk.
+hipError_t launch_dense_init(const DenseRun &d, hipStream_t s);
+// Advance `count` problems of the same form by `steps` steps: two launches per
+// step for the whole group.  scratch: dense_group_scratch_bytes() of device memory.
+hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps, void *scratch, hipStream_t s);
+size_t dense_group_scratch_bytes(const DenseRun *const *runs, int count);
+// One problem: init + group of one.
+hipError_t launch_dense_run(const DenseRun &d, void *scratch, hipStream_t s);
 
 }  // namespace ising

@@ -21,6 +21,8 @@
 // Operand layouts: J padded row-major [Mp][Kp]; S~ replica-major [R][Kp]
 // (each replica's spins contiguous), so both MFMA operands are K-contiguous.
 // State theta, m, v, s_best: replica-major [R][n].
+#include <vector>
+
 #include "internal.hpp"
 
 namespace ising {
@@ -161,25 +163,48 @@ __global__ void k_dense_init(int n, int R, int Kp, int form, int init_mode, uint
 
 // ---- the step ---------------------------------------------------------------
 
-struct DenseStepArgs {
-    int n, R, Mp, Kp, opt;
-    float lr, mu, b1, b2, eps, omb1, omb2, ib1, ib2;
-    const unsigned short *Jhi, *Jlo;
-    const float *Jf;
-    const float *h;
-    const void *S_in;
-    void *S_out;
-    float *theta, *m, *v;
-    float *Epart, *Lpart;  // [Mtiles][R]
+// Per-problem descriptor, constant over a chunk of steps: the step index tloc
+// (1-based within the chunk) is the only per-launch argument, so every problem
+// of a group advances with the same two launches per step.
+template <typename T>
+using plain_ptr = T *;
+// pointer into device global memory: accesses through it compile to global
+// (not flat) loads and stores
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T *;
+
+template <template <typename> class Ptr>
+struct DenseDescT {
+    int n, R, Mp, Kp, opt, mtiles;
+    float lr, mu, b1, b2, eps, omb1, omb2;
+    int t0;                  // global step before the chunk
+    Ptr<const float> bias;   // 1/(1-b1^t), 1/(1-b2^t) of the chunk's steps, at 2 (tloc - 1)
+    Ptr<const unsigned short> Jhi, Jlo;
+    Ptr<const float> Jf;
+    Ptr<const float> h;
+    Ptr<char> S0, S1;        // vertex buffers: S0 holds the chunk's first vertex
+    Ptr<float> theta, m, v;
+    Ptr<float> Epart, Lpart;  // [mtiles][R]
+    Ptr<double> e_best;
+    Ptr<int32_t> best_step;
+    Ptr<int8_t> s_best;
+    Ptr<double> etrace, ltrace;  // rows of the chunk's steps (nullable)
 };
+// written by the host; the kernels read the same bytes with global pointers
+using DenseDesc = DenseDescT<plain_ptr>;
+using DenseDescG = DenseDescT<global_ptr>;
+static_assert(sizeof(DenseDesc) == sizeof(DenseDescG), "descriptor layouts must agree");
 
 template <int FORM>
-__global__ __launch_bounds__(256) void k_dense_step(const DenseStepArgs a) {
+__device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int tloc, const int mt, const int nt) {
     __shared__ __align__(16) unsigned char lds[cmax(2 * (FORM == DF_FP32 ? GEMM_LDS_FP32 : GEMM_LDS_BF16), EPI_LDS)];
     __shared__ float red_e[1][BN], red_l[1][BN];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int mt = blockIdx.x, nt = blockIdx.y;
+    const void *S_in = (const void *)(((tloc - 1) & 1) ? a.S1 : a.S0);
+    void *S_out = (void *)(((tloc - 1) & 1) ? a.S0 : a.S1);
+    const float ib1 = a.opt == ISING_OPT_ADAM ? a.bias[2 * (tloc - 1)] : 1.f;
+    const float ib2 = a.opt == ISING_OPT_ADAM ? a.bias[2 * (tloc - 1) + 1] : 1.f;
     const int row0 = mt * BM, col0 = nt * BN;
     f32x16 acc[2][2];
 #pragma unroll
@@ -198,7 +223,7 @@ __global__ __launch_bounds__(256) void k_dense_step(const DenseStepArgs a) {
                 const int q = tid + 256 * u;
                 const int r = q / (KC / 4), c4 = (q % (KC / 4)) * 4;
                 pa[u] = *(const float4 *)(a.Jf + (size_t)(row0 + r) * a.Kp + k0 + c4);
-                pb[u] = (col0 + r < a.R) ? *(const float4 *)((const float *)a.S_in + (size_t)(col0 + r) * a.Kp + k0 + c4)
+                pb[u] = (col0 + r < a.R) ? *(const float4 *)((const float *)S_in + (size_t)(col0 + r) * a.Kp + k0 + c4)
                                          : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         };
@@ -242,7 +267,7 @@ __global__ __launch_bounds__(256) void k_dense_step(const DenseStepArgs a) {
                 pah[u] = *(const u16x8 *)(a.Jhi + (size_t)(row0 + r) * a.Kp + k0 + c8);
                 if (FORM == DF_BF16X2) pal[u] = *(const u16x8 *)(a.Jlo + (size_t)(row0 + r) * a.Kp + k0 + c8);
                 pb[u] = (col0 + r < a.R)
-                            ? *(const u16x8 *)((const unsigned short *)a.S_in + (size_t)(col0 + r) * a.Kp + k0 + c8)
+                            ? *(const u16x8 *)((const unsigned short *)S_in + (size_t)(col0 + r) * a.Kp + k0 + c8)
                             : u16x8{};
             }
         };
@@ -362,7 +387,7 @@ __global__ __launch_bounds__(256) void k_dense_step(const DenseStepArgs a) {
                     if (adam) {
                         mo[u] = a.b1 * mo[u] + a.omb1 * gr;
                         ve[u] = a.b2 * ve[u] + a.omb2 * (gr * gr);
-                        upd = a.lr * (mo[u] * a.ib1) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(ve[u] * a.ib2) + a.eps);
+                        upd = a.lr * (mo[u] * ib1) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(ve[u] * ib2) + a.eps);
                     } else {
                         upd = a.lr * gr;
                     }
@@ -395,11 +420,11 @@ __global__ __launch_bounds__(256) void k_dense_step(const DenseStepArgs a) {
                 }
                 const size_t sbase = (size_t)r * a.Kp + i0;  // Kp % 32 == 0, i0 % 4 == 0: aligned
                 if (FORM == DF_FP32) {
-                    *(float4 *)((float *)a.S_out + sbase) = make_float4(sf[0], sf[1], sf[2], sf[3]);
+                    *(float4 *)((float *)S_out + sbase) = make_float4(sf[0], sf[1], sf[2], sf[3]);
                 } else {
                     const uint2 w = make_uint2((uint32_t)sb[0] | ((uint32_t)sb[1] << 16),
                                                (uint32_t)sb[2] | ((uint32_t)sb[3] << 16));
-                    *(uint2 *)((unsigned short *)a.S_out + sbase) = w;
+                    *(uint2 *)((unsigned short *)S_out + sbase) = w;
                 }
             }
             // sum over the 32 spin groups of this replica (lanes 0-31 and 32-63 hold two replicas):
@@ -430,34 +455,43 @@ __global__ __launch_bounds__(256) void k_dense_step(const DenseStepArgs a) {
     }
 }
 
+template <int FORM>
+__global__ __launch_bounds__(256) void k_dense_step(const DenseDesc *__restrict__ descs,
+                                                    const int4 *__restrict__ tiles, int tloc) {
+    const int4 t = tiles[blockIdx.x];  // (problem, row tile, replica tile)
+    const DenseDescG a = ((const DenseDescG *)descs)[t.x];
+    dense_step_body<FORM>(a, tloc, t.y, t.z);
+}
+
 // one wavefront per replica: E_t from the row-tile partials (ascending), best-vertex update
-__global__ __launch_bounds__(256) void k_dense_best(int n, int R, int Kp, int mtiles, int form, int tglobal,
-                                                    const float *Epart, const float *Lpart, const void *S_t,
-                                                    double *e_best, int32_t *best_step, int8_t *s_best,
-                                                    double *etrace, double *ltrace) {
+__global__ __launch_bounds__(256) void k_dense_best(const DenseDesc *__restrict__ descs,
+                                                    const int2 *__restrict__ quads, int tloc, int form) {
+    const int2 qd = quads[blockIdx.x];  // (problem, group of four replicas)
+    const DenseDescG a = ((const DenseDescG *)descs)[qd.x];
     const int lane = threadIdx.x & 63;
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= R) return;
+    const int r = qd.y * 4 + (threadIdx.x >> 6);
+    if (r >= a.R) return;
+    const void *S_t = (const void *)(((tloc - 1) & 1) ? a.S1 : a.S0);
     float E = 0.f, L = 0.f;
-    for (int t = 0; t < mtiles; ++t) {
-        E += Epart[(size_t)t * R + r];
-        if (Lpart) L += Lpart[(size_t)t * R + r];
+    for (int t = 0; t < a.mtiles; ++t) {
+        E += a.Epart[(size_t)t * a.R + r];
+        if (a.ltrace) L += a.Lpart[(size_t)t * a.R + r];
     }
-    const bool imp = (double)E < e_best[r];
+    const bool imp = (double)E < a.e_best[r];
     if (imp) {
-        for (int i = lane; i < n; i += 64) {
-            const float s = form == DF_FP32 ? ((const float *)S_t)[(size_t)r * Kp + i]
-                                            : bf16_to_f(((const unsigned short *)S_t)[(size_t)r * Kp + i]);
-            s_best[(size_t)r * n + i] = s < 0.f ? (int8_t)-1 : (int8_t)1;
+        for (int i = lane; i < a.n; i += 64) {
+            const float sv = form == DF_FP32 ? ((const float *)S_t)[(size_t)r * a.Kp + i]
+                                             : bf16_to_f(((const unsigned short *)S_t)[(size_t)r * a.Kp + i]);
+            a.s_best[(size_t)r * a.n + i] = sv < 0.f ? (int8_t)-1 : (int8_t)1;
         }
     }
     if (lane == 0) {
         if (imp) {
-            e_best[r] = (double)E;
-            best_step[r] = tglobal;
+            a.e_best[r] = (double)E;
+            a.best_step[r] = a.t0 + tloc;
         }
-        if (etrace) etrace[r] = (double)E;
-        if (ltrace) ltrace[r] = (double)L;
+        if (a.etrace) a.etrace[(size_t)(tloc - 1) * a.R + r] = (double)E;
+        if (a.ltrace) a.ltrace[(size_t)(tloc - 1) * a.R + r] = (double)L;
     }
 }
 
@@ -479,25 +513,15 @@ hipError_t launch_dense_prepare(const DevProblem &p, int form, int Mp, int Kp, v
     return hipGetLastError();
 }
 
-hipError_t launch_dense_run(const DenseRun &d, hipStream_t s) {
-    const int mtiles = d.Mp / BM, ntiles = (d.R + BN - 1) / BN;
-    if (d.Mp % BM || d.Kp % KC || d.Mp < d.n || d.Kp < d.n) return hipErrorInvalidValue;
-    const size_t sbytes = d.form == DF_FP32 ? 4 : 2;
-    char *S0 = (char *)d.S;
-    char *S1 = S0 + (size_t)d.R * d.Kp * sbytes;
-    {  // (re)derive the vertex buffer from theta at every call; initialise the state at t0 = 0
-        const int64_t total = (int64_t)d.R * d.Kp;
-        const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
-        hipLaunchKernelGGL(k_dense_init, dim3(blocks), dim3(256), 0, s, d.n, d.R, d.Kp, d.form,
-                           d.t0 == 0 ? d.init_mode : 0, d.seed, (const float *)d.uniform, d.theta, d.m, d.v,
-                           (void *)S0, (void *)S1, d.e_best, d.best_step, d.s_best);
-    }
-    DenseStepArgs a;
+// host side of one problem's descriptor
+static DenseDesc make_desc(const DenseRun &d) {
+    DenseDesc a{};
     a.n = d.n;
     a.R = d.R;
     a.Mp = d.Mp;
     a.Kp = d.Kp;
     a.opt = d.opt;
+    a.mtiles = d.Mp / BM;
     a.lr = (float)d.lr;
     a.mu = (float)d.mu;
     a.b1 = (float)d.b1;
@@ -505,33 +529,92 @@ hipError_t launch_dense_run(const DenseRun &d, hipStream_t s) {
     a.eps = (float)d.eps;
     a.omb1 = (float)(1.0 - d.b1);
     a.omb2 = (float)(1.0 - d.b2);
+    a.t0 = d.t0;
+    a.bias = d.bias;
     a.Jhi = (const unsigned short *)d.Jhi;
     a.Jlo = (const unsigned short *)d.Jlo;
     a.Jf = (const float *)d.Jf;
     a.h = d.h;
+    const size_t sbytes = d.form == DF_FP32 ? 4 : 2;
+    a.S0 = (char *)d.S;
+    a.S1 = (char *)d.S + (size_t)d.R * d.Kp * sbytes;
     a.theta = d.theta;
     a.m = d.m;
     a.v = d.v;
     a.Epart = d.Epart;
-    a.Lpart = d.ltrace ? d.Lpart : nullptr;
-    for (int t = 1; t <= d.steps; ++t) {
-        const int tg = d.t0 + t;
-        a.ib1 = (float)(1.0 / -std::expm1(tg * std::log(d.b1)));
-        a.ib2 = (float)(1.0 / -std::expm1(tg * std::log(d.b2)));
-        // S buffer k % 2 holds the vertex of step t0 + k + 1 counted from the last (re)initialisation
-        const int cur = (t - 1) & 1;
-        a.S_in = cur ? S1 : S0;
-        a.S_out = cur ? S0 : S1;
-        dim3 grid(mtiles, ntiles);
-        if (d.form == DF_FP32) hipLaunchKernelGGL(k_dense_step<DF_FP32>, grid, dim3(256), 0, s, a);
-        else if (d.form == DF_BF16X2) hipLaunchKernelGGL(k_dense_step<DF_BF16X2>, grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(k_dense_step<DF_BF16>, grid, dim3(256), 0, s, a);
-        hipLaunchKernelGGL(k_dense_best, dim3((d.R + 3) / 4), dim3(256), 0, s, d.n, d.R, d.Kp, mtiles, d.form, tg,
-                           (const float *)d.Epart, (const float *)a.Lpart, a.S_in, d.e_best, d.best_step, d.s_best,
-                           d.etrace ? d.etrace + (size_t)(t - 1) * d.R : nullptr,
-                           d.ltrace ? d.ltrace + (size_t)(t - 1) * d.R : nullptr);
+    a.Lpart = d.Lpart;
+    a.e_best = d.e_best;
+    a.best_step = d.best_step;
+    a.s_best = d.s_best;
+    a.etrace = d.etrace;
+    a.ltrace = d.ltrace;
+    return a;
+}
+
+static size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+size_t dense_group_scratch_bytes(const DenseRun *const *runs, int count) {
+    size_t tiles = 0, quads = 0;
+    for (int k = 0; k < count; ++k) {
+        tiles += (size_t)(runs[k]->Mp / BM) * ((runs[k]->R + BN - 1) / BN);
+        quads += (size_t)(runs[k]->R + 3) / 4;
+    }
+    return align16(count * sizeof(DenseDesc)) + tiles * sizeof(int4) + quads * sizeof(int2) + 64;
+}
+
+hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps, void *scratch, hipStream_t s) {
+    if (count <= 0 || steps <= 0) return hipSuccess;
+    const int form = runs[0]->form;
+    std::vector<DenseDesc> descs;
+    std::vector<int4> tiles;
+    std::vector<int2> quads;
+    for (int k = 0; k < count; ++k) {
+        const DenseRun &d = *runs[k];
+        if (d.form != form || d.Mp % BM || d.Kp % KC || d.Mp < d.n || d.Kp < d.n) return hipErrorInvalidValue;
+        if (d.opt == ISING_OPT_ADAM && !d.bias) return hipErrorInvalidValue;
+        descs.push_back(make_desc(d));
+        for (int nt = 0; nt < (d.R + BN - 1) / BN; ++nt)
+            for (int mt = 0; mt < d.Mp / BM; ++mt) tiles.push_back(make_int4(k, mt, nt, 0));
+        for (int q = 0; q < (d.R + 3) / 4; ++q) quads.push_back(make_int2(k, q));
+    }
+    char *p = (char *)scratch;
+    DenseDesc *dd = (DenseDesc *)p;
+    int4 *dt = (int4 *)(p + align16(descs.size() * sizeof(DenseDesc)));
+    int2 *dq = (int2 *)((char *)dt + tiles.size() * sizeof(int4));
+    hipError_t e = hipMemcpyAsync(dd, descs.data(), descs.size() * sizeof(DenseDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dq, quads.data(), quads.size() * sizeof(int2), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    // the copies read the host vectors above: let them finish before the vectors go away
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (int t = 1; t <= steps; ++t) {
+        if (form == DF_FP32) hipLaunchKernelGGL(k_dense_step<DF_FP32>, dim3(tiles.size()), dim3(256), 0, s, dd, dt, t);
+        else if (form == DF_BF16X2) hipLaunchKernelGGL(k_dense_step<DF_BF16X2>, dim3(tiles.size()), dim3(256), 0, s, dd, dt, t);
+        else hipLaunchKernelGGL(k_dense_step<DF_BF16>, dim3(tiles.size()), dim3(256), 0, s, dd, dt, t);
+        hipLaunchKernelGGL(k_dense_best, dim3(quads.size()), dim3(256), 0, s, dd, dq, t, form);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_dense_init(const DenseRun &d, hipStream_t s) {
+    // (re)derive the vertex buffer from theta at every chunk; initialise the state at t0 = 0
+    const size_t sbytes = d.form == DF_FP32 ? 4 : 2;
+    char *S0 = (char *)d.S;
+    char *S1 = S0 + (size_t)d.R * d.Kp * sbytes;
+    const int64_t total = (int64_t)d.R * d.Kp;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_dense_init, dim3(blocks), dim3(256), 0, s, d.n, d.R, d.Kp, d.form,
+                       d.t0 == 0 ? d.init_mode : 0, d.seed, (const float *)d.uniform, d.theta, d.m, d.v,
+                       (void *)S0, (void *)S1, d.e_best, d.best_step, d.s_best);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_run(const DenseRun &d, void *scratch, hipStream_t s) {
+    hipError_t e = launch_dense_init(d, s);
+    if (e != hipSuccess) return e;
+    const DenseRun *one = &d;
+    return launch_dense_group(&one, 1, d.steps, scratch, s);
 }
 
 }  // namespace ising

@@ -879,6 +879,7 @@ KBFn pick_batch(int rg, int ept) {
     } else if (rg == 2) {
         if (ept == 1) return k_ds_batch<float, CK, 2, 1>;
         if (ept == 2) return k_ds_batch<float, CK, 2, 2>;
+        if (ept == 4) return k_ds_batch<float, CK, 2, 4>;
     } else if (rg == 4) {
         if (ept == 1) return k_ds_batch<float, CK, 4, 1>;
         if (ept == 2) return k_ds_batch<float, CK, 4, 2>;

@@ -126,11 +126,15 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
                     const void *uniform, int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool,
                     hipStream_t s, hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr);
 // Operands of the matrix-core engine (split J) and the problem fields of a DenseRun.
+// exact_bf16: run an FP32 request in the BF16 form when that is exact (see exact_in_bf16).
 ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, Pool &pool,
-                           hipStream_t s, DenseRun &d);
+                           hipStream_t s, DenseRun &d, bool exact_bf16);
 ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const void *uniform,
-                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s,
+                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s, bool exact_bf16,
                        hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr);
+// All couplings are integers of one magnitude w <= 256 (exact in BF16) and every
+// row sum stays below 2^24 (exact in FP32).
+bool exact_in_bf16(const Ingest &ing, int n);
 bool use_dense_engine(const ising_problem &p, const ising_params &prm);
 double ms_between(hipEvent_t a, hipEvent_t b);
 

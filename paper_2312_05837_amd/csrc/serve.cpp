@@ -180,7 +180,7 @@ ising_status admit(Server &S, Request &q) {
     HIP_TRY(ctx, pool.get("ebest", (size_t)R * 8, (void **)&q.st.e_best));
     HIP_TRY(ctx, pool.get("bstep", (size_t)R * 4, (void **)&q.st.best_step));
     if (q.dense) {
-        ST_TRY(prepare_dense(ctx, *q.red, q.prm, pool, s, q.drun));
+        ST_TRY(prepare_dense(ctx, *q.red, q.prm, pool, s, q.drun, exact_in_bf16(q.ing, q.red->n)));
         DenseRun &d = q.drun;
         d.lr = q.prm.lr;
         d.mu = q.prm.mu;
@@ -193,6 +193,12 @@ ising_status admit(Server &S, Request &q) {
         d.e_best = q.st.e_best;
         d.best_step = q.st.best_step;
         d.s_best = q.st.s_best;
+        if (q.prm.optimizer == ISING_OPT_ADAM && q.prm.steps > 0) {
+            void *bias = nullptr;
+            HIP_TRY(ctx, pool.get("dbias", (size_t)2 * q.prm.steps * 4, &bias));
+            HIP_TRY(ctx, launch_bias_table(q.prm.beta1, q.prm.beta2, 0, q.prm.steps, false, bias, s));
+            d.bias = (const float *)bias;
+        }
     } else {
         ST_TRY(prepare_ds(ctx, *q.red, q.prm, q.ing, pool, s, q.args, q.plan, /*register_only=*/true));
         q.args.theta = q.st.theta;
@@ -265,7 +271,7 @@ void run_chunk(Server &S, std::vector<Request *> &live) {
     ising_ctx *ctx = S.ctx;
     const int K = std::max(1, S.cfg.chunk_steps);
     std::map<BatchKey, std::vector<Request *>> groups;
-    int di = 0;
+    std::map<int, std::vector<DenseRun>> dense;  // by form: every dense request of a form advances together
     for (Request *q : live) {
         const int left = q->prm.steps - q->steps_done;
         if (left <= 0 || q->red == nullptr || q->red->n == 0) continue;
@@ -275,15 +281,38 @@ void run_chunk(Server &S, std::vector<Request *> &live) {
             d.t0 = q->steps_done;
             d.steps = k;
             d.init_mode = q->steps_done > 0 ? 0 : 2;
-            hipStream_t s = S.dense[(di++) % S.dense.size()];
-            if (launch_dense_run(d, s) != hipSuccess) {
+            if (d.bias) d.bias += (size_t)2 * q->steps_done;
+            if (launch_dense_init(d, S.dense[0]) != hipSuccess) {
                 q->result = ISING_EDEVICE;
-                q->error = "matrix-core launch failed";
+                q->error = "matrix-core initialisation failed";
+                continue;
             }
-            S.info.launches += 2 * k + 1;
+            dense[d.form].push_back(d);
         } else {
             const DSLaunch &l = q->plan.l;
             groups[BatchKey(l.coupling, l.rg, l.ept, l.block)].push_back(q);
+        }
+    }
+    // dense groups: problems with fewer steps left than the chunk finish inside it; split
+    // each form's group by step count so that one launch sequence fits every member
+    for (auto &g : dense) {
+        std::map<int, std::vector<const DenseRun *>> by_steps;
+        for (const DenseRun &d : g.second) by_steps[d.steps].push_back(&d);
+        for (auto &bs : by_steps) {
+            void *scratch = nullptr;
+            char key[32];
+            snprintf(key, sizeof key, "dg%d.%d", g.first, bs.first);
+            const size_t bytes = dense_group_scratch_bytes(bs.second.data(), (int)bs.second.size());
+            if (S.batch.get(key, bytes, &scratch) != hipSuccess ||
+                launch_dense_group(bs.second.data(), (int)bs.second.size(), bs.first, scratch, S.dense[0]) !=
+                    hipSuccess) {
+                for (Request *q : live)
+                    if (q->dense) {
+                        q->result = ISING_EDEVICE;
+                        q->error = "matrix-core group launch failed";
+                    }
+            }
+            S.info.launches += 2 * bs.first;
         }
     }
     for (auto &g : groups) {

@@ -79,13 +79,21 @@ def test_fp32_form_iterates(ctx, name, mk, R, lrs, opt, steps):
 
 
 def test_bf16_forms_exact_on_pm1(ctx):
-    inst = I.sk_pm1(300, 4)
+    # +-1/2 couplings: not integers, so FP32 requests keep the FP32 matrix-core form
+    # (integer +-1 ones are routed to the BF16 form, which is exact for them)
+    pm = I.sk_pm1(300, 4)
+    inst = I.Instance(300, "sk_half_300", np.zeros(300), pm.J * 0.5, integer=False)
     U = I.uniform_draws(6, 130, inst.n)
     a = _run(ctx, inst, 130, 60, "adam", 6.0, "fp32", 1, U)
     for prec in ("bf16x2", "bf16"):
         b = _run(ctx, inst, 130, 60, "adam", 6.0, prec, 1, U)
         for k in ("theta", "m", "v", "s_best", "e_best", "best_step", "energy_trace"):
             assert np.array_equal(a[k], b[k]), (prec, k)
+    # the integer +-1 instance in FP32 (routed to BF16) matches the oracle like the FP32 form
+    U2 = I.uniform_draws(9, 64, pm.n)
+    got = _run(ctx, pm, 64, 100, "gd", 0.002, "fp32", 10, U2)
+    got["loss_trace"] = np.zeros_like(got["energy_trace"])
+    compare_trajectories(pm, got, U2, 100, "gd", 0.002, 10, check_loss=False)
 
 
 @pytest.mark.parametrize("prec,tol,steps", [("bf16x2", 2e-4, 100), ("bf16", 5e-2, 20)])

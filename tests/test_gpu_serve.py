@@ -137,3 +137,37 @@ def test_failures_forced_from_the_host(ctx):
     info = P.ising_serve_query(ctx)
     P.ising_serve_stop(ctx)
     assert info["failed"] == 2 and info["canceled"] == 1 and info["completed"] == 1
+
+
+def test_large_sparse_and_grouped_dense_requests(ctx):
+    """Sparse requests that need the widest register form (several spins per lane,
+    two words of vertex bits per lane) and dense requests of different lengths,
+    which the server advances as one matrix-core group per step count."""
+    import torch
+    import paper_2312_05837_amd as P
+    from gpu_util import to_problem
+    reqs = [(I.erdos_renyi(3000, 8.0 / 2999, 11, "pm1"), 512, 101, 120),
+            (I.erdos_renyi(2600, 8.0 / 2599, 12, "pm1"), 512, 102, 60),
+            (I.sk_pm1(300, 13), 128, 103, 120),
+            (I.sk_pm1(520, 14), 256, 104, 70),
+            (I.sk_pm1(300, 15), 64, 105, 70)]
+    P.ising_serve_start(ctx, chunk_steps=50, max_resident=8)
+    keep, tickets = [], []
+    for inst, R, seed, steps in reqs:
+        st, kp = _host(inst)
+        keep.append(kp)
+        tickets.append(P.ising_submit(ctx, st, P.params(replicas=R, steps=steps, optimizer="adam", lr=6.0, mu=0.5,
+                                                         seed=seed, precision="fp32")))
+    res = [P.ising_wait(ctx, t, r[0].n) for t, r in zip(tickets, reqs)]
+    info = P.ising_serve_query(ctx)
+    P.ising_serve_stop(ctx)
+    assert info["completed"] == len(reqs) and info["failed"] == 0, [r[0] for r in res]
+    for (inst, R, seed, steps), (status, spins, energy, _) in zip(reqs, res):
+        assert status == P.ISING_OK
+        s, E, Ei, st = P.ising_solve_dev(ctx, to_problem(inst), P.params(replicas=R, steps=steps, optimizer="adam",
+                                                                          lr=6.0, mu=0.5, seed=seed,
+                                                                          precision="fp32"))
+        torch.cuda.synchronize()
+        assert np.array_equal(s.cpu().numpy(), spins), inst.n
+        assert float(E.item()) == energy
+        assert energy == oracle.energy(inst, spins)
