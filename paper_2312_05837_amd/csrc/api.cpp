@@ -261,26 +261,31 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
     a.col = p.col;
     if (plan.packed && plan.l.ept > 0) {
         // stage the +-w couplings in LDS when the image fits next to the vertex buffers
-        const int wbytes = plan.l.rg == 1 ? 1 : 4;
-        if ((int64_t)(p.n + 1) * wbytes <= 65535) {
-            int32_t *groups = nullptr, *prow = nullptr;
-            uint32_t *pcnt = nullptr;
-            HIP_TRY(ctx, pool.get("ds.pms.groups", (size_t)p.n * 4, (void **)&groups));
-            HIP_TRY(ctx, pool.get("ds.pms.prow", (size_t)(p.n + 1) * 4, (void **)&prow));
-            HIP_TRY(ctx, pool.get("ds.pms.pcnt", (size_t)p.n * 4, (void **)&pcnt));
+        DSLaunch l2 = plan.l;
+        l2.coupling = CK_PMS;
+        const int rb = pms_region_bytes(l2);
+        const int slots = l2.ept * l2.block;
+        if (2 * (int64_t)rb <= 65536 && slots / 64 <= 256) {
+            PmsWork w;
+            HIP_TRY(ctx, pool.get("ds.pms.deg", (size_t)p.n * 4, (void **)&w.deg));
+            HIP_TRY(ctx, pool.get("ds.pms.pos", (size_t)p.n * 4, (void **)&w.pos));
+            HIP_TRY(ctx, pool.get("ds.pms.perm", (size_t)slots * 4, (void **)&w.perm));
+            HIP_TRY(ctx, pool.get("ds.pms.prow", (size_t)slots * 4, (void **)&w.prow));
+            HIP_TRY(ctx, pool.get("ds.pms.pcnt", (size_t)slots * 4, (void **)&w.pcnt));
+            HIP_TRY(ctx, pool.get("ds.pms.total", 4, (void **)&w.total));
             int32_t total = 0;
-            HIP_TRY(ctx, launch_pms_format(dp, wbytes, groups, prow, pcnt, nullptr, &total, s));
-            DSLaunch l2 = plan.l;
-            l2.coupling = CK_PMS;
+            HIP_TRY(ctx, launch_pms_format(dp, l2, w, &total, s));
             if (ds_lds_bytes(l2, p.n, total) <= 160 * 1024) {
-                uint16_t *img = nullptr;
-                HIP_TRY(ctx, pool.get("ds.pms.img", (size_t)std::max(total, 1) * 8, (void **)&img));
-                HIP_TRY(ctx, launch_pms_format(dp, wbytes, groups, prow, pcnt, img, &total, s));
+                HIP_TRY(ctx, pool.get("ds.pms.tmp", (size_t)std::max<int64_t>(p.nnz, 1) * 2, (void **)&w.tmp));
+                HIP_TRY(ctx, pool.get("ds.pms.img", (size_t)std::max(total, 1) * 8, (void **)&w.img));
+                HIP_TRY(ctx, launch_pms_format(dp, l2, w, &total, s));
                 plan.l = l2;
-                a.pimg = img;
+                a.pimg = w.img;
                 a.pimg_groups = total;
-                a.prow = prow;
-                a.pcnt = pcnt;
+                a.prow = w.prow;
+                a.pcnt = w.pcnt;
+                a.pperm = w.perm;
+                a.pms_rb = rb;
             }
         }
     }

@@ -104,11 +104,13 @@ struct DSArgs {
     int32_t *best_step = nullptr;
     double *etrace = nullptr, *ltrace = nullptr;
     const void *bias = nullptr;        // 2*steps bias corrections (ADAM), state precision
-    // sign-split LDS image (CK_PMS): 4 uint16 entries per group
-    const void *pimg = nullptr;
+    // staged +-w image (CK_PMS), indexed by thread-layout position q = e * block + thread
+    const void *pimg = nullptr;        // groups of 4 uint16 byte offsets, group-major per wavefront
     int32_t pimg_groups = 0;
-    const int32_t *prow = nullptr;     // first group of each row
-    const uint32_t *pcnt = nullptr;    // n_pos | n_neg << 16
+    const int32_t *prow = nullptr;     // group 0 of position q
+    const uint32_t *pcnt = nullptr;    // degree | wavefront group count << 16
+    const int32_t *pperm = nullptr;    // spin held at position q
+    int32_t pms_rb = 0;                // bytes of one vertex region (pms_region_bytes)
 };
 
 struct DSLaunch {
@@ -129,8 +131,20 @@ hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64,
 int32_t ds_max_n(bool fp64);
 // Build the CK_PMS image; writes the total group count to *total_groups (host,
 // synchronises once).  img may be NULL to only count.
-hipError_t launch_pms_format(const DevProblem &p, int wbytes, int32_t *groups, int32_t *prow, uint32_t *pcnt,
-                             uint16_t *img, int32_t *total_groups, hipStream_t s);
+// Work buffers of the CK_PMS format: deg, pos (n); perm, prow, pcnt (ept * block);
+// tmp (nnz); total (1); img (8 bytes per group, nullptr on the sizing pass).
+struct PmsWork {
+    int32_t *deg = nullptr, *pos = nullptr, *perm = nullptr, *prow = nullptr, *total = nullptr;
+    uint32_t *pcnt = nullptr;
+    uint16_t *tmp = nullptr, *img = nullptr;
+};
+// LDS banks the CK_PMS neighbour order is spread over
+constexpr int kPmsBanks = 32;
+int pms_region_bytes(const DSLaunch &l);
+// Sizing pass (w.img == nullptr): layout tables and the group count (synchronises s).
+// Fill pass: the image.
+hipError_t launch_pms_format(const DevProblem &p, const DSLaunch &l, PmsWork &w, int32_t *total_groups,
+                             hipStream_t s);
 size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups);
 // Batched persistent engine (FP32): workgroup b runs replica group map[b].y of
 // descs[map[b].x]; all descriptors share the launch configuration l.

@@ -22,12 +22,16 @@
 //   CK_PM    all couplings +-w: entries col | (J<0) << 31.  The product counts,
 //            per replica, the neighbours with J_ij s_j = -w by adding
 //            (bit_j xor sign_ij) in packed lanes; y = w (deg - 2 count), exact.
-//   CK_PMS   the same couplings staged in LDS for the whole run: each row's
-//            neighbours split into J > 0 and J < 0 runs (each padded to a
-//            multiple of 4 with a slot whose vertex word is always 0), entries
-//            are 16-bit byte offsets of the neighbour's vertex word, so one
+//   CK_PMS   the same couplings staged in LDS for the whole run.  The vertex
+//            buffer holds each word twice, as is and complemented per
+//            replica, so a neighbour with J < 0 reads the complement and every
 //            neighbour costs one LDS read and one packed add:
-//            count = sum_{J>0} b_j + (n_neg - sum_{J<0} b_j).
+//            count = sum_j word_j(sign).  Rows are placed on threads in order of
+//            decreasing degree, so the 64 rows of a wavefront have nearly equal
+//            degree and share one loop count; a wavefront's entries are stored
+//            group-major (group k of its 64 lanes contiguous), and each row's
+//            neighbours are ordered so that at every read the lanes of a
+//            wavefront tend to hit distinct LDS banks.
 //   CK_CSRV  CSR values in the state precision.
 //   CK_DENSE dense rows in the state precision (small problems).
 #include "internal.hpp"
@@ -162,23 +166,16 @@ __device__ inline void coupling(const DSArgs &a, int i, const typename SpinWord<
     if constexpr (CK == CK_PMS) {
         using T = typename SW::T;
         const unsigned char *sb = (const unsigned char *)sc;
-        const int npos = (int)(cnt & 0xffffu), nneg = (int)(cnt >> 16);
-        const int gp = (npos + 3) >> 2, gn = (nneg + 3) >> 2;
-        uint32_t ap = 0, an = 0;
+        // every lane of a wavefront has the same group count
+        const int G = __builtin_amdgcn_readfirstlane((int)(cnt >> 16));
         const uint2 *q = img + g0;
-        for (int k = 0; k < gp; ++k) {
-            const uint2 v = q[k];
-            ap += (uint32_t)(*(const T *)(sb + (v.x & 0xffffu))) + (uint32_t)(*(const T *)(sb + (v.x >> 16))) +
-                  (uint32_t)(*(const T *)(sb + (v.y & 0xffffu))) + (uint32_t)(*(const T *)(sb + (v.y >> 16)));
+        uint32_t acc = 0;
+        for (int k = 0; k < G; ++k) {
+            const uint2 v = q[64 * k];
+            acc += (uint32_t)(*(const T *)(sb + (v.x & 0xffffu))) + (uint32_t)(*(const T *)(sb + (v.x >> 16))) +
+                   (uint32_t)(*(const T *)(sb + (v.y & 0xffffu))) + (uint32_t)(*(const T *)(sb + (v.y >> 16)));
         }
-        q += gp;
-        for (int k = 0; k < gn; ++k) {
-            const uint2 v = q[k];
-            an += (uint32_t)(*(const T *)(sb + (v.x & 0xffffu))) + (uint32_t)(*(const T *)(sb + (v.x >> 16))) +
-                  (uint32_t)(*(const T *)(sb + (v.y & 0xffffu))) + (uint32_t)(*(const T *)(sb + (v.y >> 16)));
-        }
-        const uint32_t acc = ap + (uint32_t)nneg * SW::ones - an;
-        const int deg = npos + nneg;
+        const int deg = (int)(cnt & 0xffffu);
         const Real w = (Real)a.w;
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
@@ -237,28 +234,59 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
 
     const int n = a.n, B = blockDim.x, tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, NW = B >> 6;
-    const int npad = EPT * B + 1;  // one extra vertex word that stays 0 (padding target)
+    // Vertex buffers, double-buffered by step parity.  CK_PMS: each parity holds
+    // a region of words (position q of the thread layout) and a region of their
+    // per-replica complements, a.pms_rb bytes each, with a zero word at position
+    // EPT*B for padded slots.  Other couplings: npad words per parity, indexed by
+    // spin, word n kept zero.
+    const int npad = EPT * B + 1;
+    const size_t vbytes = CK == CK_PMS ? (size_t)4 * a.pms_rb : (size_t)2 * npad * sizeof(SW);
     SW *sbuf = (SW *)smem;
-    const size_t off = ((size_t)2 * npad * sizeof(SW) + 15) & ~(size_t)15;
+    const size_t off = (vbytes + 15) & ~(size_t)15;
     Real *ep = (Real *)(smem + off);      // [2][NW][RG]
     Real *lp = ep + 2 * NW * RG;          // [2][NW][RG]
     uint32_t *flg = (uint32_t *)(lp + 2 * NW * RG);  // [2]
     uint2 *img = (uint2 *)(smem + ((off + 2 * 2 * NW * RG * sizeof(Real) + 8 + 15) & ~(size_t)15));
     int prow_r[CK == CK_PMS ? EPT : 1];
     uint32_t pcnt_r[CK == CK_PMS ? EPT : 1];
+    int row_r[CK == CK_PMS ? EPT : 1];  // spin held at position e * B + tid
     if constexpr (CK == CK_PMS) {
         const uint2 *src = (const uint2 *)a.pimg;
         for (int q = tid; q < a.pimg_groups; q += B) img[q] = src[q];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int i = e * B + tid;
-            prow_r[e] = i < n ? a.prow[i] : 0;
-            pcnt_r[e] = i < n ? a.pcnt[i] : 0u;
+            const int q = e * B + tid;
+            prow_r[e] = a.prow[q];
+            pcnt_r[e] = a.pcnt[q];
+            row_r[e] = q < n ? a.pperm[q] : 0;
         }
     }
+    auto spin_of = [&](int e) -> int {
+        if constexpr (CK == CK_PMS) return row_r[e];
+        else return e * B + tid;
+    };
+    // vertex buffer of parity par, as the coupling reads it
+    auto vbuf = [&](int par) -> SW * {
+        if constexpr (CK == CK_PMS) return (SW *)(smem + (size_t)par * 2 * a.pms_rb);
+        else return sbuf + par * npad;
+    };
+    auto put = [&](int par, int e, SW word) {
+        SW *S = vbuf(par);
+        if constexpr (CK == CK_PMS) {
+            S[e * B + tid] = word;
+            ((SW *)((unsigned char *)S + a.pms_rb))[e * B + tid] = (SW)(word ^ (SW)SWd::ones);
+        } else {
+            S[e * B + tid] = word;
+        }
+    };
     if (tid == 0) {
-        sbuf[n] = 0;
-        sbuf[npad + n] = 0;
+        if constexpr (CK == CK_PMS) {
+            vbuf(0)[EPT * B] = 0;
+            vbuf(1)[EPT * B] = 0;
+        } else {
+            sbuf[n] = 0;
+            sbuf[npad + n] = 0;
+        }
     }
     const Real *hv = (const Real *)a.h;
     Real *gth = (Real *)a.theta;
@@ -272,7 +300,8 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
 
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        const int i = e * B + tid;
+        const int q = e * B + tid;
+        const int i = spin_of(e);
         SW word = 0;
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
@@ -284,7 +313,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 xs[k] = 0;
                 cs[k] = 1;
             }
-            if (i < n) {
+            if (q < n) {
                 const size_t idx = (size_t)(r0 + r) * n + i;
                 Real t;
                 if (a.init_mode == 0) {
@@ -310,7 +339,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 }
             }
         }
-        if (i < n) sbuf[i] = word;
+        if (q < n) put(0, e, word);
         __builtin_amdgcn_sched_barrier(0);
     }
     if (tid < 2) flg[tid] = 0;
@@ -328,8 +357,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     const bool trace_l = a.ltrace != nullptr;
 
     for (int t = 1; t <= a.steps; ++t) {
-        const SW *sc = sbuf + ((t - 1) & 1) * npad;
-        SW *sn = sbuf + (t & 1) * npad;
+        const SW *sc = vbuf((t - 1) & 1);
         const Real ib1 = adam ? bct[2 * (t - 1)] : (Real)1, ib2 = adam ? bct[2 * (t - 1) + 1] : (Real)1;
         Real Ep[RG], Lp[RG];
 #pragma unroll
@@ -337,8 +365,8 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         uint32_t nxt = 0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int i = e * B + tid;
-            if (i >= n) continue;
+            if (e * B + tid >= n) continue;
+            const int i = spin_of(e);
             Real y[RG];
             if constexpr (CK == CK_PMS) coupling<Real, CK, RG>(a, i, sc, y, img, prow_r[e], pcnt_r[e]);
             else coupling<Real, CK, RG>(a, i, sc, y);
@@ -387,7 +415,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     word |= (SW)(1u << SWd::shift(r));
                 }
             }
-            sn[i] = word;
+            put(t & 1, e, word);
             // keep the scheduler from interleaving elements: bounds live ranges
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -456,8 +484,8 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        const int i = e * B + tid;
-        if (i >= n) continue;
+        if (e * B + tid >= n) continue;
+        const int i = spin_of(e);
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
             const int k = e * RG + r;
@@ -687,64 +715,138 @@ __global__ void k_format(DevProblem p, int packed, uint32_t *pm, Real *val_out, 
 // Sign-split LDS image of +-w couplings: per row, J > 0 neighbours then J < 0
 // neighbours (ascending columns), each run padded to a multiple of 4 with the
 // byte offset of the zero vertex word; entries are byte offsets col * wbytes.
-__global__ void k_pms_count(DevProblem p, int32_t *groups, uint32_t *pcnt) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
-    int np = 0, nn = 0;
-    for (int q = p.row_ptr[i]; q < p.row_ptr[i + 1]; ++q) {
-        double v;
-        if (p.vtype == ISING_I32) v = ((const int32_t *)p.val)[q];
-        else if (p.vtype == ISING_F32) v = ((const float *)p.val)[q];
-        else v = ((const double *)p.val)[q];
-        if (v > 0) ++np;
-        else if (v < 0) ++nn;
-    }
-    pcnt[i] = (uint32_t)np | ((uint32_t)nn << 16);
-    groups[i] = ((np + 3) >> 2) + ((nn + 3) >> 2);
+// ---- staged +-w image (CK_PMS) -------------------------------------------
+
+template <typename V>
+__device__ inline double csr_value(const DevProblem &p, int q) {
+    return (double)((const V *)p.val)[q];
+}
+__device__ inline double csr_value_any(const DevProblem &p, int q) {
+    if (p.vtype == ISING_I32) return csr_value<int32_t>(p, q);
+    if (p.vtype == ISING_F32) return csr_value<float>(p, q);
+    return csr_value<double>(p, q);
 }
 
-// exclusive scan of groups[0..n) into prow[0..n], prow[n] = total
-__global__ __launch_bounds__(1024) void k_pms_scan(int n, const int32_t *groups, int32_t *prow) {
-    __shared__ int part[1024];
-    const int per = (n + 1023) / 1024;
-    const int lo = threadIdx.x * per, hi = min(n, lo + per);
-    int c = 0;
-    for (int i = lo; i < hi; ++i) c += groups[i];
-    part[threadIdx.x] = c;
+// stored nonzero couplings of each row
+__global__ void k_pms_degree(DevProblem p, int32_t *deg) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    int d = 0;
+    for (int q = p.row_ptr[i]; q < p.row_ptr[i + 1]; ++q) d += csr_value_any(p, q) != 0.0;
+    deg[i] = d;
+}
+
+// position of each row in the thread layout: decreasing degree, ties by index
+__global__ __launch_bounds__(256) void k_pms_rank(int n, const int32_t *deg, int32_t *pos, int32_t *perm) {
+    __shared__ int tile[1024];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int di = i < n ? deg[i] : 0;
+    int rank = 0;
+    for (int base = 0; base < n; base += 1024) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < 1024; j += blockDim.x) tile[j] = base + j < n ? deg[base + j] : -1;
+        __syncthreads();
+        const int m = min(1024, n - base);
+        for (int j = 0; j < m; ++j) {
+            const int dj = tile[j];
+            rank += (dj > di) || (dj == di && base + j < i);
+        }
+    }
+    if (i < n) {
+        pos[i] = rank;
+        perm[rank] = i;
+    }
+}
+
+// One workgroup.  Unit u = (e, w) is the wavefront w of element e: positions
+// e * B + 64 w + lane.  Its group count is the largest ceil(deg / 4) of its rows;
+// units are laid out one after another, group-major inside a unit.
+__global__ __launch_bounds__(256) void k_pms_units(int n, int B, int units, const int32_t *deg,
+                                                   const int32_t *perm, int32_t *prow, uint32_t *pcnt,
+                                                   int32_t *total) {
+    __shared__ int gsz[256];
+    const int u = threadIdx.x;
+    const int nw = B / 64;
+    int g = 0;
+    if (u < units) {
+        const int q0 = (u / nw) * B + (u % nw) * 64;
+        for (int l = 0; l < 64; ++l)
+            if (q0 + l < n) g = max(g, (deg[perm[q0 + l]] + 3) >> 2);
+    }
+    gsz[u] = g;
     __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const int v = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    if (u == 0) {
+        int acc = 0;
+        for (int v = 0; v < units; ++v) {
+            const int c = gsz[v];
+            gsz[v] = acc;
+            acc += 64 * c;
+        }
+        *total = acc;
     }
-    int base = part[threadIdx.x] - c;
-    for (int i = lo; i < hi; ++i) {
-        prow[i] = base;
-        base += groups[i];
+    __syncthreads();
+    if (u < units) {
+        const int q0 = (u / nw) * B + (u % nw) * 64;
+        for (int l = 0; l < 64; ++l) {
+            const int q = q0 + l;
+            const int d = q < n ? deg[perm[q]] : 0;
+            prow[q] = gsz[u] + l;
+            pcnt[q] = (uint32_t)d | ((uint32_t)g << 16);
+        }
     }
-    if (threadIdx.x == 1023) prow[n] = part[1023];
 }
 
-__global__ void k_pms_fill(DevProblem p, const int32_t *prow, const uint32_t *pcnt, int wbytes, uint16_t *img) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
-    const int np = (int)(pcnt[i] & 0xffffu), nn = (int)(pcnt[i] >> 16);
-    const uint16_t pad = (uint16_t)(p.n * wbytes);
-    uint16_t *pos = img + (size_t)prow[i] * 4;
-    uint16_t *neg = pos + ((np + 3) >> 2) * 4;
-    int a = 0, b = 0;
-    for (int q = p.row_ptr[i]; q < p.row_ptr[i + 1]; ++q) {
-        double v;
-        if (p.vtype == ISING_I32) v = ((const int32_t *)p.val)[q];
-        else if (p.vtype == ISING_F32) v = ((const float *)p.val)[q];
-        else v = ((const double *)p.val)[q];
-        const uint16_t e = (uint16_t)(p.col[q] * wbytes);
-        if (v > 0) pos[a++] = e;
-        else if (v < 0) neg[b++] = e;
+// One thread per position: the row's entries (byte offset of the neighbour's
+// word, in the complement region when J < 0), ordered so that at slot m lane l
+// prefers LDS bank (l + m) mod nbanks; slots past the degree read the zero word.
+__global__ void k_pms_fill(DevProblem p, int slots, int wbytes, int rb, int nbanks, const int32_t *pos,
+                           const int32_t *perm, const int32_t *prow, const uint32_t *pcnt, uint16_t *tmp,
+                           uint16_t *img) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= slots) return;
+    const int l = q & 63;
+    const int G = (int)(pcnt[q] >> 16), deg = (int)(pcnt[q] & 0xffffu);
+    const uint16_t zero = (uint16_t)(wbytes * slots);
+    uint16_t *out = img + (size_t)prow[q] * 4;
+    if (q >= p.n) {
+        for (int m = 0; m < 4 * G; ++m) out[(size_t)(m >> 2) * 256 + (m & 3)] = zero;
+        return;
     }
-    for (; a < ((np + 3) >> 2) * 4; ++a) pos[a] = pad;
-    for (; b < ((nn + 3) >> 2) * 4; ++b) neg[b] = pad;
+    const int i = perm[q];
+    const int rs = p.row_ptr[i], re = p.row_ptr[i + 1];
+    constexpr uint16_t USED = 0xffffu;
+    for (int e = rs; e < re; ++e) {
+        const double v = csr_value_any(p, e);
+        const int j = p.col[e];
+        tmp[e] = v > 0 ? (uint16_t)(wbytes * pos[j]) : v < 0 ? (uint16_t)(rb + wbytes * pos[j]) : USED;
+    }
+    int cursor = rs;
+    for (int m = 0; m < 4 * G; ++m) {
+        uint16_t pick = zero;
+        if (m < deg) {
+            int best = -1;
+            if (deg <= 256) {
+                const int target = (l + m) & (nbanks - 1);
+                int bd = nbanks;
+                for (int e = rs; e < re; ++e) {
+                    const uint16_t o = tmp[e];
+                    if (o == USED) continue;
+                    const int d = (((o >> 2) & (nbanks - 1)) - target) & (nbanks - 1);
+                    if (d < bd) {
+                        bd = d;
+                        best = e;
+                        if (d == 0) break;
+                    }
+                }
+            } else {
+                while (tmp[cursor] == USED) ++cursor;
+                best = cursor;
+            }
+            pick = tmp[best];
+            tmp[best] = USED;
+        }
+        out[(size_t)(m >> 2) * 256 + (m & 3)] = pick;
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_select(const double *e, int R, int32_t *best) {
@@ -853,12 +955,8 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
     if (l.block % 64 || l.block < 64 || l.block > 1024 || (l.ept > 0 && (int64_t)l.ept * l.block < a.n) ||
         a.R % l.rg)
         return hipErrorInvalidValue;
-    const size_t sw = l.rg == 1 ? 1 : 4;
-    const size_t real = l.fp64 ? 8 : 4;
-    const int nw = l.block / 64;
-    const size_t sbytes = l.ept > 0 ? (size_t)2 * (l.ept * l.block + 1) * sw : (size_t)3 * a.n * sw;
-    size_t lds = ((sbytes + 15) & ~(size_t)15) + 2 * 2 * nw * l.rg * real + 8;
-    if (l.coupling == CK_PMS) lds = ((lds + 15) & ~(size_t)15) + (size_t)8 * a.pimg_groups;
+    if (l.coupling == CK_PMS && a.pms_rb != pms_region_bytes(l)) return hipErrorInvalidValue;
+    const size_t lds = ds_lds_bytes(l, a.n, a.pimg_groups);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -911,16 +1009,30 @@ hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64,
     return hipGetLastError();
 }
 
-hipError_t launch_pms_format(const DevProblem &p, int wbytes, int32_t *groups, int32_t *prow, uint32_t *pcnt,
-                             uint16_t *img, int32_t *total_groups, hipStream_t s) {
+int pms_region_bytes(const DSLaunch &l) {
+    const int wbytes = l.rg == 1 ? 1 : 4;
+    return ((l.ept * l.block + 1) * wbytes + 255) / 256 * 256;
+}
+
+hipError_t launch_pms_format(const DevProblem &p, const DSLaunch &l, PmsWork &w, int32_t *total_groups,
+                             hipStream_t s) {
+    const int slots = l.ept * l.block, units = slots / 64;
+    if (l.ept <= 0 || slots < p.n || units > 256) return hipErrorInvalidValue;
     const dim3 g((p.n + 255) / 256);
-    hipLaunchKernelGGL(k_pms_count, g, dim3(256), 0, s, p, groups, pcnt);
-    hipLaunchKernelGGL(k_pms_scan, dim3(1), dim3(1024), 0, s, p.n, groups, prow);
-    hipError_t e = hipMemcpyAsync(total_groups, prow + p.n, 4, hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
-    if (img) hipLaunchKernelGGL(k_pms_fill, g, dim3(256), 0, s, p, prow, pcnt, wbytes, img);
+    if (!w.img) {
+        hipLaunchKernelGGL(k_pms_degree, g, dim3(256), 0, s, p, w.deg);
+        hipLaunchKernelGGL(k_pms_rank, g, dim3(256), 0, s, p.n, w.deg, w.pos, w.perm);
+        hipLaunchKernelGGL(k_pms_units, dim3(1), dim3(256), 0, s, p.n, l.block, units, w.deg, w.perm, w.prow,
+                           w.pcnt, w.total);
+        hipError_t e = hipMemcpyAsync(total_groups, w.total, 4, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        return hipGetLastError();
+    }
+    const int wbytes = l.rg == 1 ? 1 : 4;
+    hipLaunchKernelGGL(k_pms_fill, dim3((slots + 255) / 256), dim3(256), 0, s, p, slots, wbytes,
+                       pms_region_bytes(l), kPmsBanks, w.pos, w.perm, w.prow, w.pcnt, w.tmp, w.img);
     return hipGetLastError();
 }
 
@@ -928,7 +1040,9 @@ size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups) {
     const size_t sw = l.rg == 1 ? 1 : 4;
     const size_t real = l.fp64 ? 8 : 4;
     const int nw = l.block / 64;
-    const size_t sbytes = l.ept > 0 ? (size_t)2 * (l.ept * l.block + 1) * sw : (size_t)3 * n * sw;
+    size_t sbytes;
+    if (l.coupling == CK_PMS) sbytes = (size_t)4 * pms_region_bytes(l);
+    else sbytes = l.ept > 0 ? (size_t)2 * (l.ept * l.block + 1) * sw : (size_t)3 * n * sw;
     size_t lds = ((sbytes + 15) & ~(size_t)15) + 2 * 2 * nw * l.rg * real + 8;
     if (l.coupling == CK_PMS) lds = ((lds + 15) & ~(size_t)15) + (size_t)8 * pimg_groups;
     return lds;

@@ -13,7 +13,9 @@ tolerance: 30 steps at lr 0.02 in FP32 and 20 steps at lr 6.0 in FP64; its long
 runs are checked through exact properties and the energy statistics.  Energies
 of integer instances are exact on both sides and compared bit for bit.  A
 replica is excluded from later steps only if a vertex sign differs where the
-oracle's |sin theta| < 1e-5 (a legitimate discontinuity); exclusions are counted.
+oracle's |sin theta| < 1e-5 (a legitimate discontinuity); such differences are
+caught at every step through the energy trace and at chunk boundaries through
+the signs, and exclusions are counted.
 """
 import numpy as np
 import pytest
@@ -74,6 +76,17 @@ CASES = [
     ("ragged_n65_r6", lambda: I.random_integer_field(I.erdos_renyi(65, 0.2, 8, "pm1"), 8, 2), 6),
 ]
 
+# Several spins per thread (the register engine beyond 1024 spins): two replicas per
+# word and four spins per thread (n = 3000, 512 replicas), one replica per word and two
+# spins per thread, and real couplings with two spins per thread.  Over 128 compared
+# replicas x 3000 spins the GD map at lr 0.01 grows rounding differences to about
+# 1.2e-5 near its unstable points, so these run at GD lr 0.005.
+MULTI = [
+    ("er3000_rg2_ept4", lambda: I.erdos_renyi(3000, 8.0 / 2999, 9, "pm1"), 512),
+    ("er1500_field_rg1_ept2", lambda: I.random_integer_field(I.erdos_renyi(1500, 0.01, 10, "pm1"), 10, 2), 16),
+    ("t1_real1500_csrv_ept2", lambda: I.table1_regular(1500, 6, "uniform", 6), 16),
+]
+
 
 from gpu_util import compare_trajectories as _compare  # noqa: E402
 
@@ -89,6 +102,12 @@ def test_fp32_iterates(ctx, name, mk, R, opt, lr, steps):
                    uniform=torch.tensor(U, dtype=torch.float32, device="cuda"))
     worst, excl = _compare(inst, got, U, steps, opt, lr, chunks)
     print(f"{name} {opt} lr={lr}: worst iterate error {worst:.2e}, excluded {excl}/{R}")
+
+
+@pytest.mark.parametrize("opt,lr,steps", [("gd", 0.005, 100), ("adam", 0.02, 30)])
+@pytest.mark.parametrize("name,mk,R", MULTI, ids=[c[0] for c in MULTI])
+def test_fp32_iterates_several_spins_per_thread(ctx, name, mk, R, opt, lr, steps):
+    test_fp32_iterates(ctx, name, mk, R, opt, lr, steps)
 
 
 @pytest.mark.parametrize("opt,lr,steps", [("adam", 6.0, 20), ("gd", 0.05, 100)])
