@@ -276,7 +276,6 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
             int32_t total = 0;
             HIP_TRY(ctx, launch_pms_format(dp, l2, w, &total, s));
             if (ds_lds_bytes(l2, p.n, total) <= 160 * 1024) {
-                HIP_TRY(ctx, pool.get("ds.pms.tmp", (size_t)std::max<int64_t>(p.nnz, 1) * 2, (void **)&w.tmp));
                 HIP_TRY(ctx, pool.get("ds.pms.img", (size_t)std::max(total, 1) * 8, (void **)&w.img));
                 HIP_TRY(ctx, launch_pms_format(dp, l2, w, &total, s));
                 plan.l = l2;

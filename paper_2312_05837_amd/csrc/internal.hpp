@@ -132,14 +132,12 @@ int32_t ds_max_n(bool fp64);
 // Build the CK_PMS image; writes the total group count to *total_groups (host,
 // synchronises once).  img may be NULL to only count.
 // Work buffers of the CK_PMS format: deg, pos (n); perm, prow, pcnt (ept * block);
-// tmp (nnz); total (1); img (8 bytes per group, nullptr on the sizing pass).
+// total (1); img (8 bytes per group, nullptr on the sizing pass).
 struct PmsWork {
     int32_t *deg = nullptr, *pos = nullptr, *perm = nullptr, *prow = nullptr, *total = nullptr;
     uint32_t *pcnt = nullptr;
-    uint16_t *tmp = nullptr, *img = nullptr;
+    uint16_t *img = nullptr;
 };
-// LDS banks the CK_PMS neighbour order is spread over
-constexpr int kPmsBanks = 32;
 int pms_region_bytes(const DSLaunch &l);
 // Sizing pass (w.img == nullptr): layout tables and the group count (synchronises s).
 // Fill pass: the image.

@@ -796,57 +796,107 @@ __global__ __launch_bounds__(256) void k_pms_units(int n, int B, int units, cons
     }
 }
 
-// One thread per position: the row's entries (byte offset of the neighbour's
-// word, in the complement region when J < 0), ordered so that at slot m lane l
-// prefers LDS bank (l + m) mod nbanks; slots past the degree read the zero word.
-__global__ void k_pms_fill(DevProblem p, int slots, int wbytes, int rb, int nbanks, const int32_t *pos,
-                           const int32_t *perm, const int32_t *prow, const uint32_t *pcnt, uint16_t *tmp,
-                           uint16_t *img) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= slots) return;
-    const int l = q & 63;
-    const int G = (int)(pcnt[q] >> 16), deg = (int)(pcnt[q] & 0xffffu);
+// Neighbour order of the staged image.  The LDS serves a wavefront's reads in two
+// halves of 32 lanes over 32 banks, so each half-wavefront of rows is scheduled on
+// its own (workgroup 2u + h: rows 32h .. 32h + 31 of unit u).  Slot by slot and
+// row by row, a row takes the remaining entry that costs least given the words
+// the earlier rows of its half already read at that slot: nothing if it is the
+// same word (a broadcast), else the number of distinct words already in its bank;
+// ties go to the lowest remaining index.  Row j at slot m depends only on row j
+// at slot m - 1 and rows < j at slot m, so the pairs (j, m) are taken along
+// anti-diagonals j + m = d, all rows of a diagonal at once, with the bank state
+// kept per slot.  An entry is the byte offset of the neighbour's word, in the
+// complement region when J < 0; slots past a row's degree read the zero word.
+// Rows with more than kPmsSchedMax entries keep CSR order.
+constexpr int kPmsSchedMax = 128;
+
+__global__ __launch_bounds__(256) void k_pms_fill(DevProblem p, int slots, int block, int wbytes, int rb,
+                                                  const int32_t *pos, const int32_t *perm, const int32_t *prow,
+                                                  const uint32_t *pcnt, uint16_t *img) {
+    __shared__ uint16_t ent[32][kPmsSchedMax];    // remaining entries of each row
+    __shared__ int rem[32];                        // their count (-1: row kept in CSR order)
+    __shared__ uint32_t bank_words[kPmsSchedMax][32];  // per slot and bank: first two distinct words
+    __shared__ uint8_t bank_count[kPmsSchedMax][32];   // and the number of distinct words
+    __shared__ uint16_t res[kPmsSchedMax][32];     // entry chosen for each slot and row
+    const int nw = block / 64, u = blockIdx.x >> 1, h = blockIdx.x & 1;
+    const int q0 = (u / nw) * block + (u % nw) * 64 + 32 * h;  // first position of this half
+    const int t = threadIdx.x, j = t >> 3, s = t & 7;          // 8 lanes per row
+    const int G = (int)(pcnt[q0] >> 16);
+    const int S = min(4 * G, kPmsSchedMax);
     const uint16_t zero = (uint16_t)(wbytes * slots);
-    uint16_t *out = img + (size_t)prow[q] * 4;
-    if (q >= p.n) {
-        for (int m = 0; m < 4 * G; ++m) out[(size_t)(m >> 2) * 256 + (m & 3)] = zero;
-        return;
-    }
-    const int i = perm[q];
-    const int rs = p.row_ptr[i], re = p.row_ptr[i + 1];
-    constexpr uint16_t USED = 0xffffu;
-    for (int e = rs; e < re; ++e) {
-        const double v = csr_value_any(p, e);
-        const int j = p.col[e];
-        tmp[e] = v > 0 ? (uint16_t)(wbytes * pos[j]) : v < 0 ? (uint16_t)(rb + wbytes * pos[j]) : USED;
-    }
-    int cursor = rs;
-    for (int m = 0; m < 4 * G; ++m) {
-        uint16_t pick = zero;
-        if (m < deg) {
-            int best = -1;
-            if (deg <= 256) {
-                const int target = (l + m) & (nbanks - 1);
-                int bd = nbanks;
-                for (int e = rs; e < re; ++e) {
-                    const uint16_t o = tmp[e];
-                    if (o == USED) continue;
-                    const int d = (((o >> 2) & (nbanks - 1)) - target) & (nbanks - 1);
-                    if (d < bd) {
-                        bd = d;
-                        best = e;
-                        if (d == 0) break;
-                    }
+    const int q = q0 + j;
+    uint16_t *out = img + (size_t)prow[q] * 4;  // slot m at out[(m / 4) * 256 + m % 4]
+    // stage each row's nonzero entries in CSR order; rows too long are written here directly
+    {
+        int d = 0;
+        const int deg = q < p.n ? (int)(pcnt[q] & 0xffffu) : 0;
+        if (q < p.n) {
+            const int i = perm[q];
+            const int rs = p.row_ptr[i], re = p.row_ptr[i + 1];
+            for (int c = rs; c < re; c += 8) {
+                const int e = c + s;
+                double v = 0.0;
+                uint16_t o = 0;
+                if (e < re) {
+                    v = csr_value_any(p, e);
+                    o = v > 0 ? (uint16_t)(wbytes * pos[p.col[e]]) : (uint16_t)(rb + wbytes * pos[p.col[e]]);
                 }
-            } else {
-                while (tmp[cursor] == USED) ++cursor;
-                best = cursor;
+                const uint32_t grp = (uint32_t)(__ballot(v != 0.0) >> (t & 56)) & 0xffu;
+                const int k = d + __popc(grp & ((1u << s) - 1u));
+                if (v != 0.0) {
+                    if (deg <= kPmsSchedMax) ent[j][k] = o;
+                    else out[(size_t)(k >> 2) * 256 + (k & 3)] = o;
+                }
+                d += __popc(grp);
             }
-            pick = tmp[best];
-            tmp[best] = USED;
+            if (deg > kPmsSchedMax)
+                for (int m = d + s; m < 4 * G; m += 8) out[(size_t)(m >> 2) * 256 + (m & 3)] = zero;
         }
-        out[(size_t)(m >> 2) * 256 + (m & 3)] = pick;
+        if (s == 0) rem[j] = deg > kPmsSchedMax ? -1 : d;
     }
+    for (int x = t; x < S * 32; x += 256) bank_count[x >> 5][x & 31] = 0;
+    __syncthreads();
+    for (int dg = 0; dg < 32 + S - 1; ++dg) {
+        const int m = dg - j;
+        const int r = rem[j];
+        const bool act = m >= 0 && m < S && r >= 0;
+        uint32_t key = 0xffffffffu;
+        if (act) {
+            for (int e = s; e < r; e += 8) {
+                const uint16_t o = ent[j][e];
+                const int b = (o >> 2) & 31;
+                const uint32_t c = bank_count[m][b], w = bank_words[m][b];
+                const bool same = (c >= 1 && o == (w & 0xffffu)) || (c >= 2 && o == (w >> 16));
+                key = min(key, ((same ? 0u : c) << 16) | (uint32_t)e);
+            }
+        }
+        // minimum over the row's 8 lanes (an aligned half-row)
+        key = min(key, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)key, 0xB1, 0xF, 0xF, false));
+        key = min(key, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)key, 0x4E, 0xF, 0xF, false));
+        key = min(key, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)key, 0x141, 0xF, 0xF, false));
+        if (act && s == 0) {
+            uint16_t o = zero;
+            if (r > 0) {
+                const int e = (int)(key & 0xffffu);
+                o = ent[j][e];
+                ent[j][e] = ent[j][r - 1];
+                rem[j] = r - 1;
+                const int b = (o >> 2) & 31;
+                const uint32_t c = bank_count[m][b], w = bank_words[m][b];
+                const bool same = (c >= 1 && o == (w & 0xffffu)) || (c >= 2 && o == (w >> 16));
+                if (!same) {
+                    if (c == 0) bank_words[m][b] = o;
+                    else if (c == 1) bank_words[m][b] = w | ((uint32_t)o << 16);
+                    bank_count[m][b] = (uint8_t)min(c + 1, 255u);
+                }
+            }
+            res[m][j] = o;
+        }
+        __syncthreads();
+    }
+    // scheduled rows: slots past kPmsSchedMax (only when a long row set the unit's length) are zero
+    if (rem[j] >= 0)
+        for (int m = s; m < 4 * G; m += 8) out[(size_t)(m >> 2) * 256 + (m & 3)] = m < S ? res[m][j] : zero;
 }
 
 __global__ __launch_bounds__(1024) void k_select(const double *e, int R, int32_t *best) {
@@ -1031,8 +1081,8 @@ hipError_t launch_pms_format(const DevProblem &p, const DSLaunch &l, PmsWork &w,
         return hipGetLastError();
     }
     const int wbytes = l.rg == 1 ? 1 : 4;
-    hipLaunchKernelGGL(k_pms_fill, dim3((slots + 255) / 256), dim3(256), 0, s, p, slots, wbytes,
-                       pms_region_bytes(l), kPmsBanks, w.pos, w.perm, w.prow, w.pcnt, w.tmp, w.img);
+    hipLaunchKernelGGL(k_pms_fill, dim3(2 * units), dim3(256), 0, s, p, slots, l.block, wbytes, pms_region_bytes(l),
+                       w.pos, w.perm, w.prow, w.pcnt, w.img);
     return hipGetLastError();
 }
 

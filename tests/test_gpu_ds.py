@@ -81,8 +81,21 @@ CASES = [
 # spins per thread, and real couplings with two spins per thread.  Over 128 compared
 # replicas x 3000 spins the GD map at lr 0.01 grows rounding differences to about
 # 1.2e-5 near its unstable points, so these run at GD lr 0.005.
+def _hub_graph(n=600, hub_deg=300, seed=12):
+    """ER graph plus one vertex joined to hub_deg others: a row far longer than the
+    rest, so one wavefront of the staged image has a long loop and a row kept in
+    CSR order."""
+    rng = np.random.default_rng(seed)
+    er = I.erdos_renyi(n, 0.02, seed, "pm1")
+    edges = [(i, int(er.col[q]), int(er.val[q])) for i in range(n) for q in range(er.row_ptr[i], er.row_ptr[i + 1])
+             if er.col[q] > i]
+    edges += [(n, int(j), int(rng.choice([-1, 1]))) for j in rng.choice(n, size=hub_deg, replace=False)]
+    return I.from_edges(n + 1, edges, np.zeros(n + 1), "er600_plus_hub300")
+
+
 MULTI = [
     ("er3000_rg2_ept4", lambda: I.erdos_renyi(3000, 8.0 / 2999, 9, "pm1"), 512),
+    ("hub_rg2", _hub_graph, 512),
     ("er1500_field_rg1_ept2", lambda: I.random_integer_field(I.erdos_renyi(1500, 0.01, 10, "pm1"), 10, 2), 16),
     ("t1_real1500_csrv_ept2", lambda: I.table1_regular(1500, 6, "uniform", 6), 16),
 ]
