@@ -82,31 +82,35 @@ struct Consts<double> {
     static constexpr double inv_twopi = 0.15915494309189533577;
 };
 
-// sin and cos of |x| <= 4 in float: quadrant k = rint(x 2/pi), reduction
-// r = x - k pi/2 with pi/2 split in three parts (each step one FMA, Cody-Waite
-// style), then Taylor polynomials on |r| <= pi/4 (sin to r^9, cos to r^10: the
-// truncation is below 2e-9) evaluated by Horner's rule, and the quadrant
-// symmetries.  Angles here are always wrapped to [-pi, pi].
+// minimax coefficients (rounded to float) of sin r = r + r^3 (C1 + C2 z + C3 z^2) and
+// cos r = 1 + z (C1 + C2 z + C3 z^2 + C4 z^3), z = r^2, |r| <= pi/4
+constexpr float SIN_C1 = -1.666666716e-01f, SIN_C2 = 8.332728408e-03f, SIN_C3 = -1.957433851e-04f;
+constexpr float COS_C1 = -5.000000000e-01f, COS_C2 = 4.166666791e-02f, COS_C3 = -1.388838165e-03f, COS_C4 = 2.455472713e-05f;
+
+// sin and cos of |x| <= 5 pi / 4 in float (angles here are wrapped to [-pi, pi]):
+// quadrant k = rint(x 2/pi) in {-2, ..., 2}, reduction r = x - k pi/2 with pi/2 split
+// in three parts (each step one FMA, Cody-Waite style), polynomials in z = r^2 on
+// |r| <= pi/4 whose coefficients minimise the maximum error of sin (relative) and
+// cos (absolute) over that interval (about 9e-9 and 1e-9, below float rounding),
+// then the rotation by k pi/2: cos(k pi/2) = 1 - |k| and sin(k pi/2) = k (2 - |k|)
+// for |k| <= 2, so both results are one exact product plus one FMA.
 __device__ inline void dsincos(float x, float *s, float *c) {
     const float k = rintf(x * 0.636619772367581343f);
     float r = __builtin_fmaf(-k, 1.57079637050628662f, x);
     r = __builtin_fmaf(-k, -4.37113882867379300e-08f, r);
     r = __builtin_fmaf(-k, -1.71512451000588190e-15f, r);
-    const float r2 = r * r;
-    float ps = __builtin_fmaf(r2, 2.75573192239858907e-06f, -1.98412698412698413e-04f);
-    ps = __builtin_fmaf(r2, ps, 8.33333333333333333e-03f);
-    ps = __builtin_fmaf(r2, ps, -1.66666666666666667e-01f);
-    const float sn = __builtin_fmaf(r * r2, ps, r);
-    float pc = __builtin_fmaf(r2, -2.75573192239858907e-07f, 2.48015873015873016e-05f);
-    pc = __builtin_fmaf(r2, pc, -1.38888888888888889e-03f);
-    pc = __builtin_fmaf(r2, pc, 4.16666666666666667e-02f);
-    pc = __builtin_fmaf(r2, pc, -0.5f);
-    const float cn = __builtin_fmaf(r2, pc, 1.0f);
-    const int q = (int)k & 3;
-    const float a = (q & 1) ? cn : sn;
-    const float b = (q & 1) ? sn : cn;
-    *s = (q & 2) ? -a : a;
-    *c = ((q + 1) & 2) ? -b : b;
+    const float z = r * r;
+    float ps = __builtin_fmaf(z, SIN_C3, SIN_C2);
+    ps = __builtin_fmaf(z, ps, SIN_C1);
+    const float sn = __builtin_fmaf(r * z, ps, r);
+    float pc = __builtin_fmaf(z, COS_C4, COS_C3);
+    pc = __builtin_fmaf(z, pc, COS_C2);
+    pc = __builtin_fmaf(z, pc, COS_C1);
+    const float cn = __builtin_fmaf(z, pc, 1.0f);
+    const float ck = 1.0f - __builtin_fabsf(k);
+    const float sk = k * (2.0f - __builtin_fabsf(k));
+    *s = __builtin_fmaf(sk, cn, ck * sn);
+    *c = __builtin_fmaf(-sk, sn, ck * cn);
 }
 __device__ inline void dsincos(double x, double *s, double *c) { sincos(x, s, c); }
 __device__ inline float dsin(float x) {
@@ -318,6 +322,11 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 Real t;
                 if (a.init_mode == 0) {
                     t = gth[idx];
+                    if (t > (Real)3.5 || t < (Real)-3.5) {  // angles this engine wrote are within pi
+                        const Real qw = drint(t * Consts<Real>::inv_twopi);
+                        t = t - qw * Consts<Real>::twopi_hi;
+                        t = t - qw * Consts<Real>::twopi_lo;
+                    }
                     if (gm) mo[k] = gm[idx];
                     if (gv) ve[k] = gv[idx];
                     if (a.s_best[idx] < 0) best |= 1u << k;
@@ -359,9 +368,10 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     for (int t = 1; t <= a.steps; ++t) {
         const SW *sc = vbuf((t - 1) & 1);
         const Real ib1 = adam ? bct[2 * (t - 1)] : (Real)1, ib2 = adam ? bct[2 * (t - 1) + 1] : (Real)1;
+        const Real lib1 = lr * ib1;
         Real Ep[RG], Lp[RG];
 #pragma unroll
-        for (int r = 0; r < RG; ++r) Ep[r] = Lp[r] = 0;
+        for (int r = 0; r < RG; ++r) Ep[r] = Lp[r] = (Real)-0.0;  // x + (-0) = x: no add for the first term
         uint32_t nxt = 0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
@@ -375,10 +385,6 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
 #pragma unroll
             for (int r = 0; r < RG; ++r) {
                 const int k = e * RG + r;
-                const bool neg = (cur >> k) & 1u;
-                const Real yh = y[r] + hh;
-                Ep[r] += neg ? -yh : yh;
-                const Real tt = neg ? yh + mu : yh - mu;
                 Real x, c;
                 if (KEEP) {
                     x = xs[k];
@@ -386,13 +392,18 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 } else {
                     dsincos(th[k], &x, &c);
                 }
-                Lp[r] += x * tt;
+                // s = sgn(sin theta) as +-1 (the vertex bit k of cur); products with it are exact
+                const Real sg = x < 0 ? (Real)-1 : (Real)1;
+                const Real yh = y[r] + hh;
+                Ep[r] = __builtin_fma(sg, yh, Ep[r]);
+                const Real tt = __builtin_fma(-mu, sg, yh);  // y - mu s + h
+                Lp[r] = __builtin_fma(x, tt, Lp[r]);
                 const Real g = c * tt;
                 Real upd;
                 if (adam) {
                     mo[k] = b1 * mo[k] + omb1 * g;
                     ve[k] = b2 * ve[k] + omb2 * (g * g);
-                    upd = lr * (mo[k] * ib1) * drcp(dsqrt(ve[k] * ib2) + eps);
+                    upd = (mo[k] * lib1) * drcp(dsqrt(ve[k] * ib2) + eps);
                 } else {
                     upd = lr * g;
                 }
@@ -550,6 +561,12 @@ __global__ __launch_bounds__(1024) void k_ds_stream(const DSArgs a) {
             Real t;
             if (a.init_mode == 0) {
                 t = gth[idx];
+                if (t > (Real)3.5 || t < (Real)-3.5) {  // angles this engine wrote are within pi
+                    const Real qw = drint(t * Consts<Real>::inv_twopi);
+                    t = t - qw * Consts<Real>::twopi_hi;
+                    t = t - qw * Consts<Real>::twopi_lo;
+                    gth[idx] = t;  // the steps read the angle back from memory
+                }
             } else {
                 const Real u = a.init_mode == 1 ? ((const Real *)a.uniform)[idx]
                                                 : draw_uniform<Real>(a.seed, r0 + r, i);
