@@ -258,21 +258,21 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             }
         }
     } else {
-        u16x8 pah[2], pal[2], pb[2];
-        auto gload = [&](int k0) {
+        // two chunks in flight in registers (sets 0 and 1 alternate), one in LDS
+        u16x8 pah[2][2], pal[2][2], pb[2][2];
+        auto gload = [&](int set, int k0) {
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int q = tid + 256 * u;
                 const int r = q >> 2, c8 = (q & 3) * 8;
-                pah[u] = *(const u16x8 *)(a.Jhi + (size_t)(row0 + r) * a.Kp + k0 + c8);
-                if (FORM == DF_BF16X2) pal[u] = *(const u16x8 *)(a.Jlo + (size_t)(row0 + r) * a.Kp + k0 + c8);
-                pb[u] = (col0 + r < a.R)
-                            ? *(const u16x8 *)((const unsigned short *)S_in + (size_t)(col0 + r) * a.Kp + k0 + c8)
-                            : u16x8{};
+                pah[set][u] = *(const u16x8 *)(a.Jhi + (size_t)(row0 + r) * a.Kp + k0 + c8);
+                if (FORM == DF_BF16X2) pal[set][u] = *(const u16x8 *)(a.Jlo + (size_t)(row0 + r) * a.Kp + k0 + c8);
+                pb[set][u] = (col0 + r < a.R)
+                                 ? *(const u16x8 *)((const unsigned short *)S_in + (size_t)(col0 + r) * a.Kp + k0 + c8)
+                                 : u16x8{};
             }
         };
-        gload(0);
-        for (int c = 0; c < nchunks; ++c) {
+        auto chunk = [&](int c, int set) {
             unsigned short *Ah = (unsigned short *)lds + (c & 1) * (2 * BM + BN) * AST;
             unsigned short *Al = Ah + BM * AST;
             unsigned short *Bs = Al + BM * AST;
@@ -280,12 +280,12 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             for (int u = 0; u < 2; ++u) {
                 const int q = tid + 256 * u;
                 const int r = q >> 2, c8 = (q & 3) * 8;
-                *(u16x8 *)(Ah + r * AST + c8) = pah[u];
-                if (FORM == DF_BF16X2) *(u16x8 *)(Al + r * AST + c8) = pal[u];
-                *(u16x8 *)(Bs + r * AST + c8) = pb[u];
+                *(u16x8 *)(Ah + r * AST + c8) = pah[set][u];
+                if (FORM == DF_BF16X2) *(u16x8 *)(Al + r * AST + c8) = pal[set][u];
+                *(u16x8 *)(Bs + r * AST + c8) = pb[set][u];
             }
             __syncthreads();
-            if (c + 1 < nchunks) gload((c + 1) * KC);
+            if (c + 2 < nchunks) gload(set, (c + 2) * KC);
 #pragma unroll
             for (int ks = 0; ks < KC; ks += 16) {
                 const int kk = ks + 8 * (lane >> 5);
@@ -310,6 +310,12 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                         acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bv[bj], acc[bi][bj], 0, 0, 0);
                     }
             }
+        };
+        gload(0, 0);
+        if (nchunks > 1) gload(1, KC);
+        for (int c = 0; c < nchunks; c += 2) {
+            chunk(c, 0);
+            if (c + 1 < nchunks) chunk(c + 1, 1);
         }
     }
     __syncthreads();  // the epilogue reuses LDS
@@ -327,6 +333,36 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
     float h4[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) h4[u] = (a.h && i0 + u < a.n) ? a.h[i0 + u] : 0.f;
+    // the state of the next (half, k) is loaded before the current one is updated, so
+    // that each load's latency overlaps a step of work
+    float nth[4], nmo[4], nve[4];
+    auto load_state = [&](int half, int k) {
+        const int r = col0 + half * 64 + (tid >> 5) + 8 * k;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) nth[u] = nmo[u] = nve[u] = 0.f;
+        if (r < a.R && i0 < a.n) {
+            const size_t base = (size_t)r * a.n + i0;
+            if (vec) {
+                const float4 t4 = *(const float4 *)(a.theta + base);
+                nth[0] = t4.x; nth[1] = t4.y; nth[2] = t4.z; nth[3] = t4.w;
+                if (adam) {
+                    const float4 m4 = *(const float4 *)(a.m + base);
+                    const float4 v4 = *(const float4 *)(a.v + base);
+                    nmo[0] = m4.x; nmo[1] = m4.y; nmo[2] = m4.z; nmo[3] = m4.w;
+                    nve[0] = v4.x; nve[1] = v4.y; nve[2] = v4.z; nve[3] = v4.w;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = i0 + u < a.n;
+                    nth[u] = ok ? a.theta[base + u] : 0.f;
+                    nmo[u] = (ok && adam) ? a.m[base + u] : 0.f;
+                    nve[u] = (ok && adam) ? a.v[base + u] : 0.f;
+                }
+            }
+        }
+    };
+    load_state(0, 0);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         if (wn == half) {
@@ -346,30 +382,20 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
         for (int k = 0; k < 8; ++k) {
             const int rl = (tid >> 5) + 8 * k;        // replica within this half
             const int r = col0 + half * 64 + rl;
+            float th[4], mo[4], ve[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                th[u] = nth[u];
+                mo[u] = nmo[u];
+                ve[u] = nve[u];
+            }
+            if (k < 7) load_state(half, k + 1);
+            else if (half == 0) load_state(1, 0);
             float Ep = 0.f, Lp = 0.f;
             if (r < a.R && i0 < a.n) {
                 const float4 y4 = *(const float4 *)(T + rl * TST + 4 * g);
                 const float yv[4] = {y4.x, y4.y, y4.z, y4.w};
                 const size_t base = (size_t)r * a.n + i0;
-                float th[4], mo[4], ve[4];
-                if (vec) {
-                    const float4 t4 = *(const float4 *)(a.theta + base);
-                    th[0] = t4.x; th[1] = t4.y; th[2] = t4.z; th[3] = t4.w;
-                    if (adam) {
-                        const float4 m4 = *(const float4 *)(a.m + base);
-                        const float4 v4 = *(const float4 *)(a.v + base);
-                        mo[0] = m4.x; mo[1] = m4.y; mo[2] = m4.z; mo[3] = m4.w;
-                        ve[0] = v4.x; ve[1] = v4.y; ve[2] = v4.z; ve[3] = v4.w;
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const bool ok = i0 + u < a.n;
-                        th[u] = ok ? a.theta[base + u] : 0.f;
-                        mo[u] = (ok && adam) ? a.m[base + u] : 0.f;
-                        ve[u] = (ok && adam) ? a.v[base + u] : 0.f;
-                    }
-                }
                 unsigned short sb[4];
                 float sf[4];
 #pragma unroll
@@ -472,17 +498,49 @@ __global__ __launch_bounds__(256) void k_dense_best(const DenseDesc *__restrict_
     const int r = qd.y * 4 + (threadIdx.x >> 6);
     if (r >= a.R) return;
     const void *S_t = (const void *)(((tloc - 1) & 1) ? a.S1 : a.S0);
+    // row-tile partials loaded by the lanes together, summed in ascending tile order
     float E = 0.f, L = 0.f;
-    for (int t = 0; t < a.mtiles; ++t) {
-        E += a.Epart[(size_t)t * a.R + r];
-        if (a.ltrace) L += a.Lpart[(size_t)t * a.R + r];
+    for (int t0 = 0; t0 < a.mtiles; t0 += 64) {
+        const int t = t0 + lane;
+        const float ev = t < a.mtiles ? a.Epart[(size_t)t * a.R + r] : 0.f;
+        const float lv = (a.ltrace && t < a.mtiles) ? a.Lpart[(size_t)t * a.R + r] : 0.f;
+        const int m = min(64, a.mtiles - t0);
+        for (int j = 0; j < m; ++j) {
+            E += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, ev), j));
+            L += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lv), j));
+        }
     }
     const bool imp = (double)E < a.e_best[r];
     if (imp) {
-        for (int i = lane; i < a.n; i += 64) {
-            const float sv = form == DF_FP32 ? ((const float *)S_t)[(size_t)r * a.Kp + i]
-                                             : bf16_to_f(((const unsigned short *)S_t)[(size_t)r * a.Kp + i]);
-            a.s_best[(size_t)r * a.n + i] = sv < 0.f ? (int8_t)-1 : (int8_t)1;
+        const size_t src = (size_t)r * a.Kp, dst = (size_t)r * a.n;
+        if ((a.n & 7) == 0) {
+            // 8 spins per lane and iteration: 16 (BF16) or 32 (FP32) bytes in, 8 bytes out
+            for (int i = 8 * lane; i < a.n; i += 512) {
+                float sv[8];
+                if (form == DF_FP32) {
+                    const float4 p0 = *(const float4 *)((const float *)S_t + src + i);
+                    const float4 p1 = *(const float4 *)((const float *)S_t + src + i + 4);
+                    sv[0] = p0.x; sv[1] = p0.y; sv[2] = p0.z; sv[3] = p0.w;
+                    sv[4] = p1.x; sv[5] = p1.y; sv[6] = p1.z; sv[7] = p1.w;
+                } else {
+                    const u16x8 p8 = *(const u16x8 *)((const unsigned short *)S_t + src + i);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) sv[u] = bf16_to_f(p8[u]);
+                }
+                uint32_t lo = 0, hi = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    lo |= (uint32_t)(uint8_t)(sv[u] < 0.f ? -1 : 1) << (8 * u);
+                    hi |= (uint32_t)(uint8_t)(sv[u + 4] < 0.f ? -1 : 1) << (8 * u);
+                }
+                *(uint2 *)(a.s_best + dst + i) = make_uint2(lo, hi);
+            }
+        } else {
+            for (int i = lane; i < a.n; i += 64) {
+                const float sv = form == DF_FP32 ? ((const float *)S_t)[src + i]
+                                                 : bf16_to_f(((const unsigned short *)S_t)[src + i]);
+                a.s_best[dst + i] = sv < 0.f ? (int8_t)-1 : (int8_t)1;
+            }
         }
     }
     if (lane == 0) {
