@@ -18,6 +18,27 @@ __device__ inline double load_val(const void *p, int vtype, int64_t k) {
 
 __device__ inline bool is_integral(double x) { return x == rint(x) && fabs(x) < 9.0e15; }
 
+// Combine one thread's findings over the workgroup and publish them with at most
+// one atomic per flag and workgroup (every thread of the workgroup must call it).
+__device__ void publish_flags(int bits, int deg, bool uni, bool integ, int32_t *flags) {
+    __shared__ int s_bits, s_deg;
+    if (threadIdx.x == 0) {
+        s_bits = 0;
+        s_deg = 0;
+    }
+    __syncthreads();
+    if (bits) atomicOr(&s_bits, bits);
+    if (deg > 0) atomicMax(&s_deg, deg);
+    const bool any_nonuni = __syncthreads_or(!uni);
+    const bool any_nonint = __syncthreads_or(!integ);
+    if (threadIdx.x == 0) {
+        if (s_bits) atomicOr(&flags[0], s_bits);
+        if (s_deg > 0) atomicMax(&flags[1], s_deg);
+        if (any_nonuni) atomicAnd(&flags[2], 0);
+        if (any_nonint) atomicAnd(&flags[3], 0);
+    }
+}
+
 // flags: [0] error bits, [1] max degree (atomicMax), [2] uniform magnitude (cleared on mismatch),
 // [3] integral (cleared on a non-integral value)
 // One 32 x 32 tile (bi, bj) with bi <= bj per workgroup: the tile and its mirror
@@ -66,9 +87,7 @@ __global__ __launch_bounds__(256) void validate_dense(DevProblem p, double w0, i
             }
         }
     }
-    if (bits) atomicOr(&flags[0], bits);
-    if (!uni) atomicAnd(&flags[2], 0);
-    if (!integ) atomicAnd(&flags[3], 0);
+    publish_flags(bits, 0, uni, integ, flags);
 }
 
 __global__ void dense_degree(DevProblem p, int32_t *flags) {
@@ -76,24 +95,27 @@ __global__ void dense_degree(DevProblem p, int32_t *flags) {
     const int n = p.n;
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (row >= n) return;
     int c = 0;
-    for (int j = lane; j < n; j += 64)
-        c += load_val(p.J, p.vtype, (int64_t)row * n + j) != 0.0;
+    if (row < n)
+        for (int j = lane; j < n; j += 64)
+            c += load_val(p.J, p.vtype, (int64_t)row * n + j) != 0.0;
     for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d);
-    if (lane == 0) atomicMax(&flags[1], c);
+    publish_flags(0, lane == 0 ? c : 0, true, true, flags);
 }
 
 __global__ void validate_csr(DevProblem p, double w0, int32_t *flags) {
     const int n = p.n;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     int bits = 0;
     bool uni = true, integ = true;
-    const int rs = p.row_ptr[i], re = p.row_ptr[i + 1];
-    if (rs < 0 || re < rs || re > p.nnz) {
-        atomicOr(&flags[0], 4);
-        return;
+    int rs = 0, re = 0;
+    if (i < n) {
+        rs = p.row_ptr[i];
+        re = p.row_ptr[i + 1];
+        if (rs < 0 || re < rs || re > p.nnz) {
+            bits = 4;
+            rs = re = 0;
+        }
     }
     int prev = -1;
     for (int k = rs; k < re; ++k) {
@@ -127,18 +149,19 @@ __global__ void validate_csr(DevProblem p, double w0, int32_t *flags) {
         }
         if (found < 0 || load_val(p.val, p.vtype, found) != a) bits |= 1;
     }
-    if (bits) atomicOr(&flags[0], bits);
-    atomicMax(&flags[1], re - rs);
-    if (!uni) atomicAnd(&flags[2], 0);
-    if (!integ) atomicAnd(&flags[3], 0);
+    publish_flags(bits, re - rs, uni, integ, flags);
 }
 
 __global__ void validate_h(DevProblem p, int32_t *flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n || p.h == nullptr) return;
-    const double a = load_val(p.h, p.vtype, i);
-    if (!isfinite(a)) atomicOr(&flags[0], 8);
-    if (!is_integral(a)) atomicAnd(&flags[3], 0);
+    int bits = 0;
+    bool integ = true;
+    if (i < p.n && p.h != nullptr) {
+        const double a = load_val(p.h, p.vtype, i);
+        if (!isfinite(a)) bits = 8;
+        if (!is_integral(a)) integ = false;
+    }
+    publish_flags(bits, 0, true, integ, flags);
 }
 
 __global__ void first_magnitude(DevProblem p, double *w) {
