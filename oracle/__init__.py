@@ -27,13 +27,13 @@ itself, which the paper pins only through the identities those tests check.
 """
 from .energy import energy, energies, cut_value, brute_force_min, local_fields
 from .prune import prune, unprune, PruneResult, fixed_order_abs_rowsum
-from .ds import ds_run, ds_loss, ds_grad, wrap_angle, DSResult
+from .ds import ds_run, ds_loss, ds_grad, ds_loss_relaxed, ds_grad_relaxed, wrap_angle, DSResult
 from .metrics import pruning_rate, chi_hat, tts_hat, speed
 from .solve import solve
 
 __all__ = [
     "energy", "energies", "cut_value", "brute_force_min", "local_fields",
     "prune", "unprune", "PruneResult", "fixed_order_abs_rowsum",
-    "ds_run", "ds_loss", "ds_grad", "wrap_angle", "DSResult",
+    "ds_run", "ds_loss", "ds_grad", "ds_loss_relaxed", "ds_grad_relaxed", "wrap_angle", "DSResult",
     "pruning_rate", "chi_hat", "tts_hat", "speed", "solve",
 ]

@@ -28,6 +28,16 @@ One step for every replica r (columns of the (n, R) arrays), step index t >= 1:
   8. theta <- theta - 2 pi rint(theta / 2 pi): sin, cos, m and v do not depend
      on the representative, so this only keeps theta small.
 
+Second reading (relaxed vertex, loss="relaxed"): s~* := sin(theta) itself, the
+relaxed flip pattern.  The loss is then smooth,
+
+    L(theta) = x^T (J - mu I) x + h^T x,   x = sin(theta),
+    dL/dtheta = cos(theta) * (2 (J - mu I) x + h)          (J symmetric),
+
+and steps 2, 4 and 6 become z = J x, L_t = x^T (z - mu x + h),
+g = cos(theta) * (2 z - 2 mu x + h); the energy of the vertex s = sgn(x) is
+still tracked with y = J s (steps 3 and 5).
+
 Initial angles (the paper says only "randomly initialized"): theta_0 = asin(U)
 with U uniform on [-1, 1), so that sin theta_0 is uniform; the draws U are an
 input (instances.uniform_draws).  Defaults for ADAM are Kingma and Ba's
@@ -85,13 +95,30 @@ def ds_grad(inst, theta, mu):
     return np.cos(theta) * (y - mu * s + inst.h.astype(np.float64)[:, None])
 
 
+def ds_loss_relaxed(inst, theta, mu):
+    """Relaxed-vertex loss x^T (J - mu I) x + h^T x, x = sin(theta), for columns of theta (n, R)."""
+    x = np.sin(theta)
+    z = np.asarray(_matrix(inst) @ x)
+    return (x * (z - mu * x + inst.h.astype(np.float64)[:, None])).sum(axis=0)
+
+
+def ds_grad_relaxed(inst, theta, mu):
+    """cos(theta) * (2 (J - mu I) sin(theta) + h) at theta (n, R)."""
+    x = np.sin(theta)
+    z = np.asarray(_matrix(inst) @ x)
+    return np.cos(theta) * (2.0 * z - 2.0 * mu * x + inst.h.astype(np.float64)[:, None])
+
+
 def ds_run(inst, U, steps: int, opt: str = "adam", lr: float = 6.0, mu: float = 0.5,
            beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
-           record: bool = False, record_sin: bool = False) -> DSResult:
+           record: bool = False, record_sin: bool = False, loss: str = "vertex") -> DSResult:
     """Run ``steps`` domain-selection steps for R replicas.
 
     U: (R, n) uniform draws on [-1, 1) (theta_0 = asin U).
+    loss: "vertex" (s~* = sgn sin theta) or "relaxed" (s~* = sin theta).
     """
+    if loss not in ("vertex", "relaxed"):
+        raise ValueError(loss)
     n = inst.n
     U = np.asarray(U, dtype=np.float64)
     R = U.shape[0]
@@ -124,13 +151,18 @@ def ds_run(inst, U, steps: int, opt: str = "adam", lr: float = 6.0, mu: float = 
         else:
             y = np.asarray(Jm @ s.astype(np.float64))
             E = (s * (y + h)).sum(axis=0)
-        tt = y - mu * s + h
-        L = (x * tt).sum(axis=0)
+        if loss == "vertex":
+            tt = y - mu * s + h
+            L = (x * tt).sum(axis=0)
+            g = c * tt
+        else:
+            z = np.asarray(Jm @ x)
+            L = (x * (z - mu * x + h)).sum(axis=0)
+            g = c * (2.0 * z - 2.0 * mu * x + h)
         better = E < e_best
         e_best = np.where(better, E, e_best)
         s_best[:, better] = s[:, better]
         best_step[better] = t
-        g = c * tt
         if opt == "gd":
             theta = theta - lr * g
         elif opt == "adam":

@@ -133,3 +133,75 @@ def test_adam_amplifies_rounding_gd_does_not():
     assert e_gd.max() < 1e-5
     assert e_ad[:30].max() < 1e-5
     assert e_ad.max() > 1e-5
+
+
+# ---- second reading of s~*: the relaxed vertex sin(theta) ------------------------------
+
+def test_relaxed_vertex_identity():
+    # at theta in {+-pi/2}^n the relaxed vertex is the vertex: L = s^T (J - mu I) s + h^T s = E(s) - mu n
+    inst = I.random_integer_field(I.sk_pm1(30, 5), 5, 4)
+    rng = np.random.default_rng(3)
+    for mu in (0.0, 0.5, 3.0):
+        s = rng.choice([-1, 1], size=(30, 5))
+        L = oracle.ds_loss_relaxed(inst, s * np.pi / 2, mu)
+        assert np.allclose(L, oracle.energies(inst, s) - mu * 30, rtol=0, atol=1e-9)
+
+
+def test_relaxed_gradient_matches_finite_difference():
+    inst = I.sk_gauss(25, 6)
+    inst.h[:] = np.random.default_rng(7).normal(size=25)
+    theta = np.random.default_rng(8).uniform(-np.pi, np.pi, size=(25, 3))
+    mu = 0.7
+    g = oracle.ds_grad_relaxed(inst, theta, mu)
+    d = 1e-6
+    for i in range(25):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += d
+        tm[i] -= d
+        fd = (oracle.ds_loss_relaxed(inst, tp, mu) - oracle.ds_loss_relaxed(inst, tm, mu)) / (2 * d)
+        assert np.allclose(fd, g[i], rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("opt,lr", [("adam", 0.05), ("gd", 0.01)])
+def test_relaxed_optimizer_matches_torch(opt, lr):
+    # autograd of the smooth loss x^T (J - mu I) x + h^T x through torch.optim
+    inst = I.random_integer_field(I.sk_pm1(20, 9), 9, 2)
+    U = I.uniform_draws(9, 4, 20)
+    mu = 0.5
+    J = torch.tensor(inst.dense().astype(np.float64))
+    h = torch.tensor(inst.h.astype(np.float64))
+    theta = torch.tensor(np.arcsin(U).T.copy(), requires_grad=True)
+    optim = (torch.optim.Adam([theta], lr=lr, betas=(0.9, 0.999), eps=1e-8) if opt == "adam"
+             else torch.optim.SGD([theta], lr=lr))
+    ref = []
+    for _ in range(40):
+        optim.zero_grad()
+        x = torch.sin(theta)
+        loss = (x * (J @ x - mu * x + h[:, None])).sum()
+        loss.backward()
+        optim.step()
+        ref.append(torch.sin(theta).detach().numpy().T.copy())
+    res = oracle.ds_run(inst, U, 40, opt=opt, lr=lr, mu=mu, record_sin=True, loss="relaxed")
+    assert np.allclose(res.sin_trace, np.array(ref), rtol=0, atol=1e-10)
+
+
+def test_relaxed_loss_trace_and_energy_consistent():
+    # step t records the loss of theta_{t-1} and the energy of its vertex
+    inst = I.random_integer_field(I.erdos_renyi(40, 0.2, 10, "pm1"), 10, 3)
+    U = I.uniform_draws(10, 6, 40)
+    T = 30
+    res = oracle.ds_run(inst, U, T, opt="adam", lr=0.5, mu=0.5, record=True, loss="relaxed")
+    prev = oracle.ds_run(inst, U, T - 1, opt="adam", lr=0.5, mu=0.5, loss="relaxed")
+    for th, t in ((np.arcsin(U).T, 0), (prev.theta.T, T - 1)):
+        assert np.allclose(res.loss_trace[t], oracle.ds_loss_relaxed(inst, th, 0.5), rtol=0, atol=1e-9)
+        s = np.where(np.sin(th) >= 0, 1, -1)
+        assert np.array_equal(res.energy_trace[t], oracle.energies(inst, s))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_relaxed_reaches_brute_force_optimum_n20(seed):
+    inst = I.sk_pm1(20, seed)
+    e_min, _, _ = oracle.brute_force_min(inst)
+    U = I.uniform_draws(seed + 20, 32, 20)
+    res = oracle.ds_run(inst, U, 1000, opt="adam", lr=6.0, mu=0.5, loss="relaxed")
+    assert res.e_best.min() == e_min
