@@ -60,6 +60,16 @@ enum { ISING_I32 = 0, ISING_F32 = 1, ISING_F64 = 2 };
 
 enum { ISING_OPT_GD = 0, ISING_OPT_ADAM = 1 };
 
+/* The local optimum s~* of the loss (Sec. III-B, loss-function equation).
+ * VERTEX: the current vertex sgn(sin theta), piecewise constant, so the step
+ * uses dL/dtheta = cos(theta) ((J - mu I) s~* + h).  RELAXED: the relaxed flip
+ * pattern sin(theta) itself, L = x^T (J - mu I) x + h^T x with x = sin(theta),
+ * dL/dtheta = cos(theta) (2 (J - mu I) x + h); the energy of the vertex
+ * sgn(sin theta) is still tracked every step.  RELAXED runs on the persistent
+ * engine only (not the matrix-core engine, the staged +-w image, the streaming
+ * form or the serving form): other requests for it fail with ISING_ENOTSUP. */
+enum { ISING_LOSS_VERTEX = 0, ISING_LOSS_RELAXED = 1 };
+
 /* Arithmetic of domain selection.  FP64 and FP32: iterates (angles, moments,
  * gradient) and coupling product in that precision.  BF16X2 and BF16 (dense
  * couplings on the matrix cores only): FP32 iterates, coupling product with J
@@ -91,7 +101,7 @@ typedef struct ising_params {
     double beta1, beta2, eps;  /* ADAM constants (Kingma-Ba defaults 0.9, 0.999, 1e-8) */
     uint64_t seed;       /* key of the counter-based initial draws */
     int32_t prune;       /* nonzero: run Algorithm 1 before domain selection */
-    int32_t reserved0;
+    int32_t loss;        /* ISING_LOSS_VERTEX (0) or ISING_LOSS_RELAXED */
 } ising_params;
 
 typedef struct ising_stats {
@@ -289,7 +299,8 @@ ising_status ising_serve_start(ising_ctx *ctx, const ising_serve_config *cfg);
 ising_status ising_serve_stop(ising_ctx *ctx);
 /* Queue a solve.  problem: host buffers, copied before the call returns.
  * params as for ising_solve; sparse requests run in FP32.  *ticket identifies
- * the request.  Thread-safe.  Errors: EINVAL (no server, malformed shape). */
+ * the request.  Thread-safe.  Errors: EINVAL (no server, malformed shape), ENOTSUP
+ * (params->loss other than ISING_LOSS_VERTEX). */
 ising_status ising_submit(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
                           uint64_t *ticket);
 /* Wait up to timeout_ms (negative: forever) for a request and copy its result

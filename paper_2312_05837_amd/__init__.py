@@ -29,6 +29,7 @@ ISING_OK, ISING_EINVAL, ISING_ENOMEM, ISING_EDEVICE, ISING_EBUSY, ISING_ETIMEDOU
 ISING_DENSE, ISING_CSR = 0, 1
 ISING_I32, ISING_F32, ISING_F64 = 0, 1, 2
 ISING_OPT_GD, ISING_OPT_ADAM = 0, 1
+ISING_LOSS_VERTEX, ISING_LOSS_RELAXED = 0, 1
 ISING_PREC_FP64, ISING_PREC_FP32, ISING_PREC_BF16X2, ISING_PREC_BF16 = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EBUSY", 5: "ETIMEDOUT",
@@ -51,7 +52,7 @@ class ising_params(C.Structure):
     _fields_ = [("replicas", C.c_int32), ("steps", C.c_int32), ("optimizer", C.c_int32),
                 ("precision", C.c_int32), ("lr", C.c_double), ("mu", C.c_double), ("beta1", C.c_double),
                 ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64), ("prune", C.c_int32),
-                ("reserved0", C.c_int32)]
+                ("loss", C.c_int32)]
 
 
 class ising_stats(C.Structure):
@@ -192,12 +193,13 @@ def csr_problem(row_ptr, col, val, h=None) -> Problem:
 
 
 def params(replicas=32, steps=100, optimizer="adam", precision="fp32", lr=6.0, mu=0.5, beta1=0.9,
-           beta2=0.999, eps=1e-8, seed=0, prune=True) -> ising_params:
+           beta2=0.999, eps=1e-8, seed=0, prune=True, loss="vertex") -> ising_params:
     opt = {"gd": ISING_OPT_GD, "adam": ISING_OPT_ADAM}[optimizer] if isinstance(optimizer, str) else optimizer
     prec = {"fp64": ISING_PREC_FP64, "fp32": ISING_PREC_FP32, "bf16x2": ISING_PREC_BF16X2,
             "bf16": ISING_PREC_BF16}[precision] if isinstance(precision, str) \
         else precision
-    return ising_params(replicas, steps, opt, prec, lr, mu, beta1, beta2, eps, seed, 1 if prune else 0, 0)
+    lo = {"vertex": ISING_LOSS_VERTEX, "relaxed": ISING_LOSS_RELAXED}[loss] if isinstance(loss, str) else loss
+    return ising_params(replicas, steps, opt, prec, lr, mu, beta1, beta2, eps, seed, 1 if prune else 0, lo)
 
 
 # ---------------------------------------------------------------------------

@@ -180,8 +180,12 @@ ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params 
         return fail(ctx, ISING_ENOTSUP, "precision not supported by the persistent engine");
     const int n = p.n, R = prm.replicas;
     if (n > ds_max_n(fp64)) return fail(ctx, ISING_ENOTSUP, "n exceeds the on-chip vertex-buffer limit");
+    if (prm.loss != ISING_LOSS_VERTEX && prm.loss != ISING_LOSS_RELAXED) return fail(ctx, ISING_EINVAL, "unknown loss");
+    const bool relaxed = prm.loss == ISING_LOSS_RELAXED;
+    if (relaxed) register_only = true;  // sin(theta) is kept in LDS next to the vertex
     DSLaunch &l = plan.l;
     l.fp64 = fp64;
+    l.relaxed = relaxed;
     plan.packed = p.format == ISING_CSR && ing.uniform_mag();
     l.coupling = p.format == ISING_DENSE ? CK_DENSE : (plan.packed ? CK_PM : CK_CSRV);
     // register-resident engine while at most 4 (spin, replica) elements per thread
@@ -210,7 +214,9 @@ ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params 
         rg = rg == 4 ? 2 : 1;  // fewer replicas per workgroup leave room for more spins per thread
     }
     if (ept == 0 && register_only)
-        return fail(ctx, ISING_ENOTSUP, "n too large for the register-resident engine");
+        return fail(ctx, ISING_ENOTSUP,
+                    relaxed ? "the relaxed loss needs the register-resident engine (n too large)"
+                            : "n too large for the register-resident engine");
     if (ept == 0) {
         // streaming: spins triple-buffered in LDS
         const size_t sw = rg == 1 ? 1 : 4;
@@ -259,7 +265,8 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
     HIP_TRY(ctx, launch_ds_format(dp, fp64, plan.packed, (uint32_t *)fmt, fmt, p.h ? hbuf : nullptr, s));
     a.row_ptr = p.row_ptr;
     a.col = p.col;
-    if (plan.packed && plan.l.ept > 0) {
+    a.loss = prm.loss;
+    if (plan.packed && plan.l.ept > 0 && !plan.l.relaxed) {
         // stage the +-w couplings in LDS when the image fits next to the vertex buffers
         DSLaunch l2 = plan.l;
         l2.coupling = CK_PMS;
@@ -338,6 +345,7 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
 ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, Pool &pool,
                            hipStream_t s, DenseRun &d, bool exact_bf16) {
     if (p.format != ISING_DENSE) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine needs dense couplings");
+    if (prm.loss != ISING_LOSS_VERTEX) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs the vertex loss");
     int form;
     // integer couplings of magnitude <= 256 are exact in BF16 and their products
     // are summed exactly in FP32, so the BF16 form gives the FP32 form's results bit for bit
@@ -429,7 +437,7 @@ ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_param
 constexpr int kDenseMfmaMinN = 256;  // n above which dense FP32 problems use MFMA
 
 bool use_dense_engine(const ising_problem &p, const ising_params &prm) {
-    if (p.format != ISING_DENSE) return false;
+    if (p.format != ISING_DENSE || prm.loss != ISING_LOSS_VERTEX) return false;
     if (prm.precision == ISING_PREC_BF16X2 || prm.precision == ISING_PREC_BF16) return true;
     return prm.precision == ISING_PREC_FP32 && p.n > kDenseMfmaMinN;
 }

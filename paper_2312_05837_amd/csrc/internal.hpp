@@ -111,6 +111,7 @@ struct DSArgs {
     const uint32_t *pcnt = nullptr;    // degree | wavefront group count << 16
     const int32_t *pperm = nullptr;    // spin held at position q
     int32_t pms_rb = 0;                // bytes of one vertex region (pms_region_bytes)
+    int32_t loss = ISING_LOSS_VERTEX;  // RELAXED: also z = J sin(theta) from an LDS copy of sin(theta)
 };
 
 struct DSLaunch {
@@ -119,6 +120,7 @@ struct DSLaunch {
     int rg = 1;      // replicas per workgroup
     int ept = 1;     // spins per thread
     int block = 64;  // threads per workgroup
+    bool relaxed = false;  // relaxed-vertex loss: LDS holds sin(theta) too (not with CK_PMS or streaming)
 };
 
 // Build the engine's device formats: pm entries (if sign-packed), values and h

@@ -225,6 +225,42 @@ __device__ inline void coupling(const DSArgs &a, int i, const typename SpinWord<
     }
 }
 
+// z = J x for the relaxed-vertex loss, x = sin(theta) staged in LDS as [spin][RG]
+// (CSR in row order, dense rows in column order).
+template <typename Real, int CK, int RG>
+__device__ inline void relaxed_product(const DSArgs &a, int i, const Real *xc, Real (&z)[RG]) {
+#pragma unroll
+    for (int r = 0; r < RG; ++r) z[r] = 0;
+    if constexpr (CK == CK_PM) {
+        const int rs = a.row_ptr[i], re = a.row_ptr[i + 1];
+        for (int q = rs; q < re; ++q) {
+            const uint32_t e = a.pm[q];
+            const Real sg = (e >> 31) ? (Real)-1 : (Real)1;
+            const Real *xj = xc + (size_t)(e & 0x7fffffffu) * RG;
+#pragma unroll
+            for (int r = 0; r < RG; ++r) z[r] = __builtin_fma(sg, xj[r], z[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < RG; ++r) z[r] *= (Real)a.w;
+    } else if constexpr (CK == CK_CSRV) {
+        const Real *val = (const Real *)a.val;
+        const int rs = a.row_ptr[i], re = a.row_ptr[i + 1];
+        for (int q = rs; q < re; ++q) {
+            const Real v = val[q];
+            const Real *xj = xc + (size_t)a.col[q] * RG;
+#pragma unroll
+            for (int r = 0; r < RG; ++r) z[r] = __builtin_fma(v, xj[r], z[r]);
+        }
+    } else if constexpr (CK == CK_DENSE) {
+        const Real *row = (const Real *)a.J + (size_t)i * a.n;
+        for (int j = 0; j < a.n; ++j) {
+            const Real v = row[j];
+#pragma unroll
+            for (int r = 0; r < RG; ++r) z[r] = __builtin_fma(v, xc[(size_t)j * RG + r], z[r]);
+        }
+    }
+}
+
 constexpr int launch_bound(int) { return 1024; }
 
 template <typename Real, int CK, int RG, int EPT>
@@ -251,6 +287,10 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     Real *lp = ep + 2 * NW * RG;          // [2][NW][RG]
     uint32_t *flg = (uint32_t *)(lp + 2 * NW * RG);  // [2]
     uint2 *img = (uint2 *)(smem + ((off + 2 * 2 * NW * RG * sizeof(Real) + 8 + 15) & ~(size_t)15));
+    // relaxed-vertex loss (never with CK_PMS): sin(theta) per parity, [npad][RG], where the image would be
+    constexpr bool CAN_RELAX = CK != CK_PMS;
+    const bool relaxed = CAN_RELAX && a.loss == ISING_LOSS_RELAXED;
+    Real *xb = (Real *)img;
     int prow_r[CK == CK_PMS ? EPT : 1];
     uint32_t pcnt_r[CK == CK_PMS ? EPT : 1];
     int row_r[CK == CK_PMS ? EPT : 1];  // spin held at position e * B + tid
@@ -342,6 +382,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     xs[k] = x;
                     cs[k] = c;
                 }
+                if (CAN_RELAX && relaxed) xb[(size_t)q * RG + r] = x;
                 if (x < 0) {
                     cur |= 1u << k;
                     word |= (SW)(1u << SWd::shift(r));
@@ -380,6 +421,9 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
             Real y[RG];
             if constexpr (CK == CK_PMS) coupling<Real, CK, RG>(a, i, sc, y, img, prow_r[e], pcnt_r[e]);
             else coupling<Real, CK, RG>(a, i, sc, y);
+            Real z[RG];
+            if constexpr (CAN_RELAX)
+                if (relaxed) relaxed_product<Real, CK, RG>(a, i, xb + (size_t)((t - 1) & 1) * npad * RG, z);
             const Real hh = hv ? hv[i] : (Real)0;
             SW word = 0;
 #pragma unroll
@@ -396,8 +440,19 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 const Real sg = x < 0 ? (Real)-1 : (Real)1;
                 const Real yh = y[r] + hh;
                 Ep[r] = __builtin_fma(sg, yh, Ep[r]);
-                const Real tt = __builtin_fma(-mu, sg, yh);  // y - mu s + h
-                Lp[r] = __builtin_fma(x, tt, Lp[r]);
+                Real tt = __builtin_fma(-mu, sg, yh);  // y - mu s + h
+                if constexpr (CAN_RELAX) {
+                    if (relaxed) {
+                        const Real zm = __builtin_fma(-mu, x, z[r]);  // z - mu x
+                        tt = zm + hh;                                 // L term: z - mu x + h
+                        Lp[r] = __builtin_fma(x, tt, Lp[r]);
+                        tt = tt + zm;                                 // gradient term: 2 z - 2 mu x + h
+                    } else {
+                        Lp[r] = __builtin_fma(x, tt, Lp[r]);
+                    }
+                } else {
+                    Lp[r] = __builtin_fma(x, tt, Lp[r]);
+                }
                 const Real g = c * tt;
                 Real upd;
                 if (adam) {
@@ -425,6 +480,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     nxt |= 1u << k;
                     word |= (SW)(1u << SWd::shift(r));
                 }
+                if (CAN_RELAX && relaxed) xb[((size_t)(t & 1) * npad + e * B + tid) * RG + r] = xn;
             }
             put(t & 1, e, word);
             // keep the scheduler from interleaving elements: bounds live ranges
@@ -1023,6 +1079,8 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
         a.R % l.rg)
         return hipErrorInvalidValue;
     if (l.coupling == CK_PMS && a.pms_rb != pms_region_bytes(l)) return hipErrorInvalidValue;
+    if ((a.loss == ISING_LOSS_RELAXED) != l.relaxed || (l.relaxed && (l.coupling == CK_PMS || l.ept <= 0)))
+        return hipErrorInvalidValue;
     const size_t lds = ds_lds_bytes(l, a.n, a.pimg_groups);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {
@@ -1112,6 +1170,7 @@ size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups) {
     else sbytes = l.ept > 0 ? (size_t)2 * (l.ept * l.block + 1) * sw : (size_t)3 * n * sw;
     size_t lds = ((sbytes + 15) & ~(size_t)15) + 2 * 2 * nw * l.rg * real + 8;
     if (l.coupling == CK_PMS) lds = ((lds + 15) & ~(size_t)15) + (size_t)8 * pimg_groups;
+    if (l.relaxed) lds = ((lds + 15) & ~(size_t)15) + (size_t)2 * (l.ept * l.block + 1) * l.rg * real;
     return lds;
 }
 

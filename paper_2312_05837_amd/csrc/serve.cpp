@@ -515,6 +515,7 @@ ising_status ising_submit(ising_ctx *ctx, const ising_problem *problem, const is
         if (!problem || problem->n <= 0 || params->replicas <= 0 || params->steps < 0) return ISING_EINVAL;
     }
     if (problem->value_type < ISING_I32 || problem->value_type > ISING_F64) return ISING_EINVAL;
+    if (params->loss != ISING_LOSS_VERTEX) return ISING_ENOTSUP;  // the batched launches run the vertex loss
     auto q = std::make_unique<Request>();
     q->prm = *params;
     q->hp = *problem;

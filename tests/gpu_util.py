@@ -57,7 +57,7 @@ def _subset(got, sel):
 
 
 def compare_trajectories(inst, got, U, steps, opt, lr, chunks, TOL=1e-5, check_loss=True, max_excluded=None,
-                         check_energy=True):
+                         check_energy=True, loss="vertex"):
     """Oracle vs GPU iterates at every chunk boundary; exact energies for integer instances.
 
     A replica is compared up to the first step where its vertex may legitimately
@@ -73,7 +73,7 @@ def compare_trajectories(inst, got, U, steps, opt, lr, chunks, TOL=1e-5, check_l
         got = _subset(got, sel)
         U = U[sel]
         R = U.shape[0]
-    ref = oracle.ds_run(inst, U, steps, opt=opt, lr=lr, mu=0.5, record=True, record_sin=True)
+    ref = oracle.ds_run(inst, U, steps, opt=opt, lr=lr, mu=0.5, record=True, record_sin=True, loss=loss)
     # vertex of step t is sgn(sin theta_{t-1}); theta_0 = asin U
     min_prev = np.empty((steps, R))
     min_prev[0] = np.abs(U).min(axis=1)

@@ -205,3 +205,18 @@ def test_relaxed_reaches_brute_force_optimum_n20(seed):
     U = I.uniform_draws(seed + 20, 32, 20)
     res = oracle.ds_run(inst, U, 1000, opt="adam", lr=6.0, mu=0.5, loss="relaxed")
     assert res.e_best.min() == e_min
+
+
+def test_relaxed_adam_amplifies_faster():
+    # the horizon of the relaxed-loss ADAM parity cases: at the paper's lr 6.0 two FP64 runs one ulp
+    # apart stay within 1e-7 for 10 steps and pass 1e-6 by step 20 (SK n = 64)
+    inst = I.sk_pm1(64, 0)
+    U = I.uniform_draws(13, 32, 64)
+    a = oracle.ds_run(inst, U, 20, opt="adam", lr=6.0, mu=0.5, record_sin=True, loss="relaxed")
+    b = oracle.ds_run(inst, np.nextafter(U, 2), 20, opt="adam", lr=6.0, mu=0.5, record_sin=True, loss="relaxed")
+
+    def sep(t):
+        return (np.abs(a.sin_trace[t - 1] - b.sin_trace[t - 1]).max(axis=1)
+                / np.abs(a.sin_trace[t - 1]).max(axis=1)).max()
+    assert sep(10) < 1e-7
+    assert sep(20) > 1e-6
