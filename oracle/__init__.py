@@ -27,7 +27,8 @@ itself, which the paper pins only through the identities those tests check.
 """
 from .energy import energy, energies, cut_value, brute_force_min, local_fields
 from .prune import prune, unprune, PruneResult, fixed_order_abs_rowsum
-from .ds import ds_run, ds_loss, ds_grad, ds_loss_relaxed, ds_grad_relaxed, wrap_angle, DSResult
+from .ds import (ds_run, ds_loss, ds_grad, ds_loss_relaxed, ds_grad_relaxed, wrap_angle, DSResult, converged,
+                 convergence_step)
 from .metrics import pruning_rate, chi_hat, tts_hat, speed
 from .solve import solve
 
@@ -35,5 +36,6 @@ __all__ = [
     "energy", "energies", "cut_value", "brute_force_min", "local_fields",
     "prune", "unprune", "PruneResult", "fixed_order_abs_rowsum",
     "ds_run", "ds_loss", "ds_grad", "ds_loss_relaxed", "ds_grad_relaxed", "wrap_angle", "DSResult",
+    "converged", "convergence_step",
     "pruning_rate", "chi_hat", "tts_hat", "speed", "solve",
 ]

@@ -38,6 +38,14 @@ and steps 2, 4 and 6 become z = J x, L_t = x^T (z - mu x + h),
 g = cos(theta) * (2 z - 2 mu x + h); the energy of the vertex s = sgn(x) is
 still tracked with y = J s (steps 3 and 5).
 
+Convergence test (Sec. IV-B, optional): with Delta L the spread (maximum minus
+minimum) of the last w = 5 losses, the paper stops when Delta L / (L_now - L_init)
+<= 0.005.  The loss decreases, so that denominator is <= 0 and the inequality as
+printed holds at once; the reading taken is Delta L <= tol |L_now - L_init| with
+L_init = L_1, checked from step t = w on.  A replica that meets it at step t stops
+after that step: its angles, moments and best vertex are final and later steps
+neither update nor score it.
+
 Initial angles (the paper says only "randomly initialized"): theta_0 = asin(U)
 with U uniform on [-1, 1), so that sin theta_0 is uniform; the draws U are an
 input (instances.uniform_draws).  Defaults for ADAM are Kingma and Ba's
@@ -64,6 +72,7 @@ class DSResult:
     loss_trace: Optional[np.ndarray] = None     # (T, R) L_t
     sin_trace: Optional[np.ndarray] = None      # (T, R, n) sin(theta_t) after step t
     spin_trace: Optional[np.ndarray] = None     # (T, R, n) s used in step t
+    conv_step: Optional[np.ndarray] = None      # (R,) step at which the convergence test held (0: never)
 
 
 def _matrix(inst):
@@ -109,13 +118,32 @@ def ds_grad_relaxed(inst, theta, mu):
     return np.cos(theta) * (2.0 * z - 2.0 * mu * x + inst.h.astype(np.float64)[:, None])
 
 
+def converged(losses, window: int, tol: float) -> bool:
+    """Convergence test on the losses L_1..L_t of one replica (t = len(losses))."""
+    t = len(losses)
+    if tol <= 0 or t < window:
+        return False
+    last = losses[t - window:]
+    return max(last) - min(last) <= tol * abs(losses[-1] - losses[0])
+
+
+def convergence_step(loss_trace, window: int = 5, tol: float = 0.005) -> int:
+    """First step t (1-based) at which the test holds on loss_trace[:t], 0 if none."""
+    for t in range(1, len(loss_trace) + 1):
+        if converged(list(loss_trace[:t]), window, tol):
+            return t
+    return 0
+
+
 def ds_run(inst, U, steps: int, opt: str = "adam", lr: float = 6.0, mu: float = 0.5,
            beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
-           record: bool = False, record_sin: bool = False, loss: str = "vertex") -> DSResult:
+           record: bool = False, record_sin: bool = False, loss: str = "vertex",
+           conv_tol: float = 0.0, conv_window: int = 5) -> DSResult:
     """Run ``steps`` domain-selection steps for R replicas.
 
     U: (R, n) uniform draws on [-1, 1) (theta_0 = asin U).
     loss: "vertex" (s~* = sgn sin theta) or "relaxed" (s~* = sin theta).
+    conv_tol > 0: each replica stops after the step at which the convergence test holds.
     """
     if loss not in ("vertex", "relaxed"):
         raise ValueError(loss)
@@ -139,6 +167,9 @@ def ds_run(inst, U, steps: int, opt: str = "adam", lr: float = 6.0, mu: float = 
     lt = np.zeros((steps, R)) if record else None
     st = np.zeros((steps, R, n)) if record_sin else None
     sp_t = np.zeros((steps, R, n), dtype=np.int8) if record_sin else None
+    active = np.ones(R, dtype=bool)
+    conv_step = np.zeros(R, dtype=np.int64)
+    hist = [[] for _ in range(R)]
 
     for t in range(1, steps + 1):
         x = np.sin(theta)
@@ -159,21 +190,32 @@ def ds_run(inst, U, steps: int, opt: str = "adam", lr: float = 6.0, mu: float = 
             z = np.asarray(Jm @ x)
             L = (x * (z - mu * x + h)).sum(axis=0)
             g = c * (2.0 * z - 2.0 * mu * x + h)
-        better = E < e_best
+        better = (E < e_best) & active
         e_best = np.where(better, E, e_best)
         s_best[:, better] = s[:, better]
         best_step[better] = t
         if opt == "gd":
-            theta = theta - lr * g
+            theta_n = theta - lr * g
+            m_n, v_n = m, v
         elif opt == "adam":
-            m = beta1 * m + (1.0 - beta1) * g
-            v = beta2 * v + (1.0 - beta2) * g * g
-            mhat = m / (1.0 - beta1 ** t)
-            vhat = v / (1.0 - beta2 ** t)
-            theta = theta - lr * mhat / (np.sqrt(vhat) + eps)
+            m_n = beta1 * m + (1.0 - beta1) * g
+            v_n = beta2 * v + (1.0 - beta2) * g * g
+            mhat = m_n / (1.0 - beta1 ** t)
+            vhat = v_n / (1.0 - beta2 ** t)
+            theta_n = theta - lr * mhat / (np.sqrt(vhat) + eps)
         else:
             raise ValueError(opt)
-        theta = wrap_angle(theta)
+        theta_n = wrap_angle(theta_n)
+        # replicas that stopped keep their state
+        theta = np.where(active[None, :], theta_n, theta)
+        m = np.where(active[None, :], m_n, m)
+        v = np.where(active[None, :], v_n, v)
+        if conv_tol > 0:
+            for r in np.nonzero(active)[0]:
+                hist[r].append(L[r])
+                if converged(hist[r], conv_window, conv_tol):
+                    active[r] = False
+                    conv_step[r] = t
         if record:
             et[t - 1] = E
             lt[t - 1] = L
@@ -181,4 +223,4 @@ def ds_run(inst, U, steps: int, opt: str = "adam", lr: float = 6.0, mu: float = 
             st[t - 1] = np.sin(theta).T
             sp_t[t - 1] = s.T
     return DSResult(theta.T.copy(), m.T.copy(), v.T.copy(), e_best, s_best.T.copy(), best_step,
-                    et, lt, st, sp_t)
+                    et, lt, st, sp_t, conv_step)

@@ -220,3 +220,34 @@ def test_relaxed_adam_amplifies_faster():
                 / np.abs(a.sin_trace[t - 1]).max(axis=1)).max()
     assert sep(10) < 1e-7
     assert sep(20) > 1e-6
+
+
+# ---- convergence test (Sec. IV-B): spread of the last 5 losses <= 0.005 |L_now - L_init| ----
+
+def test_convergence_step_closed_forms():
+    # constant losses: the spread is 0 as soon as 5 losses exist
+    assert oracle.convergence_step([3.0] * 12) == 5
+    # L_t = -t: spread 4 <= 0.005 (t - 1) first at t = 801
+    assert oracle.convergence_step(-np.arange(1, 1200, dtype=float)) == 801
+    # window 3, tol 0.5 on L = -t: spread 2 <= 0.5 (t - 1) first at t = 5
+    assert oracle.convergence_step(-np.arange(1, 20, dtype=float), window=3, tol=0.5) == 5
+    # switched off, or never met
+    assert oracle.convergence_step([1.0] * 10, tol=0.0) == 0
+    assert oracle.convergence_step([0.0, 1.0, 0.0, 1.0, 0.0, 1.0]) == 0
+
+
+def test_converged_replicas_stop_with_their_state():
+    inst = I.random_integer_field(I.erdos_renyi(60, 0.1, 14, "pm1"), 14, 2)
+    U = I.uniform_draws(14, 16, 60)
+    T = 300
+    full = oracle.ds_run(inst, U, T, opt="adam", lr=6.0, mu=0.5, record=True, record_sin=True)
+    conv = oracle.ds_run(inst, U, T, opt="adam", lr=6.0, mu=0.5, conv_tol=0.005, conv_window=5)
+    assert np.all(conv.conv_step > 0)
+    for r in range(16):
+        t = conv.conv_step[r]
+        # the step of convergence is the test applied to the losses of the run without it
+        assert t == oracle.convergence_step(full.loss_trace[:, r])
+        # state after that step, and the best vertex over steps 1..t
+        assert np.array_equal(np.sin(conv.theta[r]), full.sin_trace[t - 1, r])
+        assert conv.e_best[r] == full.energy_trace[:t, r].min()
+        assert conv.best_step[r] == int(np.argmin(full.energy_trace[:t, r])) + 1
