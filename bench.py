@@ -48,7 +48,10 @@ WORKLOADS = {
     "sk2000_bf16": ("dense SK N=2000 J~N(0,1/N), J in BF16 on MFMA", "sk2000g", 4096, 2000, "bf16"),
     "sk2000_fp32": ("dense SK N=2000 J~N(0,1/N), FP32 MFMA", "sk2000g", 4096, 2000, "fp32"),
     "er800_relaxed": ("sparse Erdos-Renyi N=800 p=0.06 +-1 weights, CSR, relaxed-vertex loss (s~* = sin theta)",
-                      "er", 1024, 5000, "fp32", "relaxed"),
+                      "er", 1024, 5000, "fp32", {"loss": "relaxed"}),
+    "t1_binary_conv": ("Table-1-shaped 6-regular N=1000, J=+-1, h=+-12, ADAM lr 6 until the convergence test "
+                       "(spread of the last 5 losses <= 0.005 of the loss decrease), at most 2000 steps",
+                       "t1binary", 1024, 2000, "fp32", {"conv_tol": 0.005, "conv_window": 5}),
 }
 # peak rates of the matrix cores (dense, no sparsity), per precision of the coupling product
 MFMA_PEAK = {"bf16x2": 2.5e15, "bf16": 2.5e15, "fp32": 157.3e12}
@@ -119,6 +122,8 @@ def make_instance(kind):
         return I.random_regular(20000, 3, 0, "pm1")
     if kind == "sk2000g":
         return I.sk_gauss(2000, 0)
+    if kind == "t1binary":
+        return I.table1_regular(1000, 6, "binary_int", 0)
     raise ValueError(kind)
 
 
@@ -292,13 +297,16 @@ def main():
         serve_bench(args)
         return
     desc, kind, R, T, prec = WORKLOADS[args.workload][:5]
-    loss = WORKLOADS[args.workload][5] if len(WORKLOADS[args.workload]) > 5 else "vertex"
+    extra = WORKLOADS[args.workload][5] if len(WORKLOADS[args.workload]) > 5 else {}
+    loss = extra.get("loss", "vertex")
+    conv_tol, conv_window = extra.get("conv_tol", 0.0), extra.get("conv_window", 5)
     lr = args.lr if args.lr is not None else (6.0 if args.optimizer == "adam" else 0.01)
     mu = 0.5
     inst = make_instance(kind)
     prob = to_device(inst)
     ctx = P.ising_create(0)
     prm = P.params(replicas=R, steps=T, optimizer=args.optimizer, precision=prec, lr=lr, mu=mu, seed=1234, loss=loss,
+                   conv_tol=conv_tol, conv_window=conv_window,
                    prune=True)
     spins = torch.empty(inst.n, dtype=torch.int8, device="cuda")
     E = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -316,7 +324,9 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = wall / args.steps * 1e3
     nG = stats[-1]["n_G"]
-    value = nG * R * T / (ms_per_step * 1e-3)
+    # with the convergence test a replica's steps end at its convergence step
+    T_eff = float(np.mean([s["mean_steps_run"] for s in stats])) if conv_tol > 0 else float(T)
+    value = nG * R * T_eff / (ms_per_step * 1e-3)
 
     # dominant kernel: the domain-selection engine, timed with HIP events on its stream
     k_ms = float(np.mean([s["t_ds_kernel_ms"] for s in stats]))
@@ -340,9 +350,9 @@ def main():
                 "flops_per_launch_sequence": ops}
     else:
         if loss == "relaxed":
-            ops = float(T) * R * (2 * nnzG + EPI_OPS_RELAXED[args.optimizer] * nG)
+            ops = T_eff * R * (2 * nnzG + EPI_OPS_RELAXED[args.optimizer] * nG)
         else:
-            ops = float(T) * R * (nnzG + EPI_OPS[args.optimizer] * nG)
+            ops = T_eff * R * (nnzG + EPI_OPS[args.optimizer] * nG)
         achieved = ops / (k_ms * 1e-3)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s",
                 "frac": achieved / ALU_PEAK_OPS, "traffic": recorded_traffic("k_ds", args.workload),
@@ -365,10 +375,12 @@ def main():
         "dtype": {"fp32": "f32", "fp64": "f64", "bf16x2": "bf16x2/f32", "bf16": "bf16/f32"}[prec],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n": inst.n, "n_G": nG, "nnz": int(inst.nnz),
-                   "replicas": R, "ds_steps": T, "optimizer": args.optimizer, "lr": lr, "mu": mu,
+                   "replicas": R, "ds_steps": T, "mean_steps_run": T_eff, "optimizer": args.optimizer, "lr": lr,
+                   "mu": mu, "conv_tol": conv_tol,
                    "precision": prec, "prune": True, "loss": loss},
         "roofline": roof,
-        "time_to_target_s": (t_pre + t_ds * best_step / T) * 1e-3,
+        # with the convergence test the solve ends when every replica has stopped
+        "time_to_target_s": ms_per_step * 1e-3 if conv_tol > 0 else (t_pre + t_ds * best_step / T) * 1e-3,
         "best_energy": e_final,
         "stage_ms": {"ingest": float(np.mean([s["t_upload_ms"] for s in stats])),
                      "prune": float(np.mean([s["t_prune_ms"] for s in stats])), "ds": t_ds,

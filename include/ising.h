@@ -102,6 +102,16 @@ typedef struct ising_params {
     uint64_t seed;       /* key of the counter-based initial draws */
     int32_t prune;       /* nonzero: run Algorithm 1 before domain selection */
     int32_t loss;        /* ISING_LOSS_VERTEX (0) or ISING_LOSS_RELAXED */
+    /* Convergence test (Sec. IV-B), off when conv_tol <= 0: a replica stops after the
+     * first step t >= conv_window at which the spread (maximum minus minimum) of its
+     * last conv_window losses is <= conv_tol * |L_t - L_1| (the paper: 5 and 0.005).
+     * Its angles, moments and best vertex are then final; the launch ends when every
+     * replica has stopped.  Persistent engine only, in one launch from step 1
+     * (ising_ds_dev with t0 == 0; not the matrix-core, streaming or serving forms:
+     * ENOTSUP there).  1 <= conv_window <= 8. */
+    int32_t conv_window;
+    int32_t reserved1;
+    double conv_tol;
 } ising_params;
 
 typedef struct ising_stats {
@@ -111,12 +121,13 @@ typedef struct ising_stats {
     int32_t best_replica;    /* replica whose vertex was returned */
     int64_t steps;           /* domain-selection steps per replica */
     int32_t best_step;       /* step at which the returned vertex was first seen */
-    int32_t reserved0;
+    int32_t converged;       /* replicas that met the convergence test (0 when it is off) */
     double eta;              /* pruning rate 1 - n_G / n */
     double constant_C;       /* constant of the reduced problem */
     double t_upload_ms, t_prune_ms, t_ds_ms, t_finish_ms, t_total_ms;
     double replica_spin_updates_per_s;  /* n_G * R * T / t_ds */
     double t_ds_kernel_ms;   /* the domain-selection kernel alone (HIP events around its launch) */
+    double mean_steps_run;   /* mean over replicas of the steps run (the convergence step or T) */
 } ising_stats;
 
 typedef struct ising_ctx ising_ctx;
@@ -223,6 +234,7 @@ typedef struct ising_ds_state {
     int32_t *best_step;   /* R step index (1-based) of e_best */
     double *energy_trace; /* nullable: steps*R energies E_t, row t-1-t0 holds step t */
     double *loss_trace;   /* nullable: steps*R losses L_t */
+    int32_t *conv_step;   /* nullable: R steps at which the convergence test held (0: never) */
 } ising_ds_state;
 
 /* Run steps t0+1 .. t0+steps of domain selection on the problem (device
@@ -300,7 +312,7 @@ ising_status ising_serve_stop(ising_ctx *ctx);
 /* Queue a solve.  problem: host buffers, copied before the call returns.
  * params as for ising_solve; sparse requests run in FP32.  *ticket identifies
  * the request.  Thread-safe.  Errors: EINVAL (no server, malformed shape), ENOTSUP
- * (params->loss other than ISING_LOSS_VERTEX). */
+ * (params->loss other than ISING_LOSS_VERTEX, or the convergence test on). */
 ising_status ising_submit(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
                           uint64_t *ticket);
 /* Wait up to timeout_ms (negative: forever) for a request and copy its result

@@ -52,15 +52,17 @@ class ising_params(C.Structure):
     _fields_ = [("replicas", C.c_int32), ("steps", C.c_int32), ("optimizer", C.c_int32),
                 ("precision", C.c_int32), ("lr", C.c_double), ("mu", C.c_double), ("beta1", C.c_double),
                 ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64), ("prune", C.c_int32),
-                ("loss", C.c_int32)]
+                ("loss", C.c_int32), ("conv_window", C.c_int32), ("reserved1", C.c_int32),
+                ("conv_tol", C.c_double)]
 
 
 class ising_stats(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_G", C.c_int32), ("rounds", C.c_int32), ("best_replica", C.c_int32),
-                ("steps", C.c_int64), ("best_step", C.c_int32), ("reserved0", C.c_int32), ("eta", C.c_double),
+                ("steps", C.c_int64), ("best_step", C.c_int32), ("converged", C.c_int32), ("eta", C.c_double),
                 ("constant_C", C.c_double), ("t_upload_ms", C.c_double), ("t_prune_ms", C.c_double),
                 ("t_ds_ms", C.c_double), ("t_finish_ms", C.c_double), ("t_total_ms", C.c_double),
-                ("replica_spin_updates_per_s", C.c_double), ("t_ds_kernel_ms", C.c_double)]
+                ("replica_spin_updates_per_s", C.c_double), ("t_ds_kernel_ms", C.c_double),
+                ("mean_steps_run", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
@@ -69,7 +71,7 @@ class ising_stats(C.Structure):
 class ising_ds_state(C.Structure):
     _fields_ = [("theta", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("s_best", C.c_void_p),
                 ("e_best", C.c_void_p), ("best_step", C.c_void_p), ("energy_trace", C.c_void_p),
-                ("loss_trace", C.c_void_p)]
+                ("loss_trace", C.c_void_p), ("conv_step", C.c_void_p)]
 
 
 class ising_serve_config(C.Structure):
@@ -193,13 +195,15 @@ def csr_problem(row_ptr, col, val, h=None) -> Problem:
 
 
 def params(replicas=32, steps=100, optimizer="adam", precision="fp32", lr=6.0, mu=0.5, beta1=0.9,
-           beta2=0.999, eps=1e-8, seed=0, prune=True, loss="vertex") -> ising_params:
+           beta2=0.999, eps=1e-8, seed=0, prune=True, loss="vertex", conv_tol=0.0,
+           conv_window=5) -> ising_params:
     opt = {"gd": ISING_OPT_GD, "adam": ISING_OPT_ADAM}[optimizer] if isinstance(optimizer, str) else optimizer
     prec = {"fp64": ISING_PREC_FP64, "fp32": ISING_PREC_FP32, "bf16x2": ISING_PREC_BF16X2,
             "bf16": ISING_PREC_BF16}[precision] if isinstance(precision, str) \
         else precision
     lo = {"vertex": ISING_LOSS_VERTEX, "relaxed": ISING_LOSS_RELAXED}[loss] if isinstance(loss, str) else loss
-    return ising_params(replicas, steps, opt, prec, lr, mu, beta1, beta2, eps, seed, 1 if prune else 0, lo)
+    return ising_params(replicas, steps, opt, prec, lr, mu, beta1, beta2, eps, seed, 1 if prune else 0, lo,
+                        conv_window, 0, conv_tol)
 
 
 # ---------------------------------------------------------------------------
@@ -381,7 +385,7 @@ def ising_ds_dev(ctx, problem, prm: ising_params, state: dict, t0: int = 0, step
     steps = prm.steps if steps is None else steps
     st = ising_ds_state(_ptr(state["theta"]), _ptr(state.get("m")), _ptr(state.get("v")), _ptr(state["s_best"]),
                         _ptr(state["e_best"]), _ptr(state["best_step"]), _ptr(state.get("energy_trace")),
-                        _ptr(state.get("loss_trace")))
+                        _ptr(state.get("loss_trace")), _ptr(state.get("conv_step")))
     _check(ctx, _lib.ising_ds_dev(ctx, C.byref(ps), C.byref(prm), _ptr(uniform), t0, steps, C.byref(st),
                                   _stream(stream)))
     return state

@@ -183,9 +183,14 @@ ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params 
     if (prm.loss != ISING_LOSS_VERTEX && prm.loss != ISING_LOSS_RELAXED) return fail(ctx, ISING_EINVAL, "unknown loss");
     const bool relaxed = prm.loss == ISING_LOSS_RELAXED;
     if (relaxed) register_only = true;  // sin(theta) is kept in LDS next to the vertex
+    const bool conv = prm.conv_tol > 0;
+    if (conv && (prm.conv_window < 1 || prm.conv_window > kConvWindowMax))
+        return fail(ctx, ISING_EINVAL, "conv_window must be in 1..8");
+    if (conv) register_only = true;  // the test runs in the register-resident engine
     DSLaunch &l = plan.l;
     l.fp64 = fp64;
     l.relaxed = relaxed;
+    l.conv = conv;
     plan.packed = p.format == ISING_CSR && ing.uniform_mag();
     l.coupling = p.format == ISING_DENSE ? CK_DENSE : (plan.packed ? CK_PM : CK_CSRV);
     // register-resident engine while at most 4 (spin, replica) elements per thread
@@ -266,6 +271,8 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
     a.row_ptr = p.row_ptr;
     a.col = p.col;
     a.loss = prm.loss;
+    a.conv_tol = prm.conv_tol > 0 ? prm.conv_tol : 0.0;
+    a.conv_window = prm.conv_window;
     if (plan.packed && plan.l.ept > 0 && !plan.l.relaxed) {
         // stage the +-w couplings in LDS when the image fits next to the vertex buffers
         DSLaunch l2 = plan.l;
@@ -310,6 +317,8 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
         return fail(ctx, ISING_EINVAL, "state buffers missing");
     if (prm.optimizer == ISING_OPT_ADAM && (!st->m || !st->v))
         return fail(ctx, ISING_EINVAL, "ADAM needs m and v buffers");
+    if (prm.conv_tol > 0 && t0 != 0)
+        return fail(ctx, ISING_ENOTSUP, "the convergence test runs in one launch from step 1 (t0 = 0)");
     DSArgs a;
     DSPlan plan;
     ST_TRY(prepare_ds(ctx, p, prm, ing, pool, s, a, plan));
@@ -327,6 +336,7 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
     a.best_step = st->best_step;
     a.etrace = st->energy_trace;
     a.ltrace = st->loss_trace;
+    a.conv_step = st->conv_step;
     if (prm.optimizer == ISING_OPT_ADAM && steps > 0) {
         void *bias = nullptr;
         HIP_TRY(ctx, pool.get("ds.bias", (size_t)2 * steps * real, &bias));
@@ -346,6 +356,7 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
                            hipStream_t s, DenseRun &d, bool exact_bf16) {
     if (p.format != ISING_DENSE) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine needs dense couplings");
     if (prm.loss != ISING_LOSS_VERTEX) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs the vertex loss");
+    if (prm.conv_tol > 0) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs fixed step counts");
     int form;
     // integer couplings of magnitude <= 256 are exact in BF16 and their products
     // are summed exactly in FP32, so the BF16 form gives the FP32 form's results bit for bit
@@ -437,7 +448,7 @@ ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_param
 constexpr int kDenseMfmaMinN = 256;  // n above which dense FP32 problems use MFMA
 
 bool use_dense_engine(const ising_problem &p, const ising_params &prm) {
-    if (p.format != ISING_DENSE || prm.loss != ISING_LOSS_VERTEX) return false;
+    if (p.format != ISING_DENSE || prm.loss != ISING_LOSS_VERTEX || prm.conv_tol > 0) return false;
     if (prm.precision == ISING_PREC_BF16X2 || prm.precision == ISING_PREC_BF16) return true;
     return prm.precision == ISING_PREC_FP32 && p.n > kDenseMfmaMinN;
 }
@@ -682,6 +693,7 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
     HIP_TRY(ctx, pool.get("solve.best", 8, (void **)&bestdev));
     HIP_TRY(ctx, pool.get("solve.sG", std::max(nG, 1), (void **)&sG));
     int32_t best_replica = -1, best_step = 0;
+    std::vector<int32_t> conv_steps;
     if (nG > 0) {
         ising_ds_state st{};
         HIP_TRY(ctx, pool.get("solve.theta", (size_t)nG * R * real, &st.theta));
@@ -692,6 +704,7 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
         HIP_TRY(ctx, pool.get("solve.sbest", (size_t)nG * R, (void **)&st.s_best));
         HIP_TRY(ctx, pool.get("solve.ebest", (size_t)R * 8, (void **)&st.e_best));
         HIP_TRY(ctx, pool.get("solve.bstep", (size_t)R * 4, (void **)&st.best_step));
+        if (params->conv_tol > 0) HIP_TRY(ctx, pool.get("solve.conv", (size_t)R * 4, (void **)&st.conv_step));
         if (dense_engine)
             ST_TRY(run_dense(ctx, *red, *params, nullptr, 0, params->steps, &st, pool, s, exact_in_bf16(ing, red->n),
                              ev[5], ev[6]));
@@ -703,6 +716,10 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
         HIP_TRY(ctx, hipStreamSynchronize(s));
         if (best_replica >= 0 && best_replica < R)
             HIP_TRY(ctx, hipMemcpyAsync(&best_step, st.best_step + best_replica, 4, hipMemcpyDeviceToHost, s));
+        if (st.conv_step) {
+            conv_steps.resize(R);
+            HIP_TRY(ctx, hipMemcpyAsync(conv_steps.data(), st.conv_step, (size_t)R * 4, hipMemcpyDeviceToHost, s));
+        }
     } else {
         HIP_TRY(ctx, hipEventRecord(ev[3], s));
     }
@@ -739,6 +756,15 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
         o.t_ds_kernel_ms = nG > 0 ? ms_between(ev[5], ev[6]) : 0.0;
         o.replica_spin_updates_per_s =
             o.t_ds_ms > 0 ? (double)nG * R * params->steps / (o.t_ds_ms * 1e-3) : 0.0;
+        o.mean_steps_run = params->steps;
+        if (!conv_steps.empty()) {
+            double sum = 0.0;
+            for (int32_t c : conv_steps) {
+                o.converged += c > 0;
+                sum += c > 0 ? c : params->steps;
+            }
+            o.mean_steps_run = sum / R;
+        }
     }
     return ISING_OK;
 }

@@ -112,7 +112,12 @@ struct DSArgs {
     const int32_t *pperm = nullptr;    // spin held at position q
     int32_t pms_rb = 0;                // bytes of one vertex region (pms_region_bytes)
     int32_t loss = ISING_LOSS_VERTEX;  // RELAXED: also z = J sin(theta) from an LDS copy of sin(theta)
+    // convergence test (off when conv_tol <= 0): each wavefront replays it on the step's losses
+    double conv_tol = 0.0;
+    int32_t conv_window = 5;
+    int32_t *conv_step = nullptr;      // nullable: R steps at which the test held (0: never)
 };
+constexpr int kConvWindowMax = 8;
 
 struct DSLaunch {
     int coupling = CK_CSRV;
@@ -121,6 +126,7 @@ struct DSLaunch {
     int ept = 1;     // spins per thread
     int block = 64;  // threads per workgroup
     bool relaxed = false;  // relaxed-vertex loss: LDS holds sin(theta) too (not with CK_PMS or streaming)
+    bool conv = false;     // convergence test: LDS holds each wavefront's window of losses
 };
 
 // Build the engine's device formats: pm entries (if sign-packed), values and h

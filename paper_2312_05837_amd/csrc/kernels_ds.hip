@@ -291,6 +291,12 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     constexpr bool CAN_RELAX = CK != CK_PMS;
     const bool relaxed = CAN_RELAX && a.loss == ISING_LOSS_RELAXED;
     Real *xb = (Real *)img;
+    // convergence test: per wavefront, the window of losses [kConvWindowMax][RG] and L_1 [RG]
+    const bool conv = a.conv_tol > 0;
+    const size_t img_off = (size_t)((unsigned char *)img - smem);
+    const size_t tail = img_off + (CK == CK_PMS ? (size_t)8 * a.pimg_groups
+                                                : (relaxed ? (size_t)2 * npad * RG * sizeof(Real) : 0));
+    Real *cring = (Real *)(smem + ((tail + 15) & ~(size_t)15)) + (size_t)wave * (kConvWindowMax + 1) * RG;
     int prow_r[CK == CK_PMS ? EPT : 1];
     uint32_t pcnt_r[CK == CK_PMS ? EPT : 1];
     int row_r[CK == CK_PMS ? EPT : 1];  // spin held at position e * B + tid
@@ -405,6 +411,9 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     const Real omb1 = (Real)(1.0 - a.b1), omb2 = (Real)(1.0 - a.b2);
     const Real *bct = (const Real *)a.bias;  // 1/(1-b1^t), 1/(1-b2^t) for this launch's steps
     const bool trace_l = a.ltrace != nullptr;
+    uint32_t done = 0;          // replicas that have stopped (identical in every wavefront)
+    int conv_t = 0;             // wave 0, lane r < RG: step at which replica r stopped
+    int tlast = a.steps;        // last step run
 
     for (int t = 1; t <= a.steps; ++t) {
         const SW *sc = vbuf((t - 1) & 1);
@@ -453,28 +462,30 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 } else {
                     Lp[r] = __builtin_fma(x, tt, Lp[r]);
                 }
-                const Real g = c * tt;
-                Real upd;
-                if (adam) {
-                    mo[k] = b1 * mo[k] + omb1 * g;
-                    ve[k] = b2 * ve[k] + omb2 * (g * g);
-                    upd = (mo[k] * lib1) * drcp(dsqrt(ve[k] * ib2) + eps);
-                } else {
-                    upd = lr * g;
-                }
-                Real tn = th[k] - upd;
-                const Real q = drint(tn * Consts<Real>::inv_twopi);
-                tn = tn - q * Consts<Real>::twopi_hi;
-                tn = tn - q * Consts<Real>::twopi_lo;
-                th[k] = tn;
-                Real xn;
-                if (KEEP) {
-                    Real cn;
-                    dsincos(tn, &xn, &cn);
-                    xs[k] = xn;
-                    cs[k] = cn;
-                } else {
-                    xn = dsin(tn);
+                Real xn = x;  // a stopped replica keeps its angle, moments and vertex
+                if (!((done >> r) & 1u)) {
+                    const Real g = c * tt;
+                    Real upd;
+                    if (adam) {
+                        mo[k] = b1 * mo[k] + omb1 * g;
+                        ve[k] = b2 * ve[k] + omb2 * (g * g);
+                        upd = (mo[k] * lib1) * drcp(dsqrt(ve[k] * ib2) + eps);
+                    } else {
+                        upd = lr * g;
+                    }
+                    Real tn = th[k] - upd;
+                    const Real q = drint(tn * Consts<Real>::inv_twopi);
+                    tn = tn - q * Consts<Real>::twopi_hi;
+                    tn = tn - q * Consts<Real>::twopi_lo;
+                    th[k] = tn;
+                    if (KEEP) {
+                        Real cn;
+                        dsincos(tn, &xn, &cn);
+                        xs[k] = xn;
+                        cs[k] = cn;
+                    } else {
+                        xn = dsin(tn);
+                    }
                 }
                 if (xn < 0) {
                     nxt |= 1u << k;
@@ -489,7 +500,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
             Ep[r] = wave_sum(Ep[r]);
-            if (trace_l) Lp[r] = wave_sum(Lp[r]);
+            if (trace_l || conv) Lp[r] = wave_sum(Lp[r]);
         }
         if (lane == 0) {
             Real *epo = ep + ((t & 1) * NW + wave) * RG;
@@ -524,7 +535,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     Ls += lp[((t & 1) * NW + w) * RG + lane];
                 }
                 const double E = (double)Es, L = (double)Ls;
-                imp = E < ebest;
+                imp = E < ebest && !((done >> lane) & 1u);  // a stopped replica is no longer scored
                 if (imp) {
                     ebest = E;
                     bstep = a.t0 + t;
@@ -535,10 +546,39 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
             const uint64_t bal = __ballot(imp);
             if (lane == 0) flg[t & 1] = (uint32_t)bal;
         }
+        if (conv) {
+            // every wavefront replays the test on the same loss (same order of summation as
+            // above), so all of them agree on which replicas stop after this step
+            bool now = false;
+            if (lane < RG && !((done >> lane) & 1u)) {
+                Real Ls = 0;
+                for (int w = 0; w < NW; ++w) Ls += lp[((t & 1) * NW + w) * RG + lane];
+                const int W = a.conv_window;
+                if (t == 1) cring[kConvWindowMax * RG + lane] = Ls;
+                cring[((t - 1) % W) * RG + lane] = Ls;
+                if (t >= W) {
+                    double mx = -INFINITY, mn = INFINITY;
+                    for (int q = 0; q < W; ++q) {
+                        const double v = (double)cring[q * RG + lane];
+                        mx = fmax(mx, v);
+                        mn = fmin(mn, v);
+                    }
+                    const double L1 = (double)cring[kConvWindowMax * RG + lane];
+                    now = mx - mn <= a.conv_tol * fabs((double)Ls - L1);
+                }
+                if (now) conv_t = a.t0 + t;
+            }
+            done |= (uint32_t)__ballot(now);
+            if (done == (1u << RG) - 1u) {  // every replica of this workgroup has stopped
+                tlast = t;
+                break;
+            }
+        }
     }
     __syncthreads();
-    if (a.steps > 0) {
-        const uint32_t f = flg[a.steps & 1];
+    if (a.conv_step && wave == 0 && lane < RG) a.conv_step[r0 + lane] = conv_t;
+    if (tlast > 0) {
+        const uint32_t f = flg[tlast & 1];
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
             if ((f >> r) & 1u) {
@@ -1171,6 +1211,7 @@ size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups) {
     size_t lds = ((sbytes + 15) & ~(size_t)15) + 2 * 2 * nw * l.rg * real + 8;
     if (l.coupling == CK_PMS) lds = ((lds + 15) & ~(size_t)15) + (size_t)8 * pimg_groups;
     if (l.relaxed) lds = ((lds + 15) & ~(size_t)15) + (size_t)2 * (l.ept * l.block + 1) * l.rg * real;
+    if (l.conv) lds = ((lds + 15) & ~(size_t)15) + (size_t)nw * (kConvWindowMax + 1) * l.rg * real;
     return lds;
 }
 

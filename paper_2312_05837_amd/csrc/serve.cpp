@@ -515,7 +515,8 @@ ising_status ising_submit(ising_ctx *ctx, const ising_problem *problem, const is
         if (!problem || problem->n <= 0 || params->replicas <= 0 || params->steps < 0) return ISING_EINVAL;
     }
     if (problem->value_type < ISING_I32 || problem->value_type > ISING_F64) return ISING_EINVAL;
-    if (params->loss != ISING_LOSS_VERTEX) return ISING_ENOTSUP;  // the batched launches run the vertex loss
+    // the batched launches run the vertex loss for fixed step counts
+    if (params->loss != ISING_LOSS_VERTEX || params->conv_tol > 0) return ISING_ENOTSUP;
     auto q = std::make_unique<Request>();
     q->prm = *params;
     q->hp = *problem;
