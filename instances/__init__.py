@@ -418,3 +418,50 @@ def make_request_instance(desc) -> Instance:
     if desc["kind"] == "sk_pm1":
         return sk_pm1(desc["n"], desc["seed"])
     return erdos_renyi(desc["n"], desc["p"], desc["seed"], "pm1")
+
+
+# ---- problem descriptions of the Table-3 shapes (Sec. IV-D) -------------------------------
+# These are inputs (edge lists, clauses, QUBO matrices); their conversion to Ising form is
+# the front-ends' work.
+
+def maxcut_regular_edges(n: int, k: int, seed: int) -> np.ndarray:
+    """Edges (m, 2) of a simple k-regular graph (MaxCut-3: k = 3), unit weights implied."""
+    rng = np.random.default_rng(seed)
+    ei, ej = random_regular_edges(n, k, rng)
+    return np.stack([ei, ej], axis=1)
+
+
+def maxcut_dense_edges(n: int, p: float, seed: int) -> np.ndarray:
+    """Edges (m, 2) of G(n, p) (MaxCut-D: p = 0.5)."""
+    rng = np.random.default_rng(seed)
+    iu, ju = np.triu_indices(n, 1)
+    mask = rng.random(iu.shape[0]) < p
+    return np.stack([iu[mask], ju[mask]], axis=1)
+
+
+def nae3sat_clauses(n: int, ratio: float, seed: int, planted: bool = False) -> np.ndarray:
+    """Random NAE-3SAT clauses (round(ratio n), 3) over distinct variables, literals +-(v + 1).
+
+    planted: clauses violated by a hidden assignment are redrawn, so it satisfies them all."""
+    rng = np.random.default_rng(seed)
+    m = int(round(ratio * n))
+    hidden = rng.choice([-1, 1], size=n)
+    out = np.zeros((m, 3), dtype=np.int64)
+    k = 0
+    while k < m:
+        v = rng.choice(n, size=3, replace=False)
+        sg = rng.choice([-1, 1], size=3)
+        if planted:
+            vals = sg * hidden[v]
+            if vals[0] == vals[1] == vals[2]:
+                continue
+        out[k] = sg * (v + 1)
+        k += 1
+    return out
+
+
+def sk_qubo_matrix(n: int, seed: int) -> np.ndarray:
+    """SK-QUBO shape: symmetric Q with off-diagonal entries iid in {0, 1}, zero diagonal."""
+    rng = np.random.default_rng(seed)
+    upper = np.triu(rng.integers(0, 2, size=(n, n)), 1)
+    return (upper + upper.T).astype(np.int64)

@@ -31,6 +31,8 @@ from .ds import (ds_run, ds_loss, ds_grad, ds_loss_relaxed, ds_grad_relaxed, wra
                  convergence_step)
 from .metrics import pruning_rate, chi_hat, tts_hat, speed
 from .solve import solve
+from .frontends import (qubo_value, qubo_to_ising, qubo_instance, maxcut_instance, cut_of,
+                        nae3sat_instance, nae_violated)
 
 __all__ = [
     "energy", "energies", "cut_value", "brute_force_min", "local_fields",
@@ -38,4 +40,6 @@ __all__ = [
     "ds_run", "ds_loss", "ds_grad", "ds_loss_relaxed", "ds_grad_relaxed", "wrap_angle", "DSResult",
     "converged", "convergence_step",
     "pruning_rate", "chi_hat", "tts_hat", "speed", "solve",
+    "qubo_value", "qubo_to_ising", "qubo_instance", "maxcut_instance", "cut_of", "nae3sat_instance",
+    "nae_violated",
 ]
