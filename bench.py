@@ -49,6 +49,10 @@ WORKLOADS = {
     "sk2000_fp32": ("dense SK N=2000 J~N(0,1/N), FP32 MFMA", "sk2000g", 4096, 2000, "fp32"),
     "er800_relaxed": ("sparse Erdos-Renyi N=800 p=0.06 +-1 weights, CSR, relaxed-vertex loss (s~* = sin theta)",
                       "er", 1024, 5000, "fp32", {"loss": "relaxed"}),
+    "maxcut3_1000": ("MaxCut-3 shape (Sec. IV-D): 3-regular N=1000, unit weights, through ising_from_maxcut",
+                     "maxcut3", 1024, 1000, "fp32"),
+    "nae3sat_1000": ("NAE-3SAT shape (Sec. IV-D): N=1000, 2110 random clauses, through ising_from_nae3sat",
+                     "nae3sat", 1024, 1000, "fp32"),
     "t1_binary_conv": ("Table-1-shaped 6-regular N=1000, J=+-1, h=+-12, ADAM lr 6 until the convergence test "
                        "(spread of the last 5 losses <= 0.005 of the loss decrease), at most 2000 steps",
                        "t1binary", 1024, 2000, "fp32", {"conv_tol": 0.005, "conv_window": 5}),
@@ -108,8 +112,25 @@ def copy_calibration():
                       "bytes_written": COPY_CALIBRATION_BYTES, "launches": 3}))
 
 
+PROBLEM = {}  # problem-level reading of the returned energy, filled by make_instance for front-end kinds
+
+
 def make_instance(kind):
+    import numpy as np
     import instances as I
+    if kind in ("maxcut3", "nae3sat"):
+        import paper_2312_05837_amd as P
+        n = 1000
+        if kind == "maxcut3":
+            edges = I.maxcut_regular_edges(n, 3, 0)
+            rp, col, val, W = P.ising_from_maxcut(n, edges)
+            PROBLEM.update(kind="maxcut", edges=int(len(edges)), read=lambda E: {"cut": (2 * W - E) / 4})
+        else:
+            cl = I.nae3sat_clauses(n, 2.11, 0)
+            rp, col, val, base = P.ising_from_nae3sat(n, cl)
+            PROBLEM.update(kind="nae3sat", clauses=int(len(cl)), read=lambda E: {"violated": (E + base) / 8})
+        return I.Instance(n, kind, np.zeros(n, dtype=np.int64), None, rp.astype(np.int64), col.astype(np.int64),
+                          val.astype(np.int64), True)
     if kind == "er":
         return I.erdos_renyi(800, 0.06, 0, "pm1")
     if kind == "torus800":
@@ -388,6 +409,9 @@ def main():
         "paper_context": {"hardware": "Apple M2 Pro core (paper, Sec. IV-C)",
                           "spin_updates_per_s_derived_from_table1": 3.2e5},
     }
+    if PROBLEM:
+        out["problem"] = {k: v for k, v in PROBLEM.items() if k != "read"}
+        out["problem"].update(PROBLEM["read"](e_final))
     P.ising_destroy(ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, R, T, args.optimizer, lr, mu, loss=loss)

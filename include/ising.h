@@ -330,6 +330,39 @@ ising_status ising_cancel(ising_ctx *ctx, uint64_t ticket);
 /* Counters of the scheduler. */
 ising_status ising_serve_query(ising_ctx *ctx, ising_serve_info *out);
 
+
+/* ---- problem front-ends (host buffers, no device work, no context) ------ */
+
+/* QUBO (the primal problem's binary form, Sec. II): minimise
+ * f(x) = x^T Q x + c^T x over x in {0,1}^n.  With x = (1 + s) / 2 and Q
+ * symmetrised as (Q + Q^T) / 2, f(x) = E(s) + *offset_out for the Ising
+ * problem J_ij = Q_ij / 4 (i != j), J_ii = 0, h_i = (sum_j Q_ij + c_i) / 2.
+ * Q: n*n row-major; c: n values or NULL (0).  J_out: n*n (dense, row-major),
+ * h_out: n; all caller-owned.  Errors: EINVAL for n <= 0, NULL buffers or
+ * non-finite entries. */
+ising_status ising_from_qubo(int32_t n, const double *Q, const double *c, double *J_out, double *h_out,
+                             double *offset_out);
+
+/* MaxCut (Sec. IV-D, MaxCut-3 / MaxCut-D): edges (2*m vertex indices, pairs
+ * a != b) with weights w (m values, NULL = 1).  The Ising problem is J = W,
+ * h = 0 (the convention of Table 3, E = 2 (m - 2 cut) for unit weights), so
+ * cut(s) = (2 *total_weight - E(s)) / 4.  Output CSR with both directions,
+ * duplicate edges summed, ascending columns.  Call once with row_ptr == NULL
+ * to get *nnz_out, then with row_ptr (n+1), col (nnz) and val (nnz).
+ * Errors: EINVAL for bad indices, self-loops or non-finite weights. */
+ising_status ising_from_maxcut(int32_t n, int64_t m, const int32_t *edges, const double *w, int32_t *row_ptr,
+                               int32_t *col, double *val, int64_t *nnz_out, double *total_weight);
+
+/* NAE-3SAT (Sec. IV-D): m clauses of three literals, +(v+1) for variable v
+ * true (spin +1) and -(v+1) for false.  A clause is violated when its three
+ * literal values are equal.  J_ab = sum of sign_a sign_b over the literal pairs
+ * of all clauses (integers, as in Table 3), h = 0; the number of violated
+ * clauses is U(s) = (E(s) + *base_out) / 8.  Output CSR with int32 values;
+ * sizing call with row_ptr == NULL as for MaxCut.  Errors: EINVAL for a zero
+ * or out-of-range literal. */
+ising_status ising_from_nae3sat(int32_t n, int64_t m, const int32_t *lits, int32_t *row_ptr, int32_t *col,
+                                int32_t *val, int64_t *nnz_out, int64_t *base_out);
+
 #ifdef __cplusplus
 }
 #endif

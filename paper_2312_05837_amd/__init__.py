@@ -119,6 +119,11 @@ _sigs = {
     "ising_wait": (C.c_int, [_P, C.c_uint64, C.c_int32, _P, C.POINTER(C.c_double), C.POINTER(ising_stats)]),
     "ising_cancel": (C.c_int, [_P, C.c_uint64]),
     "ising_serve_query": (C.c_int, [_P, C.POINTER(ising_serve_info)]),
+    "ising_from_qubo": (C.c_int, [C.c_int32, _P, _P, _P, _P, C.POINTER(C.c_double)]),
+    "ising_from_maxcut": (C.c_int, [C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_double)]),
+    "ising_from_nae3sat": (C.c_int, [C.c_int32, C.c_int64, _P, _P, _P, _P, C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64)]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -476,3 +481,53 @@ def ising_serve_query(ctx) -> dict:
     info = ising_serve_info()
     _check(ctx, _lib.ising_serve_query(ctx, C.byref(info)))
     return info.as_dict()
+
+
+# ---- problem front-ends (host buffers) ----------------------------------------------------
+
+def _host_check(status, what):
+    if status != ISING_OK:
+        raise IsingError(status, what)
+
+
+def ising_from_qubo(Q, c=None):
+    """(J, h, offset) with x^T Q x + c^T x = E(s) + offset, x = (1 + s) / 2."""
+    import numpy as np
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    n = Q.shape[0]
+    cc = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+    J = np.zeros((n, n)); h = np.zeros(n); off = C.c_double()
+    _host_check(_lib.ising_from_qubo(n, Q.ctypes.data, None if cc is None else cc.ctypes.data, J.ctypes.data,
+                                     h.ctypes.data, C.byref(off)), "ising_from_qubo")
+    return J, h, off.value
+
+
+def ising_from_maxcut(n, edges, w=None):
+    """CSR (row_ptr, col, val float64) of J = W and the total edge weight."""
+    import numpy as np
+    e = np.ascontiguousarray(np.asarray(edges).reshape(-1, 2), dtype=np.int32)
+    m = e.shape[0]
+    ww = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    nnz = C.c_int64(); W = C.c_double()
+    args = (n, m, e.ctypes.data, None if ww is None else ww.ctypes.data)
+    _host_check(_lib.ising_from_maxcut(*args, None, None, None, C.byref(nnz), C.byref(W)), "ising_from_maxcut")
+    rp = np.zeros(n + 1, dtype=np.int32); col = np.zeros(nnz.value, dtype=np.int32)
+    val = np.zeros(nnz.value, dtype=np.float64)
+    _host_check(_lib.ising_from_maxcut(*args, rp.ctypes.data, col.ctypes.data, val.ctypes.data, C.byref(nnz),
+                                       C.byref(W)), "ising_from_maxcut")
+    return rp, col, val, W.value
+
+
+def ising_from_nae3sat(n, clauses):
+    """CSR (row_ptr, col, val int32) of the NAE-3SAT couplings and base: violated = (E + base) / 8."""
+    import numpy as np
+    cl = np.ascontiguousarray(np.asarray(clauses).reshape(-1, 3), dtype=np.int32)
+    m = cl.shape[0]
+    nnz = C.c_int64(); base = C.c_int64()
+    _host_check(_lib.ising_from_nae3sat(n, m, cl.ctypes.data, None, None, None, C.byref(nnz), C.byref(base)),
+                "ising_from_nae3sat")
+    rp = np.zeros(n + 1, dtype=np.int32); col = np.zeros(nnz.value, dtype=np.int32)
+    val = np.zeros(nnz.value, dtype=np.int32)
+    _host_check(_lib.ising_from_nae3sat(n, m, cl.ctypes.data, rp.ctypes.data, col.ctypes.data, val.ctypes.data,
+                                        C.byref(nnz), C.byref(base)), "ising_from_nae3sat")
+    return rp, col, val, base.value

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libising.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "serve.cpp", "kernels_validate.hip", "kernels_energy.hip", "kernels_prune.hip", "kernels_ds.hip", "kernels_dense.hip"]
+SOURCES = ["api.cpp", "serve.cpp", "frontends.cpp", "kernels_validate.hip", "kernels_energy.hip", "kernels_prune.hip", "kernels_ds.hip", "kernels_dense.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -56,3 +56,43 @@ def test_planted_nae3sat_is_satisfiable():
     inst, base = oracle.nae3sat_instance(n, cl)
     e_min, _, _ = oracle.brute_force_min(inst)
     assert (e_min + base) // 8 == 0
+
+
+# ---- the library's front-ends (host code of the C ABI) against the oracle's -------------------
+
+def test_library_qubo_matches_oracle():
+    import paper_2312_05837_amd as P
+    rng = np.random.default_rng(11)
+    Q = rng.normal(size=(30, 30))
+    c = rng.normal(size=30)
+    J, h, off = P.ising_from_qubo(Q, c)
+    Jo, ho, offo = oracle.qubo_to_ising(Q, c)
+    assert np.allclose(J, Jo, rtol=1e-15, atol=0) and np.allclose(h, ho, rtol=1e-14, atol=1e-14)
+    assert abs(off - offo) <= 1e-12 * (1 + abs(offo))
+
+
+def test_library_maxcut_and_nae3sat_match_oracle():
+    import paper_2312_05837_amd as P
+    n = 200
+    edges = I.maxcut_regular_edges(n, 3, 7)
+    edges = np.vstack([edges, edges[:5]])                      # duplicates are summed
+    rp, col, val, W = P.ising_from_maxcut(n, edges)
+    inst, Wo = oracle.maxcut_instance(n, edges)
+    assert W == Wo
+    assert np.array_equal(rp, inst.row_ptr) and np.array_equal(col, inst.col) and np.array_equal(val, inst.val)
+    cl = I.nae3sat_clauses(n, 2.11, 8)
+    cl = np.vstack([cl, [[3, -3, 5]]])
+    rp, col, val, base = P.ising_from_nae3sat(n, cl)
+    inst, baseo = oracle.nae3sat_instance(n, cl)
+    assert base == baseo
+    assert np.array_equal(rp, inst.row_ptr) and np.array_equal(col, inst.col) and np.array_equal(val, inst.val)
+
+
+def test_library_frontends_reject_bad_input():
+    import paper_2312_05837_amd as P
+    with pytest.raises(P.IsingError):
+        P.ising_from_maxcut(4, [[0, 0]])                       # self-loop
+    with pytest.raises(P.IsingError):
+        P.ising_from_nae3sat(4, [[1, 2, 5]])                   # variable out of range
+    with pytest.raises(P.IsingError):
+        P.ising_from_qubo(np.array([[np.inf]]))
