@@ -46,10 +46,10 @@ ising_status check_problem_shape(ising_ctx *ctx, const ising_problem *p) {
 
 ising_status ingest(ising_ctx *ctx, const DevProblem &p, Pool &pool, Ingest &out, hipStream_t s) {
     void *flags = nullptr, *wdev = nullptr;
-    HIP_TRY(ctx, pool.get("ingest.flags", 16, &flags));
+    HIP_TRY(ctx, pool.get("ingest.flags", 20, &flags));
     HIP_TRY(ctx, pool.get("ingest.w", 8, &wdev));
     HIP_TRY(ctx, launch_validate(p, (int32_t *)flags, (double *)wdev, s));
-    HIP_TRY(ctx, hipMemcpyAsync(out.flags, flags, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(out.flags, flags, 20, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipMemcpyAsync(&out.w, wdev, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     const int bits = out.flags[0];
@@ -192,6 +192,10 @@ ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params 
     l.relaxed = relaxed;
     l.conv = conv;
     plan.packed = p.format == ISING_CSR && ing.uniform_mag();
+    // small integer couplings (|J| <= kPmsMaxMult, not all equal) can still be staged, each
+    // coupling repeated |J| times with unit magnitude; they keep CSR values if the image does not fit
+    plan.mult = p.format == ISING_CSR && !plan.packed && ing.integer() && ing.max_abs_int() >= 1 &&
+                ing.max_abs_int() <= kPmsMaxMult;
     l.coupling = p.format == ISING_DENSE ? CK_DENSE : (plan.packed ? CK_PM : CK_CSRV);
     // register-resident engine while at most 4 (spin, replica) elements per thread
     // fit, else the streaming engine; replicas per workgroup chosen so that there
@@ -202,6 +206,7 @@ ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params 
             if (R % cand) continue;
             if (R / cand < 256) continue;
             if (plan.packed && cand == 4 && ing.maxdeg() > 255) continue;
+            if (plan.mult && cand == 4 && (int64_t)ing.maxdeg() * ing.max_abs_int() > 255) plan.mult = false;
             rg = cand;
             break;
         }
@@ -273,7 +278,8 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
     a.loss = prm.loss;
     a.conv_tol = prm.conv_tol > 0 ? prm.conv_tol : 0.0;
     a.conv_window = prm.conv_window;
-    if (plan.packed && plan.l.ept > 0 && !plan.l.relaxed) {
+    if ((plan.packed || plan.mult) && plan.l.ept > 0 && !plan.l.relaxed) {
+        const double wunit = plan.packed ? ing.w : 1.0;
         // stage the +-w couplings in LDS when the image fits next to the vertex buffers
         DSLaunch l2 = plan.l;
         l2.coupling = CK_PMS;
@@ -288,10 +294,10 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
             HIP_TRY(ctx, pool.get("ds.pms.pcnt", (size_t)slots * 4, (void **)&w.pcnt));
             HIP_TRY(ctx, pool.get("ds.pms.total", 4, (void **)&w.total));
             int32_t total = 0;
-            HIP_TRY(ctx, launch_pms_format(dp, l2, w, &total, s));
+            HIP_TRY(ctx, launch_pms_format(dp, l2, wunit, w, &total, s));
             if (ds_lds_bytes(l2, p.n, total) <= 160 * 1024) {
                 HIP_TRY(ctx, pool.get("ds.pms.img", (size_t)std::max(total, 1) * 8, (void **)&w.img));
-                HIP_TRY(ctx, launch_pms_format(dp, l2, w, &total, s));
+                HIP_TRY(ctx, launch_pms_format(dp, l2, wunit, w, &total, s));
                 plan.l = l2;
                 a.pimg = w.img;
                 a.pimg_groups = total;
@@ -299,6 +305,7 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
                 a.pcnt = w.pcnt;
                 a.pperm = w.perm;
                 a.pms_rb = rb;
+                a.w = wunit;
             }
         }
     }

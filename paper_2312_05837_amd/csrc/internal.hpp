@@ -149,8 +149,11 @@ struct PmsWork {
 int pms_region_bytes(const DSLaunch &l);
 // Sizing pass (w.img == nullptr): layout tables and the group count (synchronises s).
 // Fill pass: the image.
-hipError_t launch_pms_format(const DevProblem &p, const DSLaunch &l, PmsWork &w, int32_t *total_groups,
-                             hipStream_t s);
+// wunit: couplings are integer multiples of it (at most kPmsMaxMult); a coupling of
+// magnitude k wunit is staged k times.
+constexpr int kPmsMaxMult = 4;
+hipError_t launch_pms_format(const DevProblem &p, const DSLaunch &l, double wunit, PmsWork &w,
+                             int32_t *total_groups, hipStream_t s);
 size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups);
 // Batched persistent engine (FP32): workgroup b runs replica group map[b].y of
 // descs[map[b].x]; all descriptors share the launch configuration l.

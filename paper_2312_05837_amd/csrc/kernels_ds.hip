@@ -840,12 +840,18 @@ __device__ inline double csr_value_any(const DevProblem &p, int q) {
     return csr_value<double>(p, q);
 }
 
-// stored nonzero couplings of each row
-__global__ void k_pms_degree(DevProblem p, int32_t *deg) {
+// entries a coupling takes in the staged image: |v| / w for couplings that are integer
+// multiples of the unit w (one for the common magnitude of +-w problems)
+__device__ inline int pms_multiplicity(double v, double wunit) {
+    return v == 0.0 ? 0 : (int)rint(fabs(v) / wunit);
+}
+
+// entries of each row (its degree counted with multiplicity)
+__global__ void k_pms_degree(DevProblem p, double wunit, int32_t *deg) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
     int d = 0;
-    for (int q = p.row_ptr[i]; q < p.row_ptr[i + 1]; ++q) d += csr_value_any(p, q) != 0.0;
+    for (int q = p.row_ptr[i]; q < p.row_ptr[i + 1]; ++q) d += pms_multiplicity(csr_value_any(p, q), wunit);
     deg[i] = d;
 }
 
@@ -923,9 +929,9 @@ __global__ __launch_bounds__(256) void k_pms_units(int n, int B, int units, cons
 // Rows with more than kPmsSchedMax entries keep CSR order.
 constexpr int kPmsSchedMax = 128;
 
-__global__ __launch_bounds__(256) void k_pms_fill(DevProblem p, int slots, int block, int wbytes, int rb,
-                                                  const int32_t *pos, const int32_t *perm, const int32_t *prow,
-                                                  const uint32_t *pcnt, uint16_t *img) {
+__global__ __launch_bounds__(256) void k_pms_fill(DevProblem p, double wunit, int slots, int block, int wbytes,
+                                                  int rb, const int32_t *pos, const int32_t *perm,
+                                                  const int32_t *prow, const uint32_t *pcnt, uint16_t *img) {
     __shared__ uint16_t ent[32][kPmsSchedMax];    // remaining entries of each row
     __shared__ int rem[32];                        // their count (-1: row kept in CSR order)
     __shared__ uint32_t bank_words[kPmsSchedMax][32];  // per slot and bank: first two distinct words
@@ -948,19 +954,26 @@ __global__ __launch_bounds__(256) void k_pms_fill(DevProblem p, int slots, int b
             const int rs = p.row_ptr[i], re = p.row_ptr[i + 1];
             for (int c = rs; c < re; c += 8) {
                 const int e = c + s;
-                double v = 0.0;
+                int mult = 0;
                 uint16_t o = 0;
                 if (e < re) {
-                    v = csr_value_any(p, e);
+                    const double v = csr_value_any(p, e);
+                    mult = pms_multiplicity(v, wunit);
                     o = v > 0 ? (uint16_t)(wbytes * pos[p.col[e]]) : (uint16_t)(rb + wbytes * pos[p.col[e]]);
                 }
-                const uint32_t grp = (uint32_t)(__ballot(v != 0.0) >> (t & 56)) & 0xffu;
-                const int k = d + __popc(grp & ((1u << s) - 1u));
-                if (v != 0.0) {
+                // inclusive prefix of the multiplicities over the row's 8 lanes
+                int incl = mult;
+                for (int off = 1; off < 8; off <<= 1) {
+                    const int y = __shfl_up(incl, off, 8);
+                    if (s >= off) incl += y;
+                }
+                const int k0 = d + incl - mult;
+                for (int u = 0; u < mult; ++u) {
+                    const int k = k0 + u;
                     if (deg <= kPmsSchedMax) ent[j][k] = o;
                     else out[(size_t)(k >> 2) * 256 + (k & 3)] = o;
                 }
-                d += __popc(grp);
+                d += __shfl(incl, 7, 8);
             }
             if (deg > kPmsSchedMax)
                 for (int m = d + s; m < 4 * G; m += 8) out[(size_t)(m >> 2) * 256 + (m & 3)] = zero;
@@ -1179,13 +1192,13 @@ int pms_region_bytes(const DSLaunch &l) {
     return ((l.ept * l.block + 1) * wbytes + 255) / 256 * 256;
 }
 
-hipError_t launch_pms_format(const DevProblem &p, const DSLaunch &l, PmsWork &w, int32_t *total_groups,
-                             hipStream_t s) {
+hipError_t launch_pms_format(const DevProblem &p, const DSLaunch &l, double wunit, PmsWork &w,
+                             int32_t *total_groups, hipStream_t s) {
     const int slots = l.ept * l.block, units = slots / 64;
     if (l.ept <= 0 || slots < p.n || units > 256) return hipErrorInvalidValue;
     const dim3 g((p.n + 255) / 256);
     if (!w.img) {
-        hipLaunchKernelGGL(k_pms_degree, g, dim3(256), 0, s, p, w.deg);
+        hipLaunchKernelGGL(k_pms_degree, g, dim3(256), 0, s, p, wunit, w.deg);
         hipLaunchKernelGGL(k_pms_rank, g, dim3(256), 0, s, p.n, w.deg, w.pos, w.perm);
         hipLaunchKernelGGL(k_pms_units, dim3(1), dim3(256), 0, s, p.n, l.block, units, w.deg, w.perm, w.prow,
                            w.pcnt, w.total);
@@ -1196,8 +1209,8 @@ hipError_t launch_pms_format(const DevProblem &p, const DSLaunch &l, PmsWork &w,
         return hipGetLastError();
     }
     const int wbytes = l.rg == 1 ? 1 : 4;
-    hipLaunchKernelGGL(k_pms_fill, dim3(2 * units), dim3(256), 0, s, p, slots, l.block, wbytes, pms_region_bytes(l),
-                       w.pos, w.perm, w.prow, w.pcnt, w.img);
+    hipLaunchKernelGGL(k_pms_fill, dim3(2 * units), dim3(256), 0, s, p, wunit, slots, l.block, wbytes,
+                       pms_region_bytes(l), w.pos, w.perm, w.prow, w.pcnt, w.img);
     return hipGetLastError();
 }
 

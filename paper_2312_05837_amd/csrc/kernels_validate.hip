@@ -20,23 +20,32 @@ __device__ inline bool is_integral(double x) { return x == rint(x) && fabs(x) < 
 
 // Combine one thread's findings over the workgroup and publish them with at most
 // one atomic per flag and workgroup (every thread of the workgroup must call it).
-__device__ void publish_flags(int bits, int deg, bool uni, bool integ, int32_t *flags) {
-    __shared__ int s_bits, s_deg;
+__device__ void publish_flags(int bits, int deg, bool uni, bool integ, int32_t *flags, int maxabs = 0) {
+    __shared__ int s_bits, s_deg, s_abs;
     if (threadIdx.x == 0) {
         s_bits = 0;
         s_deg = 0;
+        s_abs = 0;
     }
     __syncthreads();
     if (bits) atomicOr(&s_bits, bits);
     if (deg > 0) atomicMax(&s_deg, deg);
+    if (maxabs > 0) atomicMax(&s_abs, maxabs);
     const bool any_nonuni = __syncthreads_or(!uni);
     const bool any_nonint = __syncthreads_or(!integ);
     if (threadIdx.x == 0) {
         if (s_bits) atomicOr(&flags[0], s_bits);
         if (s_deg > 0) atomicMax(&flags[1], s_deg);
+        if (s_abs > 0) atomicMax(&flags[4], s_abs);
         if (any_nonuni) atomicAnd(&flags[2], 0);
         if (any_nonint) atomicAnd(&flags[3], 0);
     }
+}
+
+// |a| as an int when a is integral and below 2^30 (0 otherwise): largest integer coupling magnitude
+__device__ inline int int_magnitude(double a) {
+    const double m = fabs(a);
+    return (m == floor(m) && m < 1073741824.0) ? (int)m : 0;
 }
 
 // flags: [0] error bits, [1] max degree (atomicMax), [2] uniform magnitude (cleared on mismatch),
@@ -62,13 +71,14 @@ __global__ __launch_bounds__(256) void validate_dense(DevProblem p, double w0, i
         Bt[yy][tx] = (i2 < n && j2 < n) ? load_val(p.J, p.vtype, (int64_t)i2 * n + j2) : 0.0;
     }
     __syncthreads();
-    int bits = 0;
+    int bits = 0, mabs = 0;
     bool uni = true, integ = true;
     for (int yy = ty; yy < 32; yy += 8) {
         const int i = bi * 32 + yy, j = bj * 32 + tx;
         if (i >= n || j >= n) continue;
         const double a = A[yy][tx];
         const double m = Bt[tx][yy];  // J[j][i]
+        mabs = max(mabs, max(int_magnitude(a), int_magnitude(m)));
         if (!isfinite(a)) bits |= 8;
         if (i == j) {
             if (a != 0.0) bits |= 2;
@@ -87,7 +97,7 @@ __global__ __launch_bounds__(256) void validate_dense(DevProblem p, double w0, i
             }
         }
     }
-    publish_flags(bits, 0, uni, integ, flags);
+    publish_flags(bits, 0, uni, integ, flags, mabs);
 }
 
 __global__ void dense_degree(DevProblem p, int32_t *flags) {
@@ -106,7 +116,7 @@ __global__ void dense_degree(DevProblem p, int32_t *flags) {
 __global__ void validate_csr(DevProblem p, double w0, int32_t *flags) {
     const int n = p.n;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int bits = 0;
+    int bits = 0, mabs = 0;
     bool uni = true, integ = true;
     int rs = 0, re = 0;
     if (i < n) {
@@ -128,6 +138,7 @@ __global__ void validate_csr(DevProblem p, double w0, int32_t *flags) {
         if (j == i) bits |= 2;
         const double a = load_val(p.val, p.vtype, k);
         if (!isfinite(a)) bits |= 8;
+        mabs = max(mabs, int_magnitude(a));
         if (fabs(a) != w0) uni = false;
         if (!is_integral(a)) integ = false;
         // symmetric partner: binary search row j for column i
@@ -149,7 +160,7 @@ __global__ void validate_csr(DevProblem p, double w0, int32_t *flags) {
         }
         if (found < 0 || load_val(p.val, p.vtype, found) != a) bits |= 1;
     }
-    publish_flags(bits, re - rs, uni, integ, flags);
+    publish_flags(bits, re - rs, uni, integ, flags, mabs);
 }
 
 __global__ void validate_h(DevProblem p, int32_t *flags) {
@@ -194,6 +205,7 @@ __global__ void init_flags(int32_t *flags) {
         flags[1] = 0;
         flags[2] = 1;
         flags[3] = 1;
+        flags[4] = 0;
     }
 }
 

@@ -100,10 +100,11 @@ ising_status fail(ising_ctx *ctx, ising_status st, const std::string &msg);
 ising_status check_problem_shape(ising_ctx *ctx, const ising_problem *p);
 
 struct Ingest {
-    int32_t flags[4] = {0, 0, 1, 1};
+    int32_t flags[5] = {0, 0, 1, 1, 0};
     bool integer() const { return flags[3] != 0; }
     bool uniform_mag() const { return flags[2] != 0; }
     int maxdeg() const { return flags[1]; }
+    int max_abs_int() const { return flags[4]; }  // largest |J| when J is integral
     double w = 1.0;
 };
 
@@ -114,7 +115,8 @@ ising_status prune_core(ising_ctx *ctx, const DevProblem &p, ising_pruned &pr, h
 
 struct DSPlan {
     DSLaunch l;
-    bool packed = false;
+    bool packed = false;  // +-w couplings: sign-packed formats
+    bool mult = false;    // small integer couplings: staged image with repeated entries, if it fits
 };
 // Launch plan of the persistent engine; with register_only the streaming form is never chosen.
 ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,

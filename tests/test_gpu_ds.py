@@ -94,7 +94,24 @@ def _hub_graph(n=600, hub_deg=300, seed=12):
     return I.from_edges(n + 1, edges, np.zeros(n + 1), "er600_plus_hub300")
 
 
+def _nae3sat(n=400, seed=16):
+    import oracle as O
+    inst, _ = O.nae3sat_instance(n, I.nae3sat_clauses(n, 2.11, seed))
+    return inst
+
+
+def _er_int3(n=700, p=0.03, seed=17):
+    """ER graph with integer weights in {+-1, +-2, +-3}: staged with repeated entries."""
+    rng = np.random.default_rng(seed)
+    er = I.erdos_renyi(n, p, seed, "pm1")
+    edges = [(i, int(er.col[q]), int(er.val[q]) * int(rng.integers(1, 4)))
+             for i in range(n) for q in range(er.row_ptr[i], er.row_ptr[i + 1]) if er.col[q] > i]
+    return I.from_edges(n, edges, np.zeros(n), "er_int3")
+
+
 MULTI = [
+    ("nae3sat_mult", _nae3sat, 64),
+    ("er_int3_mult_rg4", _er_int3, 1024),
     ("er3000_rg2_ept4", lambda: I.erdos_renyi(3000, 8.0 / 2999, 9, "pm1"), 512),
     ("hub_rg2", _hub_graph, 512),
     ("er1500_field_rg1_ept2", lambda: I.random_integer_field(I.erdos_renyi(1500, 0.01, 10, "pm1"), 10, 2), 16),
