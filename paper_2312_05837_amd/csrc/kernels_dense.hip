@@ -258,21 +258,21 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             }
         }
     } else {
-        // two chunks in flight in registers (sets 0 and 1 alternate), one in LDS
-        u16x8 pah[2][2], pal[2][2], pb[2][2];
-        auto gload = [&](int set, int k0) {
+        u16x8 pah[2], pal[2], pb[2];
+        auto gload = [&](int k0) {
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int q = tid + 256 * u;
                 const int r = q >> 2, c8 = (q & 3) * 8;
-                pah[set][u] = *(const u16x8 *)(a.Jhi + (size_t)(row0 + r) * a.Kp + k0 + c8);
-                if (FORM == DF_BF16X2) pal[set][u] = *(const u16x8 *)(a.Jlo + (size_t)(row0 + r) * a.Kp + k0 + c8);
-                pb[set][u] = (col0 + r < a.R)
-                                 ? *(const u16x8 *)((const unsigned short *)S_in + (size_t)(col0 + r) * a.Kp + k0 + c8)
-                                 : u16x8{};
+                pah[u] = *(const u16x8 *)(a.Jhi + (size_t)(row0 + r) * a.Kp + k0 + c8);
+                if (FORM == DF_BF16X2) pal[u] = *(const u16x8 *)(a.Jlo + (size_t)(row0 + r) * a.Kp + k0 + c8);
+                pb[u] = (col0 + r < a.R)
+                            ? *(const u16x8 *)((const unsigned short *)S_in + (size_t)(col0 + r) * a.Kp + k0 + c8)
+                            : u16x8{};
             }
         };
-        auto chunk = [&](int c, int set) {
+        gload(0);
+        for (int c = 0; c < nchunks; ++c) {
             unsigned short *Ah = (unsigned short *)lds + (c & 1) * (2 * BM + BN) * AST;
             unsigned short *Al = Ah + BM * AST;
             unsigned short *Bs = Al + BM * AST;
@@ -280,12 +280,12 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             for (int u = 0; u < 2; ++u) {
                 const int q = tid + 256 * u;
                 const int r = q >> 2, c8 = (q & 3) * 8;
-                *(u16x8 *)(Ah + r * AST + c8) = pah[set][u];
-                if (FORM == DF_BF16X2) *(u16x8 *)(Al + r * AST + c8) = pal[set][u];
-                *(u16x8 *)(Bs + r * AST + c8) = pb[set][u];
+                *(u16x8 *)(Ah + r * AST + c8) = pah[u];
+                if (FORM == DF_BF16X2) *(u16x8 *)(Al + r * AST + c8) = pal[u];
+                *(u16x8 *)(Bs + r * AST + c8) = pb[u];
             }
             __syncthreads();
-            if (c + 2 < nchunks) gload(set, (c + 2) * KC);
+            if (c + 1 < nchunks) gload((c + 1) * KC);
 #pragma unroll
             for (int ks = 0; ks < KC; ks += 16) {
                 const int kk = ks + 8 * (lane >> 5);
@@ -310,12 +310,6 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                         acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bv[bj], acc[bi][bj], 0, 0, 0);
                     }
             }
-        };
-        gload(0, 0);
-        if (nchunks > 1) gload(1, KC);
-        for (int c = 0; c < nchunks; c += 2) {
-            chunk(c, 0);
-            if (c + 1 < nchunks) chunk(c + 1, 1);
         }
     }
     __syncthreads();  // the epilogue reuses LDS
@@ -333,38 +327,42 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
     float h4[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) h4[u] = (a.h && i0 + u < a.n) ? a.h[i0 + u] : 0.f;
-    // the state of the next (half, k) is loaded before the current one is updated, so
-    // that each load's latency overlaps a step of work
-    float nth[4], nmo[4], nve[4];
-    auto load_state = [&](int half, int k) {
-        const int r = col0 + half * 64 + (tid >> 5) + 8 * k;
+    // The state of all 8 replicas a thread updates in one half is loaded at the start of
+    // that half (before the accumulators are transposed), so that its loads are in flight
+    // together: the epilogue is bound by this traffic.
+    float sth[8][4], smo[8][4], sve[8][4];
+    auto load_half = [&](int half) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) nth[u] = nmo[u] = nve[u] = 0.f;
-        if (r < a.R && i0 < a.n) {
-            const size_t base = (size_t)r * a.n + i0;
-            if (vec) {
-                const float4 t4 = *(const float4 *)(a.theta + base);
-                nth[0] = t4.x; nth[1] = t4.y; nth[2] = t4.z; nth[3] = t4.w;
-                if (adam) {
-                    const float4 m4 = *(const float4 *)(a.m + base);
-                    const float4 v4 = *(const float4 *)(a.v + base);
-                    nmo[0] = m4.x; nmo[1] = m4.y; nmo[2] = m4.z; nmo[3] = m4.w;
-                    nve[0] = v4.x; nve[1] = v4.y; nve[2] = v4.z; nve[3] = v4.w;
-                }
-            } else {
+        for (int k = 0; k < 8; ++k) {
+            const int r = col0 + half * 64 + (tid >> 5) + 8 * k;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const bool ok = i0 + u < a.n;
-                    nth[u] = ok ? a.theta[base + u] : 0.f;
-                    nmo[u] = (ok && adam) ? a.m[base + u] : 0.f;
-                    nve[u] = (ok && adam) ? a.v[base + u] : 0.f;
+            for (int u = 0; u < 4; ++u) sth[k][u] = smo[k][u] = sve[k][u] = 0.f;
+            if (r < a.R && i0 < a.n) {
+                const size_t base = (size_t)r * a.n + i0;
+                if (vec) {
+                    const float4 t4 = *(const float4 *)(a.theta + base);
+                    sth[k][0] = t4.x; sth[k][1] = t4.y; sth[k][2] = t4.z; sth[k][3] = t4.w;
+                    if (adam) {
+                        const float4 m4 = *(const float4 *)(a.m + base);
+                        const float4 v4 = *(const float4 *)(a.v + base);
+                        smo[k][0] = m4.x; smo[k][1] = m4.y; smo[k][2] = m4.z; smo[k][3] = m4.w;
+                        sve[k][0] = v4.x; sve[k][1] = v4.y; sve[k][2] = v4.z; sve[k][3] = v4.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const bool ok = i0 + u < a.n;
+                        sth[k][u] = ok ? a.theta[base + u] : 0.f;
+                        smo[k][u] = (ok && adam) ? a.m[base + u] : 0.f;
+                        sve[k][u] = (ok && adam) ? a.v[base + u] : 0.f;
+                    }
                 }
             }
         }
     };
-    load_state(0, 0);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
+        load_half(half);
         if (wn == half) {
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj)
@@ -385,12 +383,10 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             float th[4], mo[4], ve[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                th[u] = nth[u];
-                mo[u] = nmo[u];
-                ve[u] = nve[u];
+                th[u] = sth[k][u];
+                mo[u] = smo[k][u];
+                ve[u] = sve[k][u];
             }
-            if (k < 7) load_state(half, k + 1);
-            else if (half == 0) load_state(1, 0);
             float Ep = 0.f, Lp = 0.f;
             if (r < a.R && i0 < a.n) {
                 const float4 y4 = *(const float4 *)(T + rl * TST + 4 * g);
