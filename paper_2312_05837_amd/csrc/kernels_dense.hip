@@ -34,7 +34,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BM = 128, BN = 128, KC = 32;
-constexpr int AST = KC + 8;   // LDS row stride (bf16 elements) of the A and B chunks
+constexpr int AST = KC;       // LDS row stride (bf16 elements) of the A and B chunks (16-byte units swizzled)
 constexpr int FST = KC + 1;   // LDS row stride (floats) for the FP32 form
 constexpr int TST = BM + 4;   // LDS row stride (floats) of the transposed accumulator tile
 constexpr int GEMM_LDS_BF16 = (2 * BM + BN) * AST * 2;
@@ -49,6 +49,15 @@ __device__ inline float row_sum16(float v) {
     v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false));
     v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false));
     return v;
+}
+
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also orders
+// global memory, which makes every wavefront wait for all of its outstanding
+// global loads at each barrier and so drains the operand prefetch of the K loop.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 __device__ inline unsigned short bf16_bits(float x) {
@@ -80,6 +89,18 @@ __device__ inline void fsincos(float x, float *s, float *c) {
     const float b = (q & 1) ? sn : cn;
     *s = (q & 2) ? -a : a;
     *c = ((q + 1) & 2) ? -b : b;
+}
+
+// The sign of the sine that fsincos(x) returns, from its range reduction alone: in the odd
+// quadrants the sine is +-cos(r) (|r| <= pi/4, never zero), in the even ones +-sin(r), whose
+// polynomial keeps the sign of r.  Gives the same answer as fsincos(x) followed by x < 0.
+__device__ inline bool fsin_neg(float x) {
+    const float k = rintf(x * 0.636619772367581343f);
+    float r = __builtin_fmaf(-k, 1.57079637050628662f, x);
+    r = __builtin_fmaf(-k, -4.37113882867379300e-08f, r);
+    r = __builtin_fmaf(-k, -1.71512451000588190e-15f, r);
+    const int q = (int)k & 3;
+    return q == 3 || (q == 0 && r < 0.f) || (q == 2 && r > 0.f);
 }
 
 __device__ inline uint64_t splitmix64(uint64_t seed, uint64_t c) {
@@ -195,6 +216,52 @@ using DenseDesc = DenseDescT<plain_ptr>;
 using DenseDescG = DenseDescT<global_ptr>;
 static_assert(sizeof(DenseDesc) == sizeof(DenseDescG), "descriptor layouts must agree");
 
+// One K chunk of the BF16 operands held in registers: rows r = q / 4 (q = tid, tid + 256)
+// of the J tile (hi, and lo for the split form) and of the vertex tile, 8 bf16 each.
+struct BfStage {
+    u16x8 ah0, ah1, al0, al1, b0, b1;
+};
+// Element offset of 16-byte unit u (8 bf16, u = 0..3) of row r in an LDS chunk.  The unit
+// index is XORed with ((r >> 1) ^ (r >> 3)) & 3, so that both the stage stores (four lanes
+// per row) and the MFMA fragment reads (one row per lane, one unit) touch distinct banks.
+__device__ __forceinline__ int swz(int r, int u) { return r * AST + ((u ^ (r >> 1) ^ (r >> 3)) & 3) * 8; }
+
+template <int FORM>
+__device__ __forceinline__ BfStage bf_gload(const DenseDescG &a, const void *S_in, int row0, int col0, int k0, int tid) {
+    BfStage s;
+    const int r = tid >> 2, c8 = (tid & 3) * 8;
+    const size_t ja = (size_t)(row0 + r) * a.Kp + k0 + c8, jb = ja + (size_t)64 * a.Kp;
+    s.ah0 = *(const u16x8 *)(a.Jhi + ja);
+    s.ah1 = *(const u16x8 *)(a.Jhi + jb);
+    if (FORM == DF_BF16X2) {
+        s.al0 = *(const u16x8 *)(a.Jlo + ja);
+        s.al1 = *(const u16x8 *)(a.Jlo + jb);
+    } else {
+        s.al0 = s.al1 = u16x8{};
+    }
+    // replica rows past R read row R - 1 (no branch around the load); the stage store
+    // writes zeros for them
+    const unsigned short *Sb = (const unsigned short *)S_in;
+    s.b0 = *(const u16x8 *)(Sb + (size_t)min(col0 + r, a.R - 1) * a.Kp + k0 + c8);
+    s.b1 = *(const u16x8 *)(Sb + (size_t)min(col0 + r + 64, a.R - 1) * a.Kp + k0 + c8);
+    return s;
+}
+template <int FORM>
+__device__ __forceinline__ void bf_stage_store(unsigned short *Ah, const BfStage &s, int tid, bool ok0, bool ok1) {
+    unsigned short *Al = Ah + BM * AST;
+    unsigned short *Bs = Al + BM * AST;
+    const int r = tid >> 2, u = tid & 3;
+    const int o0 = swz(r, u), o1 = swz(r + 64, u);
+    *(u16x8 *)(Ah + o0) = s.ah0;
+    *(u16x8 *)(Ah + o1) = s.ah1;
+    if (FORM == DF_BF16X2) {
+        *(u16x8 *)(Al + o0) = s.al0;
+        *(u16x8 *)(Al + o1) = s.al1;
+    }
+    *(u16x8 *)(Bs + o0) = ok0 ? s.b0 : u16x8{};
+    *(u16x8 *)(Bs + o1) = ok1 ? s.b1 : u16x8{};
+}
+
 template <int FORM>
 __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int tloc, const int mt, const int nt) {
     __shared__ __align__(16) unsigned char lds[cmax(2 * (FORM == DF_FP32 ? GEMM_LDS_FP32 : GEMM_LDS_BF16), EPI_LDS)];
@@ -240,7 +307,7 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                 Bs[r * FST + c4] = pb[u].x; Bs[r * FST + c4 + 1] = pb[u].y;
                 Bs[r * FST + c4 + 2] = pb[u].z; Bs[r * FST + c4 + 3] = pb[u].w;
             }
-            __syncthreads();
+            lds_barrier();
             if (c + 1 < nchunks) gload((c + 1) * KC);
 #pragma unroll
             for (int ks = 0; ks < KC; ks += 2) {
@@ -258,49 +325,31 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             }
         }
     } else {
-        u16x8 pah[2], pal[2], pb[2];
-        auto gload = [&](int k0) {
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int q = tid + 256 * u;
-                const int r = q >> 2, c8 = (q & 3) * 8;
-                pah[u] = *(const u16x8 *)(a.Jhi + (size_t)(row0 + r) * a.Kp + k0 + c8);
-                if (FORM == DF_BF16X2) pal[u] = *(const u16x8 *)(a.Jlo + (size_t)(row0 + r) * a.Kp + k0 + c8);
-                pb[u] = (col0 + r < a.R)
-                            ? *(const u16x8 *)((const unsigned short *)S_in + (size_t)(col0 + r) * a.Kp + k0 + c8)
-                            : u16x8{};
-            }
-        };
-        gload(0);
-        for (int c = 0; c < nchunks; ++c) {
-            unsigned short *Ah = (unsigned short *)lds + (c & 1) * (2 * BM + BN) * AST;
-            unsigned short *Al = Ah + BM * AST;
-            unsigned short *Bs = Al + BM * AST;
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int q = tid + 256 * u;
-                const int r = q >> 2, c8 = (q & 3) * 8;
-                *(u16x8 *)(Ah + r * AST + c8) = pah[u];
-                if (FORM == DF_BF16X2) *(u16x8 *)(Al + r * AST + c8) = pal[u];
-                *(u16x8 *)(Bs + r * AST + c8) = pb[u];
-            }
-            __syncthreads();
-            if (c + 1 < nchunks) gload((c + 1) * KC);
+        // Three chunks in flight in registers (stages s0, s1, s2, refilled in turn), LDS
+        // double-buffered, one LDS-only barrier per chunk.  The global loads are issued
+        // unconditionally (the last chunk is re-read past the end) so that the wait for
+        // the oldest stage is a fixed count of outstanding loads.
+        const bool bok0 = col0 + (tid >> 2) < a.R, bok1 = col0 + (tid >> 2) + 64 < a.R;
+        BfStage s0 = bf_gload<FORM>(a, S_in, row0, col0, 0, tid);
+        BfStage s1 = bf_gload<FORM>(a, S_in, row0, col0, min(1, nchunks - 1) * KC, tid);
+        BfStage s2 = bf_gload<FORM>(a, S_in, row0, col0, min(2, nchunks - 1) * KC, tid);
+        auto mfma_chunk = [&](int c) {
+            const unsigned short *Ah = (const unsigned short *)lds + (c & 1) * (2 * BM + BN) * AST;
+            const unsigned short *Al = Ah + BM * AST;
+            const unsigned short *Bs = Al + BM * AST;
 #pragma unroll
             for (int ks = 0; ks < KC; ks += 16) {
-                const int kk = ks + 8 * (lane >> 5);
+                const int u = (ks >> 3) + (lane >> 5);
                 bf16x8 ah[2], al[2], bv[2];
 #pragma unroll
                 for (int bi = 0; bi < 2; ++bi) {
-                    const int r = wm * 64 + bi * 32 + (lane & 31);
-                    ah[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Ah + r * AST + kk));
-                    if (FORM == DF_BF16X2) al[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Al + r * AST + kk));
+                    const int o = swz(wm * 64 + bi * 32 + (lane & 31), u);
+                    ah[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Ah + o));
+                    if (FORM == DF_BF16X2) al[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Al + o));
                 }
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
-                    const int cc = wn * 64 + bj * 32 + (lane & 31);
-                    bv[bj] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Bs + cc * AST + kk));
-                }
+                for (int bj = 0; bj < 2; ++bj)
+                    bv[bj] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Bs + swz(wn * 64 + bj * 32 + (lane & 31), u)));
 #pragma unroll
                 for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -310,9 +359,27 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                         acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bv[bj], acc[bi][bj], 0, 0, 0);
                     }
             }
-        }
+        };
+#define DENSE_BF_CHUNK(C, ST)                                                                          \
+    {                                                                                                  \
+        const int c_ = (C);                                                                            \
+        bf_stage_store<FORM>((unsigned short *)lds + (c_ & 1) * (2 * BM + BN) * AST, ST, tid, bok0, bok1); \
+        __builtin_amdgcn_sched_barrier(0);                                                             \
+        ST = bf_gload<FORM>(a, S_in, row0, col0, min(c_ + 3, nchunks - 1) * KC, tid);                 \
+        lds_barrier();                                                                                 \
+        mfma_chunk(c_);                                                                                \
     }
-    __syncthreads();  // the epilogue reuses LDS
+        int c = 0;
+        for (; c + 3 <= nchunks; c += 3) {
+            DENSE_BF_CHUNK(c, s0);
+            DENSE_BF_CHUNK(c + 1, s1);
+            DENSE_BF_CHUNK(c + 2, s2);
+        }
+        if (c < nchunks) DENSE_BF_CHUNK(c, s0);
+        if (c + 1 < nchunks) DENSE_BF_CHUNK(c + 1, s1);
+#undef DENSE_BF_CHUNK
+    }
+    lds_barrier();  // the epilogue reuses LDS
 
     // ---- fused epilogue.  The accumulators (C block (bi, bj), lane l, element q hold
     // row 64 wm + 32 bi + 8 (q / 4) + 4 (l / 32) + q % 4, column 64 wn + 32 bj + l % 32) are
@@ -375,7 +442,7 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                         T[nl * TST + m] = acc[bi][bj][q];
                     }
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int rl = (tid >> 5) + 8 * k;        // replica within this half
@@ -418,10 +485,9 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                     tn = tn - kq * 6.28318548202514648f;
                     tn = tn - kq * -1.7484555314695172e-07f;
                     th[u] = tn;
-                    float xn, cn;
-                    fsincos(tn, &xn, &cn);
-                    sf[u] = live ? (xn < 0.f ? -1.f : 1.f) : 0.f;
-                    sb[u] = bf16_bits(sf[u]);
+                    const bool nn = fsin_neg(tn);
+                    sf[u] = live ? (nn ? -1.f : 1.f) : 0.f;
+                    sb[u] = live ? (nn ? (unsigned short)0xBF80 : (unsigned short)0x3F80) : (unsigned short)0;  // bf16 of sf
                 }
                 if (vec) {
                     *(float4 *)(a.theta + base) = make_float4(th[0], th[1], th[2], th[3]);
@@ -469,7 +535,7 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                 red_l[0][rw + 1] = l_hi;
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
     if (tid < BN && col0 + tid < a.R) {
         a.Epart[(size_t)mt * a.R + col0 + tid] = red_e[0][tid];
