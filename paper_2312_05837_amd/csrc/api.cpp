@@ -380,7 +380,7 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
     d.n = n;
     d.R = R;
     d.Mp = (n + 127) / 128 * 128;
-    d.Kp = (n + 31) / 32 * 32;
+    d.Kp = (n + 63) / 64 * 64;  // the BF16 forms read K in chunks of 64
     d.form = form;
     d.opt = prm.optimizer;
     d.seed = prm.seed;

@@ -34,10 +34,11 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BM = 128, BN = 128, KC = 32;
-constexpr int AST = KC;       // LDS row stride (bf16 elements) of the A and B chunks (16-byte units swizzled)
+constexpr int KCB = 64;       // K chunk of the BF16 forms: one 128-byte line per row and chunk
+constexpr int AST = KCB;      // LDS row stride (bf16 elements) of the BF16 chunks (16-byte units swizzled)
 constexpr int FST = KC + 1;   // LDS row stride (floats) for the FP32 form
 constexpr int TST = BM + 4;   // LDS row stride (floats) of the transposed accumulator tile
-constexpr int GEMM_LDS_BF16 = (2 * BM + BN) * AST * 2;
+constexpr int GEMM_LDS_BF16 = (BM + BN) * AST * 2;  // J hi (or J lo) and vertex rows of one chunk
 constexpr int GEMM_LDS_FP32 = (BM + BN) * FST * 4;
 constexpr int EPI_LDS = 64 * TST * 4;
 constexpr int cmax(int x, int y) { return x > y ? x : y; }
@@ -216,55 +217,54 @@ using DenseDesc = DenseDescT<plain_ptr>;
 using DenseDescG = DenseDescT<global_ptr>;
 static_assert(sizeof(DenseDesc) == sizeof(DenseDescG), "descriptor layouts must agree");
 
-// One K chunk of the BF16 operands held in registers: rows r = q / 4 (q = tid, tid + 256)
-// of the J tile (hi, and lo for the split form) and of the vertex tile, 8 bf16 each.
+// One K chunk (64) of the BF16 operands held in registers: rows tid / 8 + 32 p (p = 0..3)
+// of the J tile (hi, and lo for the split form) and of the vertex tile, 8 bf16 at 16-byte
+// unit tid % 8.  Eight lanes read one row's 128-byte line of the chunk: the loads use whole
+// cache lines (half lines with a chunk of 32 limit the misses a CU's vector cache holds).
 struct BfStage {
-    u16x8 ah0, ah1, al0, al1, b0, b1;
+    u16x8 ah[4], al[4], b[4];
 };
-// Element offset of 16-byte unit u (8 bf16, u = 0..3) of row r in an LDS chunk.  The unit
-// index is XORed with ((r >> 1) ^ (r >> 3)) & 3, so that both the stage stores (four lanes
-// per row) and the MFMA fragment reads (one row per lane, one unit) touch distinct banks.
-__device__ __forceinline__ int swz(int r, int u) { return r * AST + ((u ^ (r >> 1) ^ (r >> 3)) & 3) * 8; }
+// Element offset of 16-byte unit u (8 bf16, u = 0..7) of row r in an LDS chunk.  The unit
+// index is XORed with (r ^ (r >> 3)) & 7, so that the MFMA fragment reads (one row per
+// lane, one unit) touch distinct banks.
+__device__ __forceinline__ int swz(int r, int u) { return r * AST + ((u ^ r ^ (r >> 3)) & 7) * 8; }
 
 template <int FORM>
 __device__ __forceinline__ BfStage bf_gload(const DenseDescG &a, const void *S_in, int row0, int col0, int k0, int tid) {
     BfStage s;
-    const int r = tid >> 2, c8 = (tid & 3) * 8;
-    const size_t ja = (size_t)(row0 + r) * a.Kp + k0 + c8, jb = ja + (size_t)64 * a.Kp;
-    s.ah0 = *(const u16x8 *)(a.Jhi + ja);
-    s.ah1 = *(const u16x8 *)(a.Jhi + jb);
-    if (FORM == DF_BF16X2) {
-        s.al0 = *(const u16x8 *)(a.Jlo + ja);
-        s.al1 = *(const u16x8 *)(a.Jlo + jb);
-    } else {
-        s.al0 = s.al1 = u16x8{};
-    }
-    // replica rows past R read row R - 1 (no branch around the load); the stage store
-    // writes zeros for them
+    const int rr = tid >> 3, c8 = (tid & 7) * 8;
     const unsigned short *Sb = (const unsigned short *)S_in;
-    s.b0 = *(const u16x8 *)(Sb + (size_t)min(col0 + r, a.R - 1) * a.Kp + k0 + c8);
-    s.b1 = *(const u16x8 *)(Sb + (size_t)min(col0 + r + 64, a.R - 1) * a.Kp + k0 + c8);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const size_t ja = (size_t)(row0 + rr + 32 * p) * a.Kp + k0 + c8;
+        s.ah[p] = *(const u16x8 *)(a.Jhi + ja);
+        s.al[p] = FORM == DF_BF16X2 ? *(const u16x8 *)(a.Jlo + ja) : u16x8{};
+        // replica rows past R read row R - 1 (no branch around the load); the stage store
+        // writes zeros for them
+        s.b[p] = *(const u16x8 *)(Sb + (size_t)min(col0 + rr + 32 * p, a.R - 1) * a.Kp + k0 + c8);
+    }
     return s;
 }
+// the J part goes to Ah (hi) and Al (lo), the vertex part to Bs
 template <int FORM>
-__device__ __forceinline__ void bf_stage_store(unsigned short *Ah, const BfStage &s, int tid, bool ok0, bool ok1) {
-    unsigned short *Al = Ah + BM * AST;
-    unsigned short *Bs = Al + BM * AST;
-    const int r = tid >> 2, u = tid & 3;
-    const int o0 = swz(r, u), o1 = swz(r + 64, u);
-    *(u16x8 *)(Ah + o0) = s.ah0;
-    *(u16x8 *)(Ah + o1) = s.ah1;
-    if (FORM == DF_BF16X2) {
-        *(u16x8 *)(Al + o0) = s.al0;
-        *(u16x8 *)(Al + o1) = s.al1;
+__device__ __forceinline__ void bf_stage_store(unsigned short *Ah, unsigned short *Al, unsigned short *Bs,
+                                               const BfStage &s, int tid, int col0, int R) {
+    const int rr = tid >> 3, u = tid & 7;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int o = swz(rr + 32 * p, u);
+        *(u16x8 *)(Ah + o) = s.ah[p];
+        if (FORM == DF_BF16X2) *(u16x8 *)(Al + o) = s.al[p];
+        *(u16x8 *)(Bs + o) = col0 + rr + 32 * p < R ? s.b[p] : u16x8{};
     }
-    *(u16x8 *)(Bs + o0) = ok0 ? s.b0 : u16x8{};
-    *(u16x8 *)(Bs + o1) = ok1 ? s.b1 : u16x8{};
 }
 
 template <int FORM>
 __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int tloc, const int mt, const int nt) {
-    __shared__ __align__(16) unsigned char lds[cmax(2 * (FORM == DF_FP32 ? GEMM_LDS_FP32 : GEMM_LDS_BF16), EPI_LDS)];
+    __shared__ __align__(16) unsigned char lds[cmax(FORM == DF_FP32    ? 2 * GEMM_LDS_FP32
+                                                    : FORM == DF_BF16X2 ? GEMM_LDS_BF16 + BM * AST * 2
+                                                                        : 2 * GEMM_LDS_BF16,
+                                                    EPI_LDS)];
     __shared__ float red_e[1][BN], red_l[1][BN];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -325,21 +325,27 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             }
         }
     } else {
-        // Three chunks in flight in registers (stages s0, s1, s2, refilled in turn), LDS
-        // double-buffered, one LDS-only barrier per chunk.  The global loads are issued
-        // unconditionally (the last chunk is re-read past the end) so that the wait for
-        // the oldest stage is a fixed count of outstanding loads.
-        const bool bok0 = col0 + (tid >> 2) < a.R, bok1 = col0 + (tid >> 2) + 64 < a.R;
+        // NST chunks in flight in registers (stages refilled in turn, NST chunks ahead), one
+        // LDS-only barrier per chunk with two LDS buffers (the BF16 form), or two barriers
+        // per chunk with one buffer (the split form, whose J hi and lo chunks leave no room
+        // for a second buffer at two workgroups per CU).  The global loads are issued
+        // unconditionally (the last chunk is re-read past the end) so that the wait for the
+        // oldest stage is a fixed count of outstanding loads.
+        constexpr int NST = FORM == DF_BF16X2 ? 2 : 3;
+        constexpr int NBUF = FORM == DF_BF16X2 ? 1 : 2;
+        constexpr int BUF = FORM == DF_BF16X2 ? (2 * BM + BN) * AST : (BM + BN) * AST;  // bf16 elements
+        const int nch = a.Kp / KCB, last = nch - 1;
         BfStage s0 = bf_gload<FORM>(a, S_in, row0, col0, 0, tid);
-        BfStage s1 = bf_gload<FORM>(a, S_in, row0, col0, min(1, nchunks - 1) * KC, tid);
-        BfStage s2 = bf_gload<FORM>(a, S_in, row0, col0, min(2, nchunks - 1) * KC, tid);
+        BfStage s1 = bf_gload<FORM>(a, S_in, row0, col0, min(1, last) * KCB, tid);
+        BfStage s2;
+        if (NST == 3) s2 = bf_gload<FORM>(a, S_in, row0, col0, min(2, last) * KCB, tid);
         auto mfma_chunk = [&](int c) {
-            const unsigned short *Ah = (const unsigned short *)lds + (c & 1) * (2 * BM + BN) * AST;
-            const unsigned short *Al = Ah + BM * AST;
-            const unsigned short *Bs = Al + BM * AST;
+            const unsigned short *Ah = (const unsigned short *)lds + (NBUF == 2 ? (c & 1) * BUF : 0);
+            const unsigned short *Bs = Ah + BM * AST;
+            const unsigned short *Al = Bs + BN * AST;
 #pragma unroll
-            for (int ks = 0; ks < KC; ks += 16) {
-                const int u = (ks >> 3) + (lane >> 5);
+            for (int ks = 0; ks < KCB / 16; ++ks) {
+                const int u = 2 * ks + (lane >> 5);
                 bf16x8 ah[2], al[2], bv[2];
 #pragma unroll
                 for (int bi = 0; bi < 2; ++bi) {
@@ -363,20 +369,30 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
 #define DENSE_BF_CHUNK(C, ST)                                                                          \
     {                                                                                                  \
         const int c_ = (C);                                                                            \
-        bf_stage_store<FORM>((unsigned short *)lds + (c_ & 1) * (2 * BM + BN) * AST, ST, tid, bok0, bok1); \
+        unsigned short *Ah_ = (unsigned short *)lds + (NBUF == 2 ? (c_ & 1) * BUF : 0);              \
+        if (NBUF == 1 && c_ > 0) lds_barrier();                                                        \
+        bf_stage_store<FORM>(Ah_, Ah_ + (BM + BN) * AST, Ah_ + BM * AST, ST, tid, col0, a.R);          \
         __builtin_amdgcn_sched_barrier(0);                                                             \
-        ST = bf_gload<FORM>(a, S_in, row0, col0, min(c_ + 3, nchunks - 1) * KC, tid);                 \
+        ST = bf_gload<FORM>(a, S_in, row0, col0, min(c_ + NST, last) * KCB, tid);                     \
         lds_barrier();                                                                                 \
         mfma_chunk(c_);                                                                                \
     }
         int c = 0;
-        for (; c + 3 <= nchunks; c += 3) {
-            DENSE_BF_CHUNK(c, s0);
-            DENSE_BF_CHUNK(c + 1, s1);
-            DENSE_BF_CHUNK(c + 2, s2);
+        if constexpr (NST == 3) {
+            for (; c + 3 <= nch; c += 3) {
+                DENSE_BF_CHUNK(c, s0);
+                DENSE_BF_CHUNK(c + 1, s1);
+                DENSE_BF_CHUNK(c + 2, s2);
+            }
+            if (c < nch) DENSE_BF_CHUNK(c, s0);
+            if (c + 1 < nch) DENSE_BF_CHUNK(c + 1, s1);
+        } else {
+            for (; c + 2 <= nch; c += 2) {
+                DENSE_BF_CHUNK(c, s0);
+                DENSE_BF_CHUNK(c + 1, s1);
+            }
+            if (c < nch) DENSE_BF_CHUNK(c, s0);
         }
-        if (c < nchunks) DENSE_BF_CHUNK(c, s0);
-        if (c + 1 < nchunks) DENSE_BF_CHUNK(c + 1, s1);
 #undef DENSE_BF_CHUNK
     }
     lds_barrier();  // the epilogue reuses LDS
@@ -690,7 +706,7 @@ hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps,
     std::vector<int2> quads;
     for (int k = 0; k < count; ++k) {
         const DenseRun &d = *runs[k];
-        if (d.form != form || d.Mp % BM || d.Kp % KC || d.Mp < d.n || d.Kp < d.n) return hipErrorInvalidValue;
+        if (d.form != form || d.Mp % BM || d.Kp % KCB || d.Mp < d.n || d.Kp < d.n) return hipErrorInvalidValue;
         if (d.opt == ISING_OPT_ADAM && !d.bias) return hipErrorInvalidValue;
         descs.push_back(make_desc(d));
         for (int nt = 0; nt < (d.R + BN - 1) / BN; ++nt)

@@ -104,7 +104,7 @@ size_t footprint(const Request &q) {
     const size_t vs = vsize(q.hp.value_type);
     size_t b = 0;
     if (q.hp.format == ISING_DENSE) {
-        const size_t Mp = (n + 127) / 128 * 128, Kp = (n + 31) / 32 * 32;
+        const size_t Mp = (n + 127) / 128 * 128, Kp = (n + 63) / 64 * 64;
         b += n * n * vs;                 // J
         b += Mp * Kp * 4;                // split or FP32 operand
         b += 2 * R * Kp * 4;             // vertex buffers
