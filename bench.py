@@ -47,6 +47,9 @@ WORKLOADS = {
     "sk2000_bf16x2": ("dense SK N=2000 J~N(0,1/N), J split hi/lo BF16 on MFMA", "sk2000g", 4096, 2000, "bf16x2"),
     "sk2000_bf16": ("dense SK N=2000 J~N(0,1/N), J in BF16 on MFMA", "sk2000g", 4096, 2000, "bf16"),
     "sk2000_fp32": ("dense SK N=2000 J~N(0,1/N), FP32 MFMA", "sk2000g", 4096, 2000, "fp32"),
+    "sk2000pm1_fp8": ("dense SK N=2000 J=+-1, J and the vertex in FP8 on MFMA (exact)", "sk2000pm1", 4096, 2000, "fp8"),
+    "sk2000pm1_bf16": ("dense SK N=2000 J=+-1, J and the vertex in BF16 on MFMA (exact)", "sk2000pm1", 4096, 2000,
+                       "bf16"),
     "er800_relaxed": ("sparse Erdos-Renyi N=800 p=0.06 +-1 weights, CSR, relaxed-vertex loss (s~* = sin theta)",
                       "er", 1024, 5000, "fp32", {"loss": "relaxed"}),
     "maxcut3_1000": ("MaxCut-3 shape (Sec. IV-D): 3-regular N=1000, unit weights, through ising_from_maxcut",
@@ -58,7 +61,7 @@ WORKLOADS = {
                        "t1binary", 1024, 2000, "fp32", {"conv_tol": 0.005, "conv_window": 5}),
 }
 # peak rates of the matrix cores (dense, no sparsity), per precision of the coupling product
-MFMA_PEAK = {"bf16x2": 2.5e15, "bf16": 2.5e15, "fp32": 157.3e12}
+MFMA_PEAK = {"bf16x2": 2.5e15, "bf16": 2.5e15, "fp8": 5.0e15, "fp32": 157.3e12}
 
 # Sources of each dominant kernel: a recorded HBM traffic figure is used only
 # while these files are unchanged since the counters were taken.
@@ -143,6 +146,8 @@ def make_instance(kind):
         return I.random_regular(20000, 3, 0, "pm1")
     if kind == "sk2000g":
         return I.sk_gauss(2000, 0)
+    if kind == "sk2000pm1":
+        return I.sk_pm1(2000, 0)
     if kind == "t1binary":
         return I.table1_regular(1000, 6, "binary_int", 0)
     raise ValueError(kind)
@@ -355,14 +360,14 @@ def main():
     if nnzG is None:
         import oracle
         nnzG = int(oracle.prune(inst).reduced.nnz)
-    dense_mfma = inst.is_dense and (prec in ("bf16x2", "bf16") or (prec == "fp32" and nG > 256))
+    dense_mfma = inst.is_dense and (prec in ("bf16x2", "bf16", "fp8") or (prec == "fp32" and nG > 256))
     if dense_mfma:
         # the coupling product J S~ on the matrix cores: 2 n_G^2 R flops per step; integer
-        # couplings of one magnitude <= 256 run the (exact) BF16 form even when FP32 is asked
+        # couplings of one magnitude run the (exact) FP8 form even when FP32 is asked
         form = prec
         if prec == "fp32" and inst.integer and len(np.unique(np.abs(inst.J[inst.J != 0]))) <= 1 \
-                and np.abs(inst.J).max() <= 256:
-            form = "bf16"
+                and np.abs(inst.J).max() * nG < 2 ** 24:
+            form = "fp8"
         ops = 2.0 * nG * nG * R * T
         achieved = ops / (k_ms * 1e-3)
         roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_PEAK[form] / 1e12, "unit": "TFLOP/s",
@@ -393,7 +398,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x2": "bf16x2/f32", "bf16": "bf16/f32"}[prec],
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x2": "bf16x2/f32", "bf16": "bf16/f32", "fp8": "fp8/f32"}[prec],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n": inst.n, "n_G": nG, "nnz": int(inst.nnz),
                    "replicas": R, "ds_steps": T, "mean_steps_run": T_eff, "optimizer": args.optimizer, "lr": lr,

@@ -74,9 +74,14 @@ enum { ISING_LOSS_VERTEX = 0, ISING_LOSS_RELAXED = 1 };
  * gradient) and coupling product in that precision.  BF16X2 and BF16 (dense
  * couplings on the matrix cores only): FP32 iterates, coupling product with J
  * split into two BF16 parts (J = J_hi + J_lo) or rounded to one BF16, the
- * vertex (+-1) exact in BF16, FP32 accumulation; the energy of the returned
- * vector is always recomputed in FP64 (or exactly for integer J). */
-enum { ISING_PREC_FP64 = 0, ISING_PREC_FP32 = 1, ISING_PREC_BF16X2 = 2, ISING_PREC_BF16 = 3 };
+ * vertex (+-1) exact in BF16, FP32 accumulation.  FP8 (dense couplings whose
+ * nonzero values are integers of one magnitude w, with n w < 2^24, e.g. +-1;
+ * ENOTSUP otherwise): J / w and the vertex exact in FP8 (E4M3) on the matrix
+ * cores, FP32 accumulation, FP32 iterates; every product and sum is exact, so
+ * the results equal the FP32 form's bit for bit, and an FP32 request on such
+ * couplings runs this form.  The energy of the returned vector is always
+ * recomputed in FP64 (or exactly for integer J). */
+enum { ISING_PREC_FP64 = 0, ISING_PREC_FP32 = 1, ISING_PREC_BF16X2 = 2, ISING_PREC_BF16 = 3, ISING_PREC_FP8 = 4 };
 
 typedef struct ising_problem {
     int32_t n;           /* spin count, > 0 */
@@ -95,7 +100,7 @@ typedef struct ising_params {
     int32_t replicas;    /* R >= 1 independent trajectories */
     int32_t steps;       /* T >= 0 iterations */
     int32_t optimizer;   /* ISING_OPT_GD or ISING_OPT_ADAM */
-    int32_t precision;   /* ISING_PREC_FP64 or ISING_PREC_FP32 */
+    int32_t precision;   /* ISING_PREC_* (BF16X2, BF16 and FP8: dense couplings only) */
     double lr;           /* learning rate (the paper uses 6.0 with ADAM) */
     double mu;           /* augmented-Lagrangian weight mu > 0 of the L1-norm form */
     double beta1, beta2, eps;  /* ADAM constants (Kingma-Ba defaults 0.9, 0.999, 1e-8) */
@@ -261,7 +266,8 @@ int32_t ising_ds_max_n(int32_t precision);
 /* The same steps for a dense problem on the matrix cores: each step is one
  * launch computing Y = J S~ for a 128-spin x 128-replica tile with MFMA
  * (precision FP32: v_mfma_f32_32x32x2_f32; BF16X2 / BF16: v_mfma_f32_32x32x16_bf16
- * on J_hi (+ J_lo)), with the elementwise update fused into the tile epilogue,
+ * on J_hi (+ J_lo); FP8, and FP32 on couplings of one integer magnitude:
+ * v_mfma_f32_32x32x64_f8f6f4 on J / w), with the elementwise update fused into the tile epilogue,
  * plus a small launch that keeps each replica's best energy.  State arrays are
  * float (theta, m, v), traces and e_best double; energies tracked during the
  * run are those of the chosen form (FP32 accumulation).  Any R >= 1; n up to

@@ -360,18 +360,22 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
 }
 
 ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, Pool &pool,
-                           hipStream_t s, DenseRun &d, bool exact_bf16) {
+                           hipStream_t s, DenseRun &d, double unit) {
     if (p.format != ISING_DENSE) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine needs dense couplings");
     if (prm.loss != ISING_LOSS_VERTEX) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs the vertex loss");
     if (prm.conv_tol > 0) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs fixed step counts");
     int form;
-    // integer couplings of magnitude <= 256 are exact in BF16 and their products
-    // are summed exactly in FP32, so the BF16 form gives the FP32 form's results bit for bit
-    if (prm.precision == ISING_PREC_FP32 && exact_bf16) form = DF_BF16;
+    // couplings of one integer magnitude w: J / w and the vertex are exact in FP8 and every
+    // product and partial sum is an integer below 2^24, so the FP8 form gives the FP32
+    // form's results bit for bit
+    if (prm.precision == ISING_PREC_FP32 && unit > 0) form = DF_FP8;
     else if (prm.precision == ISING_PREC_FP32) form = DF_FP32;
     else if (prm.precision == ISING_PREC_BF16X2) form = DF_BF16X2;
     else if (prm.precision == ISING_PREC_BF16) form = DF_BF16;
-    else return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs FP32, BF16X2 or BF16");
+    else if (prm.precision == ISING_PREC_FP8 && unit > 0) form = DF_FP8;
+    else if (prm.precision == ISING_PREC_FP8)
+        return fail(ctx, ISING_ENOTSUP, "the FP8 form needs couplings of one integer magnitude w with n w < 2^24");
+    else return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs FP32, BF16X2, BF16 or FP8");
     if (prm.replicas <= 0) return fail(ctx, ISING_EINVAL, "bad replicas");
     if (prm.optimizer != ISING_OPT_GD && prm.optimizer != ISING_OPT_ADAM)
         return fail(ctx, ISING_EINVAL, "unknown optimizer");
@@ -380,7 +384,9 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
     d.n = n;
     d.R = R;
     d.Mp = (n + 127) / 128 * 128;
-    d.Kp = (n + 63) / 64 * 64;  // the BF16 forms read K in chunks of 64
+    // the K loops read 128 bytes of each row per chunk: 64 BF16 or 128 FP8 values
+    d.Kp = form == DF_FP8 ? (n + 127) / 128 * 128 : (n + 63) / 64 * 64;
+    d.jscale = form == DF_FP8 ? (float)unit : 1.f;
     d.form = form;
     d.opt = prm.optimizer;
     d.seed = prm.seed;
@@ -394,11 +400,11 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
     if (form == DF_FP32) {
         HIP_TRY(ctx, pool.get("dn.Jf", mk * 4, &Jf));
     } else {
-        HIP_TRY(ctx, pool.get("dn.Jhi", mk * 2, &Jhi));
+        HIP_TRY(ctx, pool.get("dn.Jhi", mk * (form == DF_FP8 ? 1 : 2), &Jhi));
         if (form == DF_BF16X2) HIP_TRY(ctx, pool.get("dn.Jlo", mk * 2, &Jlo));
     }
     if (p.h) HIP_TRY(ctx, pool.get("dn.h", (size_t)n * 4, &hf));
-    HIP_TRY(ctx, pool.get("dn.S", (size_t)2 * R * d.Kp * (form == DF_FP32 ? 4 : 2), &S));
+    HIP_TRY(ctx, pool.get("dn.S", (size_t)2 * R * d.Kp * (form == DF_FP32 ? 4 : form == DF_FP8 ? 1 : 2), &S));
     HIP_TRY(ctx, pool.get("dn.Ep", (size_t)(d.Mp / 128) * R * 4, &Ep));
     HIP_TRY(ctx, pool.get("dn.Lp", (size_t)(d.Mp / 128) * R * 4, &Lp));
     HIP_TRY(ctx, launch_dense_prepare(to_dev(p), form, d.Mp, d.Kp, Jhi, Jlo, Jf, (float *)hf, s));
@@ -413,14 +419,14 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
 }
 
 ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const void *uniform,
-                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s, bool exact_bf16,
+                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s, double unit,
                        hipEvent_t kbeg, hipEvent_t kend) {
     if (steps < 0 || t0 < 0) return fail(ctx, ISING_EINVAL, "bad steps/t0");
     if (!st || !st->theta || !st->s_best || !st->e_best || !st->best_step)
         return fail(ctx, ISING_EINVAL, "state buffers missing");
     if (prm.optimizer == ISING_OPT_ADAM && (!st->m || !st->v)) return fail(ctx, ISING_EINVAL, "ADAM needs m and v");
     DenseRun d;
-    ST_TRY(prepare_dense(ctx, p, prm, pool, s, d, exact_bf16));
+    ST_TRY(prepare_dense(ctx, p, prm, pool, s, d, unit));
     d.t0 = t0;
     d.steps = steps;
     d.init_mode = t0 > 0 ? 0 : (uniform ? 1 : 2);
@@ -456,12 +462,13 @@ constexpr int kDenseMfmaMinN = 256;  // n above which dense FP32 problems use MF
 
 bool use_dense_engine(const ising_problem &p, const ising_params &prm) {
     if (p.format != ISING_DENSE || prm.loss != ISING_LOSS_VERTEX || prm.conv_tol > 0) return false;
-    if (prm.precision == ISING_PREC_BF16X2 || prm.precision == ISING_PREC_BF16) return true;
+    if (prm.precision == ISING_PREC_BF16X2 || prm.precision == ISING_PREC_BF16 || prm.precision == ISING_PREC_FP8)
+        return true;
     return prm.precision == ISING_PREC_FP32 && p.n > kDenseMfmaMinN;
 }
 
-bool exact_in_bf16(const Ingest &ing, int n) {
-    return ing.integer() && ing.uniform_mag() && ing.w <= 256.0 && (double)n * ing.w < 16777216.0;
+double exact_unit(const Ingest &ing, int n) {
+    return ing.integer() && ing.uniform_mag() && (double)n * ing.w < 16777216.0 ? ing.w : 0.0;
 }
 
 double ms_between(hipEvent_t a, hipEvent_t b) {
@@ -638,7 +645,7 @@ ising_status ising_ds_dense_dev(ising_ctx *ctx, const ising_problem *problem, co
     hipStream_t s = (hipStream_t)stream;
     Ingest ing;
     ST_TRY(ingest(ctx, to_dev(*problem), ctx->pool, ing, s));
-    return run_dense(ctx, *problem, *params, uniform, t0, steps, state, ctx->pool, s, exact_in_bf16(ing, problem->n));
+    return run_dense(ctx, *problem, *params, uniform, t0, steps, state, ctx->pool, s, exact_unit(ing, problem->n));
 }
 
 ising_status ising_select_dev(ising_ctx *ctx, const double *e_best, int32_t replicas, int32_t *best,
@@ -692,8 +699,9 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
     const int nG = red->n;
     const int R = params->replicas;
     const bool dense_engine = use_dense_engine(*red, *params);
-    if (!dense_engine && (params->precision == ISING_PREC_BF16X2 || params->precision == ISING_PREC_BF16))
-        return fail(ctx, ISING_ENOTSUP, "BF16 forms need dense couplings");
+    if (!dense_engine && (params->precision == ISING_PREC_BF16X2 || params->precision == ISING_PREC_BF16 ||
+                          params->precision == ISING_PREC_FP8))
+        return fail(ctx, ISING_ENOTSUP, "BF16 and FP8 forms need dense couplings");
     const size_t real = params->precision == ISING_PREC_FP64 ? 8 : 4;
     int32_t *bestdev = nullptr;
     int8_t *sG = nullptr;
@@ -713,7 +721,7 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
         HIP_TRY(ctx, pool.get("solve.bstep", (size_t)R * 4, (void **)&st.best_step));
         if (params->conv_tol > 0) HIP_TRY(ctx, pool.get("solve.conv", (size_t)R * 4, (void **)&st.conv_step));
         if (dense_engine)
-            ST_TRY(run_dense(ctx, *red, *params, nullptr, 0, params->steps, &st, pool, s, exact_in_bf16(ing, red->n),
+            ST_TRY(run_dense(ctx, *red, *params, nullptr, 0, params->steps, &st, pool, s, exact_unit(ing, red->n),
                              ev[5], ev[6]));
         else ST_TRY(run_ds(ctx, *red, *params, ing, nullptr, 0, params->steps, &st, pool, s, ev[5], ev[6]));
         HIP_TRY(ctx, hipEventRecord(ev[3], s));

@@ -166,13 +166,14 @@ hipError_t launch_gather_row(const int8_t *block, int32_t n, const int32_t *best
                              hipStream_t s);
 
 // ---- domain selection for dense couplings on MFMA (kernels_dense.hip) --------
-enum DenseForm { DF_FP32 = 0, DF_BF16X2 = 1, DF_BF16 = 2 };
+enum DenseForm { DF_FP32 = 0, DF_BF16X2 = 1, DF_BF16 = 2, DF_FP8 = 3 };
 
 struct DenseRun {
     int n = 0, R = 0, Mp = 0, Kp = 0, form = DF_BF16X2, opt = ISING_OPT_ADAM, t0 = 0, steps = 0, init_mode = 2;
     int reinit = 1;
     uint64_t seed = 0;
     double lr = 6.0, mu = 0.5, b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    float jscale = 1.f;  // FP8 form: the common magnitude w of the couplings (operand J / w)
     const void *Jhi = nullptr, *Jlo = nullptr, *Jf = nullptr;
     const float *h = nullptr;
     const void *uniform = nullptr;

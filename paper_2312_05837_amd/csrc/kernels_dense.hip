@@ -16,6 +16,8 @@
 //             S~ = +-1 exact in BF16, two v_mfma_f32_32x32x16_bf16 per k-step
 //             into the same FP32 accumulators
 //   DF_BF16   J_hi only
+//   DF_FP8    couplings of one integer magnitude w: J / w = -1, 0, +1 and the vertex
+//             exact in FP8 (E4M3), v_mfma_f32_32x32x64_f8f6f4, y = w (J / w) S~ exact
 // Tile: 128 spins x 128 replicas per workgroup of four wavefronts (2 x 2, each
 // 64 x 64 = 2 x 2 MFMA blocks of 32 x 32), K staged through LDS in chunks of 32.
 // Operand layouts: J padded row-major [Mp][Kp]; S~ replica-major [R][Kp]
@@ -32,6 +34,8 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BM = 128, BN = 128, KC = 32;
 constexpr int KCB = 64;       // K chunk of the BF16 forms: one 128-byte line per row and chunk
@@ -68,6 +72,11 @@ __device__ inline unsigned short bf16_bits(float x) {
     return (unsigned short)(r >> 16);
 }
 __device__ inline float bf16_to_f(unsigned short b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+// FP8 (E4M3) bytes of -1, 0, +1 as the conversion instruction writes them, so that they are
+// read back by the matrix cores in the same format
+__device__ inline unsigned char fp8_of(float x) {
+    return (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
+}
 
 // float sin/cos for |x| <= 4 (same construction as the persistent engine's)
 __device__ inline void fsincos(float x, float *s, float *c) {
@@ -126,6 +135,9 @@ __global__ void k_dense_split(DevProblem p, int Mp, int Kp, int form, unsigned s
         const double v = (i < p.n && j < p.n) ? (double)((const V *)p.J)[(size_t)i * p.n + j] : 0.0;
         if (form == DF_FP32) {
             Jf[q] = (float)v;
+        } else if (form == DF_FP8) {
+            // J / w is -1, 0 or +1 (the caller checked one integer magnitude w)
+            ((unsigned char *)Jhi)[q] = fp8_of(v == 0.0 ? 0.f : (v < 0.0 ? -1.f : 1.f));
         } else {
             const float vf = (float)v;
             const unsigned short hi = bf16_bits(vf);
@@ -170,6 +182,9 @@ __global__ void k_dense_init(int n, int R, int Kp, int form, int init_mode, uint
         if (form == DF_FP32) {
             ((float *)S)[q] = s;
             ((float *)S_other)[q] = 0.f;  // the other buffer's padding must be zero too
+        } else if (form == DF_FP8) {
+            ((unsigned char *)S)[q] = fp8_of(s);
+            ((unsigned char *)S_other)[q] = 0;
         } else {
             ((unsigned short *)S)[q] = bf16_bits(s);
             ((unsigned short *)S_other)[q] = 0;
@@ -200,6 +215,7 @@ struct DenseDescT {
     int n, R, Mp, Kp, opt, mtiles;
     float lr, mu, b1, b2, eps, omb1, omb2;
     int t0;                  // global step before the chunk
+    float jscale;            // y = jscale * (J S~) of the stored operand (w for the FP8 form, else 1)
     Ptr<const float> bias;   // 1/(1-b1^t), 1/(1-b2^t) of the chunk's steps, at 2 (tloc - 1)
     Ptr<const unsigned short> Jhi, Jlo;
     Ptr<const float> Jf;
@@ -233,15 +249,16 @@ template <int FORM>
 __device__ __forceinline__ BfStage bf_gload(const DenseDescG &a, const void *S_in, int row0, int col0, int k0, int tid) {
     BfStage s;
     const int rr = tid >> 3, c8 = (tid & 7) * 8;
+    const size_t kpu = FORM == DF_FP8 ? a.Kp >> 1 : a.Kp;  // row length in 2-byte units
     const unsigned short *Sb = (const unsigned short *)S_in;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-        const size_t ja = (size_t)(row0 + rr + 32 * p) * a.Kp + k0 + c8;
+        const size_t ja = (size_t)(row0 + rr + 32 * p) * kpu + k0 + c8;
         s.ah[p] = *(const u16x8 *)(a.Jhi + ja);
         s.al[p] = FORM == DF_BF16X2 ? *(const u16x8 *)(a.Jlo + ja) : u16x8{};
         // replica rows past R read row R - 1 (no branch around the load); the stage store
         // writes zeros for them
-        s.b[p] = *(const u16x8 *)(Sb + (size_t)min(col0 + rr + 32 * p, a.R - 1) * a.Kp + k0 + c8);
+        s.b[p] = *(const u16x8 *)(Sb + (size_t)min(col0 + rr + 32 * p, a.R - 1) * kpu + k0 + c8);
     }
     return s;
 }
@@ -331,10 +348,11 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
         // for a second buffer at two workgroups per CU).  The global loads are issued
         // unconditionally (the last chunk is re-read past the end) so that the wait for the
         // oldest stage is a fixed count of outstanding loads.
-        constexpr int NST = FORM == DF_BF16X2 ? 2 : 3;
+        constexpr int NST = FORM == DF_BF16 ? 3 : 2;  // register budget: two workgroups per CU
         constexpr int NBUF = FORM == DF_BF16X2 ? 1 : 2;
         constexpr int BUF = FORM == DF_BF16X2 ? (2 * BM + BN) * AST : (BM + BN) * AST;  // bf16 elements
-        const int nch = a.Kp / KCB, last = nch - 1;
+        // chunks of 128 bytes per row: 64 BF16 or 128 FP8 values of k
+        const int nch = (FORM == DF_FP8 ? a.Kp >> 1 : a.Kp) / KCB, last = nch - 1;
         BfStage s0 = bf_gload<FORM>(a, S_in, row0, col0, 0, tid);
         BfStage s1 = bf_gload<FORM>(a, S_in, row0, col0, min(1, last) * KCB, tid);
         BfStage s2;
@@ -343,6 +361,36 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             const unsigned short *Ah = (const unsigned short *)lds + (NBUF == 2 ? (c & 1) * BUF : 0);
             const unsigned short *Bs = Ah + BM * AST;
             const unsigned short *Al = Bs + BN * AST;
+            if constexpr (FORM == DF_FP8) {
+                // 32 bytes (k 64 ks + 32 (l / 32) .. + 31) per lane and operand; both operands put
+                // the same k in the same lane slot, so the k order inside the instruction is immaterial
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const int u = 4 * ks + 2 * (lane >> 5);
+                    i32x8 af[2], bf[2];
+#pragma unroll
+                    for (int bi = 0; bi < 2; ++bi) {
+                        const int r = wm * 64 + bi * 32 + (lane & 31);
+                        const i32x4 lo = __builtin_bit_cast(i32x4, *(const u16x8 *)(Ah + swz(r, u)));
+                        const i32x4 hi = __builtin_bit_cast(i32x4, *(const u16x8 *)(Ah + swz(r, u + 1)));
+                        af[bi] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+                    }
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj) {
+                        const int r = wn * 64 + bj * 32 + (lane & 31);
+                        const i32x4 lo = __builtin_bit_cast(i32x4, *(const u16x8 *)(Bs + swz(r, u)));
+                        const i32x4 hi = __builtin_bit_cast(i32x4, *(const u16x8 *)(Bs + swz(r, u + 1)));
+                        bf[bj] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+                    }
+#pragma unroll
+                    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < 2; ++bj)
+                            acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[bi], bf[bj], acc[bi][bj],
+                                                                                         0, 0, 0, 0, 0, 0);
+                }
+                return;
+            }
 #pragma unroll
             for (int ks = 0; ks < KCB / 16; ++ks) {
                 const int u = 2 * ks + (lane >> 5);
@@ -403,6 +451,7 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
     // thread then owns 4 consecutive spins of a replica: the state streams as float4
     // with 32 lanes covering 128 consecutive spins of one replica.
     const bool adam = a.opt == ISING_OPT_ADAM;
+    const unsigned char f8p = FORM == DF_FP8 ? fp8_of(1.f) : 0, f8m = FORM == DF_FP8 ? fp8_of(-1.f) : 0;
     float *T = (float *)lds;  // [64 replicas][TST]
     const int g = tid & 31;   // spin group: rows 4g .. 4g+3 of the tile
     const int i0 = row0 + 4 * g;
@@ -473,7 +522,10 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             float Ep = 0.f, Lp = 0.f;
             if (r < a.R && i0 < a.n) {
                 const float4 y4 = *(const float4 *)(T + rl * TST + 4 * g);
-                const float yv[4] = {y4.x, y4.y, y4.z, y4.w};
+                float yv[4] = {y4.x, y4.y, y4.z, y4.w};
+                if constexpr (FORM == DF_FP8)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) yv[u] *= a.jscale;  // exact: integers below 2^24
                 const size_t base = (size_t)r * a.n + i0;
                 unsigned short sb[4];
                 float sf[4];
@@ -522,9 +574,14 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                             }
                         }
                 }
-                const size_t sbase = (size_t)r * a.Kp + i0;  // Kp % 32 == 0, i0 % 4 == 0: aligned
+                const size_t sbase = (size_t)r * a.Kp + i0;  // Kp % 64 == 0, i0 % 4 == 0: aligned
                 if (FORM == DF_FP32) {
                     *(float4 *)((float *)S_out + sbase) = make_float4(sf[0], sf[1], sf[2], sf[3]);
+                } else if (FORM == DF_FP8) {
+                    uint32_t w = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) w |= (uint32_t)(sf[u] == 0.f ? 0 : sf[u] < 0.f ? f8m : f8p) << (8 * u);
+                    *(uint32_t *)((unsigned char *)S_out + sbase) = w;
                 } else {
                     const uint2 w = make_uint2((uint32_t)sb[0] | ((uint32_t)sb[1] << 16),
                                                (uint32_t)sb[2] | ((uint32_t)sb[3] << 16));
@@ -600,6 +657,14 @@ __global__ __launch_bounds__(256) void k_dense_best(const DenseDesc *__restrict_
                     const float4 p1 = *(const float4 *)((const float *)S_t + src + i + 4);
                     sv[0] = p0.x; sv[1] = p0.y; sv[2] = p0.z; sv[3] = p0.w;
                     sv[4] = p1.x; sv[5] = p1.y; sv[6] = p1.z; sv[7] = p1.w;
+                } else if (form == DF_FP8) {
+                    // the sign bit of an FP8 value is its top bit
+                    const uint2 p8 = *(const uint2 *)((const unsigned char *)S_t + src + i);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        sv[u] = (p8.x >> (8 * u + 7)) & 1 ? -1.f : 1.f;
+                        sv[u + 4] = (p8.y >> (8 * u + 7)) & 1 ? -1.f : 1.f;
+                    }
                 } else {
                     const u16x8 p8 = *(const u16x8 *)((const unsigned short *)S_t + src + i);
 #pragma unroll
@@ -615,8 +680,9 @@ __global__ __launch_bounds__(256) void k_dense_best(const DenseDesc *__restrict_
             }
         } else {
             for (int i = lane; i < a.n; i += 64) {
-                const float sv = form == DF_FP32 ? ((const float *)S_t)[src + i]
-                                                 : bf16_to_f(((const unsigned short *)S_t)[src + i]);
+                const float sv = form == DF_FP32  ? ((const float *)S_t)[src + i]
+                                 : form == DF_FP8 ? (((const unsigned char *)S_t)[src + i] & 0x80 ? -1.f : 1.f)
+                                                  : bf16_to_f(((const unsigned short *)S_t)[src + i]);
                 a.s_best[dst + i] = sv < 0.f ? (int8_t)-1 : (int8_t)1;
             }
         }
@@ -671,7 +737,8 @@ static DenseDesc make_desc(const DenseRun &d) {
     a.Jlo = (const unsigned short *)d.Jlo;
     a.Jf = (const float *)d.Jf;
     a.h = d.h;
-    const size_t sbytes = d.form == DF_FP32 ? 4 : 2;
+    const size_t sbytes = d.form == DF_FP32 ? 4 : d.form == DF_FP8 ? 1 : 2;
+    a.jscale = d.form == DF_FP8 ? d.jscale : 1.f;
     a.S0 = (char *)d.S;
     a.S1 = (char *)d.S + (size_t)d.R * d.Kp * sbytes;
     a.theta = d.theta;
@@ -706,7 +773,7 @@ hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps,
     std::vector<int2> quads;
     for (int k = 0; k < count; ++k) {
         const DenseRun &d = *runs[k];
-        if (d.form != form || d.Mp % BM || d.Kp % KCB || d.Mp < d.n || d.Kp < d.n) return hipErrorInvalidValue;
+        if (d.form != form || d.Mp % BM || d.Kp % (d.form == DF_FP8 ? 2 * KCB : KCB) || d.Mp < d.n || d.Kp < d.n) return hipErrorInvalidValue;
         if (d.opt == ISING_OPT_ADAM && !d.bias) return hipErrorInvalidValue;
         descs.push_back(make_desc(d));
         for (int nt = 0; nt < (d.R + BN - 1) / BN; ++nt)
@@ -727,6 +794,7 @@ hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps,
     for (int t = 1; t <= steps; ++t) {
         if (form == DF_FP32) hipLaunchKernelGGL(k_dense_step<DF_FP32>, dim3(tiles.size()), dim3(256), 0, s, dd, dt, t);
         else if (form == DF_BF16X2) hipLaunchKernelGGL(k_dense_step<DF_BF16X2>, dim3(tiles.size()), dim3(256), 0, s, dd, dt, t);
+        else if (form == DF_FP8) hipLaunchKernelGGL(k_dense_step<DF_FP8>, dim3(tiles.size()), dim3(256), 0, s, dd, dt, t);
         else hipLaunchKernelGGL(k_dense_step<DF_BF16>, dim3(tiles.size()), dim3(256), 0, s, dd, dt, t);
         hipLaunchKernelGGL(k_dense_best, dim3(quads.size()), dim3(256), 0, s, dd, dq, t, form);
     }
@@ -735,7 +803,7 @@ hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps,
 
 hipError_t launch_dense_init(const DenseRun &d, hipStream_t s) {
     // (re)derive the vertex buffer from theta at every chunk; initialise the state at t0 = 0
-    const size_t sbytes = d.form == DF_FP32 ? 4 : 2;
+    const size_t sbytes = d.form == DF_FP32 ? 4 : d.form == DF_FP8 ? 1 : 2;
     char *S0 = (char *)d.S;
     char *S1 = S0 + (size_t)d.R * d.Kp * sbytes;
     const int64_t total = (int64_t)d.R * d.Kp;

@@ -128,15 +128,17 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
                     const void *uniform, int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool,
                     hipStream_t s, hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr);
 // Operands of the matrix-core engine (split J) and the problem fields of a DenseRun.
-// exact_bf16: run an FP32 request in the BF16 form when that is exact (see exact_in_bf16).
+// unit: the common magnitude w of exact integer couplings (see exact_unit), else 0; an
+// FP32 request on such couplings runs the FP8 form, which is exact there.
 ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, Pool &pool,
-                           hipStream_t s, DenseRun &d, bool exact_bf16);
+                           hipStream_t s, DenseRun &d, double unit);
 ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const void *uniform,
-                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s, bool exact_bf16,
+                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s, double unit,
                        hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr);
-// All couplings are integers of one magnitude w <= 256 (exact in BF16) and every
-// row sum stays below 2^24 (exact in FP32).
-bool exact_in_bf16(const Ingest &ing, int n);
+// w when all nonzero couplings are integers of one magnitude w and n w < 2^24 (every
+// product of J / w with a vertex, and every partial sum, is then exact in FP8 x FP8 with
+// FP32 accumulation), else 0.
+double exact_unit(const Ingest &ing, int n);
 bool use_dense_engine(const ising_problem &p, const ising_params &prm);
 double ms_between(hipEvent_t a, hipEvent_t b);
 

@@ -3,7 +3,10 @@
 FP32 form: same bar as the persistent engine (norm-wise relative iterate error
 <= 1e-5; GD over 100 steps, ADAM over its 30-step horizon).  +-1 couplings are
 exact in BF16, so the BF16 and BF16X2 forms must reproduce the FP32 form bit
-for bit on them.  On Gaussian couplings the BF16 forms carry the representation
+for bit on them.  Couplings of one integer magnitude w run the FP8 form (J / w and
+the vertex exact in FP8, every product and sum an exact integer): it must equal
+the BF16 form bit for bit where both are exact, and FP32 requests on such
+couplings run it.  On Gaussian couplings the BF16 forms carry the representation
 error of J: J_hi + J_lo has relative error <= 2^-16 per entry and J_hi alone
 2^-8; their tolerances below are those bounds times the observed growth of the
 GD map (x10 over 100 steps), and the measured errors are printed.
@@ -123,3 +126,59 @@ def test_solve_dense_engine_energy_recomputed_fp64(ctx):
         s = s.cpu().numpy()
         assert abs(E.item() - oracle.energy(inst, s)) < 1e-9 * (np.abs(inst.J).sum())
         assert E.item() / 400 < -1.2  # SK ground states lie near E/N = -1.53 in this convention; random vertices near 0
+
+
+def test_fp8_form_exact_on_uniform_integer_couplings(ctx):
+    # J = +-3 (one integer magnitude) with integer fields, n = 300 (K padding and a ragged
+    # spin tile), R = 130 (a ragged replica tile): FP8, BF16 and FP32 requests all give the
+    # same iterates, energies and best vertices bit for bit (the FP32 request runs FP8)
+    pm = I.sk_pm1(300, 11)
+    h = np.random.default_rng(12).integers(-4, 5, size=300)
+    inst = I.Instance(300, "sk_pm3_field_300", h, pm.J * 3, integer=True)
+    U = I.uniform_draws(13, 130, inst.n)
+    a = _run(ctx, inst, 130, 60, "adam", 6.0, "fp8", 2, U)
+    for prec in ("bf16", "fp32"):
+        b = _run(ctx, inst, 130, 60, "adam", 6.0, prec, 2, U)
+        for k in ("theta", "m", "v", "s_best", "e_best", "best_step", "energy_trace"):
+            assert np.array_equal(a[k], b[k]), (prec, k)
+    # and it follows the FP64 oracle like the FP32 form (GD, 100 steps)
+    U2 = I.uniform_draws(14, 64, inst.n)
+    got = _run(ctx, inst, 64, 100, "gd", 0.001, "fp8", 10, U2)
+    got["loss_trace"] = np.zeros_like(got["energy_trace"])
+    worst, excl = compare_trajectories(inst, got, U2, 100, "gd", 0.001, 10, check_loss=False)
+    print(f"FP8 form: worst iterate error vs FP64 oracle {worst:.2e}, excluded {excl}/64")
+
+
+def test_fp8_form_rejected_for_other_couplings(ctx):
+    import torch
+    import paper_2312_05837_amd as P
+    inst = I.sk_gauss(300, 15)
+    state = P.ds_state(inst.n, 64, "fp32")
+    prm = P.params(replicas=64, steps=5, optimizer="adam", precision="fp8", lr=6.0, mu=0.5)
+    with pytest.raises(P.IsingError) as e:
+        P.ising_ds_dense_dev(ctx, to_problem(inst), prm, state, t0=0, steps=5)
+    assert e.value.status == P.ISING_ENOTSUP
+    # mixed integer magnitudes (+-1 and +-2) are not one magnitude either
+    pm = I.sk_pm1(300, 16)
+    mixed = I.Instance(300, "mixed", np.zeros(300), pm.J * np.where(np.arange(300)[:, None] % 2 == 0, 1, 2)
+                       * np.where(np.arange(300)[None, :] % 2 == 0, 1, 2), integer=True)
+    mixed.J = np.where(mixed.J != 0, mixed.J, 0)
+    assert np.array_equal(mixed.J, mixed.J.T)
+    with pytest.raises(P.IsingError):
+        P.ising_ds_dense_dev(ctx, to_problem(mixed), prm, state, t0=0, steps=5)
+    torch.cuda.synchronize()
+
+
+def test_solve_fp8_form_integer_energy(ctx):
+    import torch
+    import paper_2312_05837_amd as P
+    inst = I.sk_pm1(512, 17)
+    res = {}
+    for prec in ("fp8", "fp32", "bf16"):
+        s, E, Ei, st = P.ising_solve_dev(ctx, to_problem(inst), P.params(replicas=256, steps=200, precision=prec,
+                                                                           optimizer="adam", lr=6.0, mu=0.5))
+        torch.cuda.synchronize()
+        s = s.cpu().numpy()
+        assert Ei.item() == oracle.energy(inst, s)
+        res[prec] = (s.copy(), Ei.item())
+    assert np.array_equal(res["fp8"][0], res["fp32"][0]) and np.array_equal(res["fp8"][0], res["bf16"][0])
