@@ -62,6 +62,10 @@ WORKLOADS = {
 }
 # peak rates of the matrix cores (dense, no sparsity), per precision of the coupling product
 MFMA_PEAK = {"bf16x2": 2.5e15, "bf16": 2.5e15, "fp8": 5.0e15, "fp32": 157.3e12}
+HBM_PEAK = 8.0e12  # bytes/s
+# bytes per element of the vertex operand and of the stored couplings, per dense form
+DENSE_SB = {"fp32": 4, "bf16": 2, "bf16x2": 2, "fp8": 1}
+DENSE_JB = {"fp32": 4, "bf16": 2, "bf16x2": 4, "fp8": 1}
 
 # Sources of each dominant kernel: a recorded HBM traffic figure is used only
 # while these files are unchanged since the counters were taken.
@@ -368,12 +372,27 @@ def main():
         if prec == "fp32" and inst.integer and len(np.unique(np.abs(inst.J[inst.J != 0]))) <= 1 \
                 and np.abs(inst.J).max() * nG < 2 ** 24:
             form = "fp8"
-        ops = 2.0 * nG * nG * R * T
-        achieved = ops / (k_ms * 1e-3)
-        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_PEAK[form] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / MFMA_PEAK[form], "traffic": recorded_traffic("k_dense_step", args.workload),
-                "kernel": "k_dense_step (MFMA product + fused update) and k_dense_best, all steps", "kernel_ms": k_ms,
-                "flops_per_launch_sequence": ops}
+        # one launch pair per step.  Matrix cores: 2 n^2 R flops.  HBM, algorithmic bytes: the
+        # optimizer state read and written once (theta, m, v: 24 B; GD theta only: 8 B), the
+        # vertex operand written once and read once, the stored couplings read once.
+        # The bound is the one with the longer ideal time; the other is given beside it.
+        per_step = k_ms * 1e-3 / T
+        flops = 2.0 * nG * nG * R
+        state_b = 24 if args.optimizer == "adam" else 8
+        hbm_bytes = nG * R * (state_b + 2 * DENSE_SB[form]) + DENSE_JB[form] * nG * nG
+        mfma_frac = flops / per_step / MFMA_PEAK[form]
+        hbm_frac = hbm_bytes / per_step / HBM_PEAK
+        common = {"traffic": recorded_traffic("k_dense_step", args.workload),
+                  "kernel": "k_dense_step (MFMA product + fused update) and k_dense_best, per step",
+                  "kernel_ms": k_ms, "launch_us": per_step * 1e6, "flops_per_launch": flops,
+                  "algorithmic_bytes_per_launch": hbm_bytes, "mfma_frac": mfma_frac, "hbm_frac": hbm_frac,
+                  "mfma_peak_tflops": MFMA_PEAK[form] / 1e12, "form": form}
+        if hbm_bytes / HBM_PEAK > flops / MFMA_PEAK[form]:
+            roof = {"bound": "hbm", "achieved": hbm_bytes / per_step / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                    "frac": hbm_frac, **common}
+        else:
+            roof = {"bound": "mfma", "achieved": flops / per_step / 1e12, "peak": MFMA_PEAK[form] / 1e12,
+                    "unit": "TFLOP/s", "frac": mfma_frac, **common}
     else:
         if loss == "relaxed":
             ops = T_eff * R * (2 * nnzG + EPI_OPS_RELAXED[args.optimizer] * nG)
