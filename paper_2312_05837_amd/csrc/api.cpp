@@ -278,9 +278,10 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
     a.loss = prm.loss;
     a.conv_tol = prm.conv_tol > 0 ? prm.conv_tol : 0.0;
     a.conv_window = prm.conv_window;
-    if ((plan.packed || plan.mult) && plan.l.ept > 0 && !plan.l.relaxed) {
+    if ((plan.packed || plan.mult) && plan.l.ept > 0) {
         const double wunit = plan.packed ? ing.w : 1.0;
-        // stage the +-w couplings in LDS when the image fits next to the vertex buffers
+        // stage the +-w couplings in LDS when the image fits next to the vertex buffers (and,
+        // for the relaxed loss, next to sin(theta) and its negation)
         DSLaunch l2 = plan.l;
         l2.coupling = CK_PMS;
         const int rb = pms_region_bytes(l2);

@@ -125,7 +125,7 @@ struct DSLaunch {
     int rg = 1;      // replicas per workgroup
     int ept = 1;     // spins per thread
     int block = 64;  // threads per workgroup
-    bool relaxed = false;  // relaxed-vertex loss: LDS holds sin(theta) too (not with CK_PMS or streaming)
+    bool relaxed = false;  // relaxed-vertex loss: LDS holds sin(theta) too (not the streaming engine)
     bool conv = false;     // convergence test: LDS holds each wavefront's window of losses
 };
 

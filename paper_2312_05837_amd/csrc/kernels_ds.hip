@@ -163,11 +163,16 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// The staged-image engine with the relaxed-vertex loss is its own instantiation
+// (template coupling CK_PMSR), so that the vertex-loss one carries none of its registers.
+constexpr int CK_PMSR = 4;
+__host__ __device__ constexpr bool is_pms(int ck) { return ck == CK_PMS || ck == CK_PMSR; }
+
 template <typename Real, int CK, int RG>
 __device__ inline void coupling(const DSArgs &a, int i, const typename SpinWord<RG>::T *sc, Real (&y)[RG],
                                 const uint2 *img = nullptr, int g0 = 0, uint32_t cnt = 0) {
     using SW = SpinWord<RG>;
-    if constexpr (CK == CK_PMS) {
+    if constexpr (is_pms(CK)) {
         using T = typename SW::T;
         const unsigned char *sb = (const unsigned char *)sc;
         // every lane of a wavefront has the same group count
@@ -226,12 +231,37 @@ __device__ inline void coupling(const DSArgs &a, int i, const typename SpinWord<
 }
 
 // z = J x for the relaxed-vertex loss, x = sin(theta) staged in LDS as [spin][RG]
-// (CSR in row order, dense rows in column order).
+// (CSR in row order, dense rows in column order).  CK_PMS: the staged image's entries
+// address x and its negation, laid out like the vertex words and their complements
+// (record of position q at XS times the word's byte offset), so each neighbour is one
+// LDS read of RG values and RG adds, in the image's order, then the common magnitude.
+template <typename Real, int RG>
+struct XRec {
+    Real v[RG];
+};
 template <typename Real, int CK, int RG>
-__device__ inline void relaxed_product(const DSArgs &a, int i, const Real *xc, Real (&z)[RG]) {
+__device__ inline void relaxed_product(const DSArgs &a, int i, const Real *xc, Real (&z)[RG],
+                                       const uint2 *img = nullptr, int g0 = 0, uint32_t cnt = 0) {
 #pragma unroll
     for (int r = 0; r < RG; ++r) z[r] = 0;
-    if constexpr (CK == CK_PM) {
+    if constexpr (is_pms(CK)) {
+        constexpr int XS = RG * (int)sizeof(Real) / (int)sizeof(typename SpinWord<RG>::T);
+        const unsigned char *xb = (const unsigned char *)xc;
+        const int G = __builtin_amdgcn_readfirstlane((int)(cnt >> 16));
+        const uint2 *q = img + g0;
+        for (int k = 0; k < G; ++k) {
+            const uint2 v = q[64 * k];
+            const uint32_t e[4] = {v.x & 0xffffu, v.x >> 16, v.y & 0xffffu, v.y >> 16};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const XRec<Real, RG> x = *(const XRec<Real, RG> *)(xb + (size_t)XS * e[h]);
+#pragma unroll
+                for (int r = 0; r < RG; ++r) z[r] += x.v[r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RG; ++r) z[r] *= (Real)a.w;
+    } else if constexpr (CK == CK_PM) {
         const int rs = a.row_ptr[i], re = a.row_ptr[i + 1];
         for (int q = rs; q < re; ++q) {
             const uint32_t e = a.pm[q];
@@ -280,27 +310,31 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     // EPT*B for padded slots.  Other couplings: npad words per parity, indexed by
     // spin, word n kept zero.
     const int npad = EPT * B + 1;
-    const size_t vbytes = CK == CK_PMS ? (size_t)4 * a.pms_rb : (size_t)2 * npad * sizeof(SW);
+    const size_t vbytes = is_pms(CK) ? (size_t)4 * a.pms_rb : (size_t)2 * npad * sizeof(SW);
     SW *sbuf = (SW *)smem;
     const size_t off = (vbytes + 15) & ~(size_t)15;
     Real *ep = (Real *)(smem + off);      // [2][NW][RG]
     Real *lp = ep + 2 * NW * RG;          // [2][NW][RG]
     uint32_t *flg = (uint32_t *)(lp + 2 * NW * RG);  // [2]
     uint2 *img = (uint2 *)(smem + ((off + 2 * 2 * NW * RG * sizeof(Real) + 8 + 15) & ~(size_t)15));
-    // relaxed-vertex loss (never with CK_PMS): sin(theta) per parity, [npad][RG], where the image would be
+    // relaxed-vertex loss: sin(theta) per parity.  Other couplings: [npad][RG] where the image
+    // would be.  CK_PMS: after the image, per parity a region of records [RG] at XS times the
+    // vertex word's byte offset (XS * a.pms_rb bytes) and a region of their negations.
     constexpr bool CAN_RELAX = CK != CK_PMS;
-    const bool relaxed = CAN_RELAX && a.loss == ISING_LOSS_RELAXED;
-    Real *xb = (Real *)img;
+    constexpr int XS = RG * (int)sizeof(Real) / (int)sizeof(SW);
+    const bool relaxed = CK == CK_PMSR || (CK != CK_PMS && a.loss == ISING_LOSS_RELAXED);
+    const size_t img_off = (size_t)((unsigned char *)img - smem);
+    const size_t x_off = is_pms(CK) ? ((img_off + (size_t)8 * a.pimg_groups + 15) & ~(size_t)15) : img_off;
+    Real *xb = (Real *)(smem + x_off);
+    const size_t xpar = is_pms(CK) ? (size_t)2 * XS * a.pms_rb : (size_t)npad * RG * sizeof(Real);  // bytes per parity
     // convergence test: per wavefront, the window of losses [kConvWindowMax][RG] and L_1 [RG]
     const bool conv = a.conv_tol > 0;
-    const size_t img_off = (size_t)((unsigned char *)img - smem);
-    const size_t tail = img_off + (CK == CK_PMS ? (size_t)8 * a.pimg_groups
-                                                : (relaxed ? (size_t)2 * npad * RG * sizeof(Real) : 0));
+    const size_t tail = relaxed ? x_off + 2 * xpar : (is_pms(CK) ? img_off + (size_t)8 * a.pimg_groups : img_off);
     Real *cring = (Real *)(smem + ((tail + 15) & ~(size_t)15)) + (size_t)wave * (kConvWindowMax + 1) * RG;
-    int prow_r[CK == CK_PMS ? EPT : 1];
-    uint32_t pcnt_r[CK == CK_PMS ? EPT : 1];
-    int row_r[CK == CK_PMS ? EPT : 1];  // spin held at position e * B + tid
-    if constexpr (CK == CK_PMS) {
+    int prow_r[is_pms(CK) ? EPT : 1];
+    uint32_t pcnt_r[is_pms(CK) ? EPT : 1];
+    int row_r[is_pms(CK) ? EPT : 1];  // spin held at position e * B + tid
+    if constexpr (is_pms(CK)) {
         const uint2 *src = (const uint2 *)a.pimg;
         for (int q = tid; q < a.pimg_groups; q += B) img[q] = src[q];
 #pragma unroll
@@ -312,25 +346,37 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         }
     }
     auto spin_of = [&](int e) -> int {
-        if constexpr (CK == CK_PMS) return row_r[e];
+        if constexpr (is_pms(CK)) return row_r[e];
         else return e * B + tid;
     };
     // vertex buffer of parity par, as the coupling reads it
     auto vbuf = [&](int par) -> SW * {
-        if constexpr (CK == CK_PMS) return (SW *)(smem + (size_t)par * 2 * a.pms_rb);
+        if constexpr (is_pms(CK)) return (SW *)(smem + (size_t)par * 2 * a.pms_rb);
         else return sbuf + par * npad;
     };
     auto put = [&](int par, int e, SW word) {
         SW *S = vbuf(par);
-        if constexpr (CK == CK_PMS) {
+        if constexpr (is_pms(CK)) {
             S[e * B + tid] = word;
             ((SW *)((unsigned char *)S + a.pms_rb))[e * B + tid] = (SW)(word ^ (SW)SWd::ones);
         } else {
             S[e * B + tid] = word;
         }
     };
+    // sin(theta) of position q, replica r, for the step of parity par (and its negation for CK_PMS)
+    auto putx = [&](int par, int q, int r, Real v) {
+        unsigned char *xp = (unsigned char *)xb + (size_t)par * xpar;
+        if constexpr (is_pms(CK)) {
+            ((Real *)(xp + (size_t)q * RG * sizeof(Real)))[r] = v;
+            ((Real *)(xp + (size_t)XS * a.pms_rb + (size_t)q * RG * sizeof(Real)))[r] = -v;
+        } else {
+            ((Real *)xp)[(size_t)q * RG + r] = v;
+        }
+    };
+    if (is_pms(CK) && relaxed && tid < RG)  // the padded slot reads zero records
+        for (int par = 0; par < 2; ++par) putx(par, EPT * B, tid, (Real)0);
     if (tid == 0) {
-        if constexpr (CK == CK_PMS) {
+        if constexpr (is_pms(CK)) {
             vbuf(0)[EPT * B] = 0;
             vbuf(1)[EPT * B] = 0;
         } else {
@@ -388,7 +434,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     xs[k] = x;
                     cs[k] = c;
                 }
-                if (CAN_RELAX && relaxed) xb[(size_t)q * RG + r] = x;
+                if (CAN_RELAX && relaxed) putx(0, q, r, x);
                 if (x < 0) {
                     cur |= 1u << k;
                     word |= (SW)(1u << SWd::shift(r));
@@ -428,11 +474,15 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
             if (e * B + tid >= n) continue;
             const int i = spin_of(e);
             Real y[RG];
-            if constexpr (CK == CK_PMS) coupling<Real, CK, RG>(a, i, sc, y, img, prow_r[e], pcnt_r[e]);
+            if constexpr (is_pms(CK)) coupling<Real, CK, RG>(a, i, sc, y, img, prow_r[e], pcnt_r[e]);
             else coupling<Real, CK, RG>(a, i, sc, y);
             Real z[RG];
             if constexpr (CAN_RELAX)
-                if (relaxed) relaxed_product<Real, CK, RG>(a, i, xb + (size_t)((t - 1) & 1) * npad * RG, z);
+                if (relaxed) {
+                    const Real *xc = (const Real *)((const unsigned char *)xb + (size_t)((t - 1) & 1) * xpar);
+                    if constexpr (is_pms(CK)) relaxed_product<Real, CK, RG>(a, i, xc, z, img, prow_r[e], pcnt_r[e]);
+                    else relaxed_product<Real, CK, RG>(a, i, xc, z);
+                }
             const Real hh = hv ? hv[i] : (Real)0;
             SW word = 0;
 #pragma unroll
@@ -491,7 +541,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     nxt |= 1u << k;
                     word |= (SW)(1u << SWd::shift(r));
                 }
-                if (CAN_RELAX && relaxed) xb[((size_t)(t & 1) * npad + e * B + tid) * RG + r] = xn;
+                if (CAN_RELAX && relaxed) putx(t & 1, e * B + tid, r, xn);
             }
             put(t & 1, e, word);
             // keep the scheduler from interleaving elements: bounds live ranges
@@ -1068,7 +1118,7 @@ template <typename Real, int CK, int RG>
 KFn pick_ept(int ept) {
     switch (ept) {
         case 0:
-            if constexpr (CK != CK_PMS) return k_ds_stream<Real, CK, RG>;
+            if constexpr (!is_pms(CK)) return k_ds_stream<Real, CK, RG>;
             return nullptr;
         case 1: return k_ds<Real, CK, RG, 1>;
         case 2: return k_ds<Real, CK, RG, 2>;
@@ -1098,6 +1148,7 @@ KFn pick(int ck, int rg, int ept) {
     switch (ck) {
         case CK_PM: return pick_rg<Real, CK_PM>(rg, ept);
         case CK_PMS: return ept > 0 ? pick_rg<Real, CK_PMS>(rg, ept) : nullptr;
+        case CK_PMSR: return ept > 0 ? pick_rg<Real, CK_PMSR>(rg, ept) : nullptr;
         case CK_CSRV: return pick_rg<Real, CK_CSRV>(rg, ept);
         case CK_DENSE: return pick_rg<Real, CK_DENSE>(rg, ept);
         default: return nullptr;
@@ -1126,13 +1177,14 @@ hipError_t launch_ds_format(const DevProblem &p, bool fp64, bool packed, uint32_
 }
 
 hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
-    KFn fn = l.fp64 ? pick<double>(l.coupling, l.rg, l.ept) : pick<float>(l.coupling, l.rg, l.ept);
+    const int ck = l.coupling == CK_PMS && l.relaxed ? CK_PMSR : l.coupling;
+    KFn fn = l.fp64 ? pick<double>(ck, l.rg, l.ept) : pick<float>(ck, l.rg, l.ept);
     if (!fn) return hipErrorInvalidValue;
     if (l.block % 64 || l.block < 64 || l.block > 1024 || (l.ept > 0 && (int64_t)l.ept * l.block < a.n) ||
         a.R % l.rg)
         return hipErrorInvalidValue;
     if (l.coupling == CK_PMS && a.pms_rb != pms_region_bytes(l)) return hipErrorInvalidValue;
-    if ((a.loss == ISING_LOSS_RELAXED) != l.relaxed || (l.relaxed && (l.coupling == CK_PMS || l.ept <= 0)))
+    if ((a.loss == ISING_LOSS_RELAXED) != l.relaxed || (l.relaxed && l.ept <= 0))
         return hipErrorInvalidValue;
     const size_t lds = ds_lds_bytes(l, a.n, a.pimg_groups);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
@@ -1223,7 +1275,13 @@ size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups) {
     else sbytes = l.ept > 0 ? (size_t)2 * (l.ept * l.block + 1) * sw : (size_t)3 * n * sw;
     size_t lds = ((sbytes + 15) & ~(size_t)15) + 2 * 2 * nw * l.rg * real + 8;
     if (l.coupling == CK_PMS) lds = ((lds + 15) & ~(size_t)15) + (size_t)8 * pimg_groups;
-    if (l.relaxed) lds = ((lds + 15) & ~(size_t)15) + (size_t)2 * (l.ept * l.block + 1) * l.rg * real;
+    if (l.relaxed) {
+        // sin(theta) double-buffered; CK_PMS: records at XS = rg * real / word bytes times the word
+        // offsets, with a negated copy
+        const size_t xs = (size_t)l.rg * real / sw;
+        lds = ((lds + 15) & ~(size_t)15) + (l.coupling == CK_PMS ? (size_t)4 * xs * pms_region_bytes(l)
+                                                                   : (size_t)2 * (l.ept * l.block + 1) * l.rg * real);
+    }
     if (l.conv) lds = ((lds + 15) & ~(size_t)15) + (size_t)nw * (kConvWindowMax + 1) * l.rg * real;
     return lds;
 }
