@@ -211,16 +211,20 @@ ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params 
             break;
         }
     }
+    // register-resident engine: up to 4 spins per thread (2 with four replicas per workgroup);
+    // sparse FP32 problems with one replica per workgroup take up to 32 spins per thread, which
+    // keeps a whole replica of n = 24576 spins in one CU's registers
+    const bool wide = !fp64 && p.format == ISING_CSR;
     int ept = 0;
     for (;;) {
-        const int maxept = fp64 ? 2 : (rg == 4 ? 2 : 4);
+        const int maxept = fp64 ? 2 : (rg == 4 ? 2 : (rg == 2 || !wide ? 4 : 32));
         for (int e = 1; e <= maxept; e *= 2) {
-            if ((int64_t)e * 1024 >= n) {
+            if ((int64_t)e * ds_block_limit(e) >= n) {
                 ept = e;
                 break;
             }
         }
-        if (ept || !register_only || rg == 1) break;
+        if (ept || rg == 1 || (!register_only && !wide)) break;
         rg = rg == 4 ? 2 : 1;  // fewer replicas per workgroup leave room for more spins per thread
     }
     if (ept == 0 && register_only)
@@ -278,7 +282,7 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
     a.loss = prm.loss;
     a.conv_tol = prm.conv_tol > 0 ? prm.conv_tol : 0.0;
     a.conv_window = prm.conv_window;
-    if ((plan.packed || plan.mult) && plan.l.ept > 0) {
+    if ((plan.packed || plan.mult) && plan.l.ept > 0 && plan.l.ept <= 8) {
         const double wunit = plan.packed ? ing.w : 1.0;
         // stage the +-w couplings in LDS when the image fits next to the vertex buffers (and,
         // for the relaxed loss, next to sin(theta) and its negation)

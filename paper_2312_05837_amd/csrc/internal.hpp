@@ -137,6 +137,8 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s);
 // ADAM bias corrections 1/(1-b1^t), 1/(1-b2^t), t = t0+1..t0+steps (FP64, rounded).
 hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64, void *out, hipStream_t s);
 int32_t ds_max_n(bool fp64);
+// largest workgroup of the persistent engine with `ept` spins per thread (0: streaming)
+int ds_block_limit(int ept);
 // Build the CK_PMS image; writes the total group count to *total_groups (host,
 // synchronises once).  img may be NULL to only count.
 // Work buffers of the CK_PMS format: deg, pos (n); perm, prow, pcnt (ept * block);

@@ -291,7 +291,19 @@ __device__ inline void relaxed_product(const DSArgs &a, int i, const Real *xc, R
     }
 }
 
-constexpr int launch_bound(int) { return 1024; }
+// 32 spins per thread (one replica per workgroup, large n) keep 96 state registers per thread:
+// at most 768 threads, so that the register budget is 168
+constexpr int launch_bound(int ept) { return ept >= 32 ? 768 : 1024; }
+
+// With 8 or more spins per thread the per-spin loads (row bounds, field) and the write-back
+// addresses would be hoisted out of the step loop and kept live for every spin, which
+// exceeds the register budget; an opaque copy of the spin index (an empty asm on a
+// register, no memory access) makes them local to each use.
+template <int EPT>
+__device__ __forceinline__ int local_index(int i) {
+    if constexpr (EPT >= 8) asm volatile("" : "+v"(i));
+    return i;
+}
 
 template <typename Real, int CK, int RG, int EPT>
 __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
@@ -472,7 +484,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             if (e * B + tid >= n) continue;
-            const int i = spin_of(e);
+            const int i = local_index<EPT>(spin_of(e));
             Real y[RG];
             if constexpr (is_pms(CK)) coupling<Real, CK, RG>(a, i, sc, y, img, prow_r[e], pcnt_r[e]);
             else coupling<Real, CK, RG>(a, i, sc, y);
@@ -642,7 +654,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         if (e * B + tid >= n) continue;
-        const int i = spin_of(e);
+        const int i = local_index<EPT>(spin_of(e));
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
             const int k = e * RG + r;
@@ -1125,6 +1137,17 @@ KFn pick_ept(int ept) {
         case 4:
             if constexpr (RG <= 2) return k_ds<Real, CK, RG, 4>;
             return nullptr;
+        // one replica per workgroup, up to 32 spins per thread (FP32, sparse couplings; the staged
+        // image up to 8, where its per-spin row data still fits the registers)
+        case 8:
+            if constexpr (sizeof(Real) == 4 && RG == 1 && CK != CK_DENSE) return k_ds<Real, CK, RG, 8>;
+            return nullptr;
+        case 16:
+            if constexpr (sizeof(Real) == 4 && RG == 1 && (CK == CK_PM || CK == CK_CSRV)) return k_ds<Real, CK, RG, 16>;
+            return nullptr;
+        case 32:
+            if constexpr (sizeof(Real) == 4 && RG == 1 && (CK == CK_PM || CK == CK_CSRV)) return k_ds<Real, CK, RG, 32>;
+            return nullptr;
         default: return nullptr;
     }
 }
@@ -1157,6 +1180,8 @@ KFn pick(int ck, int rg, int ept) {
 
 }  // namespace
 
+int ds_block_limit(int ept) { return ept > 0 ? launch_bound(ept) : 1024; }
+
 int32_t ds_max_n(bool fp64) {
     // streaming engine, one replica per workgroup: three byte-per-spin LDS buffers
     (void)fp64;
@@ -1180,7 +1205,7 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
     const int ck = l.coupling == CK_PMS && l.relaxed ? CK_PMSR : l.coupling;
     KFn fn = l.fp64 ? pick<double>(ck, l.rg, l.ept) : pick<float>(ck, l.rg, l.ept);
     if (!fn) return hipErrorInvalidValue;
-    if (l.block % 64 || l.block < 64 || l.block > 1024 || (l.ept > 0 && (int64_t)l.ept * l.block < a.n) ||
+    if (l.block % 64 || l.block < 64 || l.block > ds_block_limit(l.ept) || (l.ept > 0 && (int64_t)l.ept * l.block < a.n) ||
         a.R % l.rg)
         return hipErrorInvalidValue;
     if (l.coupling == CK_PMS && a.pms_rb != pms_region_bytes(l)) return hipErrorInvalidValue;

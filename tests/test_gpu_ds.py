@@ -73,7 +73,7 @@ CASES = [
     ("er_field_csrv", lambda: I.random_integer_field(I.erdos_renyi(300, 0.05, 4, "pm1"), 4, 3), 16),
     ("gauss_dense257", lambda: I.sk_gauss(257, 5), 8),
     ("t1_uniform_real_csr", lambda: I.table1_regular(500, 6, "uniform", 6), 8),
-    ("torus50x100_stream", lambda: I.torus(50, 100, 7, "pm1"), 8),
+    ("torus50x100_ept8", lambda: I.torus(50, 100, 7, "pm1"), 8),
     ("ragged_n65_r6", lambda: I.random_integer_field(I.erdos_renyi(65, 0.2, 8, "pm1"), 8, 2), 6),
 ]
 
@@ -100,6 +100,14 @@ def _nae3sat(n=400, seed=16):
     return inst
 
 
+def _gauss_weights(inst, seed):
+    """The same graph with iid N(0, 1) weights (real couplings, kept in CSR order)."""
+    rng = np.random.default_rng(seed)
+    edges = [(i, int(inst.col[q]), float(rng.normal())) for i in range(inst.n)
+             for q in range(inst.row_ptr[i], inst.row_ptr[i + 1]) if inst.col[q] > i]
+    return I.from_edges(inst.n, edges, np.zeros(inst.n), inst.name + "_gauss", integer=False)
+
+
 def _er_int3(n=700, p=0.03, seed=17):
     """ER graph with integer weights in {+-1, +-2, +-3}: staged with repeated entries."""
     rng = np.random.default_rng(seed)
@@ -116,6 +124,14 @@ MULTI = [
     ("hub_rg2", _hub_graph, 512),
     ("er1500_field_rg1_ept2", lambda: I.random_integer_field(I.erdos_renyi(1500, 0.01, 10, "pm1"), 10, 2), 16),
     ("t1_real1500_csrv_ept2", lambda: I.table1_regular(1500, 6, "uniform", 6), 16),
+    # one replica per workgroup with 16 and 32 spins per thread (the large sparse shapes: a
+    # whole replica's state in one CU's registers; 8 spins per thread on the staged image is
+    # torus50x100_ept8 above), packed +-1 and real values, and past 24576 spins the streaming
+    # engine
+    ("reg3_12000_pm_ept16", lambda: I.random_regular(12000, 3, 18, "pm1"), 4),
+    ("torus100x200_pm_ept32", lambda: I.torus(100, 200, 19, "pm1"), 4),
+    ("reg3_20000_real_csrv_ept32", lambda: _gauss_weights(I.random_regular(20000, 3, 20, "pm1"), 21), 4),
+    ("torus150x200_stream", lambda: I.torus(150, 200, 22, "pm1"), 4),
 ]
 
 
