@@ -218,7 +218,8 @@ ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params 
     int ept = 0;
     for (;;) {
         const int maxept = fp64 ? 2 : (rg == 4 ? 2 : (rg == 2 || !wide ? 4 : 32));
-        for (int e = 1; e <= maxept; e *= 2) {
+        for (int e : {1, 2, 4, 8, 16, 28, 32}) {
+            if (e > maxept) break;
             if ((int64_t)e * ds_block_limit(e) >= n) {
                 ept = e;
                 break;
@@ -315,6 +316,15 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
         }
     }
     if (plan.packed) a.pm = (const uint32_t *)fmt;
+    // wide packed engine (one replica per workgroup, 8+ spins per thread): fixed-width neighbour
+    // rows, loaded ahead of each spin's update, when every degree fits them
+    if (plan.packed && plan.l.coupling == CK_PM && plan.l.ept >= 8 && plan.l.rg == 1 && !plan.l.relaxed &&
+        ing.maxdeg() <= kEllWidth) {
+        void *ell = nullptr;
+        HIP_TRY(ctx, pool.get("ds.ell", (size_t)plan.l.ept * kEllWidth * plan.l.block * 4, &ell));
+        HIP_TRY(ctx, launch_ell_format(dp, (const uint32_t *)fmt, plan.l.ept, plan.l.block, (uint32_t *)ell, s));
+        a.ell = (const uint32_t *)ell;
+    }
     else if (p.format == ISING_CSR) a.val = fmt;
     else a.J = fmt;
     a.h = p.h ? hbuf : nullptr;

@@ -92,6 +92,10 @@ struct DSArgs {
     const int32_t *row_ptr = nullptr;
     const int32_t *col = nullptr;
     const uint32_t *pm = nullptr;      // sign-packed entries: col | (J < 0) << 31
+    // sign-packed entries in fixed-width rows for the wide engine (8+ spins per thread, degree
+    // <= kEllWidth): [ept][kEllWidth][block], slot j of position e * block + thread holds
+    // col | (J < 0) << 31, slot 0 also the degree << 24; unused slots address the zero word n
+    const uint32_t *ell = nullptr;
     const void *val = nullptr;         // CSR values in the state precision
     const void *J = nullptr;           // dense values in the state precision
     double w = 1.0;                    // common magnitude of sign-packed couplings
@@ -118,6 +122,7 @@ struct DSArgs {
     int32_t *conv_step = nullptr;      // nullable: R steps at which the test held (0: never)
 };
 constexpr int kConvWindowMax = 8;
+constexpr int kEllWidth = 4;
 
 struct DSLaunch {
     int coupling = CK_CSRV;
@@ -139,6 +144,9 @@ hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64,
 int32_t ds_max_n(bool fp64);
 // largest workgroup of the persistent engine with `ept` spins per thread (0: streaming)
 int ds_block_limit(int ept);
+// Fixed-width neighbour rows (DSArgs::ell) from the sign-packed CSR; every degree <= kEllWidth.
+hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, int ept, int block, uint32_t *ell,
+                             hipStream_t s);
 // Build the CK_PMS image; writes the total group count to *total_groups (host,
 // synchronises once).  img may be NULL to only count.
 // Work buffers of the CK_PMS format: deg, pos (n); perm, prow, pcnt (ept * block);

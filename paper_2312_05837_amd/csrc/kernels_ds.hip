@@ -119,6 +119,18 @@ __device__ inline float dsin(float x) {
     return s;
 }
 __device__ inline double dsin(double x) { return sin(x); }
+// dsin(x) < 0 from the range reduction alone: in the odd quadrants the sine is +-cos(r)
+// (|r| <= pi/4, never zero), in the even ones +-sin(r), whose polynomial keeps the sign of r
+// (the rotation by k keeps or flips it).  The same decision as dsin(x) < 0 for |x| <= 4.
+__device__ inline bool dsin_neg(float x) {
+    const float k = rintf(x * 0.636619772367581343f);
+    float r = __builtin_fmaf(-k, 1.57079637050628662f, x);
+    r = __builtin_fmaf(-k, -4.37113882867379300e-08f, r);
+    r = __builtin_fmaf(-k, -1.71512451000588190e-15f, r);
+    const int q = (int)k & 3;
+    return q == 3 || (q == 0 && r < 0.f) || (q == 2 && r > 0.f);
+}
+__device__ inline bool dsin_neg(double x) { return sin(x) < 0; }
 __device__ inline float dasin(float x) { return asinf(x); }
 __device__ inline double dasin(double x) { return asin(x); }
 __device__ inline float dsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -167,6 +179,9 @@ __device__ inline double wave_sum(double v) {
 // (template coupling CK_PMSR), so that the vertex-loss one carries none of its registers.
 constexpr int CK_PMSR = 4;
 __host__ __device__ constexpr bool is_pms(int ck) { return ck == CK_PMS || ck == CK_PMSR; }
+// The wide packed engine with fixed-width neighbour rows (DSArgs::ell) is its own
+// instantiation too (template coupling CK_PME), with no CSR path in its step.
+constexpr int CK_PME = 5;
 
 template <typename Real, int CK, int RG>
 __device__ inline void coupling(const DSArgs &a, int i, const typename SpinWord<RG>::T *sc, Real (&y)[RG],
@@ -291,9 +306,9 @@ __device__ inline void relaxed_product(const DSArgs &a, int i, const Real *xc, R
     }
 }
 
-// 32 spins per thread (one replica per workgroup, large n) keep 96 state registers per thread:
-// at most 768 threads, so that the register budget is 168
-constexpr int launch_bound(int ept) { return ept >= 32 ? 768 : 1024; }
+// 28 or 32 spins per thread (one replica per workgroup, large n) keep 84 or 96 state registers
+// per thread: at most 768 threads, so that the register budget is 168
+constexpr int launch_bound(int ept) { return ept >= 28 ? 768 : 1024; }
 
 // With 8 or more spins per thread the per-spin loads (row bounds, field) and the write-back
 // addresses would be hoisted out of the step loop and kept live for every spin, which
@@ -481,13 +496,50 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
 #pragma unroll
         for (int r = 0; r < RG; ++r) Ep[r] = Lp[r] = (Real)-0.0;  // x + (-0) = x: no add for the first term
         uint32_t nxt = 0;
+        // wide packed engine: the fixed-width neighbour words of spin e are loaded ELL_AHEAD
+        // spins before its update (the base pointer is opaque per step, so that the loads
+        // stay inside the step instead of being hoisted for every spin)
+        constexpr bool WIDE_ELL = CK == CK_PME;
+        constexpr int ELL_AHEAD = EPT >= 28 ? 2 : 4;  // the widest variants leave little register room
+        constexpr bool use_ell = WIDE_ELL;
+        uint32_t nbw[WIDE_ELL ? EPT : 1][kEllWidth];
+        uintptr_t ellp = (uintptr_t)a.ell;
+        if constexpr (WIDE_ELL) {
+            asm volatile("" : "+s"(ellp));
+            if (use_ell)
+#pragma unroll
+                for (int e = 0; e < ELL_AHEAD && e < EPT; ++e)
+#pragma unroll
+                    for (int j = 0; j < kEllWidth; ++j)
+                        nbw[e][j] = ((const uint32_t *)ellp)[((size_t)e * kEllWidth + j) * B + tid];
+        }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
+            if constexpr (WIDE_ELL) {
+                if (use_ell && e + ELL_AHEAD < EPT)
+#pragma unroll
+                    for (int j = 0; j < kEllWidth; ++j)
+                        nbw[e + ELL_AHEAD][j] = ((const uint32_t *)ellp)[((size_t)(e + ELL_AHEAD) * kEllWidth + j) * B + tid];
+            }
             if (e * B + tid >= n) continue;
             const int i = local_index<EPT>(spin_of(e));
             Real y[RG];
-            if constexpr (is_pms(CK)) coupling<Real, CK, RG>(a, i, sc, y, img, prow_r[e], pcnt_r[e]);
-            else coupling<Real, CK, RG>(a, i, sc, y);
+            if constexpr (is_pms(CK)) {
+                coupling<Real, CK, RG>(a, i, sc, y, img, prow_r[e], pcnt_r[e]);
+            } else if constexpr (WIDE_ELL) {
+                // one replica per workgroup: the word is the spin's sign bit
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int j = 0; j < kEllWidth; ++j) {
+                    const uint32_t w = nbw[e][j];
+                    cnt += (uint32_t)sc[w & 0xffffffu] ^ ((uint32_t)((int32_t)w >> 31) & SWd::ones);
+                }
+                const int deg = (int)((nbw[e][0] >> 24) & 0x7fu);
+#pragma unroll
+                for (int r = 0; r < RG; ++r) y[r] = (Real)a.w * (Real)(deg - 2 * (int)cnt);
+            } else {
+                coupling<Real, CK, RG>(a, i, sc, y);
+            }
             Real z[RG];
             if constexpr (CAN_RELAX)
                 if (relaxed) {
@@ -525,6 +577,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     Lp[r] = __builtin_fma(x, tt, Lp[r]);
                 }
                 Real xn = x;  // a stopped replica keeps its angle, moments and vertex
+                bool xneg = x < 0;
                 if (!((done >> r) & 1u)) {
                     const Real g = c * tt;
                     Real upd;
@@ -545,11 +598,15 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                         dsincos(tn, &xn, &cn);
                         xs[k] = xn;
                         cs[k] = cn;
-                    } else {
+                        xneg = xn < 0;
+                    } else if (CAN_RELAX && relaxed) {
                         xn = dsin(tn);
+                        xneg = xn < 0;
+                    } else {
+                        xneg = dsin_neg(tn);  // only the next vertex is needed
                     }
                 }
-                if (xn < 0) {
+                if (xneg) {
                     nxt |= 1u << k;
                     word |= (SW)(1u << SWd::shift(r));
                 }
@@ -734,7 +791,7 @@ __global__ __launch_bounds__(1024) void k_ds_stream(const DSArgs a) {
                 if (gv) gv[idx] = 0;
                 a.s_best[idx] = 1;
             }
-            if (dsin(t) < 0) word |= (SW)(1u << SWd::shift(r));
+            if (dsin_neg(t)) word |= (SW)(1u << SWd::shift(r));
         }
         sbuf[1 * n + i] = word;
     }
@@ -801,7 +858,7 @@ __global__ __launch_bounds__(1024) void k_ds_stream(const DSArgs a) {
                 tn = tn - q * Consts<Real>::twopi_hi;
                 tn = tn - q * Consts<Real>::twopi_lo;
                 gth[idx] = tn;
-                if (dsin(tn) < 0) word |= (SW)(1u << SWd::shift(r));
+                if (dsin_neg(tn)) word |= (SW)(1u << SWd::shift(r));
             }
             sn[i] = word;
         }
@@ -883,6 +940,22 @@ __global__ void k_format(DevProblem p, int packed, uint32_t *pm, Real *val_out, 
             else if (p.vtype == ISING_F32) v = ((const float *)p.h)[i];
             else v = ((const double *)p.h)[i];
             h_out[i] = (Real)v;
+        }
+    }
+}
+
+// Fixed-width neighbour rows for the wide engine: slot j of position q = e * block + t
+// (spin q) at ((e * kEllWidth + j) * block + t); slot 0 carries the degree in bits 24..30
+__global__ void k_ell_format(DevProblem p, const uint32_t *pm, int ept, int block, uint32_t *ell) {
+    const int total = ept * block;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
+        const int e = q / block, t = q % block;
+        const int rs = q < p.n ? p.row_ptr[q] : 0, deg = q < p.n ? p.row_ptr[q + 1] - rs : 0;
+#pragma unroll
+        for (int j = 0; j < kEllWidth; ++j) {
+            uint32_t w = j < deg ? (pm[rs + j] & 0x80ffffffu) : (uint32_t)p.n;  // pads: the zero word
+            if (j == 0) w |= (uint32_t)deg << 24;
+            ell[((size_t)e * kEllWidth + j) * block + t] = w;
         }
     }
 }
@@ -1145,6 +1218,9 @@ KFn pick_ept(int ept) {
         case 16:
             if constexpr (sizeof(Real) == 4 && RG == 1 && (CK == CK_PM || CK == CK_CSRV)) return k_ds<Real, CK, RG, 16>;
             return nullptr;
+        case 28:
+            if constexpr (sizeof(Real) == 4 && RG == 1 && (CK == CK_PM || CK == CK_CSRV)) return k_ds<Real, CK, RG, 28>;
+            return nullptr;
         case 32:
             if constexpr (sizeof(Real) == 4 && RG == 1 && (CK == CK_PM || CK == CK_CSRV)) return k_ds<Real, CK, RG, 32>;
             return nullptr;
@@ -1172,6 +1248,15 @@ KFn pick(int ck, int rg, int ept) {
         case CK_PM: return pick_rg<Real, CK_PM>(rg, ept);
         case CK_PMS: return ept > 0 ? pick_rg<Real, CK_PMS>(rg, ept) : nullptr;
         case CK_PMSR: return ept > 0 ? pick_rg<Real, CK_PMSR>(rg, ept) : nullptr;
+        case CK_PME:
+            if constexpr (sizeof(Real) == 4) {
+                if (rg != 1) return nullptr;
+                if (ept == 8) return k_ds<Real, CK_PME, 1, 8>;
+                if (ept == 16) return k_ds<Real, CK_PME, 1, 16>;
+                if (ept == 28) return k_ds<Real, CK_PME, 1, 28>;
+                if (ept == 32) return k_ds<Real, CK_PME, 1, 32>;
+            }
+            return nullptr;
         case CK_CSRV: return pick_rg<Real, CK_CSRV>(rg, ept);
         case CK_DENSE: return pick_rg<Real, CK_DENSE>(rg, ept);
         default: return nullptr;
@@ -1188,6 +1273,14 @@ int32_t ds_max_n(bool fp64) {
     return 48 * 1024;
 }
 
+hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, int ept, int block, uint32_t *ell,
+                             hipStream_t s) {
+    if (p.format != ISING_CSR || ept <= 0 || block <= 0 || (int64_t)ept * block < p.n) return hipErrorInvalidValue;
+    const int total = ept * block;
+    hipLaunchKernelGGL(k_ell_format, dim3((total + 255) / 256), dim3(256), 0, s, p, pm, ept, block, ell);
+    return hipGetLastError();
+}
+
 hipError_t launch_ds_format(const DevProblem &p, bool fp64, bool packed, uint32_t *pm, void *val_out,
                             void *h_out, hipStream_t s) {
     const int64_t total = p.format == ISING_DENSE ? (int64_t)p.n * p.n : p.nnz;
@@ -1202,7 +1295,9 @@ hipError_t launch_ds_format(const DevProblem &p, bool fp64, bool packed, uint32_
 }
 
 hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
-    const int ck = l.coupling == CK_PMS && l.relaxed ? CK_PMSR : l.coupling;
+    const int ck = l.coupling == CK_PMS && l.relaxed ? CK_PMSR
+                 : l.coupling == CK_PM && a.ell != nullptr && !l.relaxed ? CK_PME
+                                                                          : l.coupling;
     KFn fn = l.fp64 ? pick<double>(ck, l.rg, l.ept) : pick<float>(ck, l.rg, l.ept);
     if (!fn) return hipErrorInvalidValue;
     if (l.block % 64 || l.block < 64 || l.block > ds_block_limit(l.ept) || (l.ept > 0 && (int64_t)l.ept * l.block < a.n) ||

@@ -124,13 +124,14 @@ MULTI = [
     ("hub_rg2", _hub_graph, 512),
     ("er1500_field_rg1_ept2", lambda: I.random_integer_field(I.erdos_renyi(1500, 0.01, 10, "pm1"), 10, 2), 16),
     ("t1_real1500_csrv_ept2", lambda: I.table1_regular(1500, 6, "uniform", 6), 16),
-    # one replica per workgroup with 16 and 32 spins per thread (the large sparse shapes: a
+    # one replica per workgroup with 16, 28 and 32 spins per thread (the large sparse shapes: a
     # whole replica's state in one CU's registers; 8 spins per thread on the staged image is
     # torus50x100_ept8 above), packed +-1 and real values, and past 24576 spins the streaming
     # engine
     ("reg3_12000_pm_ept16", lambda: I.random_regular(12000, 3, 18, "pm1"), 4),
-    ("torus100x200_pm_ept32", lambda: I.torus(100, 200, 19, "pm1"), 4),
-    ("reg3_20000_real_csrv_ept32", lambda: _gauss_weights(I.random_regular(20000, 3, 20, "pm1"), 21), 4),
+    ("torus100x200_pm_ept28", lambda: I.torus(100, 200, 19, "pm1"), 4),
+    ("reg3_20000_real_csrv_ept28", lambda: _gauss_weights(I.random_regular(20000, 3, 20, "pm1"), 21), 4),
+    ("reg3_24000_pm_ept32", lambda: I.random_regular(24000, 3, 23, "pm1"), 4),
     ("torus150x200_stream", lambda: I.torus(150, 200, 22, "pm1"), 4),
 ]
 
