@@ -217,6 +217,52 @@ def cpu_baseline(inst, replicas, steps, opt, lr, mu, budget_s=15.0, loss="vertex
             "best_energy_sample": float(res["energy"])}
 
 
+def ttt_bench(args):
+    """Time to the plain FP32 form's target energy on the SK-2000 Gaussian instance (R = 4096):
+    the FP32 form's best energy after 2000 steps is the target; each reduced-precision form is
+    solved with the same seed for increasing step counts (a shorter run is a prefix of a longer
+    one), and its time to target is the wall time of the first count whose returned vector,
+    re-evaluated exactly in FP64, reaches the target."""
+    import numpy as np
+    import torch
+    import paper_2312_05837_amd as P
+    inst = make_instance("sk2000g")
+    prob = to_device(inst)
+    ctx = P.ising_create(0)
+    R, T = 4096, 2000
+    spins = torch.empty(inst.n, dtype=torch.int8, device="cuda")
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def solve(prec, steps):
+        prm = P.params(replicas=R, steps=steps, optimizer="adam", precision=prec, lr=6.0, mu=0.5, seed=1234,
+                       prune=True)
+        P.ising_solve_dev(ctx, prob, prm, spins, E, None)  # warm-up of this shape
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.ising_solve_dev(ctx, prob, prm, spins, E, None)
+        torch.cuda.synchronize()
+        return float(E.item()), time.perf_counter() - t0
+
+    e_target, t_fp32 = solve("fp32", T)
+    forms = {"fp32": {"steps": T, "time_s": t_fp32, "energy": e_target}}
+    for prec in ("bf16x2", "bf16"):
+        forms[prec] = {"steps": None, "time_s": None, "energy_at_T": None}
+        for steps in (125, 250, 500, 1000, 2000):
+            e, t = solve(prec, steps)
+            if steps == T:
+                forms[prec]["energy_at_T"] = e
+            if e <= e_target:
+                forms[prec].update(steps=steps, time_s=t, energy=e, speedup_vs_fp32=t_fp32 / t)
+                break
+        if forms[prec]["energy_at_T"] is None:
+            forms[prec]["energy_at_T"] = solve(prec, T)[0]
+    P.ising_destroy(ctx)
+    print(json.dumps({"metric": "time-to-target energy", "unit": "s", "higher_is_better": False, "n_gpus": 1,
+                      "data": "synthetic", "config": {"workload": "SK N=2000, J~N(0,1/N), R=4096, ADAM lr 6",
+                                                      "target": "best energy of the FP32 form after 2000 steps"},
+                      "target_energy": e_target, "forms": forms}))
+
+
 def serve_bench(args):
     """Continuous-batching server vs plain per-instance solves on a Poisson request stream."""
     import numpy as np
@@ -321,7 +367,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed solves")
     ap.add_argument("--warmup", type=int, default=2, help="untimed solves")
-    ap.add_argument("--workload", default="er800", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--workload", default="er800", choices=sorted(WORKLOADS) + ["serve", "sk2000_ttt"])
     ap.add_argument("--optimizer", default="adam", choices=["adam", "gd"])
     ap.add_argument("--lr", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -347,6 +393,9 @@ def main():
         return
     if args.workload == "serve":
         serve_bench(args)
+        return
+    if args.workload == "sk2000_ttt":
+        ttt_bench(args)
         return
     desc, kind, R, T, prec = WORKLOADS[args.workload][:5]
     extra = WORKLOADS[args.workload][5] if len(WORKLOADS[args.workload]) > 5 else {}
