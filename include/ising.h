@@ -290,7 +290,7 @@ ising_status ising_select_dev(ising_ctx *ctx, const double *e_best, int32_t repl
  * `chunk_steps` steps per iteration: sparse requests with the same launch shape
  * share one launch of the persistent engine (one workgroup per request x
  * replica group), dense requests run the matrix-core engine on `dense_streams`
- * streams.  Finished requests are harvested (best replica, retrieval, exact
+ * streams, its launches replayed from HIP graphs.  Finished requests are harvested (best replica, retrieval, exact
  * energy) and their memory is freed, so newly arrived requests are admitted
  * while others run.  A request's result depends only on its own problem and
  * parameters: it is bit-identical alone and in any mix. */
@@ -299,7 +299,11 @@ typedef struct ising_serve_config {
     int32_t max_resident;     /* requests resident at once (0: 64) */
     int32_t chunk_steps;      /* steps per scheduling iteration (0: 100) */
     int32_t dense_streams;    /* streams for dense requests (0: 4) */
-    int32_t reserved0;
+    /* 0: each dense group's chunk of launches (two per step) is captured once into a HIP
+     * graph and replayed while the group's shape and step count stay the same (the
+     * per-problem descriptors are re-uploaded before every replay); nonzero: launched one
+     * by one.  Results are the same either way. */
+    int32_t no_graphs;
 } ising_serve_config;
 
 typedef struct ising_serve_info {

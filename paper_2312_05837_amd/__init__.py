@@ -76,7 +76,7 @@ class ising_ds_state(C.Structure):
 
 class ising_serve_config(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_resident", C.c_int32), ("chunk_steps", C.c_int32),
-                ("dense_streams", C.c_int32), ("reserved0", C.c_int32)]
+                ("dense_streams", C.c_int32), ("no_graphs", C.c_int32)]
 
 
 class ising_serve_info(C.Structure):
@@ -447,8 +447,8 @@ def host_problem(n, J=None, row_ptr=None, col=None, val=None, h=None):
     return st, keep
 
 
-def ising_serve_start(ctx, hbm_budget_bytes=0, max_resident=0, chunk_steps=0, dense_streams=0):
-    cfg = ising_serve_config(hbm_budget_bytes, max_resident, chunk_steps, dense_streams, 0)
+def ising_serve_start(ctx, hbm_budget_bytes=0, max_resident=0, chunk_steps=0, dense_streams=0, graphs=True):
+    cfg = ising_serve_config(hbm_budget_bytes, max_resident, chunk_steps, dense_streams, 0 if graphs else 1)
     _check(ctx, _lib.ising_serve_start(ctx, C.byref(cfg)))
 
 

@@ -204,6 +204,15 @@ hipError_t launch_dense_init(const DenseRun &d, hipStream_t s);
 // Advance `count` problems of the same form by `steps` steps: two launches per
 // step for the whole group.  scratch: dense_group_scratch_bytes() of device memory.
 hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps, void *scratch, hipStream_t s);
+// The same in two parts, for callers that capture the kernels in a graph: the upload of the
+// group's descriptors and work lists to scratch (host-synchronous), and the 2 * steps kernel
+// launches alone (no copies or fills), which read everything per-problem from scratch.
+struct DenseGroupShape {
+    int form = DF_BF16X2, descs = 0, tiles = 0, quads = 0;
+};
+hipError_t dense_group_upload(const DenseRun *const *runs, int count, void *scratch, hipStream_t s,
+                              DenseGroupShape *shape);
+hipError_t dense_group_launch(const DenseGroupShape &shape, void *scratch, int steps, hipStream_t s);
 size_t dense_group_scratch_bytes(const DenseRun *const *runs, int count);
 // One problem: init + group of one.
 hipError_t launch_dense_run(const DenseRun &d, void *scratch, hipStream_t s);

@@ -765,15 +765,17 @@ size_t dense_group_scratch_bytes(const DenseRun *const *runs, int count) {
     return align16(count * sizeof(DenseDesc)) + tiles * sizeof(int4) + quads * sizeof(int2) + 64;
 }
 
-hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps, void *scratch, hipStream_t s) {
-    if (count <= 0 || steps <= 0) return hipSuccess;
+hipError_t dense_group_upload(const DenseRun *const *runs, int count, void *scratch, hipStream_t s,
+                              DenseGroupShape *shape) {
+    if (count <= 0) return hipErrorInvalidValue;
     const int form = runs[0]->form;
     std::vector<DenseDesc> descs;
     std::vector<int4> tiles;
     std::vector<int2> quads;
     for (int k = 0; k < count; ++k) {
         const DenseRun &d = *runs[k];
-        if (d.form != form || d.Mp % BM || d.Kp % (d.form == DF_FP8 ? 2 * KCB : KCB) || d.Mp < d.n || d.Kp < d.n) return hipErrorInvalidValue;
+        if (d.form != form || d.Mp % BM || d.Kp % (d.form == DF_FP8 ? 2 * KCB : KCB) || d.Mp < d.n || d.Kp < d.n)
+            return hipErrorInvalidValue;
         if (d.opt == ISING_OPT_ADAM && !d.bias) return hipErrorInvalidValue;
         descs.push_back(make_desc(d));
         for (int nt = 0; nt < (d.R + BN - 1) / BN; ++nt)
@@ -791,14 +793,35 @@ hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps,
     // the copies read the host vectors above: let them finish before the vectors go away
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
+    shape->form = form;
+    shape->descs = count;
+    shape->tiles = (int)tiles.size();
+    shape->quads = (int)quads.size();
+    return hipSuccess;
+}
+
+hipError_t dense_group_launch(const DenseGroupShape &shape, void *scratch, int steps, hipStream_t s) {
+    char *p = (char *)scratch;
+    // the layout of dense_group_upload: descriptors, then tiles, then quads
+    const DenseDesc *dd = (const DenseDesc *)p;
+    const int4 *dt = (const int4 *)(p + align16((size_t)shape.descs * sizeof(DenseDesc)));
+    const int2 *dq = (const int2 *)((const char *)dt + (size_t)shape.tiles * sizeof(int4));
     for (int t = 1; t <= steps; ++t) {
-        if (form == DF_FP32) hipLaunchKernelGGL(k_dense_step<DF_FP32>, dim3(tiles.size()), dim3(256), 0, s, dd, dt, t);
-        else if (form == DF_BF16X2) hipLaunchKernelGGL(k_dense_step<DF_BF16X2>, dim3(tiles.size()), dim3(256), 0, s, dd, dt, t);
-        else if (form == DF_FP8) hipLaunchKernelGGL(k_dense_step<DF_FP8>, dim3(tiles.size()), dim3(256), 0, s, dd, dt, t);
-        else hipLaunchKernelGGL(k_dense_step<DF_BF16>, dim3(tiles.size()), dim3(256), 0, s, dd, dt, t);
-        hipLaunchKernelGGL(k_dense_best, dim3(quads.size()), dim3(256), 0, s, dd, dq, t, form);
+        if (shape.form == DF_FP32) hipLaunchKernelGGL(k_dense_step<DF_FP32>, dim3(shape.tiles), dim3(256), 0, s, dd, dt, t);
+        else if (shape.form == DF_BF16X2) hipLaunchKernelGGL(k_dense_step<DF_BF16X2>, dim3(shape.tiles), dim3(256), 0, s, dd, dt, t);
+        else if (shape.form == DF_FP8) hipLaunchKernelGGL(k_dense_step<DF_FP8>, dim3(shape.tiles), dim3(256), 0, s, dd, dt, t);
+        else hipLaunchKernelGGL(k_dense_step<DF_BF16>, dim3(shape.tiles), dim3(256), 0, s, dd, dt, t);
+        hipLaunchKernelGGL(k_dense_best, dim3(shape.quads), dim3(256), 0, s, dd, dq, t, shape.form);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps, void *scratch, hipStream_t s) {
+    if (count <= 0 || steps <= 0) return hipSuccess;
+    DenseGroupShape shape;
+    hipError_t e = dense_group_upload(runs, count, scratch, s, &shape);
+    if (e != hipSuccess) return e;
+    return dense_group_launch(shape, scratch, steps, s);
 }
 
 hipError_t launch_dense_init(const DenseRun &d, hipStream_t s) {

@@ -94,6 +94,16 @@ struct Server {
     hipStream_t main = nullptr;
     std::vector<hipStream_t> dense;
     Pool batch;  // descriptor and work-map buffers of the batched launches
+    // replayable launch sequences of the dense groups, by group key: valid while the group's
+    // shape, step count and scratch buffer are unchanged (the kernels read everything else
+    // from the descriptors uploaded before each replay)
+    struct DenseGraph {
+        DenseGroupShape shape;
+        int steps = 0;
+        void *scratch = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::map<std::string, DenseGraph> graphs;
 };
 
 namespace {
@@ -305,9 +315,39 @@ void run_chunk(Server &S, std::vector<Request *> &live) {
             char key[32];
             snprintf(key, sizeof key, "dg%d.%d", g.first, bs.first);
             const size_t bytes = dense_group_scratch_bytes(bs.second.data(), (int)bs.second.size());
-            if (S.batch.get(key, bytes, &scratch) != hipSuccess ||
-                launch_dense_group(bs.second.data(), (int)bs.second.size(), bs.first, scratch, S.dense[0]) !=
-                    hipSuccess) {
+            hipError_t e = S.batch.get(key, bytes, &scratch);
+            if (e == hipSuccess && S.cfg.no_graphs) {
+                e = launch_dense_group(bs.second.data(), (int)bs.second.size(), bs.first, scratch, S.dense[0]);
+            } else if (e == hipSuccess) {
+                DenseGroupShape shape;
+                e = dense_group_upload(bs.second.data(), (int)bs.second.size(), scratch, S.dense[0], &shape);
+                Server::DenseGraph &G = S.graphs[key];
+                const bool same = G.exec && G.steps == bs.first && G.scratch == scratch && G.shape.form == shape.form &&
+                                  G.shape.descs == shape.descs && G.shape.tiles == shape.tiles &&
+                                  G.shape.quads == shape.quads;
+                if (e == hipSuccess && !same) {
+                    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+                    G = Server::DenseGraph();
+                    hipGraph_t graph = nullptr;
+                    e = hipStreamBeginCapture(S.dense[0], hipStreamCaptureModeThreadLocal);
+                    if (e == hipSuccess) {
+                        const hipError_t el = dense_group_launch(shape, scratch, bs.first, S.dense[0]);
+                        const hipError_t ec = hipStreamEndCapture(S.dense[0], &graph);
+                        e = el != hipSuccess ? el : ec;
+                    }
+                    if (e == hipSuccess) e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+                    if (graph) (void)hipGraphDestroy(graph);
+                    if (e == hipSuccess) {
+                        G.shape = shape;
+                        G.steps = bs.first;
+                        G.scratch = scratch;
+                    } else {
+                        G.exec = nullptr;
+                    }
+                }
+                if (e == hipSuccess) e = hipGraphLaunch(G.exec, S.dense[0]);
+            }
+            if (e != hipSuccess) {
                 for (Request *q : live)
                     if (q->dense) {
                         q->result = ISING_EDEVICE;
@@ -499,6 +539,8 @@ ising_status ising_serve_stop(ising_ctx *ctx) {
     if (S->thr.joinable()) S->thr.join();
     (void)hipSetDevice(ctx->device);
     (void)hipStreamDestroy(S->main);
+    for (auto &g : S->graphs)
+        if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
     for (auto s : S->dense) (void)hipStreamDestroy(s);
     S->batch.release();
     delete S;

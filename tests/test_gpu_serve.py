@@ -171,3 +171,21 @@ def test_large_sparse_and_grouped_dense_requests(ctx):
         assert np.array_equal(s.cpu().numpy(), spins), inst.n
         assert float(E.item()) == energy
         assert energy == oracle.energy(inst, spins)
+
+
+def test_dense_graph_replays_equal_eager_launches(ctx):
+    """Dense groups replay a captured launch sequence while their shape and step count stay
+    the same (here four replays per group, with eager descriptor uploads and the sparse
+    requests' launches in between); every result equals the one-by-one launches bit for bit."""
+    import paper_2312_05837_amd as P
+    pm = I.sk_pm1(400, 21)
+    reqs = [(I.sk_pm1(300, 22), 128, 201), (pm, 256, 202),
+            (I.Instance(400, "sk_pm3", np.zeros(400, dtype=np.int64), pm.J * 3, integer=True), 64, 203),
+            (I.erdos_renyi(600, 8.0 / 599, 23, "pm1"), 128, 204)]
+    graphs, _ = _serve(ctx, reqs, steps=100, chunk=20, max_resident=8)
+    eager, _ = _serve(ctx, reqs, steps=100, chunk=20, max_resident=8, graphs=False)
+    for (inst, _, _), g, e in zip(reqs, graphs, eager):
+        assert g[0] == P.ISING_OK and e[0] == P.ISING_OK
+        assert np.array_equal(g[1], e[1]) and g[2] == e[2], inst.name
+        assert g[3]["best_step"] == e[3]["best_step"] and g[3]["best_replica"] == e[3]["best_replica"]
+        assert g[2] == oracle.energy(inst, g[1])
