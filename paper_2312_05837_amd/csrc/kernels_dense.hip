@@ -389,29 +389,29 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                             acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[bi], bf[bj], acc[bi][bj],
                                                                                          0, 0, 0, 0, 0, 0);
                 }
-                return;
-            }
+            } else {
 #pragma unroll
-            for (int ks = 0; ks < KCB / 16; ++ks) {
-                const int u = 2 * ks + (lane >> 5);
-                bf16x8 ah[2], al[2], bv[2];
+                for (int ks = 0; ks < KCB / 16; ++ks) {
+                    const int u = 2 * ks + (lane >> 5);
+                    bf16x8 ah[2], al[2], bv[2];
 #pragma unroll
-                for (int bi = 0; bi < 2; ++bi) {
-                    const int o = swz(wm * 64 + bi * 32 + (lane & 31), u);
-                    ah[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Ah + o));
-                    if (FORM == DF_BF16X2) al[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Al + o));
-                }
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
-                    bv[bj] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Bs + swz(wn * 64 + bj * 32 + (lane & 31), u)));
-#pragma unroll
-                for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                    for (int bj = 0; bj < 2; ++bj) {
-                        if (FORM == DF_BF16X2)
-                            acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bv[bj], acc[bi][bj], 0, 0, 0);
-                        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+                    for (int bi = 0; bi < 2; ++bi) {
+                        const int o = swz(wm * 64 + bi * 32 + (lane & 31), u);
+                        ah[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Ah + o));
+                        if (FORM == DF_BF16X2) al[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Al + o));
                     }
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj)
+                        bv[bj] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Bs + swz(wn * 64 + bj * 32 + (lane & 31), u)));
+#pragma unroll
+                    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < 2; ++bj) {
+                            if (FORM == DF_BF16X2)
+                                acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+                            acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+                        }
+                }
             }
         };
 #define DENSE_BF_CHUNK(C, ST)                                                                          \
