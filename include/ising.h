@@ -255,8 +255,12 @@ typedef struct ising_ds_state {
  * state is read from `state` and continued.
  * Energies of integer problems are exact.  One kernel launch per call; every
  * replica is handled by one workgroup, whose angles and moments stay in
- * registers across all steps.  ENOTSUP if n is beyond the on-chip limit
- * (ising_ds_max_n). */
+ * registers across all steps: up to 4 spins per thread (n <= 4096), and for
+ * sparse FP32 problems with one replica per workgroup up to 32 spins per
+ * thread (n <= 24576); larger sparse problems up to ising_ds_max_n stream the
+ * angles and moments through device memory each step (FP64 above 2048 spins
+ * too).  The relaxed loss and the convergence test need the register-resident
+ * form.  ENOTSUP if n is beyond the on-chip limit (ising_ds_max_n). */
 ising_status ising_ds_dev(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
                           const void *uniform, int32_t t0, int32_t steps, ising_ds_state *state,
                           void *stream);
