@@ -70,8 +70,10 @@ DENSE_JB = {"fp32": 4, "bf16": 2, "bf16x2": 4, "fp8": 1}
 # Sources of each dominant kernel: a recorded HBM traffic figure is used only
 # while these files are unchanged since the counters were taken.
 KERNEL_SOURCES = {
-    "k_ds": ["paper_2312_05837_amd/csrc/kernels_ds.hip", "paper_2312_05837_amd/csrc/internal.hpp"],
-    "k_dense_step": ["paper_2312_05837_amd/csrc/kernels_dense.hip", "paper_2312_05837_amd/csrc/internal.hpp"],
+    "k_ds": ["paper_2312_05837_amd/csrc/kernels_ds.hip", "paper_2312_05837_amd/csrc/internal.hpp",
+             "paper_2312_05837_amd/build.py"],
+    "k_dense_step": ["paper_2312_05837_amd/csrc/kernels_dense.hip", "paper_2312_05837_amd/csrc/internal.hpp",
+                     "paper_2312_05837_amd/build.py"],
 }
 COPY_CALIBRATION_BYTES = 1 << 30
 

@@ -111,9 +111,11 @@ typedef struct ising_params {
      * first step t >= conv_window at which the spread (maximum minus minimum) of its
      * last conv_window losses is <= conv_tol * |L_t - L_1| (the paper: 5 and 0.005).
      * Its angles, moments and best vertex are then final; the launch ends when every
-     * replica has stopped.  Persistent engine only, in one launch from step 1
-     * (ising_ds_dev with t0 == 0; not the matrix-core, streaming or serving forms:
-     * ENOTSUP there).  1 <= conv_window <= 8. */
+     * replica has stopped.  Persistent engine (register-resident form) and the
+     * serving form, where a request whose replicas have all stopped finishes at the
+     * end of that chunk; ising_ds_dev continues the test across calls through the
+     * state's conv_step and conv_state (not the matrix-core or streaming forms: ENOTSUP
+     * there).  1 <= conv_window <= 8. */
     int32_t conv_window;
     int32_t reserved1;
     double conv_tol;
@@ -240,6 +242,9 @@ typedef struct ising_ds_state {
     double *energy_trace; /* nullable: steps*R energies E_t, row t-1-t0 holds step t */
     double *loss_trace;   /* nullable: steps*R losses L_t */
     int32_t *conv_step;   /* nullable: R steps at which the convergence test held (0: never) */
+    void *conv_state;     /* nullable: R*9 values of the state precision, the convergence test's
+                             window of losses and L_1, written by every call and read by a call
+                             with t0 > 0 (needed, with conv_step, to continue the test) */
 } ising_ds_state;
 
 /* Run steps t0+1 .. t0+steps of domain selection on the problem (device
@@ -325,8 +330,11 @@ ising_status ising_serve_start(ising_ctx *ctx, const ising_serve_config *cfg);
 ising_status ising_serve_stop(ising_ctx *ctx);
 /* Queue a solve.  problem: host buffers, copied before the call returns.
  * params as for ising_solve; sparse requests run in FP32.  *ticket identifies
- * the request.  Thread-safe.  Errors: EINVAL (no server, malformed shape), ENOTSUP
- * (params->loss other than ISING_LOSS_VERTEX, or the convergence test on). */
+ * the request.  Thread-safe.  With the convergence test on, a request runs on the
+ * persistent engine in FP32 and finishes at the end of the chunk in which its last
+ * replica stopped (its result as from ising_solve with the same params).  Errors:
+ * EINVAL (no server, malformed shape), ENOTSUP (params->loss other than
+ * ISING_LOSS_VERTEX; the convergence test with a precision other than FP32). */
 ising_status ising_submit(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
                           uint64_t *ticket);
 /* Wait up to timeout_ms (negative: forever) for a request and copy its result

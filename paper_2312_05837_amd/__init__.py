@@ -71,7 +71,7 @@ class ising_stats(C.Structure):
 class ising_ds_state(C.Structure):
     _fields_ = [("theta", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("s_best", C.c_void_p),
                 ("e_best", C.c_void_p), ("best_step", C.c_void_p), ("energy_trace", C.c_void_p),
-                ("loss_trace", C.c_void_p), ("conv_step", C.c_void_p)]
+                ("loss_trace", C.c_void_p), ("conv_step", C.c_void_p), ("conv_state", C.c_void_p)]
 
 
 class ising_serve_config(C.Structure):
@@ -366,7 +366,10 @@ def ising_ds_max_n(precision=ISING_PREC_FP32) -> int:
     return _lib.ising_ds_max_n(precision)
 
 
-def ds_state(n: int, replicas: int, precision="fp32", optimizer="adam", steps_trace: int = 0):
+CONV_STATE_WIDTH = 9  # conv_window (at most 8) losses and L_1 per replica
+
+
+def ds_state(n: int, replicas: int, precision="fp32", optimizer="adam", steps_trace: int = 0, conv: bool = False):
     """Allocate an ising_ds_state's tensors (dict) on the current device."""
     import torch
     dev = torch.device("cuda")
@@ -380,6 +383,10 @@ def ds_state(n: int, replicas: int, precision="fp32", optimizer="adam", steps_tr
     if steps_trace:
         st["energy_trace"] = torch.zeros((steps_trace, replicas), dtype=torch.float64, device=dev)
         st["loss_trace"] = torch.zeros((steps_trace, replicas), dtype=torch.float64, device=dev)
+    if conv:
+        # the convergence test carried between calls: stop steps and the window of losses
+        st["conv_step"] = torch.zeros(replicas, dtype=torch.int32, device=dev)
+        st["conv_state"] = torch.zeros((replicas, CONV_STATE_WIDTH), dtype=dt, device=dev)
     return st
 
 
@@ -390,7 +397,7 @@ def ising_ds_dev(ctx, problem, prm: ising_params, state: dict, t0: int = 0, step
     steps = prm.steps if steps is None else steps
     st = ising_ds_state(_ptr(state["theta"]), _ptr(state.get("m")), _ptr(state.get("v")), _ptr(state["s_best"]),
                         _ptr(state["e_best"]), _ptr(state["best_step"]), _ptr(state.get("energy_trace")),
-                        _ptr(state.get("loss_trace")), _ptr(state.get("conv_step")))
+                        _ptr(state.get("loss_trace")), _ptr(state.get("conv_step")), _ptr(state.get("conv_state")))
     _check(ctx, _lib.ising_ds_dev(ctx, C.byref(ps), C.byref(prm), _ptr(uniform), t0, steps, C.byref(st),
                                   _stream(stream)))
     return state

@@ -339,8 +339,8 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
         return fail(ctx, ISING_EINVAL, "state buffers missing");
     if (prm.optimizer == ISING_OPT_ADAM && (!st->m || !st->v))
         return fail(ctx, ISING_EINVAL, "ADAM needs m and v buffers");
-    if (prm.conv_tol > 0 && t0 != 0)
-        return fail(ctx, ISING_ENOTSUP, "the convergence test runs in one launch from step 1 (t0 = 0)");
+    if (prm.conv_tol > 0 && t0 != 0 && (!st->conv_step || !st->conv_state))
+        return fail(ctx, ISING_EINVAL, "continuing the convergence test (t0 > 0) needs conv_step and conv_state");
     DSArgs a;
     DSPlan plan;
     ST_TRY(prepare_ds(ctx, p, prm, ing, pool, s, a, plan));
@@ -359,6 +359,7 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
     a.etrace = st->energy_trace;
     a.ltrace = st->loss_trace;
     a.conv_step = st->conv_step;
+    a.conv_state = st->conv_state;
     if (prm.optimizer == ISING_OPT_ADAM && steps > 0) {
         void *bias = nullptr;
         HIP_TRY(ctx, pool.get("ds.bias", (size_t)2 * steps * real, &bias));

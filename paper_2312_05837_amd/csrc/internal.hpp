@@ -120,6 +120,9 @@ struct DSArgs {
     double conv_tol = 0.0;
     int32_t conv_window = 5;
     int32_t *conv_step = nullptr;      // nullable: R steps at which the test held (0: never)
+    // R * (kConvWindowMax + 1) values of the state precision: the last conv_window losses by
+    // global step mod conv_window, then L_1; read when t0 > 0, written at the end of the call
+    void *conv_state = nullptr;
 };
 constexpr int kConvWindowMax = 8;
 constexpr int kEllWidth = 4;

@@ -487,6 +487,20 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     uint32_t done = 0;          // replicas that have stopped (identical in every wavefront)
     int conv_t = 0;             // wave 0, lane r < RG: step at which replica r stopped
     int tlast = a.steps;        // last step run
+    if (conv && a.t0 > 0) {
+        // continuing a run: the replicas that stopped in an earlier call (conv_step > 0) and the
+        // window of losses and L_1 carried in conv_state, copied into this wavefront's ring
+        uint32_t stopped = 0;
+#pragma unroll
+        for (int r = 0; r < RG; ++r)
+            if (a.conv_step[r0 + r] > 0) stopped |= 1u << r;
+        done = stopped;
+        if (lane < RG) {
+            conv_t = a.conv_step[r0 + lane];
+            const Real *cs = (const Real *)a.conv_state + (size_t)(r0 + lane) * (kConvWindowMax + 1);
+            for (int q = 0; q <= kConvWindowMax; ++q) cring[q * RG + lane] = cs[q];
+        }
+    }
 
     for (int t = 1; t <= a.steps; ++t) {
         const SW *sc = vbuf((t - 1) & 1);
@@ -672,10 +686,10 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
             if (lane < RG && !((done >> lane) & 1u)) {
                 Real Ls = 0;
                 for (int w = 0; w < NW; ++w) Ls += lp[((t & 1) * NW + w) * RG + lane];
-                const int W = a.conv_window;
-                if (t == 1) cring[kConvWindowMax * RG + lane] = Ls;
-                cring[((t - 1) % W) * RG + lane] = Ls;
-                if (t >= W) {
+                const int W = a.conv_window, tg = a.t0 + t;  // the test runs on the global step
+                if (tg == 1) cring[kConvWindowMax * RG + lane] = Ls;
+                cring[((tg - 1) % W) * RG + lane] = Ls;
+                if (tg >= W) {
                     double mx = -INFINITY, mn = INFINITY;
                     for (int q = 0; q < W; ++q) {
                         const double v = (double)cring[q * RG + lane];
@@ -685,7 +699,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     const double L1 = (double)cring[kConvWindowMax * RG + lane];
                     now = mx - mn <= a.conv_tol * fabs((double)Ls - L1);
                 }
-                if (now) conv_t = a.t0 + t;
+                if (now) conv_t = tg;
             }
             done |= (uint32_t)__ballot(now);
             if (done == (1u << RG) - 1u) {  // every replica of this workgroup has stopped
@@ -696,6 +710,10 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     }
     __syncthreads();
     if (a.conv_step && wave == 0 && lane < RG) a.conv_step[r0 + lane] = conv_t;
+    if (conv && a.conv_state && wave == 0 && lane < RG) {
+        Real *cs = (Real *)a.conv_state + (size_t)(r0 + lane) * (kConvWindowMax + 1);
+        for (int q = 0; q <= kConvWindowMax; ++q) cs[q] = cring[q * RG + lane];
+    }
     if (tlast > 0) {
         const uint32_t f = flg[tlast & 1];
 #pragma unroll

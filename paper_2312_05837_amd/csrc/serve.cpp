@@ -73,6 +73,7 @@ struct Request {
     DenseRun drun; // matrix-core engine (dense)
     ising_ds_state st{};
     int steps_done = 0;
+    std::vector<int32_t> conv_steps;  // convergence test: per replica, the step at which it stopped
     int dense_stream = 0;
 };
 
@@ -180,7 +181,7 @@ ising_status admit(Server &S, Request &q) {
     }
     q.dense = use_dense_engine(*q.red, q.prm);
     if (!q.dense && q.prm.precision != ISING_PREC_FP32)
-        return fail(ctx, ISING_ENOTSUP, "served sparse problems run in FP32");
+        return fail(ctx, ISING_ENOTSUP, "served requests off the matrix cores (sparse, or with the convergence test) run in FP32");
     HIP_TRY(ctx, pool.get("theta", (size_t)nG * R * 4, &q.st.theta));
     if (q.prm.optimizer == ISING_OPT_ADAM) {
         HIP_TRY(ctx, pool.get("m", (size_t)nG * R * 4, &q.st.m));
@@ -219,6 +220,11 @@ ising_status admit(Server &S, Request &q) {
         q.args.s_best = q.st.s_best;
         q.args.e_best = q.st.e_best;
         q.args.best_step = q.st.best_step;
+        if (q.prm.conv_tol > 0) {
+            // the test's stop steps and window of losses, carried from chunk to chunk
+            HIP_TRY(ctx, pool.get("convstep", (size_t)R * 4, (void **)&q.args.conv_step));
+            HIP_TRY(ctx, pool.get("convstate", (size_t)R * (kConvWindowMax + 1) * 4, &q.args.conv_state));
+        }
         if (q.prm.optimizer == ISING_OPT_ADAM && q.prm.steps > 0) {
             // bias corrections of every step of the request, indexed from its first step
             void *bias = nullptr;
@@ -273,6 +279,15 @@ ising_status finish(Server &S, Request &q) {
     o.steps = q.prm.steps;
     o.eta = 1.0 - (double)nG / n;
     o.constant_C = q.prm.prune ? q.pr->C : 0.0;
+    o.mean_steps_run = q.prm.steps;
+    if (!q.conv_steps.empty()) {
+        double sum = 0.0;
+        for (int32_t c : q.conv_steps) {
+            o.converged += c > 0;
+            sum += c > 0 ? c : q.prm.steps;
+        }
+        o.mean_steps_run = sum / R;
+    }
     return ISING_OK;
 }
 
@@ -392,7 +407,19 @@ void run_chunk(Server &S, std::vector<Request *> &live) {
     }
     (void)hipStreamSynchronize(S.main);
     for (hipStream_t s : S.dense) (void)hipStreamSynchronize(s);
-    for (Request *q : live) q->steps_done = std::min(q->prm.steps, q->steps_done + K);
+    for (Request *q : live) {
+        q->steps_done = std::min(q->prm.steps, q->steps_done + K);
+        // a request whose replicas have all met the convergence test is finished
+        if (q->args.conv_step && !q->dense && q->result == ISING_OK) {
+            q->conv_steps.resize(q->prm.replicas);
+            if (hipMemcpy(q->conv_steps.data(), q->args.conv_step, (size_t)q->prm.replicas * 4,
+                          hipMemcpyDeviceToHost) == hipSuccess) {
+                bool all = true;
+                for (int32_t c : q->conv_steps) all = all && c > 0;
+                if (all) q->steps_done = q->prm.steps;
+            }
+        }
+    }
     S.info.chunks += 1;
     (void)ctx;
 }
@@ -559,8 +586,8 @@ ising_status ising_submit(ising_ctx *ctx, const ising_problem *problem, const is
         if (!problem || problem->n <= 0 || params->replicas <= 0 || params->steps < 0) return ISING_EINVAL;
     }
     if (problem->value_type < ISING_I32 || problem->value_type > ISING_F64) return ISING_EINVAL;
-    // the batched launches run the vertex loss for fixed step counts
-    if (params->loss != ISING_LOSS_VERTEX || params->conv_tol > 0) return ISING_ENOTSUP;
+    // the batched launches run the vertex loss (fixed step counts, or until the convergence test)
+    if (params->loss != ISING_LOSS_VERTEX) return ISING_ENOTSUP;
     auto q = std::make_unique<Request>();
     q->prm = *params;
     q->hp = *problem;

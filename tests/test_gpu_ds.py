@@ -372,7 +372,37 @@ def test_convergence_in_solve_stats(ctx):
     torch.cuda.synchronize()
     assert st["converged"] == 64 and st["mean_steps_run"] < T / 4
     assert float(E.item()) == oracle.energy(inst, s.cpu().numpy())
-    with pytest.raises(P.IsingError) as e:  # the test runs in one launch from step 1
+    with pytest.raises(P.IsingError) as e:  # continuing the test needs its carried state
         P.ising_ds_dev(ctx, to_problem(inst), P.params(replicas=8, steps=10, conv_tol=0.005),
                        P.ds_state(inst.n, 8), t0=5, steps=10)
-    assert e.value.status == P.ISING_ENOTSUP
+    assert e.value.status == P.ISING_EINVAL
+
+
+@pytest.mark.parametrize("name,mk,R,prec", CONV, ids=[c[0] for c in CONV])
+def test_convergence_across_calls_equals_one_launch(ctx, name, mk, R, prec):
+    # the test's window and stop steps carried through the state: four calls of 100 steps give
+    # the one-launch run's angles, moments, stop steps and best vertices bit for bit
+    import torch
+    import paper_2312_05837_amd as P
+    from gpu_util import to_problem
+    inst = mk()
+    T = 400
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    U = torch.tensor(I.uniform_draws(17, R, inst.n), dtype=dt, device="cuda")
+    prob = to_problem(inst)
+    prm = P.params(replicas=R, steps=T, optimizer="adam", lr=6.0, mu=0.5, precision=prec, conv_tol=0.005,
+                   conv_window=5)
+    one = P.ds_state(inst.n, R, prec, conv=True)
+    P.ising_ds_dev(ctx, prob, prm, one, t0=0, steps=T, uniform=U)
+    chunked = P.ds_state(inst.n, R, prec, conv=True)
+    t0 = 0
+    for k in (3, 7, 13, 29, 48, 300):  # uneven calls: the window of losses straddles every boundary
+        P.ising_ds_dev(ctx, prob, prm, chunked, t0=t0, steps=k, uniform=U if t0 == 0 else None)
+        t0 += k
+    assert t0 == T
+    torch.cuda.synchronize()
+    for k in ("theta", "m", "v", "s_best", "e_best", "best_step", "conv_step"):
+        assert torch.equal(one[k], chunked[k]), k
+    conv = one["conv_step"].cpu().numpy()
+    assert (conv > 0).sum() >= R // 4, conv
+    assert np.any(conv > 10), conv  # replicas stop in a later call than the first ones

@@ -189,3 +189,39 @@ def test_dense_graph_replays_equal_eager_launches(ctx):
         assert np.array_equal(g[1], e[1]) and g[2] == e[2], inst.name
         assert g[3]["best_step"] == e[3]["best_step"] and g[3]["best_replica"] == e[3]["best_replica"]
         assert g[2] == oracle.energy(inst, g[1])
+
+
+def test_convergence_test_in_serving(ctx):
+    """Requests with the convergence test: each result (vector, energy, replicas stopped, mean
+    steps run) equals the plain solve's, and a request whose replicas have all stopped is
+    finished at the end of that chunk instead of running its full step count."""
+    import torch
+    import paper_2312_05837_amd as P
+    from gpu_util import to_problem
+    reqs = [(I.table1_regular(400, 6, "binary_int", 31), 64, 301), (I.table1_regular(600, 6, "binary_int", 32), 128, 302),
+            (I.random_integer_field(I.erdos_renyi(500, 8.0 / 499, 33, "pm1"), 33, 3), 64, 303)]
+    T = 1000
+    P.ising_serve_start(ctx, chunk_steps=50, max_resident=8)
+    keep, tickets = [], []
+    for inst, R, seed in reqs:
+        st, kp = _host(inst)
+        keep.append(kp)
+        tickets.append(P.ising_submit(ctx, st, P.params(replicas=R, steps=T, optimizer="adam", lr=6.0, mu=0.5,
+                                                         seed=seed, precision="fp32", conv_tol=0.005)))
+    res = [P.ising_wait(ctx, tk, r[0].n) for tk, r in zip(tickets, reqs)]
+    info = P.ising_serve_query(ctx)
+    P.ising_serve_stop(ctx)
+    assert info["completed"] == len(reqs) and info["failed"] == 0
+    full = [st["converged"] == R for (_, R, _), (_, _, _, st) in zip(reqs, res)]
+    assert any(full)
+    if all(full):
+        assert info["chunks"] < T // 50  # finished before the full step count
+    for (inst, R, seed), (status, spins, energy, stats) in zip(reqs, res):
+        assert status == P.ISING_OK
+        s, E, Ei, st = P.ising_solve_dev(ctx, to_problem(inst), P.params(replicas=R, steps=T, optimizer="adam",
+                                                                          lr=6.0, mu=0.5, seed=seed,
+                                                                          precision="fp32", conv_tol=0.005))
+        torch.cuda.synchronize()
+        assert np.array_equal(s.cpu().numpy(), spins), inst.name
+        assert float(E.item()) == energy == oracle.energy(inst, spins)
+        assert stats["converged"] == st["converged"] and stats["mean_steps_run"] == st["mean_steps_run"]
