@@ -94,7 +94,9 @@ struct DSArgs {
     const uint32_t *pm = nullptr;      // sign-packed entries: col | (J < 0) << 31
     // sign-packed entries in fixed-width rows for the wide engine (8+ spins per thread, degree
     // <= kEllWidth): [ept][kEllWidth][block], slot j of position e * block + thread holds
-    // col | (J < 0) << 31, slot 0 also the degree << 24; unused slots address the zero word n
+    // col | (J < 0) << 31, slot 0 also the degree << 24, slot 1 the spin's integer field (7-bit
+    // two's complement) << 24 (the engine reads no separate field then); unused slots address
+    // the zero word n
     const uint32_t *ell = nullptr;
     const void *val = nullptr;         // CSR values in the state precision
     const void *J = nullptr;           // dense values in the state precision
@@ -148,8 +150,10 @@ int32_t ds_max_n(bool fp64);
 // largest workgroup of the persistent engine with `ept` spins per thread (0: streaming)
 int ds_block_limit(int ept);
 // Fixed-width neighbour rows (DSArgs::ell) from the sign-packed CSR; every degree <= kEllWidth.
-hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, int ept, int block, uint32_t *ell,
-                             hipStream_t s);
+// hf: the field in FP32 (nullable); a field that is not an integer in [-63, 63] sets *bad
+// (device, cleared by the caller), and such rows must not be used.
+hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, int ept, int block,
+                             uint32_t *ell, int32_t *bad, hipStream_t s);
 // Build the CK_PMS image; writes the total group count to *total_groups (host,
 // synchronises once).  img may be NULL to only count.
 // Work buffers of the CK_PMS format: deg, pos (n); perm, prow, pcnt (ept * block);

@@ -133,6 +133,19 @@ __device__ inline bool dsin_neg(float x) {
 __device__ inline bool dsin_neg(double x) { return sin(x) < 0; }
 __device__ inline float dasin(float x) { return asinf(x); }
 __device__ inline double dasin(double x) { return asin(x); }
+// a word in global memory, addressed as such (an address made opaque to the compiler would
+// otherwise be read with flat loads, which a wait for LDS reads also waits for)
+using GlobalU32 = __attribute__((address_space(1))) uint32_t;
+
+// a compile-time flag passed to a generic lambda
+template <bool B>
+struct Flag {
+    static constexpr bool value = B;
+};
+
+// fused multiply-add in the state precision (the plain builtin takes and returns double)
+__device__ inline float dfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double dfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ inline float dsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ inline double dsqrt(double x) { return sqrt(x); }
 __device__ inline float drint(float x) { return rintf(x); }
@@ -283,7 +296,7 @@ __device__ inline void relaxed_product(const DSArgs &a, int i, const Real *xc, R
             const Real sg = (e >> 31) ? (Real)-1 : (Real)1;
             const Real *xj = xc + (size_t)(e & 0x7fffffffu) * RG;
 #pragma unroll
-            for (int r = 0; r < RG; ++r) z[r] = __builtin_fma(sg, xj[r], z[r]);
+            for (int r = 0; r < RG; ++r) z[r] = dfma(sg, xj[r], z[r]);
         }
 #pragma unroll
         for (int r = 0; r < RG; ++r) z[r] *= (Real)a.w;
@@ -294,14 +307,14 @@ __device__ inline void relaxed_product(const DSArgs &a, int i, const Real *xc, R
             const Real v = val[q];
             const Real *xj = xc + (size_t)a.col[q] * RG;
 #pragma unroll
-            for (int r = 0; r < RG; ++r) z[r] = __builtin_fma(v, xj[r], z[r]);
+            for (int r = 0; r < RG; ++r) z[r] = dfma(v, xj[r], z[r]);
         }
     } else if constexpr (CK == CK_DENSE) {
         const Real *row = (const Real *)a.J + (size_t)i * a.n;
         for (int j = 0; j < a.n; ++j) {
             const Real v = row[j];
 #pragma unroll
-            for (int r = 0; r < RG; ++r) z[r] = __builtin_fma(v, xc[(size_t)j * RG + r], z[r]);
+            for (int r = 0; r < RG; ++r) z[r] = dfma(v, xc[(size_t)j * RG + r], z[r]);
         }
     }
 }
@@ -494,7 +507,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
 #pragma unroll
         for (int r = 0; r < RG; ++r)
             if (a.conv_step[r0 + r] > 0) stopped |= 1u << r;
-        done = stopped;
+        done = (uint32_t)__builtin_amdgcn_readfirstlane((int)stopped);  // uniform: kept in a scalar register
         if (lane < RG) {
             conv_t = a.conv_step[r0 + lane];
             const Real *cs = (const Real *)a.conv_state + (size_t)(r0 + lane) * (kConvWindowMax + 1);
@@ -525,7 +538,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 for (int e = 0; e < ELL_AHEAD && e < EPT; ++e)
 #pragma unroll
                     for (int j = 0; j < kEllWidth; ++j)
-                        nbw[e][j] = ((const uint32_t *)ellp)[((size_t)e * kEllWidth + j) * B + tid];
+                        nbw[e][j] = ((const GlobalU32 *)ellp)[((size_t)e * kEllWidth + j) * B + tid];
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
@@ -533,7 +546,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 if (use_ell && e + ELL_AHEAD < EPT)
 #pragma unroll
                     for (int j = 0; j < kEllWidth; ++j)
-                        nbw[e + ELL_AHEAD][j] = ((const uint32_t *)ellp)[((size_t)(e + ELL_AHEAD) * kEllWidth + j) * B + tid];
+                        nbw[e + ELL_AHEAD][j] = ((const GlobalU32 *)ellp)[((size_t)(e + ELL_AHEAD) * kEllWidth + j) * B + tid];
             }
             if (e * B + tid >= n) continue;
             const int i = local_index<EPT>(spin_of(e));
@@ -549,8 +562,10 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     cnt += (uint32_t)sc[w & 0xffffffu] ^ ((uint32_t)((int32_t)w >> 31) & SWd::ones);
                 }
                 const int deg = (int)((nbw[e][0] >> 24) & 0x7fu);
+                const int hk = (int)((int32_t)(nbw[e][1] << 1) >> 25);  // the integer field, bits 24..30
+                // w (deg - 2 count) + h: integers, exact in the state precision
 #pragma unroll
-                for (int r = 0; r < RG; ++r) y[r] = (Real)a.w * (Real)(deg - 2 * (int)cnt);
+                for (int r = 0; r < RG; ++r) y[r] = (Real)a.w * (Real)(deg - 2 * (int)cnt) + (Real)hk;
             } else {
                 coupling<Real, CK, RG>(a, i, sc, y);
             }
@@ -561,8 +576,13 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     if constexpr (is_pms(CK)) relaxed_product<Real, CK, RG>(a, i, xc, z, img, prow_r[e], pcnt_r[e]);
                     else relaxed_product<Real, CK, RG>(a, i, xc, z);
                 }
-            const Real hh = hv ? hv[i] : (Real)0;
+            const Real hh = WIDE_ELL ? (Real)0 : hv ? hv[i] : (Real)0;  // fixed-width rows: in y
             SW word = 0;
+            // The replicas' updates.  A replica stopped by the convergence test keeps its angle,
+            // moments and vertex; until one has stopped (always, without the test) the loop runs
+            // without that per-replica test, whose branches would keep the compiler from
+            // interleaving the replicas' updates.
+            auto replicas = [&](auto check) __attribute__((always_inline)) {
 #pragma unroll
             for (int r = 0; r < RG; ++r) {
                 const int k = e * RG + r;
@@ -576,23 +596,23 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 // s = sgn(sin theta) as +-1 (the vertex bit k of cur); products with it are exact
                 const Real sg = x < 0 ? (Real)-1 : (Real)1;
                 const Real yh = y[r] + hh;
-                Ep[r] = __builtin_fma(sg, yh, Ep[r]);
-                Real tt = __builtin_fma(-mu, sg, yh);  // y - mu s + h
+                Ep[r] = dfma(sg, yh, Ep[r]);
+                Real tt = dfma(-mu, sg, yh);  // y - mu s + h
                 if constexpr (CAN_RELAX) {
                     if (relaxed) {
-                        const Real zm = __builtin_fma(-mu, x, z[r]);  // z - mu x
+                        const Real zm = dfma(-mu, x, z[r]);  // z - mu x
                         tt = zm + hh;                                 // L term: z - mu x + h
-                        Lp[r] = __builtin_fma(x, tt, Lp[r]);
+                        Lp[r] = dfma(x, tt, Lp[r]);
                         tt = tt + zm;                                 // gradient term: 2 z - 2 mu x + h
                     } else {
-                        Lp[r] = __builtin_fma(x, tt, Lp[r]);
+                        Lp[r] = dfma(x, tt, Lp[r]);
                     }
                 } else {
-                    Lp[r] = __builtin_fma(x, tt, Lp[r]);
+                    Lp[r] = dfma(x, tt, Lp[r]);
                 }
                 Real xn = x;  // a stopped replica keeps its angle, moments and vertex
                 bool xneg = x < 0;
-                if (!((done >> r) & 1u)) {
+                if (!decltype(check)::value || !((done >> r) & 1u)) {
                     const Real g = c * tt;
                     Real upd;
                     if (adam) {
@@ -625,6 +645,13 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     word |= (SW)(1u << SWd::shift(r));
                 }
                 if (CAN_RELAX && relaxed) putx(t & 1, e * B + tid, r, xn);
+            }
+            };
+            if constexpr (RG == 1) {
+                replicas(Flag<true>{});  // one replica: nothing to interleave
+            } else {
+                if (done) replicas(Flag<true>{});
+                else replicas(Flag<false>{});
             }
             put(t & 1, e, word);
             // keep the scheduler from interleaving elements: bounds live ranges
@@ -963,16 +990,28 @@ __global__ void k_format(DevProblem p, int packed, uint32_t *pm, Real *val_out, 
 }
 
 // Fixed-width neighbour rows for the wide engine: slot j of position q = e * block + t
-// (spin q) at ((e * kEllWidth + j) * block + t); slot 0 carries the degree in bits 24..30
-__global__ void k_ell_format(DevProblem p, const uint32_t *pm, int ept, int block, uint32_t *ell) {
+// (spin q) at ((e * kEllWidth + j) * block + t); slot 0 carries the degree in bits 24..30,
+// slot 1 the spin's field as a 7-bit two's-complement integer in the same bits
+__global__ void k_ell_format(DevProblem p, const uint32_t *pm, const float *hf, int ept, int block,
+                             uint32_t *ell, int32_t *bad) {
     const int total = ept * block;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
         const int e = q / block, t = q % block;
         const int rs = q < p.n ? p.row_ptr[q] : 0, deg = q < p.n ? p.row_ptr[q + 1] - rs : 0;
+        int hk = 0;
+        if (hf && q < p.n) {
+            const float hv = hf[q];
+            hk = (int)hv;
+            if (!((float)hk == hv && hk >= -63 && hk <= 63)) {
+                atomicOr(bad, 1);
+                hk = 0;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < kEllWidth; ++j) {
             uint32_t w = j < deg ? (pm[rs + j] & 0x80ffffffu) : (uint32_t)p.n;  // pads: the zero word
             if (j == 0) w |= (uint32_t)deg << 24;
+            if (j == 1) w |= ((uint32_t)hk & 0x7fu) << 24;
             ell[((size_t)e * kEllWidth + j) * block + t] = w;
         }
     }
@@ -1291,11 +1330,12 @@ int32_t ds_max_n(bool fp64) {
     return 48 * 1024;
 }
 
-hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, int ept, int block, uint32_t *ell,
-                             hipStream_t s) {
-    if (p.format != ISING_CSR || ept <= 0 || block <= 0 || (int64_t)ept * block < p.n) return hipErrorInvalidValue;
+hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, int ept, int block,
+                             uint32_t *ell, int32_t *bad, hipStream_t s) {
+    if (p.format != ISING_CSR || ept <= 0 || block <= 0 || (int64_t)ept * block < p.n || !bad)
+        return hipErrorInvalidValue;
     const int total = ept * block;
-    hipLaunchKernelGGL(k_ell_format, dim3((total + 255) / 256), dim3(256), 0, s, p, pm, ept, block, ell);
+    hipLaunchKernelGGL(k_ell_format, dim3((total + 255) / 256), dim3(256), 0, s, p, pm, hf, ept, block, ell, bad);
     return hipGetLastError();
 }
 

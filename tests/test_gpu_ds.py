@@ -132,6 +132,11 @@ MULTI = [
     ("torus100x200_pm_ept28", lambda: I.torus(100, 200, 19, "pm1"), 4),
     ("reg3_20000_real_csrv_ept28", lambda: _gauss_weights(I.random_regular(20000, 3, 20, "pm1"), 21), 4),
     ("reg3_24000_pm_ept32", lambda: I.random_regular(24000, 3, 23, "pm1"), 4),
+    # integer fields: |h| <= 63 ride in the fixed-width rows' spare bits; larger ones keep the
+    # sign-packed CSR rows
+    ("torus100x200_field3_rows_ept28", lambda: I.random_integer_field(I.torus(100, 200, 24, "pm1"), 24, 3), 4),
+    ("reg3_12000_field100_csr_ept16", lambda: I.random_integer_field(I.random_regular(12000, 3, 25, "pm1"), 25, 100),
+     4),
     ("torus150x200_stream", lambda: I.torus(150, 200, 22, "pm1"), 4),
 ]
 
