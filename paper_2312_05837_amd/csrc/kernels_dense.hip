@@ -770,17 +770,40 @@ hipError_t dense_group_upload(const DenseRun *const *runs, int count, void *scra
     if (count <= 0) return hipErrorInvalidValue;
     const int form = runs[0]->form;
     std::vector<DenseDesc> descs;
-    std::vector<int4> tiles;
     std::vector<int2> quads;
+    // XCD-aware tile order.  Workgroups go to the 8 XCDs round-robin by index, each XCD with
+    // its own L2, and a step's tiles run together.  Each problem's tiles are split into a
+    // 2 x 4 grid of blocks (halves of the row tiles by quarters of the replica tiles), one
+    // block per XCD: an XCD then reads half of J and a quarter of the vertex operand, where
+    // a row-tile-fastest order would have every XCD read all of the vertex operand.  Only the
+    // order of independent tiles changes.
+    constexpr int kXcds = 8, kRowGroups = 2, kColGroups = kXcds / kRowGroups;
+    std::vector<int4> per_xcd[kXcds];
     for (int k = 0; k < count; ++k) {
         const DenseRun &d = *runs[k];
         if (d.form != form || d.Mp % BM || d.Kp % (d.form == DF_FP8 ? 2 * KCB : KCB) || d.Mp < d.n || d.Kp < d.n)
             return hipErrorInvalidValue;
         if (d.opt == ISING_OPT_ADAM && !d.bias) return hipErrorInvalidValue;
         descs.push_back(make_desc(d));
-        for (int nt = 0; nt < (d.R + BN - 1) / BN; ++nt)
-            for (int mt = 0; mt < d.Mp / BM; ++mt) tiles.push_back(make_int4(k, mt, nt, 0));
+        const int MT = d.Mp / BM, NT = (d.R + BN - 1) / BN;
+        for (int nt = 0; nt < NT; ++nt)
+            for (int mt = 0; mt < MT; ++mt) {
+                const int x = (mt * kRowGroups / MT) * kColGroups + nt * kColGroups / NT;
+                per_xcd[x].push_back(make_int4(k, mt, nt, 0));
+            }
         for (int q = 0; q < (d.R + 3) / 4; ++q) quads.push_back(make_int2(k, q));
+    }
+    // position p goes to XCD p % 8: deal the blocks' tiles out in that order (uneven blocks
+    // leave a tail in another order, which only costs locality)
+    std::vector<int4> tiles;
+    size_t next[kXcds] = {};
+    for (bool more = true; more;) {
+        more = false;
+        for (int x = 0; x < kXcds; ++x)
+            if (next[x] < per_xcd[x].size()) {
+                tiles.push_back(per_xcd[x][next[x]++]);
+                more = true;
+            }
     }
     char *p = (char *)scratch;
     DenseDesc *dd = (DenseDesc *)p;
