@@ -93,7 +93,7 @@ struct DSArgs {
     const int32_t *col = nullptr;
     const uint32_t *pm = nullptr;      // sign-packed entries: col | (J < 0) << 31
     // sign-packed entries in fixed-width rows for the wide engine (8+ spins per thread, degree
-    // <= kEllWidth): [ept][kEllWidth][block], slot j of position e * block + thread holds
+    // <= kEllWidth): [ept][block][kEllWidth], slot j of position e * block + thread holds
     // col | (J < 0) << 31, slot 0 also the degree << 24, slot 1 the spin's integer field (7-bit
     // two's complement) << 24 (the engine reads no separate field then); unused slots address
     // the zero word n

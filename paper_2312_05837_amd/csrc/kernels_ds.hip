@@ -136,6 +136,8 @@ __device__ inline double dasin(double x) { return asin(x); }
 // a word in global memory, addressed as such (an address made opaque to the compiler would
 // otherwise be read with flat loads, which a wait for LDS reads also waits for)
 using GlobalU32 = __attribute__((address_space(1))) uint32_t;
+using U32x4 = uint32_t __attribute__((ext_vector_type(4)));
+using GlobalU32x4 = __attribute__((address_space(1))) U32x4;
 
 // a compile-time flag passed to a generic lambda
 template <bool B>
@@ -529,24 +531,21 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         constexpr bool WIDE_ELL = CK == CK_PME;
         constexpr int ELL_AHEAD = EPT >= 28 ? 2 : 4;  // the widest variants leave little register room
         constexpr bool use_ell = WIDE_ELL;
-        uint32_t nbw[WIDE_ELL ? EPT : 1][kEllWidth];
+        // a spin's kEllWidth words are contiguous: one 16-byte load per lane, coalesced over the wave
+        static_assert(kEllWidth == 4, "one 16-byte load per spin");
+        U32x4 nbw[WIDE_ELL ? EPT : 1];
         uintptr_t ellp = (uintptr_t)a.ell;
         if constexpr (WIDE_ELL) {
             asm volatile("" : "+s"(ellp));
             if (use_ell)
 #pragma unroll
-                for (int e = 0; e < ELL_AHEAD && e < EPT; ++e)
-#pragma unroll
-                    for (int j = 0; j < kEllWidth; ++j)
-                        nbw[e][j] = ((const GlobalU32 *)ellp)[((size_t)e * kEllWidth + j) * B + tid];
+                for (int e = 0; e < ELL_AHEAD && e < EPT; ++e) nbw[e] = ((const GlobalU32x4 *)ellp)[(size_t)e * B + tid];
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             if constexpr (WIDE_ELL) {
                 if (use_ell && e + ELL_AHEAD < EPT)
-#pragma unroll
-                    for (int j = 0; j < kEllWidth; ++j)
-                        nbw[e + ELL_AHEAD][j] = ((const GlobalU32 *)ellp)[((size_t)(e + ELL_AHEAD) * kEllWidth + j) * B + tid];
+                    nbw[e + ELL_AHEAD] = ((const GlobalU32x4 *)ellp)[(size_t)(e + ELL_AHEAD) * B + tid];
             }
             if (e * B + tid >= n) continue;
             const int i = local_index<EPT>(spin_of(e));
@@ -990,7 +989,7 @@ __global__ void k_format(DevProblem p, int packed, uint32_t *pm, Real *val_out, 
 }
 
 // Fixed-width neighbour rows for the wide engine: slot j of position q = e * block + t
-// (spin q) at ((e * kEllWidth + j) * block + t); slot 0 carries the degree in bits 24..30,
+// (spin q) at (q * kEllWidth + j); slot 0 carries the degree in bits 24..30,
 // slot 1 the spin's field as a 7-bit two's-complement integer in the same bits
 __global__ void k_ell_format(DevProblem p, const uint32_t *pm, const float *hf, int ept, int block,
                              uint32_t *ell, int32_t *bad) {
@@ -1012,7 +1011,7 @@ __global__ void k_ell_format(DevProblem p, const uint32_t *pm, const float *hf, 
             uint32_t w = j < deg ? (pm[rs + j] & 0x80ffffffu) : (uint32_t)p.n;  // pads: the zero word
             if (j == 0) w |= (uint32_t)deg << 24;
             if (j == 1) w |= ((uint32_t)hk & 0x7fu) << 24;
-            ell[((size_t)e * kEllWidth + j) * block + t] = w;
+            ell[((size_t)e * block + t) * kEllWidth + j] = w;
         }
     }
 }
