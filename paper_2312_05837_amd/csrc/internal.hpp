@@ -94,7 +94,8 @@ struct DSArgs {
     const uint32_t *pm = nullptr;      // sign-packed entries: col | (J < 0) << 31
     // sign-packed entries in fixed-width rows for the wide engine (8+ spins per thread, degree
     // <= kEllWidth): [ept][block][kEllWidth], slot j of position e * block + thread holds
-    // col | (J < 0) << 31, slot 0 also the degree << 24, slot 1 the spin's integer field (7-bit
+    // 2 col + (J < 0) (the neighbour's vertex byte or its complement), slot 0 also the degree
+    // << 24, slot 1 the spin's integer field (7-bit
     // two's complement) << 24 (the engine reads no separate field then); unused slots address
     // the zero word n
     const uint32_t *ell = nullptr;
@@ -171,7 +172,8 @@ int pms_region_bytes(const DSLaunch &l);
 constexpr int kPmsMaxMult = 4;
 hipError_t launch_pms_format(const DevProblem &p, const DSLaunch &l, double wunit, PmsWork &w,
                              int32_t *total_groups, hipStream_t s);
-size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups);
+// twin: the fixed-width-row form, whose vertex buffers hold each word and its complement
+size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups, bool twin = false);
 // Batched persistent engine (FP32): workgroup b runs replica group map[b].y of
 // descs[map[b].x]; all descriptors share the launch configuration l.
 hipError_t launch_ds_batch(const DSArgs *descs, const int2 *map, int nwg, const DSLaunch &l, size_t lds,

@@ -349,10 +349,13 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     // Vertex buffers, double-buffered by step parity.  CK_PMS: each parity holds
     // a region of words (position q of the thread layout) and a region of their
     // per-replica complements, a.pms_rb bytes each, with a zero word at position
-    // EPT*B for padded slots.  Other couplings: npad words per parity, indexed by
-    // spin, word n kept zero.
+    // EPT*B for padded slots.  CK_PME: per parity, each spin's word and its complement side by
+    // side (byte 2 i + c), so that a row entry 2 col + (J < 0) reads the neighbour's term of the
+    // count directly; entry 2 n is kept zero.  Other couplings: npad words per parity, indexed
+    // by spin, word n kept zero.
+    constexpr bool TWIN = CK == CK_PME;
     const int npad = EPT * B + 1;
-    const size_t vbytes = is_pms(CK) ? (size_t)4 * a.pms_rb : (size_t)2 * npad * sizeof(SW);
+    const size_t vbytes = is_pms(CK) ? (size_t)4 * a.pms_rb : (size_t)2 * npad * sizeof(SW) * (TWIN ? 2 : 1);
     SW *sbuf = (SW *)smem;
     const size_t off = (vbytes + 15) & ~(size_t)15;
     Real *ep = (Real *)(smem + off);      // [2][NW][RG]
@@ -394,13 +397,16 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     // vertex buffer of parity par, as the coupling reads it
     auto vbuf = [&](int par) -> SW * {
         if constexpr (is_pms(CK)) return (SW *)(smem + (size_t)par * 2 * a.pms_rb);
-        else return sbuf + par * npad;
+        else return sbuf + par * npad * (TWIN ? 2 : 1);
     };
     auto put = [&](int par, int e, SW word) {
         SW *S = vbuf(par);
         if constexpr (is_pms(CK)) {
             S[e * B + tid] = word;
             ((SW *)((unsigned char *)S + a.pms_rb))[e * B + tid] = (SW)(word ^ (SW)SWd::ones);
+        } else if constexpr (TWIN) {
+            static_assert(sizeof(SW) == 1, "one byte per spin and copy");
+            ((uint16_t *)S)[e * B + tid] = (uint16_t)((uint32_t)word | ((uint32_t)(word ^ (SW)SWd::ones) << 8));
         } else {
             S[e * B + tid] = word;
         }
@@ -421,6 +427,9 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         if constexpr (is_pms(CK)) {
             vbuf(0)[EPT * B] = 0;
             vbuf(1)[EPT * B] = 0;
+        } else if constexpr (TWIN) {
+            ((uint16_t *)vbuf(0))[n] = 0;
+            ((uint16_t *)vbuf(1))[n] = 0;
         } else {
             sbuf[n] = 0;
             sbuf[npad + n] = 0;
@@ -557,8 +566,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 uint32_t cnt = 0;
 #pragma unroll
                 for (int j = 0; j < kEllWidth; ++j) {
-                    const uint32_t w = nbw[e][j];
-                    cnt += (uint32_t)sc[w & 0xffffffu] ^ ((uint32_t)((int32_t)w >> 31) & SWd::ones);
+                    cnt += (uint32_t)sc[nbw[e][j] & 0xffffffu];  // the word or its complement
                 }
                 const int deg = (int)((nbw[e][0] >> 24) & 0x7fu);
                 const int hk = (int)((int32_t)(nbw[e][1] << 1) >> 25);  // the integer field, bits 24..30
@@ -989,7 +997,7 @@ __global__ void k_format(DevProblem p, int packed, uint32_t *pm, Real *val_out, 
 }
 
 // Fixed-width neighbour rows for the wide engine: slot j of position q = e * block + t
-// (spin q) at (q * kEllWidth + j); slot 0 carries the degree in bits 24..30,
+// (spin q) at (q * kEllWidth + j), entry 2 col + (J < 0) in bits 0..23; slot 0 carries the degree in bits 24..30,
 // slot 1 the spin's field as a 7-bit two's-complement integer in the same bits
 __global__ void k_ell_format(DevProblem p, const uint32_t *pm, const float *hf, int ept, int block,
                              uint32_t *ell, int32_t *bad) {
@@ -1008,7 +1016,8 @@ __global__ void k_ell_format(DevProblem p, const uint32_t *pm, const float *hf, 
         }
 #pragma unroll
         for (int j = 0; j < kEllWidth; ++j) {
-            uint32_t w = j < deg ? (pm[rs + j] & 0x80ffffffu) : (uint32_t)p.n;  // pads: the zero word
+            // entry 2 col + (J < 0): the neighbour's vertex byte or its complement; pads: 2 n, zero
+            uint32_t w = j < deg ? 2u * (pm[rs + j] & 0x7fffffffu) + (pm[rs + j] >> 31) : 2u * (uint32_t)p.n;
             if (j == 0) w |= (uint32_t)deg << 24;
             if (j == 1) w |= ((uint32_t)hk & 0x7fu) << 24;
             ell[((size_t)e * block + t) * kEllWidth + j] = w;
@@ -1363,7 +1372,7 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
     if (l.coupling == CK_PMS && a.pms_rb != pms_region_bytes(l)) return hipErrorInvalidValue;
     if ((a.loss == ISING_LOSS_RELAXED) != l.relaxed || (l.relaxed && l.ept <= 0))
         return hipErrorInvalidValue;
-    const size_t lds = ds_lds_bytes(l, a.n, a.pimg_groups);
+    const size_t lds = ds_lds_bytes(l, a.n, a.pimg_groups, ck == CK_PME);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1443,13 +1452,13 @@ hipError_t launch_pms_format(const DevProblem &p, const DSLaunch &l, double wuni
     return hipGetLastError();
 }
 
-size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups) {
+size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups, bool twin) {
     const size_t sw = l.rg == 1 ? 1 : 4;
     const size_t real = l.fp64 ? 8 : 4;
     const int nw = l.block / 64;
     size_t sbytes;
     if (l.coupling == CK_PMS) sbytes = (size_t)4 * pms_region_bytes(l);
-    else sbytes = l.ept > 0 ? (size_t)2 * (l.ept * l.block + 1) * sw : (size_t)3 * n * sw;
+    else sbytes = l.ept > 0 ? (size_t)2 * (l.ept * l.block + 1) * sw * (twin ? 2 : 1) : (size_t)3 * n * sw;
     size_t lds = ((sbytes + 15) & ~(size_t)15) + 2 * 2 * nw * l.rg * real + 8;
     if (l.coupling == CK_PMS) lds = ((lds + 15) & ~(size_t)15) + (size_t)8 * pimg_groups;
     if (l.relaxed) {
