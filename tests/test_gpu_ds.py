@@ -163,6 +163,16 @@ def test_fp32_iterates_several_spins_per_thread(ctx, name, mk, R, opt, lr, steps
     test_fp32_iterates(ctx, name, mk, R, opt, lr, steps)
 
 
+@pytest.mark.parametrize("opt,lr,steps", [("gd", 0.0005, 100), ("adam", 0.002, 30)])
+def test_fp32_iterates_field_at_row_bits_range(ctx, opt, lr, steps):
+    # the fixed-width rows' spare bits end to end: h uniform on [-63, 63] (about 300 spins at
+    # +-63).  Fields this large make each step move an angle by up to lr (|y| + mu + 63), so the
+    # step sizes are a tenth of the other several-spins cases', keeping the map as well
+    # conditioned; vertices and exact energies are checked at every step as everywhere.
+    test_fp32_iterates(ctx, "torus100x200_field63_rows_ept28",
+                       lambda: I.random_integer_field(I.torus(100, 200, 26, "pm1"), 26, 63), 4, opt, lr, steps)
+
+
 @pytest.mark.parametrize("opt,lr,steps", [("adam", 6.0, 20), ("gd", 0.05, 100)])
 @pytest.mark.parametrize("name,mk,R", [CASES[0], CASES[1], CASES[3], CASES[4], CASES[5], CASES[6], CASES[8]],
                          ids=[c[0] for c in [CASES[0], CASES[1], CASES[3], CASES[4], CASES[5], CASES[6], CASES[8]]])
