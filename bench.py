@@ -27,6 +27,9 @@ sys.path.insert(0, ROOT)
 # VALU lane-operations per second of one MI355X without packed math:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# the FP32 vector rate in lane operations (157.3 TFLOP/s counts an FMA as two): twice the figure
+# above, reached with packed FP32, which this build does not use; reported beside it
+FP32_VECTOR_LANE_OPS = 157.3e12 / 2
 # Algorithmic operations of one (spin, replica) update besides the coupling
 # product, counted from the step's formulas (sin, cos, sign, y+h, energy and
 # loss accumulation, t, g, moments, bias corrections, sqrt, division, update,
@@ -525,7 +528,7 @@ def main():
             ops = T_eff * R * (nnzG + EPI_OPS[args.optimizer] * nG)
         achieved = ops / (k_ms * 1e-3)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                "frac": achieved / ALU_PEAK_OPS, "traffic": recorded_traffic("k_ds", args.workload),
+                "frac": achieved / ALU_PEAK_OPS, "frac_of_fp32_vector_rate": achieved / FP32_VECTOR_LANE_OPS, "traffic": recorded_traffic("k_ds", args.workload),
                 "kernel": "k_ds (persistent domain-selection engine)", "kernel_ms": k_ms, "ops_per_launch": ops}
     prec_err = precision_error(ctx, inst, prob, prec, dense_mfma, loss) \
         if prec != "fp64" and conv_tol == 0 else None
