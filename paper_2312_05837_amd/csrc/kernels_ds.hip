@@ -32,6 +32,11 @@
 //            group-major (group k of its 64 lanes contiguous), and each row's
 //            neighbours are ordered so that at every read the lanes of a
 //            wavefront tend to hit distinct LDS banks.
+//   CK_PME   +-w couplings of degree <= 4 with one replica per workgroup and 8+
+//            spins per thread: fixed-width rows in global memory, a spin's four
+//            entries 2 col + (J < 0) in one 16-byte word loaded a few spins ahead,
+//            into a vertex buffer holding each spin's byte and its complement;
+//            an integer field rides in the rows' spare bits.
 //   CK_CSRV  CSR values in the state precision.
 //   CK_DENSE dense rows in the state precision (small problems).
 #include "internal.hpp"
