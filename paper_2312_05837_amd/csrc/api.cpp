@@ -335,6 +335,13 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
     else if (p.format == ISING_CSR) a.val = fmt;
     else a.J = fmt;
     a.h = p.h ? hbuf : nullptr;
+    {
+        // no field and integer couplings whose |J| summed over all entries stays below 2^24:
+        // every product and energy sum of the FP32 engine is then an exact integer
+        const double jmax = ing.uniform_mag() ? ing.w : (double)ing.max_abs_int();
+        const double entries = p.format == ISING_CSR ? (double)p.nnz : (double)p.n * p.n;
+        a.exact_sums = !p.h && ing.integer() && jmax > 0 && jmax * entries < 16777216.0;
+    }
     return ISING_OK;
 }
 

@@ -119,6 +119,9 @@ struct DSArgs {
     const int32_t *pperm = nullptr;    // spin held at position q
     int32_t pms_rb = 0;                // bytes of one vertex region (pms_region_bytes)
     int32_t loss = ISING_LOSS_VERTEX;  // RELAXED: also z = J sin(theta) from an LDS copy of sin(theta)
+    // nonzero: no field, and every coupling product and energy sum is an integer below 2^24 in the
+    // state precision (integer w, w * nnz < 2^24), so sums may be taken in any order
+    int32_t exact_sums = 0;
     // convergence test (off when conv_tol <= 0): each wavefront replays it on the step's losses
     double conv_tol = 0.0;
     int32_t conv_window = 5;

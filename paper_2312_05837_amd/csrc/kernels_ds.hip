@@ -164,7 +164,28 @@ __device__ inline double dsqrt(double x) { return sqrt(x); }
 __device__ inline float drint(float x) { return rintf(x); }
 __device__ inline float drcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double drcp(double x) { return 1.0 / x; }
+
 __device__ inline double drint(double x) { return rint(x); }
+
+// One GD or ADAM step of an angle, wrapped to [-pi, pi] with the two-constant 2 pi: the same
+// operations in every engine form, with contraction off so that only the written FMAs fuse.
+template <typename Real>
+__device__ __forceinline__ Real angle_step(Real th, Real &mo, Real &ve, Real g, bool adam, Real b1, Real omb1,
+                                           Real b2, Real omb2, Real lib1, Real lr, Real ib2, Real eps) {
+#pragma clang fp contract(off)
+    Real upd;
+    if (adam) {
+        mo = dfma(b1, mo, omb1 * g);
+        ve = dfma(b2, ve, omb2 * (g * g));
+        upd = (mo * lib1) * drcp(dsqrt(ve * ib2) + eps);
+    } else {
+        upd = lr * g;
+    }
+    Real tn = th - upd;
+    const Real q = drint(tn * Consts<Real>::inv_twopi);
+    tn = dfma(-q, Consts<Real>::twopi_hi, tn);
+    return dfma(-q, Consts<Real>::twopi_lo, tn);
+}
 
 // Output number (c + 1) of SplitMix64 seeded with `seed` (Steele, Lea, Flood 2014).
 __device__ inline uint64_t splitmix64(uint64_t seed, uint64_t c) {
@@ -631,19 +652,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 Real xn = x;  // a stopped replica keeps its angle, moments and vertex
                 bool xneg = x < 0;
                 if (!decltype(check)::value || !((done >> r) & 1u)) {
-                    const Real g = c * tt;
-                    Real upd;
-                    if (adam) {
-                        mo[k] = b1 * mo[k] + omb1 * g;
-                        ve[k] = b2 * ve[k] + omb2 * (g * g);
-                        upd = (mo[k] * lib1) * drcp(dsqrt(ve[k] * ib2) + eps);
-                    } else {
-                        upd = lr * g;
-                    }
-                    Real tn = th[k] - upd;
-                    const Real q = drint(tn * Consts<Real>::inv_twopi);
-                    tn = tn - q * Consts<Real>::twopi_hi;
-                    tn = tn - q * Consts<Real>::twopi_lo;
+                    const Real tn = angle_step(th[k], mo[k], ve[k], c * tt, adam, b1, omb1, b2, omb2, lib1, lr, ib2, eps);
                     th[k] = tn;
                     if (KEEP) {
                         Real cn;
@@ -792,6 +801,186 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     }
 }
 
+
+// Split-step form of the staged-image engine for four replicas per workgroup and one spin
+// per thread (FP32, vertex loss, no field, exact integer sums; no traces or convergence test).
+// With one spin per thread the 4 n (spin, replica) updates of a workgroup would run on
+// ceil(n / 64) wavefronts, 4 of them on one SIMD for n = 800, which then sets the step time.
+// Here a step is
+//   A: thread q < n computes y of position q for the four replicas from the staged image
+//      (as the engine does) and puts them in LDS;
+//   B: all 1024 threads update (position, replica) items j = k 1024 + thread, each thread
+//      always the same replica (j mod 4), so the updates spread evenly over 16 wavefronts.
+// Every item runs the engine's own operations (angle_step, dsincos), the vertex bytes are
+// written where the engine writes its words, and the energy sums are exact integers in any
+// order: the results are the engine's bit for bit.
+constexpr int kSplitBlock = 1024, kSplitItems = 4;
+
+size_t split_lds_bytes(int pms_rb, int pimg_groups, int bimg) {
+    size_t off = ((size_t)4 * pms_rb + 15) & ~(size_t)15;
+    off += (size_t)2 * (kSplitBlock / 64) * 4 * sizeof(float) + 8;
+    off = (off + 15) & ~(size_t)15;
+    off += (size_t)8 * pimg_groups;
+    off = (off + 15) & ~(size_t)15;
+    return off + (size_t)bimg * 4 * sizeof(float);
+}
+
+__global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bimg) {
+    constexpr int RG = 4, NW = kSplitBlock / 64, KI = kSplitItems;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = a.n, r0 = blockIdx.x * RG;
+    const int rr = tid & 3;  // this thread's replica in every item
+    size_t off = ((size_t)4 * a.pms_rb + 15) & ~(size_t)15;
+    float *ep = (float *)(smem + off);  // [2][NW][RG]
+    uint32_t *flg = (uint32_t *)(ep + 2 * NW * RG);
+    off = (off + (size_t)2 * NW * RG * sizeof(float) + 8 + 15) & ~(size_t)15;
+    uint2 *img = (uint2 *)(smem + off);
+    off = (off + (size_t)8 * a.pimg_groups + 15) & ~(size_t)15;
+    float *yb = (float *)(smem + off);  // [bimg][RG]
+    auto vbuf = [&](int par) -> uint32_t * { return (uint32_t *)(smem + (size_t)par * 2 * a.pms_rb); };
+    auto put_byte = [&](int par, int q, int r, bool neg) {
+        unsigned char *w = (unsigned char *)vbuf(par);
+        w[4 * q + r] = neg ? 1 : 0;               // field r of the word (one bit per replica)
+        w[a.pms_rb + 4 * q + r] = neg ? 0 : 1;    // and of its complement
+    };
+    {
+        const uint2 *src = (const uint2 *)a.pimg;
+        for (int q = tid; q < a.pimg_groups; q += kSplitBlock) img[q] = src[q];
+    }
+    int prow = 0;
+    uint32_t pcnt = 0;
+    if (tid < n) {
+        prow = a.prow[tid];
+        pcnt = a.pcnt[tid];
+    }
+    if (tid == 0) {
+        vbuf(0)[bimg] = 0;
+        vbuf(1)[bimg] = 0;
+    }
+    float *gth = (float *)a.theta, *gm = (float *)a.m, *gv = (float *)a.v;
+    const bool adam = a.opt == ISING_OPT_ADAM;
+    float th[KI], mo[KI], ve[KI], xs[KI], cs[KI];
+    int spin[KI];
+    uint32_t cur = 0, prv = 0, best = 0;
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+        const int j = k * kSplitBlock + tid;
+        th[k] = mo[k] = ve[k] = xs[k] = 0.f;
+        cs[k] = 1.f;
+        spin[k] = 0;
+        if (j >= 4 * n) continue;
+        const int q = j >> 2, i = a.pperm[q];
+        spin[k] = i;
+        const size_t idx = (size_t)(r0 + rr) * n + i;
+        float t;
+        if (a.init_mode == 0) {
+            t = gth[idx];
+            if (t > 3.5f || t < -3.5f) {  // as the engine: angles it wrote are within pi
+                const float qw = drint(t * Consts<float>::inv_twopi);
+                t = t - qw * Consts<float>::twopi_hi;
+                t = t - qw * Consts<float>::twopi_lo;
+            }
+            if (gm) mo[k] = gm[idx];
+            if (gv) ve[k] = gv[idx];
+            if (a.s_best[idx] < 0) best |= 1u << k;
+        } else {
+            const float u = a.init_mode == 1 ? ((const float *)a.uniform)[idx] : draw_uniform<float>(a.seed, r0 + rr, i);
+            t = dasin(u);
+        }
+        th[k] = t;
+        float x, c;
+        dsincos(t, &x, &c);
+        xs[k] = x;
+        cs[k] = c;
+        if (x < 0) cur |= 1u << k;
+        put_byte(0, q, rr, x < 0);
+    }
+    if (tid < 2) flg[tid] = 0;
+    double ebest = INFINITY;
+    int bstep = 0;
+    if (wave == 0 && lane < RG && a.init_mode == 0) {
+        ebest = a.e_best[r0 + lane];
+        bstep = a.best_step[r0 + lane];
+    }
+    __syncthreads();
+
+    const float lr = (float)a.lr, mu = (float)a.mu, b1 = (float)a.b1, b2 = (float)a.b2, eps = (float)a.eps;
+    const float omb1 = (float)(1.0 - a.b1), omb2 = (float)(1.0 - a.b2);
+    const float *bct = (const float *)a.bias;
+    for (int t = 1; t <= a.steps; ++t) {
+        const uint32_t *sc = vbuf((t - 1) & 1);
+        const float ib1 = adam ? bct[2 * (t - 1)] : 1.f, ib2 = adam ? bct[2 * (t - 1) + 1] : 1.f;
+        const float lib1 = lr * ib1;
+        // A: the coupling product of position tid for the four replicas
+        if (tid < n) {
+            float y[RG];
+            coupling<float, CK_PMS, RG>(a, 0, sc, y, img, prow, pcnt);
+            *(float4 *)(yb + 4 * tid) = make_float4(y[0], y[1], y[2], y[3]);
+        }
+        __syncthreads();
+        // B: the items' updates
+        float Ep = -0.f;
+        uint32_t nxt = 0;
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            const int j = k * kSplitBlock + tid;
+            if (j >= 4 * n) continue;
+            const int q = j >> 2;
+            const float x = xs[k], c = cs[k];
+            const float sg = x < 0 ? -1.f : 1.f;
+            const float yh = yb[j] + 0.f;  // no field
+            Ep = dfma(sg, yh, Ep);
+            const float tt = dfma(-mu, sg, yh);
+            const float tn = angle_step(th[k], mo[k], ve[k], c * tt, adam, b1, omb1, b2, omb2, lib1, lr, ib2, eps);
+            th[k] = tn;
+            float xn, cn;
+            dsincos(tn, &xn, &cn);
+            xs[k] = xn;
+            cs[k] = cn;
+            if (xn < 0) nxt |= 1u << k;
+            put_byte(t & 1, q, rr, xn < 0);
+        }
+        // per-replica sums over the lanes of this replica (exact integers: any order)
+#pragma unroll
+        for (int d = 4; d < 64; d <<= 1) Ep += __shfl_xor(Ep, d);
+        if (lane < RG) ep[((t & 1) * NW + wave) * RG + lane] = Ep;
+        __syncthreads();
+        if ((flg[(t - 1) & 1] >> rr) & 1u) best = prv;
+        prv = cur;
+        cur = nxt;
+        if (wave == 0) {
+            bool imp = false;
+            if (lane < RG) {
+                float Es = 0;
+                for (int w = 0; w < NW; ++w) Es += ep[((t & 1) * NW + w) * RG + lane];
+                const double E = (double)Es;
+                imp = E < ebest;
+                if (imp) {
+                    ebest = E;
+                    bstep = a.t0 + t;
+                }
+            }
+            const uint64_t bal = __ballot(imp);
+            if (lane == 0) flg[t & 1] = (uint32_t)bal;
+        }
+    }
+    __syncthreads();
+    if (a.steps > 0 && ((flg[a.steps & 1] >> rr) & 1u)) best = prv;
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+        const int j = k * kSplitBlock + tid;
+        if (j >= 4 * n) continue;
+        const size_t idx = (size_t)(r0 + rr) * n + spin[k];
+        gth[idx] = th[k];
+        if (gm) gm[idx] = mo[k];
+        if (gv) gv[idx] = ve[k];
+        a.s_best[idx] = ((best >> k) & 1u) ? (int8_t)-1 : (int8_t)1;
+    }
+    if (wave == 0 && lane < RG) {
+        a.e_best[r0 + lane] = ebest;
+        a.best_step[r0 + lane] = bstep;
+    }
+}
 
 template <typename Real, int CK, int RG, int EPT>
 __global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
@@ -1383,6 +1572,19 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
     if (l.coupling == CK_PMS && a.pms_rb != pms_region_bytes(l)) return hipErrorInvalidValue;
     if ((a.loss == ISING_LOSS_RELAXED) != l.relaxed || (l.relaxed && l.ept <= 0))
         return hipErrorInvalidValue;
+    if (ck == CK_PMS && !l.fp64 && l.rg == 4 && l.ept == 1 && a.exact_sums && !a.etrace && !a.ltrace &&
+        a.conv_tol <= 0 && !a.conv_step && l.block <= kSplitBlock) {
+        // the split-step form (same results, updates spread over all 16 wavefronts)
+        const size_t lds = split_lds_bytes(a.pms_rb, a.pimg_groups, l.block);
+        if (lds <= 160 * 1024) {
+            if (lds > 64 * 1024) {
+                hipError_t e = hipFuncSetAttribute((const void *)k_ds_split, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL(k_ds_split, dim3(a.R / 4), dim3(kSplitBlock), lds, s, a, l.block);
+            return hipGetLastError();
+        }
+    }
     const size_t lds = ds_lds_bytes(l, a.n, a.pimg_groups, ck == CK_PME);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {

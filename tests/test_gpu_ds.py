@@ -421,3 +421,48 @@ def test_convergence_across_calls_equals_one_launch(ctx, name, mk, R, prec):
     conv = one["conv_step"].cpu().numpy()
     assert (conv > 0).sum() >= R // 4, conv
     assert np.any(conv > 10), conv  # replicas stop in a later call than the first ones
+
+
+# ---- split-step form: four replicas per workgroup, one spin per thread, exact sums -----------
+
+SPLIT = [
+    ("er800", lambda: I.erdos_renyi(800, 0.06, 31, "pm1")),
+    ("torus20x40", lambda: I.torus(20, 40, 32, "pm1")),
+    ("er1000_int3", lambda: _er_int3()),
+    ("er700_ragged", lambda: I.erdos_renyi(700, 0.05, 33, "pm1")),
+]
+
+
+@pytest.mark.parametrize("opt,lr", [("adam", 6.0), ("gd", 0.05)])
+@pytest.mark.parametrize("name,mk", SPLIT, ids=[c[0] for c in SPLIT])
+def test_split_step_equals_engine(ctx, name, mk, opt, lr):
+    # Without a trace these problems run the split-step form; asking for the energy trace runs
+    # the engine.  The two give the same angles, moments, best vertices and energies bit for
+    # bit, in one call and continued over three calls.
+    import torch
+    import paper_2312_05837_amd as P
+    from gpu_util import to_problem
+    inst = mk()
+    R, T = 1024, 60
+    U = torch.tensor(I.uniform_draws(41, R, inst.n), dtype=torch.float32, device="cuda")
+    prob = to_problem(inst)
+    prm = P.params(replicas=R, steps=T, optimizer=opt, lr=lr, mu=0.5)
+    split = P.ds_state(inst.n, R, optimizer=opt)
+    P.ising_ds_dev(ctx, prob, prm, split, t0=0, steps=T, uniform=U)
+    engine = P.ds_state(inst.n, R, optimizer=opt, steps_trace=T)
+    P.ising_ds_dev(ctx, prob, prm, engine, t0=0, steps=T, uniform=U)
+    chunked = P.ds_state(inst.n, R, optimizer=opt)
+    for t0 in (0, 25, 40):
+        P.ising_ds_dev(ctx, prob, prm, chunked, t0=t0, steps={0: 25, 25: 15, 40: 20}[t0],
+                       uniform=U if t0 == 0 else None)
+    torch.cuda.synchronize()
+    keys = ("theta", "m", "v", "s_best", "e_best", "best_step") if opt == "adam" else \
+        ("theta", "s_best", "e_best", "best_step")
+    for k in keys:
+        assert torch.equal(split[k], engine[k]), k
+        assert torch.equal(split[k], chunked[k]), k
+    # the best energies are those of the best vertices
+    sb = split["s_best"].cpu().numpy()
+    eb = split["e_best"].cpu().numpy()
+    for r in (0, 1, 2, 3, R - 1):
+        assert eb[r] == oracle.energy(inst, sb[r]), r
