@@ -529,7 +529,9 @@ def main():
         achieved = ops / (k_ms * 1e-3)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s",
                 "frac": achieved / ALU_PEAK_OPS, "frac_of_fp32_vector_rate": achieved / FP32_VECTOR_LANE_OPS, "traffic": recorded_traffic("k_ds", args.workload),
-                "kernel": "k_ds (persistent domain-selection engine)", "kernel_ms": k_ms, "ops_per_launch": ops}
+                "kernel": "k_ds (persistent domain-selection engine; its split-step form k_ds_split where the "
+                          "problem has four replicas per workgroup, one spin per thread and exact sums)",
+                "kernel_ms": k_ms, "ops_per_launch": ops}
     prec_err = precision_error(ctx, inst, prob, prec, dense_mfma, loss) \
         if prec != "fp64" and conv_tol == 0 else None
     # measured peak beside the nominal one: a plain device copy (after the timed region)
