@@ -430,6 +430,7 @@ SPLIT = [
     ("torus20x40", lambda: I.torus(20, 40, 32, "pm1")),
     ("er1000_int3", lambda: _er_int3()),
     ("er700_ragged", lambda: I.erdos_renyi(700, 0.05, 33, "pm1")),
+    ("er1000_all16", lambda: I.erdos_renyi(1000, 0.01, 34, "pm1")),  # positions on all 16 wavefronts
 ]
 
 
