@@ -940,9 +940,12 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
             if (xn < 0) nxt |= 1u << k;
             put_byte(t & 1, q, rr, xn < 0);
         }
-        // per-replica sums over the lanes of this replica (exact integers: any order)
-#pragma unroll
-        for (int d = 4; d < 64; d <<= 1) Ep += __shfl_xor(Ep, d);
+        // per-replica sums (exact integers: any order): the four lanes of a replica in each row of
+        // 16 lanes by two DPP rotations, then across the four rows by two lane exchanges
+        Ep += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, Ep), 0x124, 0xF, 0xF, false));
+        Ep += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, Ep), 0x128, 0xF, 0xF, false));
+        Ep += __shfl_xor(Ep, 16);
+        Ep += __shfl_xor(Ep, 32);
         if (lane < RG) ep[((t & 1) * NW + wave) * RG + lane] = Ep;
         __syncthreads();
         if ((flg[(t - 1) & 1] >> rr) & 1u) best = prv;
