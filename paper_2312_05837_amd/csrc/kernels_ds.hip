@@ -928,7 +928,8 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
             const int q = j >> 2;
             const float x = xs[k], c = cs[k];
             const float sg = x < 0 ? -1.f : 1.f;
-            const float yh = yb[j] + 0.f;  // no field
+            // no field: the engine's y + 0 is y here (y = w (deg - 2 count) with w > 0 is never -0)
+            const float yh = yb[j];
             Ep = dfma(sg, yh, Ep);
             const float tt = dfma(-mu, sg, yh);
             const float tn = angle_step(th[k], mo[k], ve[k], c * tt, adam, b1, omb1, b2, omb2, lib1, lr, ib2, eps);
