@@ -825,6 +825,7 @@ size_t split_lds_bytes(int pms_rb, int pimg_groups, int bimg) {
     return off + (size_t)bimg * 4 * sizeof(float);
 }
 
+template <bool ADAM>  // the optimizer as a compile-time choice: no per-item branch
 __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bimg) {
     constexpr int RG = 4, NW = kSplitBlock / 64, KI = kSplitItems;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -858,7 +859,7 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
         vbuf(1)[bimg] = 0;
     }
     float *gth = (float *)a.theta, *gm = (float *)a.m, *gv = (float *)a.v;
-    const bool adam = a.opt == ISING_OPT_ADAM;
+    constexpr bool adam = ADAM;
     float th[KI], mo[KI], ve[KI], xs[KI], cs[KI];
     int spin[KI];
     uint32_t cur = 0, prv = 0, best = 0;
@@ -1581,11 +1582,12 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
         // the split-step form (same results, updates spread over all 16 wavefronts)
         const size_t lds = split_lds_bytes(a.pms_rb, a.pimg_groups, l.block);
         if (lds <= 160 * 1024) {
+            const auto fn = a.opt == ISING_OPT_ADAM ? k_ds_split<true> : k_ds_split<false>;
             if (lds > 64 * 1024) {
-                hipError_t e = hipFuncSetAttribute((const void *)k_ds_split, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
                 if (e != hipSuccess) return e;
             }
-            hipLaunchKernelGGL(k_ds_split, dim3(a.R / 4), dim3(kSplitBlock), lds, s, a, l.block);
+            hipLaunchKernelGGL(fn, dim3(a.R / 4), dim3(kSplitBlock), lds, s, a, l.block);
             return hipGetLastError();
         }
     }
