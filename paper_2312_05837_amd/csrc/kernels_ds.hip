@@ -367,7 +367,8 @@ __device__ __forceinline__ int local_index(int i) {
     return i;
 }
 
-template <typename Real, int CK, int RG, int EPT>
+// OPT: the optimizer as a compile-time choice (0 GD, 1 ADAM) or -1 to read it at run time
+template <typename Real, int CK, int RG, int EPT, int OPT = -1>
 __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     using SWd = SpinWord<RG>;
     using SW = typename SWd::T;
@@ -471,7 +472,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     Real *gth = (Real *)a.theta;
     Real *gm = (Real *)a.m;
     Real *gv = (Real *)a.v;
-    const bool adam = a.opt == ISING_OPT_ADAM;
+    const bool adam = OPT >= 0 ? OPT == 1 : a.opt == ISING_OPT_ADAM;
 
     Real th[NE], mo[NE], ve[NE];
     Real xs[KEEP ? NE : 1], cs[KEEP ? NE : 1];
@@ -987,9 +988,9 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
     }
 }
 
-template <typename Real, int CK, int RG, int EPT>
+template <typename Real, int CK, int RG, int EPT, int OPT = -1>
 __global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
-    ds_body<Real, CK, RG, EPT>(a, blockIdx.x * RG);
+    ds_body<Real, CK, RG, EPT, OPT>(a, blockIdx.x * RG);
 }
 
 // Batched form for serving: workgroup b runs replica group map[b].y of problem
@@ -1513,7 +1514,7 @@ KFn pick_rg(int rg, int ept) {
 }
 
 template <typename Real>
-KFn pick(int ck, int rg, int ept) {
+KFn pick(int ck, int rg, int ept, bool adam) {
     switch (ck) {
         case CK_PM: return pick_rg<Real, CK_PM>(rg, ept);
         case CK_PMS: return ept > 0 ? pick_rg<Real, CK_PMS>(rg, ept) : nullptr;
@@ -1521,10 +1522,11 @@ KFn pick(int ck, int rg, int ept) {
         case CK_PME:
             if constexpr (sizeof(Real) == 4) {
                 if (rg != 1) return nullptr;
-                if (ept == 8) return k_ds<Real, CK_PME, 1, 8>;
-                if (ept == 16) return k_ds<Real, CK_PME, 1, 16>;
-                if (ept == 28) return k_ds<Real, CK_PME, 1, 28>;
-                if (ept == 32) return k_ds<Real, CK_PME, 1, 32>;
+                // the optimizer compiled in (these kernels run the longest per launch)
+                if (ept == 8) return adam ? k_ds<Real, CK_PME, 1, 8, 1> : k_ds<Real, CK_PME, 1, 8, 0>;
+                if (ept == 16) return adam ? k_ds<Real, CK_PME, 1, 16, 1> : k_ds<Real, CK_PME, 1, 16, 0>;
+                if (ept == 28) return adam ? k_ds<Real, CK_PME, 1, 28, 1> : k_ds<Real, CK_PME, 1, 28, 0>;
+                if (ept == 32) return adam ? k_ds<Real, CK_PME, 1, 32, 1> : k_ds<Real, CK_PME, 1, 32, 0>;
             }
             return nullptr;
         case CK_CSRV: return pick_rg<Real, CK_CSRV>(rg, ept);
@@ -1569,7 +1571,8 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
     const int ck = l.coupling == CK_PMS && l.relaxed ? CK_PMSR
                  : l.coupling == CK_PM && a.ell != nullptr && !l.relaxed ? CK_PME
                                                                           : l.coupling;
-    KFn fn = l.fp64 ? pick<double>(ck, l.rg, l.ept) : pick<float>(ck, l.rg, l.ept);
+    const bool adam = a.opt == ISING_OPT_ADAM;
+    KFn fn = l.fp64 ? pick<double>(ck, l.rg, l.ept, adam) : pick<float>(ck, l.rg, l.ept, adam);
     if (!fn) return hipErrorInvalidValue;
     if (l.block % 64 || l.block < 64 || l.block > ds_block_limit(l.ept) || (l.ept > 0 && (int64_t)l.ept * l.block < a.n) ||
         a.R % l.rg)
