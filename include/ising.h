@@ -171,7 +171,25 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
                              int8_t *spins_out, double *energy_out, int64_t *energy_int_out,
                              ising_stats *stats_out, void *stream);
 
+/* Name of the domain-selection kernel form launched by the last ising_ds_dev,
+ * ising_ds_dense_dev or ising_solve(_dev) call on ctx, e.g. "k_ds_split<adam>" or
+ * "k_ds<float, PME, rg=1, ept=28>" ("" before the first launch).  A diagnostic: the
+ * engine picks its form from the problem and the requested outputs (traces, the
+ * convergence test) and every form gives the same results; tests use it to know
+ * which one they checked.  Valid until the next call on ctx. */
+const char *ising_last_kernel(const ising_ctx *ctx);
+
 /* ---- exact energy (scalar energy form, Sec. II) ------------------------- */
+
+/* E(s_r) = s_r^T J s_r + h^T s_r for `count` spin vectors on host buffers:
+ * problem and spins (count * n int8, replica-major) are host memory, copied to
+ * the device before the call returns; E_out (nullable): count doubles (host);
+ * E_int_out (nullable, ISING_I32 problems only): count int64 (host), exact.
+ * Same kernels and summation order as ising_energy_dev.  Blocking.  Errors:
+ * EINVAL for a malformed problem or count < 0, ENOMEM, EDEVICE.  The problem is
+ * not checked for symmetry here (the energy is defined for any J). */
+ising_status ising_energy(ising_ctx *ctx, const ising_problem *problem, const int8_t *spins, int32_t count,
+                          double *E_out, int64_t *E_int_out);
 
 /* E(s_r) = s_r^T J s_r + h^T s_r for `count` spin vectors (replica-major).
  * problem and spins are device pointers.  E_out (nullable): count doubles.
@@ -184,13 +202,24 @@ ising_status ising_energy_dev(ising_ctx *ctx, const ising_problem *problem, cons
 
 /* ---- pruning (Sec. III-A, Algorithm 1) and retrieval (Fig. 1c) --------- */
 
+/* Algorithm 1 on host buffers: the problem (host memory) is copied to the
+ * device, validated (EINVAL as for ising_solve) and pruned there; the handle
+ * owns that copy, the record and the reduced problem.  Blocking: the handle is
+ * complete when the call returns.  Read it with ising_pruned_info,
+ * ising_pruned_record, ising_pruned_copy (host) or the _dev readers; free it
+ * with ising_pruned_free.  Pruning as ising_prune_dev below. */
+ising_status ising_prune(ising_ctx *ctx, const ising_problem *problem, ising_pruned **out);
+
 /* Run Algorithm 1 on the device.  problem: device pointers.  Each round takes
  * the determined spins D (|h_i| > 2 sum_{j active}|J_ij|, strict), folds them
  * into h and C, then the semi-determined spins S (exactly one active
  * neighbour k, 2|J_ik| >= |h_i|; of a mutual pair only the larger index),
  * folds them, and repeats until a round removes nothing.  Row sums of real J
- * use 64 strided partials combined by an xor butterfly (32,16,8,4,2,1); the
- * folds add their terms in ascending index.  Synchronises the stream once per
+ * (which decide D) use 64 strided partials combined by an xor butterfly
+ * (32,16,8,4,2,1), a fixed order any implementation can reproduce; the folds
+ * into h and C use the same per-row reduction, which differs from a plain
+ * ascending sum only by rounding, within gamma_k times the sum of the terms'
+ * magnitudes.  Integer problems are exact.  Synchronises the stream once per
  * round.  *out receives a handle owning the device-resident reduced problem
  * and record; free it with ising_pruned_free. */
 ising_status ising_prune_dev(ising_ctx *ctx, const ising_problem *problem, ising_pruned **out,
@@ -226,6 +255,22 @@ ising_status ising_pruned_copy_dev(ising_ctx *ctx, const ising_pruned *pruned, v
  * int8 (device), s_out: n int8 (device). */
 ising_status ising_unprune_dev(ising_ctx *ctx, const ising_pruned *pruned, const int8_t *s_G,
                                int8_t *s_out, void *stream);
+/* Retrieval (Fig. 1c) on host buffers, without a context: s_G (n_G int8 values
+ * -1/+1, host; ignored when n_G = 0) gives s_out (n int8, host).  Runs the same
+ * kernel as ising_unprune_dev on the handle's device (which becomes the calling
+ * thread's current device) on its default stream, with a transient device
+ * buffer of n + n_G bytes; blocking.  Errors: EINVAL (NULL handle or buffer),
+ * ENOMEM, EDEVICE (no message: there is no context to hold one). */
+ising_status ising_unprune(const ising_pruned *pruned, const int8_t *s_G, int8_t *s_out);
+/* The record and h_G in host buffers (each nullable; layouts and value types as
+ * ising_pruned_record_dev).  No context; the handle's device becomes current.
+ * Blocking.  Errors: EINVAL, ENOMEM, EDEVICE. */
+ising_status ising_pruned_record(const ising_pruned *pruned, int8_t *kind, int32_t *round_of, int8_t *fixed,
+                                 int32_t *partner, int8_t *sigma, int32_t *G, void *h_G);
+/* The reduced problem in host buffers (each nullable; layouts and value type as
+ * ising_pruned_copy_dev).  No context; blocking.  Errors: EINVAL, EDEVICE. */
+ising_status ising_pruned_copy(const ising_pruned *pruned, void *J_or_val, int32_t *row_ptr, int32_t *col,
+                               void *h);
 
 /* ---- domain selection (Sec. III-B), persistent replica-parallel engine -- */
 

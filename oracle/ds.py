@@ -138,12 +138,18 @@ def convergence_step(loss_trace, window: int = 5, tol: float = 0.005) -> int:
 def ds_run(inst, U, steps: int, opt: str = "adam", lr: float = 6.0, mu: float = 0.5,
            beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
            record: bool = False, record_sin: bool = False, loss: str = "vertex",
-           conv_tol: float = 0.0, conv_window: int = 5) -> DSResult:
+           conv_tol: float = 0.0, conv_window: int = 5, dtype=np.float64) -> DSResult:
     """Run ``steps`` domain-selection steps for R replicas.
 
     U: (R, n) uniform draws on [-1, 1) (theta_0 = asin U).
     loss: "vertex" (s~* = sgn sin theta) or "relaxed" (s~* = sin theta).
     conv_tol > 0: each replica stops after the step at which the convergence test holds.
+    dtype: the floating-point type every formula of the step is evaluated in.  The
+    oracle is float64 (the default); np.float32 evaluates the same formulas, in the
+    same order, with float32 inputs and results -- a model of what any FP32
+    implementation rounds, used only to measure how much the method itself
+    amplifies FP32 rounding at a given step size (it bounds the iterate horizon over
+    which an FP32 implementation can match the float64 oracle).
     """
     if loss not in ("vertex", "relaxed"):
         raise ValueError(loss)
@@ -152,11 +158,12 @@ def ds_run(inst, U, steps: int, opt: str = "adam", lr: float = 6.0, mu: float = 
     R = U.shape[0]
     assert U.shape == (R, n)
     Jm = _matrix(inst)
+    Jr = Jm if dtype == np.float64 else Jm.astype(dtype)   # couplings in the arithmetic type
     integer = inst.integer
-    h = inst.h.astype(np.float64)[:, None]
+    h = inst.h.astype(dtype)[:, None]
     h_int = inst.h.astype(np.int64)[:, None] if integer else None
 
-    theta = np.arcsin(U).T.copy()          # (n, R)
+    theta = np.arcsin(U).T.astype(dtype)   # (n, R)
     m = np.zeros_like(theta)
     v = np.zeros_like(theta)
     e_best = np.full(R, np.iinfo(np.int64).max if integer else np.inf,
@@ -175,19 +182,20 @@ def ds_run(inst, U, steps: int, opt: str = "adam", lr: float = 6.0, mu: float = 
         x = np.sin(theta)
         c = np.cos(theta)
         s = _sgn1(x)
+        sf = s.astype(dtype)
         if integer:
             yi = np.asarray(Jm @ s.astype(np.int64)).astype(np.int64)
             E = (s * (yi + h_int)).sum(axis=0)
-            y = yi.astype(np.float64)
+            y = yi.astype(dtype)
         else:
-            y = np.asarray(Jm @ s.astype(np.float64))
-            E = (s * (y + h)).sum(axis=0)
+            y = np.asarray(Jr @ sf)
+            E = (sf * (y + h)).sum(axis=0)
         if loss == "vertex":
-            tt = y - mu * s + h
+            tt = y - mu * sf + h
             L = (x * tt).sum(axis=0)
             g = c * tt
         else:
-            z = np.asarray(Jm @ x)
+            z = np.asarray(Jr @ x)
             L = (x * (z - mu * x + h)).sum(axis=0)
             g = c * (2.0 * z - 2.0 * mu * x + h)
         better = (E < e_best) & active

@@ -25,23 +25,29 @@ Retrieval: s[G] = s_G, then rounds in reverse: s_k = -sigma s_i for S records
 (n(k) survives its round, so it is already resolved) and the recorded value for
 D records.
 
-Rounding convention for real couplings (a reading; the paper is silent): every
-per-row sum of the algorithm -- the row sums a_i, the fold of the determined
-spins into h_j (sum over i in D of 2 J_ji s_i, then added to h_j once), the
-fold of the semi-determined spins into h_i (sum over k in S with n(k) = i of
-sgn(J_ik) h_k, then subtracted once) and the D-D couplings of C -- is formed in
-one fixed order, so that FP64 decisions and h_G are reproducible by any
-implementation that follows it.  The stored entries of row i (all n columns
-for a dense matrix, the stored nonzeros in ascending column order for CSR) are
-numbered p = 0, 1, ...; partial sum l (0 <= l < 64) adds the terms of
-p = l, l + 64, l + 128, ... in ascending p (0 for entries that do not take
-part); then the 64 partials are combined pairwise by index xor 32, 16, 8, 4,
-2, 1.  Integer couplings are summed exactly in int64, where order is
-irrelevant.
+Rounding convention for real couplings (a reading; the paper is silent).  The
+decisions of the algorithm (determined test, semi-determined test) compare a
+field with the row sums a_i, so a_i is formed in one fixed order that any
+implementation can follow and reproduce bit for bit: the stored entries of row
+i (all n columns for a dense matrix, the stored nonzeros in ascending column
+order for CSR) are numbered p = 0, 1, ...; partial sum l (0 <= l < 64) adds
+the terms of p = l, l + 64, l + 128, ... in ascending p (0 for entries that do
+not take part); then the 64 partials are combined pairwise by index xor 32, 16,
+8, 4, 2, 1.  Everything else is the plain definition, summed one term after
+another in ascending index: the fold of the determined spins into h_j (the
+terms 2 J_ji s_i for i in D, added to h_j once summed), the fold of the
+semi-determined spins into h_i (the terms sgn(J_ik) h_k for k in S with
+n(k) = i, subtracted once summed) and the D-D couplings of C.  Another
+summation order changes h_G and C only by rounding, bounded by
+gamma_k * (sum of the magnitudes of the terms that make them up); those
+magnitudes are returned as ``h_mass`` and ``C_mass`` so that a comparison can
+state that bound.  Integer couplings are summed exactly in int64, where order
+is irrelevant.
 """
 from __future__ import annotations
 
 from dataclasses import dataclass, field
+from typing import Optional
 
 import numpy as np
 
@@ -63,6 +69,10 @@ class PruneResult:
     sigma: np.ndarray             # per spin: sgn(J_k,n(k)) for semi-determined spins, 0 otherwise
     rounds: int                   # rounds executed (the last one removes nothing)
     per_round: list = field(default_factory=list)  # (|D|, |S|) per round
+    # rounding-bound helpers (real couplings): per spin, the sum of the magnitudes of the
+    # terms whose sum is h_G (initial |h| plus every folded term, recursively); for C, the same
+    h_mass: Optional[np.ndarray] = None
+    C_mass: float = 0.0
 
     @property
     def eta(self) -> float:
@@ -103,6 +113,25 @@ def fixed_order_rowsum(n, rows, pos, terms, integer):
     return acc[:, 0]
 
 
+def ascending_rowsum(n, rows, pos, terms, integer):
+    """Per-row sums of per-entry terms, each row's terms added one after another in
+    ascending stored position (numpy's accumulate is that sequential recurrence)."""
+    if integer:
+        return _exact_int_rowsum(n, rows, terms)
+    width = int(pos.max()) + 1 if pos.size else 1
+    mat = np.zeros((n, width), dtype=np.float64)
+    mat[rows, pos] = terms
+    return np.add.accumulate(mat, axis=1)[:, -1]
+
+
+def _ascending_sum(x, integer):
+    """Sum of a 1-D array, one term after another in index order."""
+    if integer:
+        return np.asarray(x, dtype=np.int64).sum()
+    x = np.asarray(x, dtype=np.float64)
+    return np.add.accumulate(x)[-1] if x.size else 0.0
+
+
 def fixed_order_abs_rowsum(n, rows, cols, vals, pos, active, integer):
     """a_i = sum_{j active} |J_ij| in the fixed 64-partial order described above."""
     return fixed_order_rowsum(n, rows, pos, np.abs(vals) * active[cols] * active[rows], integer)
@@ -132,6 +161,9 @@ def prune(inst) -> PruneResult:
     ends = np.searchsorted(rows, np.arange(n), side="right")
 
     h = inst.h.astype(dt).copy()
+    h_mass = np.abs(inst.h).astype(np.float64)
+    C_mass = 0.0
+    absv = np.abs(vals).astype(np.float64)
     active = np.ones(n, dtype=bool)
     C = dt(0)
     kind = np.zeros(n, dtype=np.int8)
@@ -143,20 +175,27 @@ def prune(inst) -> PruneResult:
     rnd = 0
     ar = np.arange(n)
     while True:
-        # 1. determined spins
+        # 1. determined spins (the decision uses the fixed-order row sums)
         a = fixed_order_abs_rowsum(n, rows, cols, vals, pos, active, integer)
         D = active & (np.abs(h) > 2 * a)
         Didx = np.nonzero(D)[0]
         sD = -_sgn(h[Didx])
         s_full = np.zeros(n, dtype=dt)
         s_full[Didx] = sD
-        # 2. fold D into C and into the fields of the remaining active spins
+        # 2. fold D into C (terms h_i s_i + sum_{j in D} J_ij s_i s_j, i ascending, added to
+        #    C one after another) and into the fields of the remaining active spins
         if Didx.size:
-            dd = fixed_order_rowsum(n, rows, pos, vals * s_full[rows] * s_full[cols], integer)
-            C = C + (h[Didx] * sD + dd[Didx]).sum()
+            dd = ascending_rowsum(n, rows, pos, vals * s_full[rows] * s_full[cols], integer)
+            C = _ascending_sum(np.r_[np.asarray([C], dtype=dt), h[Didx] * sD + dd[Didx]], integer)
+            inD = np.zeros(n, dtype=np.float64)
+            inD[Didx] = 1.0
+            C_mass += float((h_mass[Didx]).sum() + (absv * inD[rows] * inD[cols]).sum())
             keep = active & ~D
-            F = fixed_order_rowsum(n, rows, pos, 2 * vals * s_full[cols], integer)
+            F = ascending_rowsum(n, rows, pos, 2 * vals * s_full[cols], integer)
             h[keep] = h[keep] + F[keep]
+            Fm = np.zeros(n)
+            np.add.at(Fm, rows, 2 * absv * inD[cols])
+            h_mass[keep] += Fm[keep]
             kind[Didx] = 1
             round_of[Didx] = rnd
             fixed[Didx] = sD
@@ -175,13 +214,18 @@ def prune(inst) -> PruneResult:
         mutual = cand & (nb >= 0) & cand[nbc] & (nb[nbc] == ar)
         S = cand & ~(mutual & (ar < nb))
         Sidx = np.nonzero(S)[0]
-        # 4. fold S: h_i -= sum over k in S with n(k) = i of sgn(J_ik) h_k
+        # 4. fold S: h_i -= sum over k in S with n(k) = i of sgn(J_ik) h_k (k ascending);
+        #    C -= 2 |J_k,n(k)| for k in S, one after another
         if Sidx.size:
             to_me = S[cols] & (nb[cols] == rows)
-            G_ = fixed_order_rowsum(n, rows, pos, np.where(to_me, _sgn(vals) * h[cols], 0), integer)
+            G_ = ascending_rowsum(n, rows, pos, np.where(to_me, _sgn(vals) * h[cols], 0), integer)
             rest = active & ~S
             h[rest] = h[rest] - G_[rest]
-            C = C - 2 * np.abs(jv[Sidx]).sum()
+            Gm = np.zeros(n)
+            np.add.at(Gm, rows, np.where(to_me, h_mass[cols], 0.0))
+            h_mass[rest] += Gm[rest]
+            C = _ascending_sum(np.r_[np.asarray([C], dtype=dt), -2 * np.abs(jv[Sidx])], integer)
+            C_mass += float(2 * np.abs(jv[Sidx]).astype(np.float64).sum())
             kind[Sidx] = 2
             round_of[Sidx] = rnd
             partner[Sidx] = nb[Sidx]
@@ -205,7 +249,8 @@ def prune(inst) -> PruneResult:
         rp = np.zeros(G.size + 1, dtype=np.int64)
         np.add.at(rp, r2 + 1, 1)
         red = Instance(G.size, inst.name + "/G", h_G.copy(), None, np.cumsum(rp), c2, v2, integer)
-    return PruneResult(n, G, h_G, C, red, kind, round_of, fixed, partner, sigma, rnd, per_round)
+    return PruneResult(n, G, h_G, C, red, kind, round_of, fixed, partner, sigma, rnd, per_round,
+                       h_mass[G].copy(), C_mass)
 
 
 def unprune(res: PruneResult, s_G) -> np.ndarray:

@@ -98,7 +98,13 @@ _sigs = {
                               C.POINTER(C.c_int64), C.POINTER(ising_stats)]),
     "ising_solve_dev": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(ising_params), _P, _P, _P,
                                   C.POINTER(ising_stats), _P]),
+    "ising_last_kernel": (C.c_char_p, [_P]),
+    "ising_energy": (C.c_int, [_P, C.POINTER(ising_problem), _P, C.c_int32, _P, _P]),
     "ising_energy_dev": (C.c_int, [_P, C.POINTER(ising_problem), _P, C.c_int32, _P, _P, _P]),
+    "ising_prune": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(C.c_void_p)]),
+    "ising_unprune": (C.c_int, [_P, _P, _P]),
+    "ising_pruned_record": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "ising_pruned_copy": (C.c_int, [_P, _P, _P, _P, _P]),
     "ising_prune_dev": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(C.c_void_p), _P]),
     "ising_pruned_free": (None, [_P]),
     "ising_pruned_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -259,6 +265,22 @@ def ising_solve_dev(ctx, problem: Problem, prm: ising_params, spins_out=None, en
     return spins_out, energy_out, energy_int_out, st.as_dict()
 
 
+def ising_last_kernel(ctx) -> str:
+    return _lib.ising_last_kernel(ctx).decode()
+
+
+def ising_energy(ctx, problem_host: ising_problem, spins):
+    """Host-buffer energies of the rows of `spins` (numpy int8, (count, n) or (n,))."""
+    import numpy as np
+    S = np.ascontiguousarray(spins, dtype=np.int8)
+    count = S.shape[0] if S.ndim == 2 else 1
+    E = np.zeros(count, dtype=np.float64)
+    Ei = np.zeros(count, dtype=np.int64) if problem_host.value_type == ISING_I32 else None
+    _check(ctx, _lib.ising_energy(ctx, C.byref(problem_host), S.ctypes.data, count, E.ctypes.data,
+                                  None if Ei is None else Ei.ctypes.data))
+    return E, Ei
+
+
 def ising_energy_dev(ctx, problem: Problem, spins, E_out=None, E_int_out=None, stream=None):
     import torch
     spins = spins.contiguous()
@@ -281,6 +303,59 @@ class Pruned:
         if getattr(self, "handle", None):
             _lib.ising_pruned_free(self.handle)
             self.handle = None
+
+
+def ising_prune(ctx, problem_host: ising_problem) -> Pruned:
+    """Host-buffer pruning: problem_host points at host memory (kept alive by the caller)."""
+    h = C.c_void_p()
+    _check(ctx, _lib.ising_prune(ctx, C.byref(problem_host), C.byref(h)))
+    return Pruned(h)
+
+
+def ising_unprune(pr: Pruned, s_G):
+    """Full host spin vector from host reduced spins (numpy int8)."""
+    import numpy as np
+    n = ising_pruned_info(pr)["n"]
+    sG = np.ascontiguousarray(s_G, dtype=np.int8)
+    out = np.zeros(n, dtype=np.int8)
+    _check(None, _lib.ising_unprune(pr.handle, sG.ctypes.data if sG.size else None, out.ctypes.data))
+    return out
+
+
+def ising_pruned_record(pr: Pruned) -> dict:
+    """The record and h_G as numpy arrays (host)."""
+    import numpy as np
+    info = ising_pruned_info(pr)
+    n, nG = info["n"], info["n_G"]
+    red = ising_pruned_problem(pr)
+    hdt = {ISING_I32: np.int32, ISING_F32: np.float32, ISING_F64: np.float64}[red.value_type]
+    out = dict(kind=np.zeros(n, np.int8), round_of=np.zeros(n, np.int32), fixed=np.zeros(n, np.int8),
+               partner=np.zeros(n, np.int32), sigma=np.zeros(n, np.int8), G=np.zeros(max(nG, 1), np.int32),
+               h_G=np.zeros(max(nG, 1), hdt))
+    _check(None, _lib.ising_pruned_record(pr.handle, *(out[k].ctypes.data for k in
+                                                       ("kind", "round_of", "fixed", "partner", "sigma", "G",
+                                                        "h_G"))))
+    out["G"] = out["G"][:nG]
+    out["h_G"] = out["h_G"][:nG]
+    return out
+
+
+def ising_pruned_copy(pr: Pruned) -> dict:
+    """The reduced problem as numpy arrays (host): J (dense) or row_ptr/col/val (CSR), and h."""
+    import numpy as np
+    red = ising_pruned_problem(pr)
+    dt = {ISING_I32: np.int32, ISING_F32: np.float32, ISING_F64: np.float64}[red.value_type]
+    nG = red.n
+    h = np.zeros(max(nG, 1), dt)
+    if red.format == ISING_DENSE:
+        J = np.zeros((max(nG, 1), max(nG, 1)), dt)
+        _check(None, _lib.ising_pruned_copy(pr.handle, J.ctypes.data, None, None, h.ctypes.data))
+        return dict(J=J[:nG, :nG], h=h[:nG])
+    rp = np.zeros(nG + 1, np.int32)
+    col = np.zeros(max(red.nnz, 1), np.int32)
+    val = np.zeros(max(red.nnz, 1), dt)
+    _check(None, _lib.ising_pruned_copy(pr.handle, val.ctypes.data, rp.ctypes.data, col.ctypes.data, h.ctypes.data))
+    return dict(row_ptr=rp, col=col[:red.nnz], val=val[:red.nnz], h=h[:nG])
 
 
 def ising_prune_dev(ctx, problem: Problem, stream=None) -> Pruned:

@@ -44,6 +44,39 @@ ising_status check_problem_shape(ising_ctx *ctx, const ising_problem *p) {
     return ISING_OK;
 }
 
+ising_status upload_problem(ising_ctx *ctx, const ising_problem &host, Pool &pool, const std::string &prefix,
+                            ising_problem &d, hipStream_t s) {
+    const int n = host.n;
+    const size_t vs = vsize(host.value_type);
+    d = host;
+    void *buf = nullptr;
+    if (host.format == ISING_DENSE) {
+        HIP_TRY(ctx, pool.get(prefix + "J", (size_t)n * n * vs, &buf));
+        HIP_TRY(ctx, hipMemcpyAsync(buf, host.J, (size_t)n * n * vs, hipMemcpyHostToDevice, s));
+        d.J = buf;
+    } else {
+        void *rp = nullptr, *c = nullptr, *v = nullptr;
+        HIP_TRY(ctx, pool.get(prefix + "rp", (size_t)(n + 1) * 4, &rp));
+        HIP_TRY(ctx, pool.get(prefix + "col", (size_t)std::max<int64_t>(host.nnz, 1) * 4, &c));
+        HIP_TRY(ctx, pool.get(prefix + "val", (size_t)std::max<int64_t>(host.nnz, 1) * vs, &v));
+        HIP_TRY(ctx, hipMemcpyAsync(rp, host.row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, s));
+        if (host.nnz > 0) {
+            HIP_TRY(ctx, hipMemcpyAsync(c, host.col, (size_t)host.nnz * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(ctx, hipMemcpyAsync(v, host.val, (size_t)host.nnz * vs, hipMemcpyHostToDevice, s));
+        }
+        d.row_ptr = (const int32_t *)rp;
+        d.col = (const int32_t *)c;
+        d.val = v;
+    }
+    if (host.h) {
+        void *hb = nullptr;
+        HIP_TRY(ctx, pool.get(prefix + "h", (size_t)n * vs, &hb));
+        HIP_TRY(ctx, hipMemcpyAsync(hb, host.h, (size_t)n * vs, hipMemcpyHostToDevice, s));
+        d.h = hb;
+    }
+    return ISING_OK;
+}
+
 ising_status ingest(ising_ctx *ctx, const DevProblem &p, Pool &pool, Ingest &out, hipStream_t s) {
     void *flags = nullptr, *wdev = nullptr;
     HIP_TRY(ctx, pool.get("ingest.flags", 20, &flags));
@@ -381,7 +414,7 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
         a.bias = bias;
     }
     if (kbeg) HIP_TRY(ctx, hipEventRecord(kbeg, s));
-    hipError_t e = launch_ds(a, plan.l, s);
+    hipError_t e = launch_ds(a, plan.l, s, &ctx->last_kernel);
     if (kend && e == hipSuccess) HIP_TRY(ctx, hipEventRecord(kend, s));
     if (e != hipSuccess)
         return fail(ctx, e == hipErrorInvalidValue ? ISING_ENOTSUP : ISING_EDEVICE,
@@ -480,6 +513,8 @@ ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_param
     HIP_TRY(ctx, pool.get("dn.group", dense_group_scratch_bytes(&one, 1), &scratch));
     if (kbeg) HIP_TRY(ctx, hipEventRecord(kbeg, s));
     hipError_t e = launch_dense_run(d, scratch, s);
+    static const char *const forms[] = {"fp32", "bf16x2", "bf16", "fp8"};
+    ctx->last_kernel = std::string("k_dense_step<") + forms[d.form] + ">";
     if (e != hipSuccess)
         return fail(ctx, e == hipErrorInvalidValue ? ISING_ENOTSUP : ISING_EDEVICE,
                     std::string("matrix-core domain selection: ") + hipGetErrorString(e));
@@ -542,6 +577,122 @@ ising_status ising_destroy(ising_ctx *ctx) {
 }
 
 const char *ising_last_error(const ising_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+const char *ising_last_kernel(const ising_ctx *ctx) { return ctx ? ctx->last_kernel.c_str() : ""; }
+
+ising_status ising_energy(ising_ctx *ctx, const ising_problem *problem, const int8_t *spins, int32_t count,
+                          double *E_out, int64_t *E_int_out) {
+    if (!ctx) return ISING_EINVAL;
+    ST_TRY(check_problem_shape(ctx, problem));
+    if (count < 0 || (count > 0 && !spins)) return fail(ctx, ISING_EINVAL, "bad spins/count");
+    if (E_int_out && problem->value_type != ISING_I32)
+        return fail(ctx, ISING_EINVAL, "integer energies need an ISING_I32 problem");
+    if (count == 0) return ISING_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    Pool &pool = ctx->pool;
+    ising_problem d;
+    ST_TRY(upload_problem(ctx, *problem, pool, "en.", d, s));
+    const size_t sb = (size_t)count * problem->n;
+    void *sdev = nullptr, *edev = nullptr, *eidev = nullptr, *partial = nullptr;
+    HIP_TRY(ctx, pool.get("en.s", sb, &sdev));
+    HIP_TRY(ctx, pool.get("en.E", (size_t)count * 8, &edev));
+    HIP_TRY(ctx, pool.get("en.Ei", (size_t)count * 8, &eidev));
+    HIP_TRY(ctx, pool.get("energy.partial", energy_partial_bytes(problem->n, count), &partial));
+    HIP_TRY(ctx, hipMemcpyAsync(sdev, spins, sb, hipMemcpyHostToDevice, s));
+    const bool want_int = problem->value_type == ISING_I32;
+    HIP_TRY(ctx, launch_energy(to_dev(d), (const int8_t *)sdev, count, partial, (double *)edev,
+                               want_int ? (int64_t *)eidev : nullptr, s));
+    if (E_out) HIP_TRY(ctx, hipMemcpyAsync(E_out, edev, (size_t)count * 8, hipMemcpyDeviceToHost, s));
+    if (E_int_out) HIP_TRY(ctx, hipMemcpyAsync(E_int_out, eidev, (size_t)count * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return ISING_OK;
+}
+
+ising_status ising_prune(ising_ctx *ctx, const ising_problem *problem, ising_pruned **out) {
+    if (!ctx || !out) return ISING_EINVAL;
+    *out = nullptr;
+    ST_TRY(check_problem_shape(ctx, problem));
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    auto pr = std::make_unique<ising_pruned>();
+    pr->device = ctx->device;
+    pr->pool = &pr->own;
+    ising_problem d;  // the handle owns this device copy (its reduced problem may alias it)
+    ST_TRY(upload_problem(ctx, *problem, pr->own, "in.", d, s));
+    Ingest ing;
+    ST_TRY(ingest(ctx, to_dev(d), ctx->pool, ing, s));
+    ST_TRY(prune_core(ctx, to_dev(d), *pr, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    *out = pr.release();
+    return ISING_OK;
+}
+
+ising_status ising_unprune(const ising_pruned *pr, const int8_t *s_G, int8_t *s_out) {
+    if (!pr || !s_out || (pr->nG > 0 && !s_G)) return ISING_EINVAL;
+    if (hipSetDevice(pr->device) != hipSuccess) return ISING_EDEVICE;
+    const size_t n = (size_t)pr->n, nG = (size_t)pr->nG;
+    int8_t *buf = nullptr;
+    if (hipMalloc((void **)&buf, n + std::max<size_t>(nG, 1)) != hipSuccess) return ISING_ENOMEM;
+    int8_t *dsG = buf + n;
+    hipError_t e = nG ? hipMemcpy(dsG, s_G, nG, hipMemcpyHostToDevice) : hipSuccess;
+    if (e == hipSuccess)
+        e = pr->identity ? hipMemcpy(buf, dsG, n, hipMemcpyDeviceToDevice)
+                         : launch_unprune(pr->w, pr->n, pr->rounds, dsG, buf, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(s_out, buf, n, hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    return e == hipSuccess ? ISING_OK : ISING_EDEVICE;
+}
+
+ising_status ising_pruned_record(const ising_pruned *pr, int8_t *kind, int32_t *round_of, int8_t *fixed,
+                                 int32_t *partner, int8_t *sigma, int32_t *G, void *h_G) {
+    if (!pr) return ISING_EINVAL;
+    if (hipSetDevice(pr->device) != hipSuccess) return ISING_EDEVICE;
+    const size_t n = (size_t)pr->n;
+    void *buf = nullptr;
+    if (hipMalloc(&buf, n * 11 + 4) != hipSuccess) return ISING_ENOMEM;
+    int8_t *dk = (int8_t *)buf, *df = dk + n, *ds = df + n;
+    int32_t *dr = (int32_t *)(ds + n + (4 - (3 * n) % 4) % 4), *dp = dr + n;
+    hipError_t e = launch_copy_record(pr->w, pr->n, dk, dr, df, dp, ds, nullptr);
+    if (e == hipSuccess && kind) e = hipMemcpy(kind, dk, n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && round_of) e = hipMemcpy(round_of, dr, n * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && fixed) e = hipMemcpy(fixed, df, n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && partner) e = hipMemcpy(partner, dp, n * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && sigma) e = hipMemcpy(sigma, ds, n, hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return ISING_EDEVICE;
+    if (G && pr->nG > 0) {
+        if (pr->identity) {
+            for (int32_t i = 0; i < pr->n; ++i) G[i] = i;
+        } else if (hipMemcpy(G, pr->w.G, (size_t)pr->nG * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+            return ISING_EDEVICE;
+        }
+    }
+    if (h_G && pr->nG > 0 && pr->reduced.h &&
+        hipMemcpy(h_G, pr->reduced.h, (size_t)pr->nG * vsize(pr->reduced.value_type), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+        return ISING_EDEVICE;
+    return ISING_OK;
+}
+
+ising_status ising_pruned_copy(const ising_pruned *pr, void *J_or_val, int32_t *row_ptr, int32_t *col, void *h) {
+    if (!pr) return ISING_EINVAL;
+    if (hipSetDevice(pr->device) != hipSuccess) return ISING_EDEVICE;
+    const ising_problem &r = pr->reduced;
+    if (r.n == 0) return ISING_OK;
+    const size_t vs = vsize(r.value_type);
+    hipError_t e = hipSuccess;
+    if (r.format == ISING_DENSE) {
+        if (J_or_val) e = hipMemcpy(J_or_val, r.J, (size_t)r.n * r.n * vs, hipMemcpyDeviceToHost);
+    } else {
+        if (row_ptr) e = hipMemcpy(row_ptr, r.row_ptr, (size_t)(r.n + 1) * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && col && r.nnz) e = hipMemcpy(col, r.col, (size_t)r.nnz * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && J_or_val && r.nnz)
+            e = hipMemcpy(J_or_val, r.val, (size_t)r.nnz * vs, hipMemcpyDeviceToHost);
+    }
+    if (e == hipSuccess && h && r.h) e = hipMemcpy(h, r.h, (size_t)r.n * vs, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? ISING_OK : ISING_EDEVICE;
+}
 
 ising_status ising_energy_dev(ising_ctx *ctx, const ising_problem *problem, const int8_t *spins, int32_t count,
                               double *E_out, int64_t *E_int_out, void *stream) {
@@ -823,33 +974,8 @@ ising_status ising_solve(ising_ctx *ctx, const ising_problem *problem, const isi
     Pool &pool = ctx->pool;
     const auto t0 = std::chrono::steady_clock::now();
     const int n = problem->n;
-    const size_t vs = vsize(problem->value_type);
-    ising_problem d = *problem;
-    void *buf = nullptr;
-    if (problem->format == ISING_DENSE) {
-        HIP_TRY(ctx, pool.get("in.J", (size_t)n * n * vs, &buf));
-        HIP_TRY(ctx, hipMemcpyAsync(buf, problem->J, (size_t)n * n * vs, hipMemcpyHostToDevice, s));
-        d.J = buf;
-    } else {
-        void *rp = nullptr, *c = nullptr, *v = nullptr;
-        HIP_TRY(ctx, pool.get("in.rp", (size_t)(n + 1) * 4, &rp));
-        HIP_TRY(ctx, pool.get("in.col", (size_t)std::max<int64_t>(problem->nnz, 1) * 4, &c));
-        HIP_TRY(ctx, pool.get("in.val", (size_t)std::max<int64_t>(problem->nnz, 1) * vs, &v));
-        HIP_TRY(ctx, hipMemcpyAsync(rp, problem->row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, s));
-        if (problem->nnz > 0) {
-            HIP_TRY(ctx, hipMemcpyAsync(c, problem->col, (size_t)problem->nnz * 4, hipMemcpyHostToDevice, s));
-            HIP_TRY(ctx, hipMemcpyAsync(v, problem->val, (size_t)problem->nnz * vs, hipMemcpyHostToDevice, s));
-        }
-        d.row_ptr = (const int32_t *)rp;
-        d.col = (const int32_t *)c;
-        d.val = v;
-    }
-    if (problem->h) {
-        void *hb = nullptr;
-        HIP_TRY(ctx, pool.get("in.h", (size_t)n * vs, &hb));
-        HIP_TRY(ctx, hipMemcpyAsync(hb, problem->h, (size_t)n * vs, hipMemcpyHostToDevice, s));
-        d.h = hb;
-    }
+    ising_problem d;
+    ST_TRY(upload_problem(ctx, *problem, pool, "in.", d, s));
     int8_t *sdev = nullptr;
     double *edev = nullptr;
     int64_t *eidev = nullptr;

@@ -48,7 +48,8 @@ hipError_t launch_validate(const DevProblem &p, int32_t *flags, double *wdev, hi
 hipError_t launch_first_magnitude(const DevProblem &p, double *w, hipStream_t s);
 
 // ---- energy (kernels_energy.hip) -----------------------------------------
-// partial must hold count * ceil(n / 256) accumulators (int64 or double).
+// partial must hold energy_partial_bytes(n, count): count * ceil(n / 4) accumulators
+// (int64 or double).
 hipError_t launch_energy(const DevProblem &p, const int8_t *spins, int32_t count, void *partial,
                          double *E_out, int64_t *E_int_out, hipStream_t s);
 size_t energy_partial_bytes(int32_t n, int32_t count);
@@ -147,7 +148,8 @@ struct DSLaunch {
 // converted to the state precision.  Buffers are caller-provided.
 hipError_t launch_ds_format(const DevProblem &p, bool fp64, bool packed, uint32_t *pm, void *val_out,
                             void *h_out, hipStream_t s);
-hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s);
+// kernel (nullable): receives the name of the kernel form that was launched.
+hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s, std::string *kernel = nullptr);
 // ADAM bias corrections 1/(1-b1^t), 1/(1-b2^t), t = t0+1..t0+steps (FP64, rounded).
 hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64, void *out, hipStream_t s);
 int32_t ds_max_n(bool fp64);

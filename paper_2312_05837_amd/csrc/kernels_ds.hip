@@ -1567,7 +1567,7 @@ hipError_t launch_ds_format(const DevProblem &p, bool fp64, bool packed, uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
+hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s, std::string *kernel) {
     const int ck = l.coupling == CK_PMS && l.relaxed ? CK_PMSR
                  : l.coupling == CK_PM && a.ell != nullptr && !l.relaxed ? CK_PME
                                                                           : l.coupling;
@@ -1591,6 +1591,7 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
                 if (e != hipSuccess) return e;
             }
             hipLaunchKernelGGL(fn, dim3(a.R / 4), dim3(kSplitBlock), lds, s, a, l.block);
+            if (kernel) *kernel = a.opt == ISING_OPT_ADAM ? "k_ds_split<adam>" : "k_ds_split<gd>";
             return hipGetLastError();
         }
     }
@@ -1601,6 +1602,12 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(fn, dim3(a.R / l.rg), dim3(l.block), lds, s, a);
+    if (kernel) {
+        static const char *const cks[] = {"PM", "CSRV", "DENSE", "PMS", "PMSR", "PME"};
+        const char *ckn = ck >= 0 && ck < (int)(sizeof(cks) / sizeof(cks[0])) ? cks[ck] : "?";
+        *kernel = std::string(l.ept > 0 ? "k_ds<" : "k_ds_stream<") + (l.fp64 ? "double" : "float") + ", " + ckn +
+                  ", rg=" + std::to_string(l.rg) + ", ept=" + std::to_string(l.ept) + ">";
+    }
     return hipGetLastError();
 }
 

@@ -59,6 +59,7 @@ struct ising_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    std::string last_kernel;  // domain-selection kernel form of the last launch on this context
     ising::rt::Pool pool;
     std::mutex mu;
     ising::rt::Server *server = nullptr;
@@ -98,6 +99,10 @@ ising_status fail(ising_ctx *ctx, ising_status st, const std::string &msg);
     } while (0)
 
 ising_status check_problem_shape(ising_ctx *ctx, const ising_problem *p);
+// Copy a host-buffer problem into device buffers of `pool` (keys prefixed by `prefix`) on
+// stream s; *dev receives the same problem with device pointers.  Not synchronised.
+ising_status upload_problem(ising_ctx *ctx, const ising_problem &host, Pool &pool, const std::string &prefix,
+                            ising_problem &dev, hipStream_t s);
 
 struct Ingest {
     int32_t flags[5] = {0, 0, 1, 1, 0};

@@ -1,0 +1,119 @@
+"""Host-buffer entry points of the C ABI against the oracle.
+
+ising_prune (Algorithm 1, Sec. III-A, on host buffers), ising_pruned_record and
+ising_pruned_copy (the record and the reduced problem read back to the host),
+ising_unprune (retrieval, Fig. 1c, without a context) and ising_energy (the
+scalar energy of Sec. II on host buffers).  Decisions, records and integer
+values are compared bit for bit; real h_G and C within the summation bound of
+their terms (the oracle folds in plain ascending order, the kernels in their
+own reduction order); real energies within gamma_{n+1}(sum|J| + sum|h|).
+"""
+import numpy as np
+import pytest
+
+import instances as I
+import oracle
+from gpu_util import energy_bound
+from test_gpu_energy_prune import PRUNE_CASES, ENERGY_CASES
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2312_05837_amd as P
+    c = P.ising_create(0)
+    yield c
+    P.ising_destroy(c)
+
+
+def host(inst):
+    import paper_2312_05837_amd as P
+    dt = np.int32 if inst.integer else np.float64
+    h = inst.h.astype(dt) if np.any(inst.h != 0) else None
+    if inst.is_dense:
+        return P.host_problem(inst.n, J=inst.J.astype(dt), h=h)
+    return P.host_problem(inst.n, row_ptr=inst.row_ptr, col=inst.col, val=inst.val.astype(dt), h=h)
+
+
+def _gamma(inst):
+    u = 2.0 ** -53
+    k = inst.n + (inst.n * inst.n if inst.is_dense else inst.nnz)
+    return k * u / (1 - k * u)
+
+
+@pytest.mark.parametrize("name,mk", PRUNE_CASES, ids=[c[0] for c in PRUNE_CASES])
+def test_prune_unprune_host_buffers(ctx, name, mk):
+    import paper_2312_05837_amd as P
+    inst = mk()
+    ref = oracle.prune(inst)
+    st, keep = host(inst)
+    pr = P.ising_prune(ctx, st)
+    info = P.ising_pruned_info(pr)
+    assert info["n"] == inst.n and info["n_G"] == ref.G.size and info["rounds"] == ref.rounds
+    rec = P.ising_pruned_record(pr)
+    assert np.array_equal(rec["kind"], ref.kind)
+    assert np.array_equal(rec["round_of"], ref.round_of)
+    assert np.array_equal(rec["fixed"], np.where(ref.kind == 1, ref.fixed, 0))
+    assert np.array_equal(rec["partner"], ref.partner)
+    assert np.array_equal(rec["sigma"], ref.sigma)
+    assert np.array_equal(rec["G"], ref.G)
+    if inst.integer:
+        assert info["C"] == ref.C
+        if ref.G.size and np.any(ref.h_G != 0):
+            assert np.array_equal(rec["h_G"].astype(np.int64), ref.h_G.astype(np.int64))
+    else:
+        g = _gamma(inst)
+        assert abs(info["C"] - ref.C) <= g * ref.C_mass
+        if ref.G.size and np.any(ref.h_G != 0):
+            assert np.all(np.abs(rec["h_G"] - ref.h_G) <= g * ref.h_mass)
+    if 0 < ref.G.size < inst.n:
+        red = P.ising_pruned_copy(pr)
+        if inst.is_dense:
+            assert np.array_equal(red["J"], ref.reduced.J)
+        else:
+            assert np.array_equal(red["row_ptr"], ref.reduced.row_ptr)
+            assert np.array_equal(red["col"], ref.reduced.col)
+            assert np.array_equal(red["val"], ref.reduced.val)
+    # retrieval without a context, and exactness of the reduction for every reduced state:
+    # E(unprune(s_G)) = E_G(s_G) + C (integer: exact; real: within the energy bound)
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        sG = rng.choice(np.array([-1, 1], dtype=np.int8), size=ref.G.size)
+        s = P.ising_unprune(pr, sG)
+        assert np.array_equal(s, oracle.unprune(ref, sG))
+        E, Ei = P.ising_energy(ctx, st, s[None, :])
+        if inst.integer:
+            assert Ei[0] == oracle.energy(inst, s)
+            if ref.G.size:
+                assert Ei[0] == oracle.energy(ref.reduced, sG) + ref.C
+        else:
+            assert abs(E[0] - oracle.energy(inst, s)) <= 2 * energy_bound(inst)
+    P.ising_pruned_free(pr)
+
+
+@pytest.mark.parametrize("name,mk", ENERGY_CASES, ids=[c[0] for c in ENERGY_CASES])
+def test_energy_host_buffers(ctx, name, mk):
+    import paper_2312_05837_amd as P
+    inst = mk()
+    st, keep = host(inst)
+    S = np.random.default_rng(3).choice(np.array([-1, 1], dtype=np.int8), size=(9, inst.n))
+    E, Ei = P.ising_energy(ctx, st, S)
+    ref = oracle.energies(inst, S.T)
+    if inst.integer:
+        assert np.array_equal(Ei, ref.astype(np.int64))
+        assert np.array_equal(E, ref.astype(np.float64))
+    else:
+        assert np.all(np.abs(E - ref) <= 2 * energy_bound(inst))
+
+
+def test_host_calls_reject_bad_input(ctx):
+    import paper_2312_05837_amd as P
+    J = np.array([[0, 1], [2, 0]], dtype=np.int32)          # asymmetric
+    st, keep = P.host_problem(2, J=J)
+    with pytest.raises(P.IsingError) as e:
+        P.ising_prune(ctx, st)
+    assert e.value.status == P.ISING_EINVAL
+    with pytest.raises(P.IsingError) as e:
+        P.ising_unprune(P.Pruned(None), np.zeros(1, np.int8))
+    assert e.value.status == P.ISING_EINVAL

@@ -61,11 +61,13 @@ def _worst(inst, got, U, steps, opt, lr, chunks):
     return worst, ref
 
 
-CASES = [  # name, maker, replicas, (GD lr, ADAM lr) inside the non-amplifying range of each instance
+CASES = [  # name, maker, replicas, (GD lr, ADAM lr): the standard 0.01 / 0.02 unless the formulas
+    # evaluated in float32 depart from the float64 oracle by more than 1e-5 at the standard step
+    # (sk_pm1_300 GD: 4.2e-5; test_oracle_ds.py::test_fp32_rounding_exceeds_the_bar_at_rejected_step_sizes)
     ("sk_pm1_300", lambda: I.sk_pm1(300, 1), 200, (0.002, 0.02)),
     ("gauss_300", lambda: I.sk_gauss(300, 2), 200, (0.01, 0.02)),
     ("gauss_field_130", lambda: I.Instance(130, "g130", np.random.default_rng(3).normal(size=130),
-                                           I.sk_gauss(130, 3).J, integer=False), 70, (0.01, 0.005))]
+                                           I.sk_gauss(130, 3).J, integer=False), 70, (0.01, 0.02))]
 
 
 @pytest.mark.parametrize("opt,steps", [("gd", 100), ("adam", 30)])
@@ -92,7 +94,9 @@ def test_bf16_forms_exact_on_pm1(ctx):
         b = _run(ctx, inst, 130, 60, "adam", 6.0, prec, 1, U)
         for k in ("theta", "m", "v", "s_best", "e_best", "best_step", "energy_trace"):
             assert np.array_equal(a[k], b[k]), (prec, k)
-    # the integer +-1 instance in FP32 (routed to BF16) matches the oracle like the FP32 form
+    # the integer +-1 instance in FP32 (routed to BF16) matches the oracle like the FP32 form, at GD
+    # lr 0.002: at the standard 0.01 the formulas evaluated in float32 depart from the float64
+    # oracle by 3.1e-5 on these draws (test_oracle_ds.py::test_fp32_rounding_exceeds_the_bar_at_rejected_step_sizes)
     U2 = I.uniform_draws(9, 64, pm.n)
     got = _run(ctx, pm, 64, 100, "gd", 0.002, "fp32", 10, U2)
     got["loss_trace"] = np.zeros_like(got["energy_trace"])
@@ -141,7 +145,9 @@ def test_fp8_form_exact_on_uniform_integer_couplings(ctx):
         b = _run(ctx, inst, 130, 60, "adam", 6.0, prec, 2, U)
         for k in ("theta", "m", "v", "s_best", "e_best", "best_step", "energy_trace"):
             assert np.array_equal(a[k], b[k]), (prec, k)
-    # and it follows the FP64 oracle like the FP32 form (GD, 100 steps)
+    # and it follows the FP64 oracle like the FP32 form (GD, 100 steps, lr 0.001: at the standard
+    # 0.01 the formulas evaluated in float32 depart from the float64 oracle by 3.6e-2 on these
+    # draws, test_oracle_ds.py::test_fp32_rounding_exceeds_the_bar_at_rejected_step_sizes)
     U2 = I.uniform_draws(14, 64, inst.n)
     got = _run(ctx, inst, 64, 100, "gd", 0.001, "fp8", 10, U2)
     got["loss_trace"] = np.zeros_like(got["energy_trace"])
@@ -182,3 +188,21 @@ def test_solve_fp8_form_integer_energy(ctx):
         assert Ei.item() == oracle.energy(inst, s)
         res[prec] = (s.copy(), Ei.item())
     assert np.array_equal(res["fp8"][0], res["fp32"][0]) and np.array_equal(res["fp8"][0], res["bf16"][0])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x2", 2e-4)])
+def test_full_size_sk2000(ctx, prec, tol):
+    # the precision-form workload at its own size: dense SK N = 2000, J ~ N(0, 1/N), R = 256
+    # replicas (the oracle on the first and last 64), GD lr 0.01 over 100 steps in 10 calls.
+    # FP32: the FP32 matrix-core form at the FP32 bar.  BF16X2: J as hi + lo BF16 parts
+    # (relative error <= 2^-16 per entry) at the BF16X2 bar.
+    import paper_2312_05837_amd as P
+    inst = I.sk_gauss(2000, 0)
+    R = 256
+    U = I.uniform_draws(5, R, inst.n)
+    got = _run(ctx, inst, R, 100, "gd", 0.01, prec, 10, U)
+    assert P.ising_last_kernel(ctx) == f"k_dense_step<{prec}>", P.ising_last_kernel(ctx)
+    got["loss_trace"] = np.zeros_like(got["energy_trace"])
+    worst, excl = compare_trajectories(inst, got, U, 100, "gd", 0.01, 10, TOL=tol, check_loss=False,
+                                       max_excluded=8)
+    print(f"sk2000 {prec}: worst iterate error vs FP64 oracle {worst:.2e}, excluded {excl}/128")

@@ -79,9 +79,12 @@ CASES = [
 
 # Several spins per thread (the register engine beyond 1024 spins): two replicas per
 # word and four spins per thread (n = 3000, 512 replicas), one replica per word and two
-# spins per thread, and real couplings with two spins per thread.  Over 128 compared
-# replicas x 3000 spins the GD map at lr 0.01 grows rounding differences to about
-# 1.2e-5 near its unstable points, so these run at GD lr 0.005.
+# spins per thread, and real couplings with two spins per thread.  GD runs at the standard
+# lr 0.01 except on two instances where the method itself carries FP32 rounding past the
+# bar at that step size (the same formulas evaluated in float32 depart from the float64
+# oracle by 1.4e-5 and 1.3e-5 within 100 steps: test_oracle_ds.py::
+# test_fp32_rounding_exceeds_the_bar_at_rejected_step_sizes); those run at lr 0.005.
+GD_LR_BELOW_STANDARD = {"er_int3_mult_rg4": 0.005, "er3000_rg2_ept4": 0.005}
 def _hub_graph(n=600, hub_deg=300, seed=12):
     """ER graph plus one vertex joined to hub_deg others: a row far longer than the
     rest, so one wavefront of the staged image has a long loop and a row kept in
@@ -157,18 +160,21 @@ def test_fp32_iterates(ctx, name, mk, R, opt, lr, steps):
     print(f"{name} {opt} lr={lr}: worst iterate error {worst:.2e}, excluded {excl}/{R}")
 
 
-@pytest.mark.parametrize("opt,lr,steps", [("gd", 0.005, 100), ("adam", 0.02, 30)])
+@pytest.mark.parametrize("opt,steps", [("gd", 100), ("adam", 30)])
 @pytest.mark.parametrize("name,mk,R", MULTI, ids=[c[0] for c in MULTI])
-def test_fp32_iterates_several_spins_per_thread(ctx, name, mk, R, opt, lr, steps):
+def test_fp32_iterates_several_spins_per_thread(ctx, name, mk, R, opt, steps):
+    lr = GD_LR_BELOW_STANDARD.get(name, 0.01) if opt == "gd" else 0.02
     test_fp32_iterates(ctx, name, mk, R, opt, lr, steps)
 
 
-@pytest.mark.parametrize("opt,lr,steps", [("gd", 0.0005, 100), ("adam", 0.002, 30)])
+@pytest.mark.parametrize("opt,lr,steps", [("gd", 0.0005, 100), ("adam", 0.02, 30)])
 def test_fp32_iterates_field_at_row_bits_range(ctx, opt, lr, steps):
     # the fixed-width rows' spare bits end to end: h uniform on [-63, 63] (about 300 spins at
-    # +-63).  Fields this large make each step move an angle by up to lr (|y| + mu + 63), so the
-    # step sizes are a tenth of the other several-spins cases', keeping the map as well
-    # conditioned; vertices and exact energies are checked at every step as everywhere.
+    # +-63).  Fields this large make each GD step move an angle by up to lr (|y| + mu + 63): at
+    # lr 0.001 the formulas evaluated in float32 already depart from the float64 oracle by
+    # 1.2e-5 (test_oracle_ds.py::test_fp32_rounding_exceeds_the_bar_at_rejected_step_sizes), so GD
+    # runs at lr 0.0005; ADAM normalises the step and runs at the standard lr 0.02.  Vertices and
+    # exact energies are checked at every step as everywhere.
     test_fp32_iterates(ctx, "torus100x200_field63_rows_ept28",
                        lambda: I.random_integer_field(I.torus(100, 200, 26, "pm1"), 26, 63), 4, opt, lr, steps)
 
@@ -291,16 +297,28 @@ RELAXED = [
 
 
 # The relaxed loss's gradient term 2z - 2 mu x + h is real and crosses zero smoothly, and ADAM's
-# normalisation turns the rounding of near-zero gradients into much larger steps: a float32
-# emulation of these formulas departs from the FP64 oracle by 6e-6 at step 10 and 1e-5 at step 30
-# on ER n = 800 (lr 0.02), where the vertex loss stays at 2e-7 and 8e-6.  FP32 ADAM is therefore
-# compared over 20 steps at lr 0.005 (emulation: 4e-6).  In FP64 at the paper's lr 6.0 two oracle
-# runs one ulp apart separate by 2e-8 at step 10 and 3e-5 at step 20 (ER n = 800), so FP64 ADAM is
-# compared over 10 steps.
-@pytest.mark.parametrize("prec,opt,lr,steps", [("fp32", "gd", 0.005, 100), ("fp32", "adam", 0.005, 20),
+# normalisation turns the rounding of near-zero gradients into much larger steps, so FP32 ADAM is
+# compared over 20 steps.  FP32 runs at the standard step sizes (GD 0.01, ADAM 0.02) except:
+# - where the formulas evaluated in float32 already depart from the float64 oracle by more than
+#   1e-5 at the standard step size (sk64 and er800 GD: 1.0e-5 and 4.8e-5; t1 ADAM: 1.5e-5;
+#   test_oracle_ds.py::test_fp32_rounding_exceeds_the_bar_at_rejected_step_sizes), and
+# - two cases that the float32 model keeps below the bar (5.0e-6 and 6.7e-6) but where the kernels'
+#   FP32 rounding (their own sin/cos and the order of the relaxed product's sums) measured 1.1e-5
+#   (er_field GD 0.01) and 2.8e-5 (er800 ADAM 0.02): their lower step size rests on that
+#   measurement, not on a pin.
+# In FP64 at the paper's lr 6.0 two oracle runs one ulp apart separate by 2e-8 at step 10 and 3e-5
+# at step 20 (ER n = 800), so FP64 ADAM is compared over 10 steps.
+RELAXED_FP32_LR_BELOW_STANDARD = {("sk64_dense", "gd"): 0.005, ("er800_pm1_packed_rg4", "gd"): 0.005,
+                                  ("er_field_csrv", "gd"): 0.005, ("t1_uniform_real_csr_ept2", "adam"): 0.005,
+                                  ("er800_pm1_packed_rg4", "adam"): 0.005}
+
+
+@pytest.mark.parametrize("prec,opt,lr,steps", [("fp32", "gd", 0.01, 100), ("fp32", "adam", 0.02, 20),
                                                 ("fp64", "gd", 0.05, 100), ("fp64", "adam", 6.0, 10)])
 @pytest.mark.parametrize("name,mk,R", RELAXED, ids=[c[0] for c in RELAXED])
 def test_relaxed_loss_iterates(ctx, name, mk, R, prec, opt, lr, steps):
+    if prec == "fp32":
+        lr = RELAXED_FP32_LR_BELOW_STANDARD.get((name, opt), lr)
     import torch
     inst = mk()
     U = I.uniform_draws(13, R, inst.n)
@@ -467,3 +485,60 @@ def test_split_step_equals_engine(ctx, name, mk, opt, lr):
     eb = split["e_best"].cpu().numpy()
     for r in (0, 1, 2, 3, R - 1):
         assert eb[r] == oracle.energy(inst, sb[r]), r
+
+
+# ---- the split-step form against the oracle (the kernel the benchmark times) --------------
+
+SPLIT_ORACLE = [
+    ("er800", lambda: I.erdos_renyi(800, 0.06, 31, "pm1")),
+    ("torus20x40", lambda: I.torus(20, 40, 32, "pm1")),
+]
+
+
+@pytest.mark.parametrize("opt,lr,steps,chunks", [("gd", 0.01, 100, 10), ("adam", 0.02, 30, 3)])
+@pytest.mark.parametrize("name,mk", SPLIT_ORACLE, ids=[c[0] for c in SPLIT_ORACLE])
+def test_split_step_matches_oracle(ctx, name, mk, opt, lr, steps, chunks):
+    # No trace and no convergence test on a +-1 instance with R = 1024: the split-step form runs
+    # (checked through ising_last_kernel after every call).  The calls continue one another
+    # (t0 carried), and after each the angles, best energies, best steps and best vertices of
+    # the first and last 64 replicas are compared with the FP64 oracle at that step.
+    import torch
+    import paper_2312_05837_amd as P
+    inst = mk()
+    R = 1024
+    U = I.uniform_draws(43, R, inst.n)
+    sel = np.r_[0:64, R - 64:R]
+    prob = to_problem(inst)
+    prm = P.params(replicas=R, steps=steps, optimizer=opt, lr=lr, mu=0.5)
+    state = P.ds_state(inst.n, R, optimizer=opt)
+    ref = oracle.ds_run(inst, U[sel], steps, opt=opt, lr=lr, mu=0.5, record=True, record_sin=True)
+    # the vertex of step t is sgn(sin theta_{t-1}): the smallest |sin| each step's vertex came from
+    min_prev = np.empty((steps, sel.size))
+    min_prev[0] = np.abs(U[sel]).min(axis=1)
+    min_prev[1:] = np.abs(ref.sin_trace[:-1]).min(axis=2)
+    per = steps // chunks
+    live = np.ones(sel.size, dtype=bool)
+    worst = 0.0
+    Ut = torch.tensor(U, dtype=torch.float32, device="cuda")
+    for c in range(chunks):
+        P.ising_ds_dev(ctx, prob, prm, state, t0=c * per, steps=per, uniform=Ut if c == 0 else None)
+        torch.cuda.synchronize()
+        assert P.ising_last_kernel(ctx).startswith("k_ds_split"), P.ising_last_kernel(ctx)
+        t = (c + 1) * per
+        sin_gpu = np.sin(state["theta"].cpu().numpy().astype(np.float64)[sel])
+        sin_ref = ref.sin_trace[t - 1]
+        err = iterate_error(sin_gpu, sin_ref)
+        e_ref = ref.energy_trace[:t].min(axis=0).astype(np.float64)
+        bs_ref = ref.energy_trace[:t].argmin(axis=0) + 1
+        sb_ref = ref.spin_trace[bs_ref - 1, np.arange(sel.size)]
+        e_gpu = state["e_best"].cpu().numpy()[sel]
+        bs_gpu = state["best_step"].cpu().numpy()[sel]
+        sb_gpu = state["s_best"].cpu().numpy()[sel]
+        same = (err <= TOL) & (e_gpu == e_ref) & (bs_gpu == bs_ref) & np.all(sb_gpu == sb_ref, axis=1)
+        for r in np.nonzero(live & ~same)[0]:
+            # a difference is allowed only after a vertex came from a near-zero angle
+            assert min_prev[:t, r].min() < TOL, (name, opt, t, r, err[r], e_gpu[r], e_ref[r])
+            live[r] = False
+        worst = max(worst, err[live].max())
+    assert (~live).sum() <= sel.size // 16, (~live).sum()
+    print(f"split {name} {opt} lr={lr}: worst iterate error {worst:.2e}, excluded {(~live).sum()}/{sel.size}")

@@ -5,6 +5,7 @@ import pytest
 import instances as I
 import oracle
 from gpu_util import to_problem, as_float32_instance, energy_bound
+from test_oracle_prune import _star_real
 
 pytestmark = pytest.mark.gpu
 
@@ -75,6 +76,9 @@ PRUNE_CASES = [
     ("path4", lambda: I.from_edges(4, [(0, 1, 1), (1, 2, 1), (2, 3, 1)], np.zeros(4))),
     ("all_determined", lambda: I.from_edges(3, [(0, 1, 1)], np.array([5, -5, 2]))),
     ("long_path", lambda: I.from_edges(301, [(i, i + 1, 1 if i % 3 else -1) for i in range(300)], np.zeros(301))),
+    # real folds whose value depends on the summation order (see the oracle's pins)
+    ("star_real_D", lambda: _star_real(70, 0.4, 2.0 ** -56, -1.0, -1.0, 0.0)),
+    ("star_real_S", lambda: _star_real(70, 0.5, 0.5, 0.8, 2.0 ** -55, 0.0)),
 ]
 
 
@@ -108,11 +112,17 @@ def test_prune_bit_exact(ctx, name, mk):
         if ref.G.size:
             assert np.array_equal(rec["h_G"].astype(np.int64), ref.h_G.astype(np.int64))
     else:
-        scale = np.abs(inst.dense() if inst.is_dense else inst.val).sum() + np.abs(inst.h).sum()
-        assert abs(info["C"] - ref.C) <= 1e-12 * scale
+        # The decisions above compare fields with row sums formed in one fixed order on both
+        # sides; the folds into h and C are plain ascending sums in the oracle and the device's
+        # own reduction order in the kernels, so h_G and C agree to the summation bound
+        # gamma_k * (sum of the magnitudes of their terms), k = n + nnz terms at most.
+        u = 2.0 ** -53
+        k = inst.n + (inst.n * inst.n if inst.is_dense else inst.nnz)
+        gamma = k * u / (1 - k * u)
+        assert abs(info["C"] - ref.C) <= gamma * ref.C_mass, (info["C"], ref.C, ref.C_mass)
         if ref.G.size:
-            # fixed-order folds: h_G is bitwise equal
-            assert np.array_equal(rec["h_G"], ref.h_G)
+            err = np.abs(rec["h_G"] - ref.h_G)
+            assert np.all(err <= gamma * ref.h_mass), (err.max(), (gamma * ref.h_mass).min())
     if ref.G.size and red is not None and ref.G.size < inst.n:
         if inst.is_dense:
             assert np.array_equal(red.J.cpu().numpy(), ref.reduced.J)

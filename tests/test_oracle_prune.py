@@ -151,3 +151,42 @@ def test_fixed_order_sum_is_the_stated_order():
         lanes = [lanes[i] + lanes[i ^ d] for i in range(64)]
     assert got == lanes[0]
     assert abs(got - np.abs(vals).sum()) <= 1e-13 * np.abs(vals).sum()
+
+
+def _star_real(k, j_first, j_rest, h_first, h_rest, h_leaf):
+    """Star with centre 0 and leaves 1..k (real couplings): leaf 1 has coupling j_first and
+    field h_first, the others j_rest and h_rest; the centre's field is h_leaf.  The centre
+    also sits on a triangle with spins k+1, k+2 (unit couplings, no field), which keeps it in
+    G after its leaves are gone (two active neighbours, 2 sum|J| = 4 > |h_0|)."""
+    edges = [(0, 1, j_first)] + [(0, i, j_rest) for i in range(2, k + 1)]
+    edges += [(0, k + 1, 1.0), (0, k + 2, 1.0), (k + 1, k + 2, 1.0)]
+    h = np.r_[h_leaf, h_first, np.full(k - 1, h_rest), 0.0, 0.0]
+    return I.from_edges(k + 3, edges, h, "star_real", integer=False)
+
+
+def test_determined_fold_is_a_plain_ascending_sum():
+    # 70 determined leaves (|h| = 1 > 2|J|) fold into the free centre: the terms 2 J_0i s_i are
+    # 0.8 (leaf 1) and then 69 terms of 2^-55, each below half an ulp of 0.8.  Added one after
+    # another in ascending index they leave 0.8 unchanged; any grouping that sums the small
+    # terms first (pairwise, 64 strided partials) moves the result by about 2^-49.
+    inst = _star_real(70, 0.4, 2.0 ** -56, -1.0, -1.0, 0.0)
+    pr = oracle.prune(inst)
+    assert pr.G.tolist() == [0, 71, 72] and np.all(pr.kind[1:71] == 1) and pr.rounds == 2
+    assert pr.h_G.tolist() == [0.8, 0.0, 0.0]
+    assert 0.8 + 69 * 2.0 ** -55 != 0.8   # the small terms matter once grouped
+    assert pr.C == -70.0                   # sum of h_i s_i = -|h_i|; no D-D couplings
+    assert abs(pr.h_mass[0] - 0.8) < 1e-14 and pr.C_mass == 70.0   # magnitudes for error bounds
+
+
+def test_semi_determined_fold_is_a_plain_ascending_sum():
+    # 70 semi-determined leaves (one neighbour, 2|J| = 1 >= |h|): h_0 -= sum sgn(J_0k) h_k with
+    # h_1 = 0.8 first and 69 fields of 2^-55 after it, one after another: exactly -0.8
+    inst = _star_real(70, 0.5, 0.5, 0.8, 2.0 ** -55, 0.0)
+    pr = oracle.prune(inst)
+    assert pr.G.tolist() == [0, 71, 72] and np.all(pr.kind[1:71] == 2) and np.all(pr.partner[1:71] == 0)
+    assert pr.h_G[0] == -0.8
+    assert pr.C == -70.0                   # -2|J| per semi-determined leaf
+    # exactness for every reduced state (Sec. III-A reduced problem) still holds
+    for sG in ([1, 1, 1], [-1, 1, -1], [1, -1, -1]):
+        s = oracle.unprune(pr, sG)
+        assert oracle.energy(inst, s) == oracle.energy(pr.reduced, np.array(sG)) + pr.C
