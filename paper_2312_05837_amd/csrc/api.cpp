@@ -118,23 +118,27 @@ ising_status prune_core(ising_ctx *ctx, const DevProblem &p, ising_pruned &pr, h
     HIP_TRY(ctx, pool.get("pr.jv", (size_t)n * 8, &w.jv));
     HIP_TRY(ctx, pool.get("pr.cpart", (size_t)n * 8, &w.cpart));
     HIP_TRY(ctx, pool.get("pr.C", 8, &w.C));
-    HIP_TRY(ctx, pool.get("pr.counts", 16, (void **)&w.counts));
+    HIP_TRY(ctx, pool.get("pr.counts", 32, (void **)&w.counts));
 
     pr.n = n;
     pr.vtype = p.vtype;
     pr.format = p.format;
     HIP_TRY(ctx, launch_prune_init(p, w, s));
-    int32_t counts[4] = {0, 0, 0, 0};
-    int round = 0;
+    // Rounds are enqueued in batches of 2, 4, 8, ... (at most 64): the round that removes
+    // nothing raises a device-side flag that turns every later round into empty launches, so
+    // the host reads the counters once per batch (once for most problems).  Every round
+    // removes at least one spin, so at most n + 1 rounds run.
+    int32_t counts[6] = {0, 0, 0, 0, 0, 0};
+    int round = 0, batch = 2;
     for (;;) {
-        HIP_TRY(ctx, launch_prune_round(p, w, round, s));
-        HIP_TRY(ctx, hipMemcpyAsync(counts, w.counts, 8, hipMemcpyDeviceToHost, s));
+        for (int b = 0; b < batch; ++b) HIP_TRY(ctx, launch_prune_round(p, w, round++, s));
+        HIP_TRY(ctx, hipMemcpyAsync(counts, w.counts, 24, hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipStreamSynchronize(s));
-        ++round;
-        if (counts[0] == 0 && counts[1] == 0) break;
+        if (counts[4]) break;
         if (round > n + 1) return fail(ctx, ISING_EDEVICE, "pruning did not terminate");
+        batch = std::min(2 * batch, 64);
     }
-    pr.rounds = round;
+    pr.rounds = counts[5];
     if (integer) {
         int64_t c = 0;
         HIP_TRY(ctx, hipMemcpyAsync(&c, w.C, 8, hipMemcpyDeviceToHost, s));

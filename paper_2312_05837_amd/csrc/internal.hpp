@@ -63,7 +63,9 @@ struct PruneWork {
     void *jv;       // coupling to the unique neighbour: int64 or double
     void *cpart;    // per-spin contribution to C this phase
     void *C;        // accumulated constant (one int64 or double)
-    int32_t *counts;  // [0] = |D| this round, [1] = |S| this round, [2] = n_G, [3] = nnz_G
+    // [0] = |D| this round, [1] = |S| this round, [2] = n_G, [3] = nnz_G, [4] = done (a round
+    // removed nothing; later rounds return at once), [5] = rounds executed
+    int32_t *counts;
 };
 hipError_t launch_prune_init(const DevProblem &p, const PruneWork &w, hipStream_t s);
 hipError_t launch_prune_round(const DevProblem &p, const PruneWork &w, int32_t round, hipStream_t s);

@@ -14,6 +14,11 @@
 // Every per-row sum runs on one wavefront in the same fixed order as the row
 // sums (64 strided partials, xor butterfly), with coalesced reads of the row.
 // Integer problems work in int64 (exact); real problems in FP64.
+//
+// Rounds are enqueued ahead of the host's knowledge of whether they are needed:
+// the round that removes nothing sets a done flag (counts[4]) and counts the
+// rounds executed (counts[5]); every kernel of a later round sees the flag and
+// returns at once, so the host reads the counters once per batch of rounds.
 #include "internal.hpp"
 
 namespace ising {
@@ -34,6 +39,8 @@ __global__ void k_init(DevProblem p, PruneWork w) {
         w.counts[0] = w.counts[1] = 0;
         w.counts[2] = p.n;
         w.counts[3] = 0;
+        w.counts[4] = 0;
+        w.counts[5] = 0;
     }
     if (i >= p.n) return;
     w.active[i] = 1;
@@ -48,12 +55,21 @@ __global__ void k_init(DevProblem p, PruneWork w) {
 }
 
 __global__ void k_round_begin(int32_t *counts) {
-    if (threadIdx.x == 0) counts[0] = counts[1] = 0;
+    if (threadIdx.x == 0 && !counts[4]) counts[0] = counts[1] = 0;
+}
+
+// after a round: count it, and set the done flag if it removed nothing
+__global__ void k_round_end(int32_t *counts) {
+    if (threadIdx.x == 0 && !counts[4]) {
+        counts[5] += 1;
+        if (counts[0] == 0 && counts[1] == 0) counts[4] = 1;
+    }
 }
 
 // one wavefront per row
 template <typename V, typename W>
 __global__ __launch_bounds__(256) void k_rowsum_D(DevProblem p, PruneWork w) {
+    if (w.counts[4]) return;  // an earlier round removed nothing
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= p.n) return;
@@ -108,6 +124,7 @@ __device__ inline W wave_sum_fixed(W acc) {
 // one wavefront per row j
 template <typename V, typename W>
 __global__ __launch_bounds__(256) void k_fold_D(DevProblem p, PruneWork w, int round) {
+    if (w.counts[4]) return;  // an earlier round removed nothing
     const int lane = threadIdx.x & 63;
     const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= p.n) return;
@@ -143,6 +160,7 @@ __global__ __launch_bounds__(256) void k_fold_D(DevProblem p, PruneWork w, int r
 // one wavefront per row k: active degree and the unique neighbour
 template <typename V, typename W>
 __global__ __launch_bounds__(256) void k_degree(DevProblem p, PruneWork w) {
+    if (w.counts[4]) return;  // an earlier round removed nothing
     const int lane = threadIdx.x & 63;
     const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (k >= p.n) return;
@@ -177,6 +195,7 @@ __global__ __launch_bounds__(256) void k_degree(DevProblem p, PruneWork w) {
 }
 
 __global__ void k_select_S(int n, PruneWork w) {
+    if (w.counts[4]) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     bool s = false;
@@ -191,6 +210,7 @@ __global__ void k_select_S(int n, PruneWork w) {
 // one wavefront per row i
 template <typename V, typename W>
 __global__ __launch_bounds__(256) void k_fold_S(DevProblem p, PruneWork w, int round) {
+    if (w.counts[4]) return;  // an earlier round removed nothing
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= p.n) return;
@@ -229,6 +249,7 @@ __global__ __launch_bounds__(256) void k_fold_S(DevProblem p, PruneWork w, int r
 template <typename W>
 __global__ __launch_bounds__(1024) void k_accumulate_C(int n, PruneWork w) {
     __shared__ W red[1024];
+    if (w.counts[4]) return;  // uniform over the workgroup: read before any barrier
     const W *cp = (const W *)w.cpart;
     W acc = 0;
     for (int i = threadIdx.x; i < n; i += 1024) acc = acc + cp[i];
@@ -376,6 +397,7 @@ hipError_t round_impl(const DevProblem &p, const PruneWork &w, int32_t round, hi
     hipLaunchKernelGGL(k_select_S, g1(p.n), dim3(256), 0, s, p.n, w);
     hipLaunchKernelGGL((k_fold_S<V, W>), dim3((p.n + 3) / 4), dim3(256), 0, s, p, w, round);
     hipLaunchKernelGGL((k_accumulate_C<W>), dim3(1), dim3(1024), 0, s, p.n, w);
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, w.counts);
     return hipGetLastError();
 }
 

@@ -17,6 +17,8 @@
 // result is bit-identical alone and in any mix.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -105,6 +107,10 @@ struct Server {
         hipGraphExec_t exec = nullptr;
     };
     std::map<std::string, DenseGraph> graphs;
+    // failure handling tests only (environment ISING_SERVE_TEST_FAIL_DENSE_STEPS, read at start):
+    // a dense group advancing this many steps in a chunk reports a launch failure instead of
+    // launching (0: off)
+    int test_fail_dense_steps = 0;
 };
 
 namespace {
@@ -298,7 +304,8 @@ void run_chunk(Server &S, std::vector<Request *> &live) {
     ising_ctx *ctx = S.ctx;
     const int K = std::max(1, S.cfg.chunk_steps);
     std::map<BatchKey, std::vector<Request *>> groups;
-    std::map<int, std::vector<DenseRun>> dense;  // by form: every dense request of a form advances together
+    // by form: every dense request of a form advances together (run and its request)
+    std::map<int, std::vector<std::pair<DenseRun, Request *>>> dense;
     for (Request *q : live) {
         const int left = q->prm.steps - q->steps_done;
         if (left <= 0 || q->red == nullptr || q->red->n == 0) continue;
@@ -314,7 +321,7 @@ void run_chunk(Server &S, std::vector<Request *> &live) {
                 q->error = "matrix-core initialisation failed";
                 continue;
             }
-            dense[d.form].push_back(d);
+            dense[d.form].emplace_back(d, q);
         } else {
             const DSLaunch &l = q->plan.l;
             groups[BatchKey(l.coupling, l.rg, l.ept, l.block)].push_back(q);
@@ -323,15 +330,26 @@ void run_chunk(Server &S, std::vector<Request *> &live) {
     // dense groups: problems with fewer steps left than the chunk finish inside it; split
     // each form's group by step count so that one launch sequence fits every member
     for (auto &g : dense) {
-        std::map<int, std::vector<const DenseRun *>> by_steps;
-        for (const DenseRun &d : g.second) by_steps[d.steps].push_back(&d);
-        for (auto &bs : by_steps) {
+        struct StepGroup {
+            std::vector<const DenseRun *> runs;
+            std::vector<Request *> reqs;
+        };
+        std::map<int, StepGroup> by_steps;
+        for (const auto &dq : g.second) {
+            StepGroup &sg = by_steps[dq.first.steps];
+            sg.runs.push_back(&dq.first);
+            sg.reqs.push_back(dq.second);
+        }
+        for (auto &bsg : by_steps) {
+            const std::pair<const int, std::vector<const DenseRun *>> bs(bsg.first, bsg.second.runs);
             void *scratch = nullptr;
             char key[32];
             snprintf(key, sizeof key, "dg%d.%d", g.first, bs.first);
             const size_t bytes = dense_group_scratch_bytes(bs.second.data(), (int)bs.second.size());
             hipError_t e = S.batch.get(key, bytes, &scratch);
-            if (e == hipSuccess && S.cfg.no_graphs) {
+            if (e == hipSuccess && S.test_fail_dense_steps > 0 && bs.first == S.test_fail_dense_steps) {
+                e = hipErrorLaunchFailure;
+            } else if (e == hipSuccess && S.cfg.no_graphs) {
                 e = launch_dense_group(bs.second.data(), (int)bs.second.size(), bs.first, scratch, S.dense[0]);
             } else if (e == hipSuccess) {
                 DenseGroupShape shape;
@@ -363,11 +381,11 @@ void run_chunk(Server &S, std::vector<Request *> &live) {
                 if (e == hipSuccess) e = hipGraphLaunch(G.exec, S.dense[0]);
             }
             if (e != hipSuccess) {
-                for (Request *q : live)
-                    if (q->dense) {
-                        q->result = ISING_EDEVICE;
-                        q->error = "matrix-core group launch failed";
-                    }
+                // only this group's requests: the other groups' launches are independent
+                for (Request *q : bsg.second.reqs) {
+                    q->result = ISING_EDEVICE;
+                    q->error = "matrix-core group launch failed";
+                }
             }
             S.info.launches += 2 * bs.first;
         }
@@ -545,6 +563,7 @@ ising_status ising_serve_start(ising_ctx *ctx, const ising_serve_config *cfg) {
         if (cfg->dense_streams > 0) c.dense_streams = cfg->dense_streams;
     }
     S->cfg = c;
+    if (const char *f = std::getenv("ISING_SERVE_TEST_FAIL_DENSE_STEPS")) S->test_fail_dense_steps = std::atoi(f);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamCreateWithFlags(&S->main, hipStreamNonBlocking));
     S->dense.resize(c.dense_streams);

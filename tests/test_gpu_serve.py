@@ -108,6 +108,39 @@ def test_requests_arriving_while_others_run_are_admitted(ctx):
     assert info["chunks"] < 120
 
 
+def test_failing_dense_group_leaves_the_others_running(ctx, monkeypatch):
+    # A dense group whose launch fails marks only its own requests.  The failure is forced from
+    # the host: with ISING_SERVE_TEST_FAIL_DENSE_STEPS=50 (read when the server starts) a dense
+    # group advancing 50 steps in a chunk reports a launch failure instead of launching.  A
+    # long sparse request keeps the server busy so that the two dense requests, submitted back
+    # to back, are admitted at the same chunk boundary: request A (50 steps) forms the failing
+    # group, request B (100 steps) its own group in the same chunk.
+    import time as _t
+    import paper_2312_05837_amd as P
+    monkeypatch.setenv("ISING_SERVE_TEST_FAIL_DENSE_STEPS", "50")
+    P.ising_serve_start(ctx, chunk_steps=100)
+    monkeypatch.delenv("ISING_SERVE_TEST_FAIL_DENSE_STEPS")
+    c = I.erdos_renyi(2000, 4.0 / 1999, 7, "pm1")
+    a, b = I.sk_pm1(300, 8), I.sk_pm1(320, 9)
+    stc, kc = _host(c)
+    sta, ka = _host(a)
+    stb, kb = _host(b)
+    prm_b = P.params(replicas=128, steps=100, optimizer="adam", lr=6.0, mu=0.5, seed=3, precision="fp32")
+    tc = P.ising_submit(ctx, stc, P.params(replicas=256, steps=3000, seed=1))
+    _t.sleep(0.02)
+    ta = P.ising_submit(ctx, sta, P.params(replicas=128, steps=50, optimizer="adam", lr=6.0, mu=0.5, seed=2))
+    tb = P.ising_submit(ctx, stb, prm_b)
+    ra, rb, rc = P.ising_wait(ctx, ta, a.n), P.ising_wait(ctx, tb, b.n), P.ising_wait(ctx, tc, c.n)
+    info = P.ising_serve_query(ctx)
+    P.ising_serve_stop(ctx)
+    assert ra[0] == P.ISING_EDEVICE
+    assert rb[0] == P.ISING_OK and rc[0] == P.ISING_OK
+    assert info["failed"] == 1 and info["completed"] == 2
+    # the surviving dense request's result is the plain solve's
+    spins, energy, _, _ = P.ising_solve(ctx, stb, prm_b)
+    assert np.array_equal(rb[1], spins) and rb[2] == energy == oracle.energy(b, spins)
+
+
 def test_failures_forced_from_the_host(ctx):
     import paper_2312_05837_amd as P
     P.ising_serve_start(ctx, hbm_budget_bytes=4 << 20, max_resident=4, chunk_steps=10)
