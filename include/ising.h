@@ -200,6 +200,20 @@ ising_status ising_energy(ising_ctx *ctx, const ising_problem *problem, const in
 ising_status ising_energy_dev(ising_ctx *ctx, const ising_problem *problem, const int8_t *spins,
                               int32_t count, double *E_out, int64_t *E_int_out, void *stream);
 
+/* ising_energy_dev for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, with the per-block partial sums kept in a static device
+ * array of the library (8 MiB per GPU, held until the process ends) instead of a
+ * buffer allocated on demand.  The call allocates nothing.  Limit: count *
+ * ceil(n / 4) * 8 bytes <= 8 MiB (e.g. 1024 vectors of n = 4096, 104 of
+ * n = 20000); larger requests fail with EINVAL before any work is enqueued.
+ * Every call on one GPU shares that GPU's array, so calls that overlap on one
+ * GPU (concurrent streams or threads) race and must be serialised by the
+ * caller; the array needs no clearing (every partial is written before it is
+ * read).  Arguments, layouts and errors as ising_energy_dev. */
+ising_status ising_energy_dev_noalloc(ising_ctx *ctx, const ising_problem *problem, const int8_t *spins,
+                                      int32_t count, double *E_out, int64_t *E_int_out, void *stream);
+
 /* ---- pruning (Sec. III-A, Algorithm 1) and retrieval (Fig. 1c) --------- */
 
 /* Algorithm 1 on host buffers: the problem (host memory) is copied to the

@@ -101,6 +101,7 @@ _sigs = {
     "ising_last_kernel": (C.c_char_p, [_P]),
     "ising_energy": (C.c_int, [_P, C.POINTER(ising_problem), _P, C.c_int32, _P, _P]),
     "ising_energy_dev": (C.c_int, [_P, C.POINTER(ising_problem), _P, C.c_int32, _P, _P, _P]),
+    "ising_energy_dev_noalloc": (C.c_int, [_P, C.POINTER(ising_problem), _P, C.c_int32, _P, _P, _P]),
     "ising_prune": (C.c_int, [_P, C.POINTER(ising_problem), C.POINTER(C.c_void_p)]),
     "ising_unprune": (C.c_int, [_P, _P, _P]),
     "ising_pruned_record": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
@@ -279,6 +280,16 @@ def ising_energy(ctx, problem_host: ising_problem, spins):
     _check(ctx, _lib.ising_energy(ctx, C.byref(problem_host), S.ctypes.data, count, E.ctypes.data,
                                   None if Ei is None else Ei.ctypes.data))
     return E, Ei
+
+
+def ising_energy_dev_noalloc(ctx, problem: Problem, spins, E_out, E_int_out=None, stream=None):
+    """ising_energy_dev with caller-provided outputs and the library's static scratch."""
+    spins = spins.contiguous()
+    count = spins.shape[0] if spins.dim() == 2 else 1
+    ps = problem.struct()
+    _check(ctx, _lib.ising_energy_dev_noalloc(ctx, C.byref(ps), _ptr(spins), count, _ptr(E_out), _ptr(E_int_out),
+                                              _stream(stream)))
+    return E_out, E_int_out
 
 
 def ising_energy_dev(ctx, problem: Problem, spins, E_out=None, E_int_out=None, stream=None):

@@ -564,6 +564,13 @@ ising_status ising_create(int device, ising_ctx **out) {
         delete c;
         return ISING_EDEVICE;
     }
+    // the static scratch of ising_energy_dev_noalloc: its address on this device, once
+    void *scratch = nullptr;
+    if (energy_scratch_address(device, &scratch) != hipSuccess) {
+        (void)hipStreamDestroy(c->stream);
+        delete c;
+        return ISING_EDEVICE;
+    }
     *out = c;
     return ISING_OK;
 }
@@ -610,6 +617,24 @@ ising_status ising_energy(ising_ctx *ctx, const ising_problem *problem, const in
     if (E_out) HIP_TRY(ctx, hipMemcpyAsync(E_out, edev, (size_t)count * 8, hipMemcpyDeviceToHost, s));
     if (E_int_out) HIP_TRY(ctx, hipMemcpyAsync(E_int_out, eidev, (size_t)count * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
+    return ISING_OK;
+}
+
+ising_status ising_energy_dev_noalloc(ising_ctx *ctx, const ising_problem *problem, const int8_t *spins,
+                                      int32_t count, double *E_out, int64_t *E_int_out, void *stream) {
+    if (!ctx) return ISING_EINVAL;
+    ST_TRY(check_problem_shape(ctx, problem));
+    if (count < 0 || (count > 0 && !spins)) return fail(ctx, ISING_EINVAL, "bad spins/count");
+    if (E_int_out && problem->value_type != ISING_I32)
+        return fail(ctx, ISING_EINVAL, "integer energies need an ISING_I32 problem");
+    if (energy_partial_bytes(problem->n, count) > kEnergyScratchBytes)
+        return fail(ctx, ISING_EINVAL,
+                    "count * ceil(n / 4) * 8 bytes of partial sums exceed the static scratch of " +
+                        std::to_string(kEnergyScratchBytes) + " bytes");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    void *partial = nullptr;
+    HIP_TRY(ctx, energy_scratch_address(ctx->device, &partial));
+    HIP_TRY(ctx, launch_energy(to_dev(*problem), spins, count, partial, E_out, E_int_out, (hipStream_t)stream));
     return ISING_OK;
 }
 

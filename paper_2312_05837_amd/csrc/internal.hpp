@@ -53,6 +53,11 @@ hipError_t launch_first_magnitude(const DevProblem &p, double *w, hipStream_t s)
 hipError_t launch_energy(const DevProblem &p, const int8_t *spins, int32_t count, void *partial,
                          double *E_out, int64_t *E_int_out, hipStream_t s);
 size_t energy_partial_bytes(int32_t n, int32_t count);
+// Size of the library's static device scratch for the energy partials (the entry point that
+// allocates nothing), and its address on `device`, looked up once per device with that device
+// current (the lookup is made by ising_create; later calls return the kept address).
+constexpr size_t kEnergyScratchBytes = (size_t)8 << 20;
+hipError_t energy_scratch_address(int device, void **ptr);
 
 // ---- pruning (kernels_prune.hip) -------------------------------------------
 struct PruneWork {

@@ -3,6 +3,8 @@
 // free).  Real problems accumulate in FP64: one wavefront per row (64 strided
 // partials over the row's stored positions, xor butterfly), the four rows of a
 // block in index order, blocks in ascending order -- reproducible run to run.
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace ising {
@@ -55,10 +57,40 @@ __global__ void energy_finish(const Acc *partial, int nblocks, int count, double
     if (E_int_out) E_int_out[r] = (int64_t)t;
 }
 
+// Scratch for the energy partials of the entry point that allocates nothing: one array per
+// GPU the library runs on, held until the process ends.  Host code never uses this name as an
+// address (on the host it is only a stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kEnergyScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
 
 size_t energy_partial_bytes(int32_t n, int32_t count) {
     return (size_t)count * ((n + EB - 1) / EB) * 8;
+}
+
+hipError_t energy_scratch_address(int device, void **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_ptr[device] = p;
+    }
+    *ptr = scratch_ptr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_energy(const DevProblem &p, const int8_t *spins, int32_t count, void *partial,
