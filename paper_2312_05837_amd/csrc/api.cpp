@@ -354,20 +354,20 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
     }
     if (plan.packed) a.pm = (const uint32_t *)fmt;
     // wide packed engine (one replica per workgroup, 8+ spins per thread): fixed-width neighbour
-    // rows, loaded ahead of each spin's update, when every degree fits them
-    // (a field rides in the rows' spare bits: integer couplings, |h| <= 63 integers)
+    // rows, loaded ahead of each spin's update, when every degree fits them (a field rides in the
+    // rows as w deg + h: integer couplings and integer fields)
     if (plan.packed && plan.l.coupling == CK_PM && plan.l.ept >= 8 && plan.l.rg == 1 && !plan.l.relaxed &&
-        ing.maxdeg() <= kEllWidth && (!p.h || ing.integer())) {
+        ing.maxdeg() <= kEllWidth && p.n < 32768 && (!p.h || ing.integer())) {
         void *ell = nullptr, *bad = nullptr;
-        HIP_TRY(ctx, pool.get("ds.ell", (size_t)plan.l.ept * kEllWidth * plan.l.block * 4, &ell));
+        HIP_TRY(ctx, pool.get("ds.ell", (size_t)plan.l.ept * kEllWords * plan.l.block * 4, &ell));
         HIP_TRY(ctx, pool.get("ds.ell.bad", 4, &bad));
         HIP_TRY(ctx, hipMemsetAsync(bad, 0, 4, s));
-        HIP_TRY(ctx, launch_ell_format(dp, (const uint32_t *)fmt, p.h ? (const float *)hbuf : nullptr, plan.l.ept,
-                                       plan.l.block, (uint32_t *)ell, (int32_t *)bad, s));
+        HIP_TRY(ctx, launch_ell_format(dp, (const uint32_t *)fmt, p.h ? (const float *)hbuf : nullptr, ing.w,
+                                       plan.l.ept, plan.l.block, (uint32_t *)ell, (int32_t *)bad, s));
         int32_t hbad = 0;
         HIP_TRY(ctx, hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipStreamSynchronize(s));
-        if (!hbad) a.ell = (const uint32_t *)ell;  // else the CSR rows (fields beyond the spare bits)
+        if (!hbad) a.ell = (const uint32_t *)ell;  // else the CSR rows (non-integer fields)
     }
     else if (p.format == ISING_CSR) a.val = fmt;
     else a.J = fmt;

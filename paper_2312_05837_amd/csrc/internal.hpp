@@ -101,11 +101,10 @@ struct DSArgs {
     const int32_t *col = nullptr;
     const uint32_t *pm = nullptr;      // sign-packed entries: col | (J < 0) << 31
     // sign-packed entries in fixed-width rows for the wide engine (8+ spins per thread, degree
-    // <= kEllWidth): [ept][block][kEllWidth], slot j of position e * block + thread holds
-    // 2 col + (J < 0) (the neighbour's vertex byte or its complement), slot 0 also the degree
-    // << 24, slot 1 the spin's integer field (7-bit
-    // two's complement) << 24 (the engine reads no separate field then); unused slots address
-    // the zero word n
+    // <= kEllWidth): [ept][block][kEllWords words] per position e * block + thread: words 0 and 1 the
+    // 16-bit entries 2 col + (J < 0) of its neighbours (the neighbour's vertex byte or its
+    // complement; unused entries address the zero byte 2 n), word 2 the float w deg + h (the
+    // engine reads no separate field then)
     const uint32_t *ell = nullptr;
     const void *val = nullptr;         // CSR values in the state precision
     const void *J = nullptr;           // dense values in the state precision
@@ -139,7 +138,8 @@ struct DSArgs {
     void *conv_state = nullptr;
 };
 constexpr int kConvWindowMax = 8;
-constexpr int kEllWidth = 4;
+constexpr int kEllWidth = 4;  // neighbour slots per fixed-width row
+constexpr int kEllWords = 3;  // 32-bit words per row record: two words of 16-bit entries, the base
 
 struct DSLaunch {
     int coupling = CK_CSRV;
@@ -162,11 +162,12 @@ hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64,
 int32_t ds_max_n(bool fp64);
 // largest workgroup of the persistent engine with `ept` spins per thread (0: streaming)
 int ds_block_limit(int ept);
-// Fixed-width neighbour rows (DSArgs::ell) from the sign-packed CSR; every degree <= kEllWidth.
-// hf: the field in FP32 (nullable); a field that is not an integer in [-63, 63] sets *bad
-// (device, cleared by the caller), and such rows must not be used.
-hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, int ept, int block,
-                             uint32_t *ell, int32_t *bad, hipStream_t s);
+// Fixed-width neighbour rows (DSArgs::ell) from the sign-packed CSR; every degree <= kEllWidth,
+// n < 32768.  hf: the field in FP32 (nullable); w: the couplings' common magnitude.  A field
+// that is not an integer below 2^23 in magnitude sets *bad (device, cleared by the caller), and
+// such rows must not be used.
+hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, double w, int ept,
+                             int block, uint32_t *ell, int32_t *bad, hipStream_t s);
 // Build the CK_PMS image; writes the total group count to *total_groups (host,
 // synchronises once).  img may be NULL to only count.
 // Work buffers of the CK_PMS format: deg, pos (n); perm, prow, pcnt (ept * block);

@@ -142,6 +142,23 @@ __device__ inline bool dsin_neg(double x) { return sin(x) < 0; }
 // same decision there, in 11 instructions instead of 2.
 __device__ inline bool wrapped_sin_neg(float x) { return (x < 0.f) != (__builtin_fabsf(x) >= 3.14159274f); }
 __device__ inline bool wrapped_sin_neg(double x) { return dsin_neg(x); }
+// cos x for a wrapped angle (|x| exceeds pi by at most a rounding error): cos x = -sin f with
+// f = |x| - pi/2 in [-pi/2, pi/2] (pi/2 in two parts), and sin f = f + f^3 (S1 + S2 z + S3 z^2 + S4 z^3),
+// z = f^2, coefficients (rounded to float) fitted to the relative error of sin on [0, pi/2] by
+// iteratively reweighted least squares (Lawson's algorithm): 6e-9, below float rounding.  Eight
+// instructions; a float emulation over 2e7 random angles and 2e6 around 0, +-pi/2 and +-pi gives
+// at most 1.8 ulp.
+constexpr float WCOS_S1 = -1.6666660e-01f, WCOS_S2 = 8.3330665e-03f, WCOS_S3 = -1.9809604e-04f,
+                WCOS_S4 = 2.6057808e-06f;
+__device__ inline float wrapped_cos(float x) {
+    const float f = (__builtin_fabsf(x) - 1.57079637050628662f) - -4.37113882867379300e-08f;
+    const float z = f * f;
+    float p = __builtin_fmaf(z, WCOS_S4, WCOS_S3);
+    p = __builtin_fmaf(z, p, WCOS_S2);
+    p = __builtin_fmaf(z, p, WCOS_S1);
+    return __builtin_fmaf(-f * z, p, -f);
+}
+__device__ inline double wrapped_cos(double x) { return cos(x); }
 __device__ inline float dasin(float x) { return asinf(x); }
 __device__ inline double dasin(double x) { return asin(x); }
 // a word in global memory, addressed as such (an address made opaque to the compiler would
@@ -149,6 +166,20 @@ __device__ inline double dasin(double x) { return asin(x); }
 using GlobalU32 = __attribute__((address_space(1))) uint32_t;
 using U32x4 = uint32_t __attribute__((ext_vector_type(4)));
 using GlobalU32x4 = __attribute__((address_space(1))) U32x4;
+// a fixed-width row record: three 32-bit words, 12 bytes apart (a 3-element vector type would
+// occupy 16 bytes)
+struct Rec3 {
+    uint32_t w[3];
+};
+// record idx of an array of Rec3 at base (global memory; the three loads merge into one)
+__device__ __forceinline__ Rec3 load_rec3(uintptr_t base, size_t idx) {
+    const GlobalU32 *p = (const GlobalU32 *)(base + idx * sizeof(Rec3));
+    Rec3 r;
+    r.w[0] = p[0];
+    r.w[1] = p[1];
+    r.w[2] = p[2];
+    return r;
+}
 
 // a compile-time flag passed to a generic lambda
 template <bool B>
@@ -178,6 +209,38 @@ __device__ __forceinline__ Real angle_step(Real th, Real &mo, Real &ve, Real g, 
         mo = dfma(b1, mo, omb1 * g);
         ve = dfma(b2, ve, omb2 * (g * g));
         upd = (mo * lib1) * drcp(dsqrt(ve * ib2) + eps);
+    } else {
+        upd = lr * g;
+    }
+    Real tn = th - upd;
+    const Real q = drint(tn * Consts<Real>::inv_twopi);
+    tn = dfma(-q, Consts<Real>::twopi_hi, tn);
+    return dfma(-q, Consts<Real>::twopi_lo, tn);
+}
+
+// The same step for the fixed-width-row form, with the moments kept scaled in registers,
+// mo = m / (1 - b1) and ve = v / (1 - b2), so that each moment update is one FMA:
+// m' = b1 m + (1 - b1) g  <=>  mo' = b1 mo + g, and likewise for v with g^2; the update
+// lr m_hat / (sqrt(v_hat) + eps) is then (mo a1) / (sqrt(ve a2) + eps) with a1 = lr (1 - b1) / (1 - b1^t)
+// and a2 = (1 - b2) / (1 - b2^t) per step.  The moments are scaled when they are read and unscaled
+// when they are written back, so the state holds m and v as in every other form.
+template <typename Real>
+__device__ __forceinline__ Real angle_step_scaled(Real th, Real &mo, Real &ve, Real g, bool adam, Real b1, Real b2,
+                                                  Real a1, Real lr, Real a2, Real eps) {
+#pragma clang fp contract(off)
+    Real upd;
+    if (adam) {
+        if constexpr (sizeof(Real) == 4) {
+            // mo = mo b1 + g and ve = ve b2 + g^2, each written in place (the compiler's accumulate
+            // form would write into g's register and copy back: two moves per update)
+            const Real g2 = g * g;
+            asm("v_fma_f32 %0, %0, %1, %2" : "+v"(mo) : "v"(b1), "v"(g));
+            asm("v_fma_f32 %0, %0, %1, %2" : "+v"(ve) : "v"(b2), "v"(g2));
+        } else {
+            mo = dfma(b1, mo, g);
+            ve = dfma(b2, ve, g * g);
+        }
+        upd = (mo * a1) * drcp(dsqrt(ve * a2) + eps);
     } else {
         upd = lr * g;
     }
@@ -367,13 +430,19 @@ __device__ __forceinline__ int local_index(int i) {
     return i;
 }
 
-// OPT: the optimizer as a compile-time choice (0 GD, 1 ADAM) or -1 to read it at run time
-template <typename Real, int CK, int RG, int EPT, int OPT = -1>
+// OPT: the optimizer as a compile-time choice (0 GD, 1 ADAM) or -1 to read it at run time.
+// LOSS (fixed-width-row form only): false for runs that need no loss (no loss trace and no
+// convergence test), whose update then evaluates cos(theta) alone and takes the vertex sign
+// from the bit it already holds; true computes sin(theta) as well, for the loss.  Both run
+// the same update of the angles, so their trajectories are identical.
+template <typename Real, int CK, int RG, int EPT, int OPT = -1, bool LOSS = true>
 __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     using SWd = SpinWord<RG>;
     using SW = typename SWd::T;
     constexpr int NE = EPT * RG;
-    constexpr bool KEEP = NE * (int)sizeof(Real) <= 32;  // keep sin/cos of theta in registers
+    // keep sin/cos of theta in registers (not in the fixed-width-row form, which evaluates
+    // cos(theta) once per update)
+    constexpr bool KEEP = NE * (int)sizeof(Real) <= 32 && CK != CK_PME;
     static_assert(NE <= 32, "one 32-bit mask per thread");
     extern __shared__ __align__(16) unsigned char smem[];
 
@@ -498,13 +567,13 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 Real t;
                 if (a.init_mode == 0) {
                     t = gth[idx];
-                    if (t > (Real)3.5 || t < (Real)-3.5) {  // angles this engine wrote are within pi
+                    if (t > (Real)3.15 || t < (Real)-3.15) {  // angles the engines write are within pi_f
                         const Real qw = drint(t * Consts<Real>::inv_twopi);
                         t = t - qw * Consts<Real>::twopi_hi;
                         t = t - qw * Consts<Real>::twopi_lo;
                     }
-                    if (gm) mo[k] = gm[idx];
-                    if (gv) ve[k] = gv[idx];
+                    if (gm) mo[k] = CK == CK_PME ? gm[idx] / (Real)(1.0 - a.b1) : gm[idx];
+                    if (gv) ve[k] = CK == CK_PME ? gv[idx] / (Real)(1.0 - a.b2) : gv[idx];
                     if (a.s_best[idx] < 0) best |= 1u << k;
                 } else {
                     const Real u = a.init_mode == 1 ? ((const Real *)a.uniform)[idx]
@@ -563,6 +632,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         const SW *sc = vbuf((t - 1) & 1);
         const Real ib1 = adam ? bct[2 * (t - 1)] : (Real)1, ib2 = adam ? bct[2 * (t - 1) + 1] : (Real)1;
         const Real lib1 = lr * ib1;
+        const Real sa1 = lib1 * omb1, sa2 = ib2 * omb2;  // the scaled-moment form's factors
         Real Ep[RG], Lp[RG];
 #pragma unroll
         for (int r = 0; r < RG; ++r) Ep[r] = Lp[r] = (Real)-0.0;  // x + (-0) = x: no add for the first term
@@ -573,39 +643,64 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         constexpr bool WIDE_ELL = CK == CK_PME;
         constexpr int ELL_AHEAD = EPT >= 28 ? 2 : 4;  // the widest variants leave little register room
         constexpr bool use_ell = WIDE_ELL;
-        // a spin's kEllWidth words are contiguous: one 16-byte load per lane, coalesced over the wave
-        static_assert(kEllWidth == 4, "one 16-byte load per spin");
-        U32x4 nbw[WIDE_ELL ? EPT : 1];
+        // a spin's record is contiguous: one 12-byte load per lane, coalesced over the wave (a
+        // record with an unused word let that word's register be reused while its load was in
+        // flight, which made every spin wait for the load issued ahead of it)
+        static_assert(kEllWidth == 4 && kEllWords == 3 && sizeof(Rec3) == 12, "four 16-bit entries and the base in 12 bytes");
+        Rec3 nbw[WIDE_ELL ? EPT : 1];
+        // the neighbour bytes of each spin's count, read from LDS at its update (reading them a
+        // spin ahead measured slower: the extra live registers forced waits on the row loads)
+        uint32_t nb8[WIDE_ELL ? EPT : 1][4];
+        uint32_t nbase[WIDE_ELL ? EPT : 1];
+        auto read_nb = [&](int e) __attribute__((always_inline)) {
+            if constexpr (WIDE_ELL) {
+                const Rec3 rw = nbw[e];
+                nb8[e][0] = sc[rw.w[0] & 0xffffu];
+                nb8[e][1] = sc[rw.w[0] >> 16];
+                nb8[e][2] = sc[rw.w[1] & 0xffffu];
+                nb8[e][3] = sc[rw.w[1] >> 16];
+                nbase[e] = rw.w[2];
+            }
+        };
         uintptr_t ellp = (uintptr_t)a.ell;
         if constexpr (WIDE_ELL) {
             asm volatile("" : "+s"(ellp));
             if (use_ell)
 #pragma unroll
-                for (int e = 0; e < ELL_AHEAD && e < EPT; ++e) nbw[e] = ((const GlobalU32x4 *)ellp)[(size_t)e * B + tid];
+                for (int e = 0; e < ELL_AHEAD && e < EPT; ++e) nbw[e] = load_rec3(ellp, (size_t)e * B + tid);
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             if constexpr (WIDE_ELL) {
-                if (use_ell && e + ELL_AHEAD < EPT)
-                    nbw[e + ELL_AHEAD] = ((const GlobalU32x4 *)ellp)[(size_t)(e + ELL_AHEAD) * B + tid];
+                if (use_ell && e + ELL_AHEAD < EPT)  // a uniform base per spin plus the lane's offset
+                    nbw[e + ELL_AHEAD] = load_rec3(ellp + (size_t)(e + ELL_AHEAD) * B * sizeof(Rec3), tid);
             }
-            if (e * B + tid >= n) continue;
-            const int i = local_index<EPT>(spin_of(e));
+            if constexpr (WIDE_ELL) {
+                // positions e B .. e B + B - 1: a scalar test first (all in range for every e but
+                // the last ones), the per-lane test only where the range ends; the limit is made
+                // opaque per step so that the per-lane masks are not all kept across the step loop
+                int lim = n - e * B;
+                asm volatile("" : "+s"(lim));
+                if (lim < B && tid >= lim) continue;
+            } else {
+                if (e * B + tid >= n) continue;
+            }
+            // (the fixed-width-row form needs no spin index: its rows and vertex are by position)
+            const int i = WIDE_ELL ? e * B + tid : local_index<EPT>(spin_of(e));
             Real y[RG];
             if constexpr (is_pms(CK)) {
                 coupling<Real, CK, RG>(a, i, sc, y, img, prow_r[e], pcnt_r[e]);
             } else if constexpr (WIDE_ELL) {
-                // one replica per workgroup: the word is the spin's sign bit
-                uint32_t cnt = 0;
+                // one replica per workgroup: a byte per spin and copy (the vertex or its complement)
+                read_nb(e);
+                const uint32_t cnt = nb8[e][0] + nb8[e][1] + nb8[e][2] + nb8[e][3];
+                // y = w (deg - 2 count) + h = base - 2 w count (exact for integer w and h).  (The
+                // base word is copied out of the vector first: a bit cast applied to a vector
+                // element directly has been compiled as a cast of element 0.)
+                const uint32_t base_bits = nbase[e];
 #pragma unroll
-                for (int j = 0; j < kEllWidth; ++j) {
-                    cnt += (uint32_t)sc[nbw[e][j] & 0xffffffu];  // the word or its complement
-                }
-                const int deg = (int)((nbw[e][0] >> 24) & 0x7fu);
-                const int hk = (int)((int32_t)(nbw[e][1] << 1) >> 25);  // the integer field, bits 24..30
-                // w (deg - 2 count) + h: integers, exact in the state precision
-#pragma unroll
-                for (int r = 0; r < RG; ++r) y[r] = (Real)a.w * (Real)(deg - 2 * (int)cnt) + (Real)hk;
+                for (int r = 0; r < RG; ++r)
+                    y[r] = dfma((Real)(-2.0 * a.w), (Real)(int)cnt, (Real)__builtin_bit_cast(float, base_bits));
             } else {
                 coupling<Real, CK, RG>(a, i, sc, y);
             }
@@ -626,19 +721,35 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
 #pragma unroll
             for (int r = 0; r < RG; ++r) {
                 const int k = e * RG + r;
-                Real x, c;
-                if (KEEP) {
-                    x = xs[k];
-                    c = cs[k];
+                Real x = 0, c;
+                Real sg;
+                if constexpr (WIDE_ELL) {
+                    // the fixed-width-row form: the vertex sign is bit k of cur (read through an
+                    // opaque copy, so that no spin's sign is computed ahead of its update);
+                    // cos(theta) drives the update, sin(theta) only the loss (LOSS)
+                    const uint32_t cb = cur;
+                    sg = (Real)__builtin_bit_cast(float, 0x3f800000u | ((cb << (31 - k)) & 0x80000000u));
+                    c = wrapped_cos(th[k]);
+                    if constexpr (LOSS) {
+                        Real cunused;
+                        dsincos(th[k], &x, &cunused);
+                    }
                 } else {
-                    dsincos(th[k], &x, &c);
+                    if (KEEP) {
+                        x = xs[k];
+                        c = cs[k];
+                    } else {
+                        dsincos(th[k], &x, &c);
+                    }
+                    // s = sgn(sin theta) as +-1 (the vertex bit k of cur); products with it are exact
+                    sg = x < 0 ? (Real)-1 : (Real)1;
                 }
-                // s = sgn(sin theta) as +-1 (the vertex bit k of cur); products with it are exact
-                const Real sg = x < 0 ? (Real)-1 : (Real)1;
-                const Real yh = y[r] + hh;
+                const Real yh = WIDE_ELL ? y[r] : y[r] + hh;  // fixed-width rows: the field is in y
                 Ep[r] = dfma(sg, yh, Ep[r]);
                 Real tt = dfma(-mu, sg, yh);  // y - mu s + h
-                if constexpr (CAN_RELAX) {
+                if constexpr (WIDE_ELL) {
+                    if constexpr (LOSS) Lp[r] = dfma(x, tt, Lp[r]);
+                } else if constexpr (CAN_RELAX) {
                     if (relaxed) {
                         const Real zm = dfma(-mu, x, z[r]);  // z - mu x
                         tt = zm + hh;                                 // L term: z - mu x + h
@@ -651,9 +762,11 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     Lp[r] = dfma(x, tt, Lp[r]);
                 }
                 Real xn = x;  // a stopped replica keeps its angle, moments and vertex
-                bool xneg = x < 0;
+                bool xneg = WIDE_ELL ? sg < 0 : x < 0;
                 if (!decltype(check)::value || !((done >> r) & 1u)) {
-                    const Real tn = angle_step(th[k], mo[k], ve[k], c * tt, adam, b1, omb1, b2, omb2, lib1, lr, ib2, eps);
+                    const Real tn = WIDE_ELL ? angle_step_scaled(th[k], mo[k], ve[k], c * tt, adam, b1, b2, sa1, lr, sa2, eps)
+                                             : angle_step(th[k], mo[k], ve[k], c * tt, adam, b1, omb1, b2, omb2, lib1, lr,
+                                                          ib2, eps);
                     th[k] = tn;
                     if (KEEP) {
                         Real cn;
@@ -668,7 +781,13 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                         xneg = wrapped_sin_neg(tn);  // only the next vertex is needed
                     }
                 }
-                if (xneg) {
+                if constexpr (WIDE_ELL) {
+                    const uint32_t xb = xneg ? 1u : 0u;
+                    // nxt |= xb << k as one shift-or with the shift as an immediate (the compiler's
+                    // select of 0 / 1 << k keeps every such constant in a register)
+                    asm("v_lshl_or_b32 %0, %1, %2, %0" : "+v"(nxt) : "v"(xb), "i"(k));
+                    word = (SW)xb;
+                } else if (xneg) {
                     nxt |= 1u << k;
                     word |= (SW)(1u << SWd::shift(r));
                 }
@@ -676,7 +795,9 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
             }
             };
             if constexpr (RG == 1) {
-                replicas(Flag<true>{});  // one replica: nothing to interleave
+                // one replica: nothing to interleave (and without the loss no convergence test)
+                if constexpr (WIDE_ELL && !LOSS) replicas(Flag<false>{});
+                else replicas(Flag<true>{});
             } else {
                 if (done) replicas(Flag<true>{});
                 else replicas(Flag<false>{});
@@ -790,8 +911,8 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
             const int k = e * RG + r;
             const size_t idx = (size_t)(r0 + r) * n + i;
             gth[idx] = th[k];
-            if (gm) gm[idx] = mo[k];
-            if (gv) gv[idx] = ve[k];
+            if (gm) gm[idx] = CK == CK_PME ? mo[k] * (Real)(1.0 - a.b1) : mo[k];
+            if (gv) gv[idx] = CK == CK_PME ? ve[k] * (Real)(1.0 - a.b2) : ve[k];
             a.s_best[idx] = ((best >> k) & 1u) ? (int8_t)-1 : (int8_t)1;
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -988,9 +1109,9 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
     }
 }
 
-template <typename Real, int CK, int RG, int EPT, int OPT = -1>
+template <typename Real, int CK, int RG, int EPT, int OPT = -1, bool LOSS = true>
 __global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
-    ds_body<Real, CK, RG, EPT, OPT>(a, blockIdx.x * RG);
+    ds_body<Real, CK, RG, EPT, OPT, LOSS>(a, blockIdx.x * RG);
 }
 
 // Batched form for serving: workgroup b runs replica group map[b].y of problem
@@ -1202,32 +1323,35 @@ __global__ void k_format(DevProblem p, int packed, uint32_t *pm, Real *val_out, 
     }
 }
 
-// Fixed-width neighbour rows for the wide engine: slot j of position q = e * block + t
-// (spin q) at (q * kEllWidth + j), entry 2 col + (J < 0) in bits 0..23; slot 0 carries the degree in bits 24..30,
-// slot 1 the spin's field as a 7-bit two's-complement integer in the same bits
-__global__ void k_ell_format(DevProblem p, const uint32_t *pm, const float *hf, int ept, int block,
+// Fixed-width neighbour rows for the wide engine, one 12-byte record per position q = e * block + t
+// (spin q): words 0 and 1 hold the entries 2 col + (J < 0) of its (at most four) neighbours, two
+// 16-bit entries per word (the neighbour's vertex byte or its complement; pads 2 n, a zero byte),
+// and word 2 the float base = w deg + h, so that y = w (deg - 2 count) + h = base - 2 w count is one
+// FMA (exact for integer w and h).  A field that is not an integer below 2^23 in magnitude sets
+// *bad (such rows must not be used).
+__global__ void k_ell_format(DevProblem p, const uint32_t *pm, const float *hf, double w, int ept, int block,
                              uint32_t *ell, int32_t *bad) {
     const int total = ept * block;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
         const int e = q / block, t = q % block;
         const int rs = q < p.n ? p.row_ptr[q] : 0, deg = q < p.n ? p.row_ptr[q + 1] - rs : 0;
-        int hk = 0;
+        double hk = 0.0;
         if (hf && q < p.n) {
             const float hv = hf[q];
-            hk = (int)hv;
-            if (!((float)hk == hv && hk >= -63 && hk <= 63)) {
+            if (!(hv == rintf(hv) && fabsf(hv) < 8388608.f)) {
                 atomicOr(bad, 1);
-                hk = 0;
+            } else {
+                hk = (double)hv;
             }
         }
+        uint32_t ent[kEllWidth];
 #pragma unroll
-        for (int j = 0; j < kEllWidth; ++j) {
-            // entry 2 col + (J < 0): the neighbour's vertex byte or its complement; pads: 2 n, zero
-            uint32_t w = j < deg ? 2u * (pm[rs + j] & 0x7fffffffu) + (pm[rs + j] >> 31) : 2u * (uint32_t)p.n;
-            if (j == 0) w |= (uint32_t)deg << 24;
-            if (j == 1) w |= ((uint32_t)hk & 0x7fu) << 24;
-            ell[((size_t)e * block + t) * kEllWidth + j] = w;
-        }
+        for (int j = 0; j < kEllWidth; ++j)
+            ent[j] = j < deg ? 2u * (pm[rs + j] & 0x7fffffffu) + (pm[rs + j] >> 31) : 2u * (uint32_t)p.n;
+        uint32_t *o = ell + ((size_t)e * block + t) * kEllWords;
+        o[0] = ent[0] | (ent[1] << 16);
+        o[1] = ent[2] | (ent[3] << 16);
+        o[2] = __float_as_uint((float)(w * (double)deg + hk));
     }
 }
 
@@ -1514,7 +1638,7 @@ KFn pick_rg(int rg, int ept) {
 }
 
 template <typename Real>
-KFn pick(int ck, int rg, int ept, bool adam) {
+KFn pick(int ck, int rg, int ept, bool adam, bool loss) {
     switch (ck) {
         case CK_PM: return pick_rg<Real, CK_PM>(rg, ept);
         case CK_PMS: return ept > 0 ? pick_rg<Real, CK_PMS>(rg, ept) : nullptr;
@@ -1523,10 +1647,16 @@ KFn pick(int ck, int rg, int ept, bool adam) {
             if constexpr (sizeof(Real) == 4) {
                 if (rg != 1) return nullptr;
                 // the optimizer compiled in (these kernels run the longest per launch)
-                if (ept == 8) return adam ? k_ds<Real, CK_PME, 1, 8, 1> : k_ds<Real, CK_PME, 1, 8, 0>;
-                if (ept == 16) return adam ? k_ds<Real, CK_PME, 1, 16, 1> : k_ds<Real, CK_PME, 1, 16, 0>;
-                if (ept == 28) return adam ? k_ds<Real, CK_PME, 1, 28, 1> : k_ds<Real, CK_PME, 1, 28, 0>;
-                if (ept == 32) return adam ? k_ds<Real, CK_PME, 1, 32, 1> : k_ds<Real, CK_PME, 1, 32, 0>;
+                // and whether the loss is needed (a trace or the convergence test)
+#define ISING_PME(E)                                                                                 \
+    if (ept == E)                                                                                    \
+        return loss ? (adam ? k_ds<Real, CK_PME, 1, E, 1, true> : k_ds<Real, CK_PME, 1, E, 0, true>) \
+                    : (adam ? k_ds<Real, CK_PME, 1, E, 1, false> : k_ds<Real, CK_PME, 1, E, 0, false>);
+                ISING_PME(8)
+                ISING_PME(16)
+                ISING_PME(28)
+                ISING_PME(32)
+#undef ISING_PME
             }
             return nullptr;
         case CK_CSRV: return pick_rg<Real, CK_CSRV>(rg, ept);
@@ -1545,12 +1675,14 @@ int32_t ds_max_n(bool fp64) {
     return 48 * 1024;
 }
 
-hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, int ept, int block,
-                             uint32_t *ell, int32_t *bad, hipStream_t s) {
-    if (p.format != ISING_CSR || ept <= 0 || block <= 0 || (int64_t)ept * block < p.n || !bad)
+hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, double w, int ept,
+                             int block, uint32_t *ell, int32_t *bad, hipStream_t s) {
+    // entries 2 col + 1 < 2^16 in 16 bits
+    if (p.format != ISING_CSR || ept <= 0 || block <= 0 || (int64_t)ept * block < p.n || !bad || p.n >= 32768)
         return hipErrorInvalidValue;
     const int total = ept * block;
-    hipLaunchKernelGGL(k_ell_format, dim3((total + 255) / 256), dim3(256), 0, s, p, pm, hf, ept, block, ell, bad);
+    hipLaunchKernelGGL(k_ell_format, dim3((total + 255) / 256), dim3(256), 0, s, p, pm, hf, w, ept, block, ell,
+                       bad);
     return hipGetLastError();
 }
 
@@ -1572,7 +1704,8 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s, std::str
                  : l.coupling == CK_PM && a.ell != nullptr && !l.relaxed ? CK_PME
                                                                           : l.coupling;
     const bool adam = a.opt == ISING_OPT_ADAM;
-    KFn fn = l.fp64 ? pick<double>(ck, l.rg, l.ept, adam) : pick<float>(ck, l.rg, l.ept, adam);
+    const bool need_loss = a.ltrace != nullptr || a.conv_tol > 0;
+    KFn fn = l.fp64 ? pick<double>(ck, l.rg, l.ept, adam, need_loss) : pick<float>(ck, l.rg, l.ept, adam, need_loss);
     if (!fn) return hipErrorInvalidValue;
     if (l.block % 64 || l.block < 64 || l.block > ds_block_limit(l.ept) || (l.ept > 0 && (int64_t)l.ept * l.block < a.n) ||
         a.R % l.rg)
@@ -1606,7 +1739,8 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s, std::str
         static const char *const cks[] = {"PM", "CSRV", "DENSE", "PMS", "PMSR", "PME"};
         const char *ckn = ck >= 0 && ck < (int)(sizeof(cks) / sizeof(cks[0])) ? cks[ck] : "?";
         *kernel = std::string(l.ept > 0 ? "k_ds<" : "k_ds_stream<") + (l.fp64 ? "double" : "float") + ", " + ckn +
-                  ", rg=" + std::to_string(l.rg) + ", ept=" + std::to_string(l.ept) + ">";
+                  ", rg=" + std::to_string(l.rg) + ", ept=" + std::to_string(l.ept) +
+                  (ck == CK_PME ? (need_loss ? ", loss" : ", no loss") : "") + ">";
     }
     return hipGetLastError();
 }
