@@ -354,20 +354,19 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
     }
     if (plan.packed) a.pm = (const uint32_t *)fmt;
     // wide packed engine (one replica per workgroup, 8+ spins per thread): fixed-width neighbour
-    // rows, loaded ahead of each spin's update, when every degree fits them (a field rides in the
-    // rows as w deg + h: integer couplings and integer fields)
+    // rows and a per-position field, loaded ahead of each spin's update, when every degree fits
+    // them; the workgroup is then the launch bound of its spins per thread
     if (plan.packed && plan.l.coupling == CK_PM && plan.l.ept >= 8 && plan.l.rg == 1 && !plan.l.relaxed &&
-        ing.maxdeg() <= kEllWidth && p.n < 32768 && (!p.h || ing.integer())) {
-        void *ell = nullptr, *bad = nullptr;
-        HIP_TRY(ctx, pool.get("ds.ell", (size_t)plan.l.ept * kEllWords * plan.l.block * 4, &ell));
-        HIP_TRY(ctx, pool.get("ds.ell.bad", 4, &bad));
-        HIP_TRY(ctx, hipMemsetAsync(bad, 0, 4, s));
-        HIP_TRY(ctx, launch_ell_format(dp, (const uint32_t *)fmt, p.h ? (const float *)hbuf : nullptr, ing.w,
-                                       plan.l.ept, plan.l.block, (uint32_t *)ell, (int32_t *)bad, s));
-        int32_t hbad = 0;
-        HIP_TRY(ctx, hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipStreamSynchronize(s));
-        if (!hbad) a.ell = (const uint32_t *)ell;  // else the CSR rows (non-integer fields)
+        ing.maxdeg() <= kEllWidth && (int64_t)plan.l.ept * ds_block_limit(plan.l.ept) < 32768) {
+        plan.l.block = ds_block_limit(plan.l.ept);
+        void *ell = nullptr, *hrow = nullptr;
+        const size_t pos = (size_t)plan.l.ept * plan.l.block;
+        HIP_TRY(ctx, pool.get("ds.ell", pos * kEllWidth * 4, &ell));
+        HIP_TRY(ctx, pool.get("ds.ell.h", pos * 4, &hrow));
+        HIP_TRY(ctx, launch_ell_format(dp, (const uint32_t *)fmt, p.h ? (const float *)hbuf : nullptr, plan.l.ept,
+                                       plan.l.block, (uint32_t *)ell, (float *)hrow, s));
+        a.ell = (const uint32_t *)ell;
+        a.ellh = (const float *)hrow;
     }
     else if (p.format == ISING_CSR) a.val = fmt;
     else a.J = fmt;

@@ -101,11 +101,12 @@ struct DSArgs {
     const int32_t *col = nullptr;
     const uint32_t *pm = nullptr;      // sign-packed entries: col | (J < 0) << 31
     // sign-packed entries in fixed-width rows for the wide engine (8+ spins per thread, degree
-    // <= kEllWidth): [ept][block][kEllWords words] per position e * block + thread: words 0 and 1 the
-    // 16-bit entries 2 col + (J < 0) of its neighbours (the neighbour's vertex byte or its
-    // complement; unused entries address the zero byte 2 n), word 2 the float w deg + h (the
-    // engine reads no separate field then)
+    // <= kEllWidth, block = launch bound of its spins per thread): [ept][block][kEllWidth words]
+    // per position e * block + thread, the entries 2 col + (J < 0) of its neighbours (the byte of
+    // the neighbour's term sgn(J) s in the vertex buffer; unused entries address the zero pair
+    // 2 ept block); ellh: [ept][block] FP32, the position's field (0 without one or past n)
     const uint32_t *ell = nullptr;
+    const float *ellh = nullptr;
     const void *val = nullptr;         // CSR values in the state precision
     const void *J = nullptr;           // dense values in the state precision
     double w = 1.0;                    // common magnitude of sign-packed couplings
@@ -138,8 +139,7 @@ struct DSArgs {
     void *conv_state = nullptr;
 };
 constexpr int kConvWindowMax = 8;
-constexpr int kEllWidth = 4;  // neighbour slots per fixed-width row
-constexpr int kEllWords = 3;  // 32-bit words per row record: two words of 16-bit entries, the base
+constexpr int kEllWidth = 4;  // neighbour slots per fixed-width row, one 32-bit word each
 
 struct DSLaunch {
     int coupling = CK_CSRV;
@@ -162,12 +162,11 @@ hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64,
 int32_t ds_max_n(bool fp64);
 // largest workgroup of the persistent engine with `ept` spins per thread (0: streaming)
 int ds_block_limit(int ept);
-// Fixed-width neighbour rows (DSArgs::ell) from the sign-packed CSR; every degree <= kEllWidth,
-// n < 32768.  hf: the field in FP32 (nullable); w: the couplings' common magnitude.  A field
-// that is not an integer below 2^23 in magnitude sets *bad (device, cleared by the caller), and
-// such rows must not be used.
-hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, double w, int ept,
-                             int block, uint32_t *ell, int32_t *bad, hipStream_t s);
+// Fixed-width neighbour rows (DSArgs::ell, DSArgs::ellh) from the sign-packed CSR; every
+// degree <= kEllWidth, block = ds_block_limit(ept), ept * block < 32768.  hf: the field in FP32
+// (nullable).  ell: ept * block * kEllWidth words; hrow: ept * block floats.
+hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, int ept, int block,
+                             uint32_t *ell, float *hrow, hipStream_t s);
 // Build the CK_PMS image; writes the total group count to *total_groups (host,
 // synchronises once).  img may be NULL to only count.
 // Work buffers of the CK_PMS format: deg, pos (n); perm, prow, pcnt (ept * block);
@@ -185,7 +184,8 @@ int pms_region_bytes(const DSLaunch &l);
 constexpr int kPmsMaxMult = 4;
 hipError_t launch_pms_format(const DevProblem &p, const DSLaunch &l, double wunit, PmsWork &w,
                              int32_t *total_groups, hipStream_t s);
-// twin: the fixed-width-row form, whose vertex buffers hold each word and its complement
+// Dynamic LDS bytes of a launch.  twin: the fixed-width-row form, whose vertex buffers (each
+// sign and its negation) are a static array of 2 twin_stride(ept, block) bytes besides these
 size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups, bool twin = false);
 // Batched persistent engine (FP32): workgroup b runs replica group map[b].y of
 // descs[map[b].x]; all descriptors share the launch configuration l.

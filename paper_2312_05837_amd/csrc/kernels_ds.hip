@@ -166,25 +166,30 @@ __device__ inline double dasin(double x) { return asin(x); }
 using GlobalU32 = __attribute__((address_space(1))) uint32_t;
 using U32x4 = uint32_t __attribute__((ext_vector_type(4)));
 using GlobalU32x4 = __attribute__((address_space(1))) U32x4;
-// a fixed-width row record: three 32-bit words, 12 bytes apart (a 3-element vector type would
-// occupy 16 bytes)
-struct Rec3 {
-    uint32_t w[3];
-};
-// record idx of an array of Rec3 at base (global memory; the three loads merge into one)
-__device__ __forceinline__ Rec3 load_rec3(uintptr_t base, size_t idx) {
-    const GlobalU32 *p = (const GlobalU32 *)(base + idx * sizeof(Rec3));
-    Rec3 r;
-    r.w[0] = p[0];
-    r.w[1] = p[1];
-    r.w[2] = p[2];
-    return r;
+using GlobalF32 = __attribute__((address_space(1))) float;
+using LdsU8 = __attribute__((address_space(3))) uint8_t;
+using LdsI8 = __attribute__((address_space(3))) const int8_t;
+using LdsU16 = __attribute__((address_space(3))) uint16_t;
+// Bytes per parity of the fixed-width-row form's vertex buffer: a signed byte per position and
+// copy (+-1 and its negation) for ept * block positions and the zero pair, rounded to 16.
+__host__ __device__ constexpr int twin_stride(int ept, int block) { return (2 * (ept * block + 1) + 15) / 16 * 16; }
+// The fixed-width-row form's vertex buffers: a static LDS array per kernel.  Its address is fixed
+// when the kernel is compiled, so a read at (row entry + parity offset) or (own position + offset)
+// carries the constant part as the instruction's immediate offset instead of an add per access.
+template <int BYTES>
+__device__ __forceinline__ unsigned char *twin_lds() {
+    __shared__ __align__(16) unsigned char buf[BYTES];
+    return buf;
 }
-
 // a compile-time flag passed to a generic lambda
 template <bool B>
 struct Flag {
     static constexpr bool value = B;
+};
+// a compile-time integer passed to a generic lambda
+template <int V>
+struct IntC {
+    static constexpr int value = V;
 };
 
 // fused multiply-add in the state precision (the plain builtin takes and returns double)
@@ -223,7 +228,8 @@ __device__ __forceinline__ Real angle_step(Real th, Real &mo, Real &ve, Real g, 
 // m' = b1 m + (1 - b1) g  <=>  mo' = b1 mo + g, and likewise for v with g^2; the update
 // lr m_hat / (sqrt(v_hat) + eps) is then (mo a1) / (sqrt(ve a2) + eps) with a1 = lr (1 - b1) / (1 - b1^t)
 // and a2 = (1 - b2) / (1 - b2^t) per step.  The moments are scaled when they are read and unscaled
-// when they are written back, so the state holds m and v as in every other form.
+// when they are written back, so the state holds m and v as in every other form.  The angle is
+// returned unwrapped: wrap_angle below is the wrap.
 template <typename Real>
 __device__ __forceinline__ Real angle_step_scaled(Real th, Real &mo, Real &ve, Real g, bool adam, Real b1, Real b2,
                                                   Real a1, Real lr, Real a2, Real eps) {
@@ -240,11 +246,17 @@ __device__ __forceinline__ Real angle_step_scaled(Real th, Real &mo, Real &ve, R
             mo = dfma(b1, mo, g);
             ve = dfma(b2, ve, g * g);
         }
-        upd = (mo * a1) * drcp(dsqrt(ve * a2) + eps);
-    } else {
-        upd = lr * g;
+        // th - a1 mo / (sqrt(ve a2) + eps), the last product and the difference in one FMA
+        const Real q = mo * drcp(dsqrt(ve * a2) + eps);
+        return dfma(-q, a1, th);
     }
-    Real tn = th - upd;
+    return dfma(-g, lr, th);
+}
+
+// theta - 2 pi rint(theta / 2 pi) with 2 pi in two parts; the identity for |theta| < 3, where the
+// quotient rounds to 0
+template <typename Real>
+__device__ __forceinline__ Real wrap_angle(Real tn) {
     const Real q = drint(tn * Consts<Real>::inv_twopi);
     tn = dfma(-q, Consts<Real>::twopi_hi, tn);
     return dfma(-q, Consts<Real>::twopi_lo, tn);
@@ -451,13 +463,20 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     // Vertex buffers, double-buffered by step parity.  CK_PMS: each parity holds
     // a region of words (position q of the thread layout) and a region of their
     // per-replica complements, a.pms_rb bytes each, with a zero word at position
-    // EPT*B for padded slots.  CK_PME: per parity, each spin's word and its complement side by
-    // side (byte 2 i + c), so that a row entry 2 col + (J < 0) reads the neighbour's term of the
-    // count directly; entry 2 n is kept zero.  Other couplings: npad words per parity, indexed
-    // by spin, word n kept zero.
+    // EPT*B for padded slots.  CK_PME: per parity (TWS bytes), each spin's sign s as a signed
+    // byte and its negation side by side (bytes 2 i, 2 i + 1), so that a row entry
+    // 2 col + (J < 0) reads the neighbour's term sgn(J) s_col directly; the pair at position
+    // EPT LB is kept zero for unused entries.  Other couplings: npad words per parity, indexed by
+    // spin, word n kept zero.
     constexpr bool TWIN = CK == CK_PME;
+    // The fixed-width-row form runs with B = launch_bound(EPT) (checked at launch), so its
+    // positions e LB + tid and the parity stride of its vertex buffer are compile-time constants
+    // and its LDS reads and writes take them as immediate offsets.
+    constexpr int LB = launch_bound(EPT);
+    constexpr int TWS = twin_stride(EPT, LB);
     const int npad = EPT * B + 1;
-    const size_t vbytes = is_pms(CK) ? (size_t)4 * a.pms_rb : (size_t)2 * npad * sizeof(SW) * (TWIN ? 2 : 1);
+    // (the fixed-width-row form's vertex buffers are static, outside the dynamic LDS)
+    const size_t vbytes = is_pms(CK) ? (size_t)4 * a.pms_rb : TWIN ? 0 : (size_t)2 * npad * sizeof(SW);
     SW *sbuf = (SW *)smem;
     const size_t off = (vbytes + 15) & ~(size_t)15;
     Real *ep = (Real *)(smem + off);      // [2][NW][RG]
@@ -475,7 +494,10 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     Real *xb = (Real *)(smem + x_off);
     const size_t xpar = is_pms(CK) ? (size_t)2 * XS * a.pms_rb : (size_t)npad * RG * sizeof(Real);  // bytes per parity
     // convergence test: per wavefront, the window of losses [kConvWindowMax][RG] and L_1 [RG]
-    const bool conv = a.conv_tol > 0;
+    // (the fixed-width-row form without the loss runs neither the test nor a loss trace; its
+    // launch checks that)
+    constexpr bool NOLOSS = CK == CK_PME && !LOSS;
+    const bool conv = !NOLOSS && a.conv_tol > 0;
     const size_t tail = relaxed ? x_off + 2 * xpar : (is_pms(CK) ? img_off + (size_t)8 * a.pimg_groups : img_off);
     Real *cring = (Real *)(smem + ((tail + 15) & ~(size_t)15)) + (size_t)wave * (kConvWindowMax + 1) * RG;
     int prow_r[is_pms(CK) ? EPT : 1];
@@ -496,10 +518,27 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         if constexpr (is_pms(CK)) return row_r[e];
         else return e * B + tid;
     };
+    // Fixed-width-row form: twb, the LDS address of its buffers (parity par at twb + par TWS);
+    // tw0, tw1 the lane's own pair (2 tid) from twb and from twb + 32768, kept opaque so that
+    // each access to position e takes the base whose immediate offset stays below 2^16.
+    uint32_t twb = 0, tw0 = 0, tw1 = 0;
+    if constexpr (TWIN) {
+        twb = (uint32_t)(size_t)(LdsU8 *)twin_lds<2 * TWS>();
+        tw0 = twb + 2 * tid;
+        tw1 = tw0 + 32768;
+        asm volatile("" : "+v"(tw0), "+v"(tw1));
+    }
+    // the lane's pair of position e in parity par (compile-time constants in the step, where the
+    // choice of base folds away; either base gives the same address)
+    auto tw_pos = [&](int par, int e) -> uint32_t {
+        const int off = par * TWS + 2 * e * LB;
+        return off < 65536 ? tw0 + off : tw1 + (off - 32768);
+    };
     // vertex buffer of parity par, as the coupling reads it
     auto vbuf = [&](int par) -> SW * {
         if constexpr (is_pms(CK)) return (SW *)(smem + (size_t)par * 2 * a.pms_rb);
-        else return sbuf + par * npad * (TWIN ? 2 : 1);
+        else if constexpr (TWIN) return (SW *)nullptr;  // addressed through tw_pos and twb
+        else return sbuf + par * npad;
     };
     auto put = [&](int par, int e, SW word) {
         SW *S = vbuf(par);
@@ -508,7 +547,9 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
             ((SW *)((unsigned char *)S + a.pms_rb))[e * B + tid] = (SW)(word ^ (SW)SWd::ones);
         } else if constexpr (TWIN) {
             static_assert(sizeof(SW) == 1, "one byte per spin and copy");
-            ((uint16_t *)S)[e * B + tid] = (uint16_t)((uint32_t)word | ((uint32_t)(word ^ (SW)SWd::ones) << 8));
+            (void)S;
+            // word 1 (s = -1): bytes -1, +1; word 0 (s = +1): bytes +1, -1
+            *(LdsU16 *)(size_t)tw_pos(par, e) = word ? (uint16_t)0x01FFu : (uint16_t)0xFF01u;
         } else {
             S[e * B + tid] = word;
         }
@@ -530,8 +571,8 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
             vbuf(0)[EPT * B] = 0;
             vbuf(1)[EPT * B] = 0;
         } else if constexpr (TWIN) {
-            ((uint16_t *)vbuf(0))[n] = 0;
-            ((uint16_t *)vbuf(1))[n] = 0;
+            *(LdsU16 *)(size_t)(twb + 2 * EPT * LB) = 0;
+            *(LdsU16 *)(size_t)(twb + TWS + 2 * EPT * LB) = 0;
         } else {
             sbuf[n] = 0;
             sbuf[npad + n] = 0;
@@ -600,7 +641,8 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     if (tid < 2) flg[tid] = 0;
     double ebest = INFINITY;
     int bstep = 0;
-    if (wave == 0 && lane < RG && a.init_mode == 0) {
+    // (the fixed-width-row form scores the vertices in every wavefront)
+    if ((TWIN || wave == 0) && lane < RG && a.init_mode == 0) {
         ebest = a.e_best[r0 + lane];
         bstep = a.best_step[r0 + lane];
     }
@@ -609,7 +651,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     const Real lr = (Real)a.lr, mu = (Real)a.mu, b1 = (Real)a.b1, b2 = (Real)a.b2, eps = (Real)a.eps;
     const Real omb1 = (Real)(1.0 - a.b1), omb2 = (Real)(1.0 - a.b2);
     const Real *bct = (const Real *)a.bias;  // 1/(1-b1^t), 1/(1-b2^t) for this launch's steps
-    const bool trace_l = a.ltrace != nullptr;
+    const bool trace_l = !NOLOSS && a.ltrace != nullptr;
     uint32_t done = 0;          // replicas that have stopped (identical in every wavefront)
     int conv_t = 0;             // wave 0, lane r < RG: step at which replica r stopped
     int tlast = a.steps;        // last step run
@@ -628,8 +670,26 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         }
     }
 
-    for (int t = 1; t <= a.steps; ++t) {
-        const SW *sc = vbuf((t - 1) & 1);
+    // Fixed-width-row form: the vertex is not kept as bits in registers; when a vertex scores
+    // best, each lane copies its signs from the parity that holds it (its own positions, which
+    // only it writes) before the step that overwrites them.
+    bool twimp = false;  // the vertex scored in the last step is the best so far
+    auto tw_keep = [&](int par) __attribute__((always_inline)) {
+        uint32_t b = 0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) b |= (*(LdsI8 *)(size_t)tw_pos(par, e) < 0 ? 1u : 0u) << e;
+        best = b;
+    };
+    // One step t (read parity (t - 1) & 1); returns true when every replica has stopped.
+    auto step = [&](auto PC, const int t) __attribute__((always_inline)) -> bool {
+        // read parity: compile-time for the fixed-width-row form (RP = 0 at odd t, 1 at even t)
+        constexpr int RPc = decltype(PC)::value;
+        const int rpar = RPc >= 0 ? RPc : ((t - 1) & 1);
+        const SW *sc = vbuf(rpar);
+        if constexpr (TWIN) {
+            // the vertex scored in the previous step, s^(t-2), is still in the write parity
+            if (twimp) tw_keep(1 - RPc);
+        }
         const Real ib1 = adam ? bct[2 * (t - 1)] : (Real)1, ib2 = adam ? bct[2 * (t - 1) + 1] : (Real)1;
         const Real lib1 = lr * ib1;
         const Real sa1 = lib1 * omb1, sa2 = ib2 * omb2;  // the scaled-moment form's factors
@@ -643,64 +703,55 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         constexpr bool WIDE_ELL = CK == CK_PME;
         constexpr int ELL_AHEAD = EPT >= 28 ? 2 : 4;  // the widest variants leave little register room
         constexpr bool use_ell = WIDE_ELL;
-        // a spin's record is contiguous: one 12-byte load per lane, coalesced over the wave (a
-        // record with an unused word let that word's register be reused while its load was in
-        // flight, which made every spin wait for the load issued ahead of it)
-        static_assert(kEllWidth == 4 && kEllWords == 3 && sizeof(Rec3) == 12, "four 16-bit entries and the base in 12 bytes");
-        Rec3 nbw[WIDE_ELL ? EPT : 1];
-        // the neighbour bytes of each spin's count, read from LDS at its update (reading them a
-        // spin ahead measured slower: the extra live registers forced waits on the row loads)
-        uint32_t nb8[WIDE_ELL ? EPT : 1][4];
-        uint32_t nbase[WIDE_ELL ? EPT : 1];
-        auto read_nb = [&](int e) __attribute__((always_inline)) {
-            if constexpr (WIDE_ELL) {
-                const Rec3 rw = nbw[e];
-                nb8[e][0] = sc[rw.w[0] & 0xffffu];
-                nb8[e][1] = sc[rw.w[0] >> 16];
-                nb8[e][2] = sc[rw.w[1] & 0xffffu];
-                nb8[e][3] = sc[rw.w[1] >> 16];
-                nbase[e] = rw.w[2];
-            }
-        };
+        // a spin's record is contiguous: its four entries in one 16-byte load per lane, coalesced
+        // over the wave (every word used: a record with an unused word let that word's register be
+        // reused while its load was in flight, which made every spin wait for the load issued
+        // ahead of it); the field (or 0) of each position in a separate array, loaded with it
+        static_assert(kEllWidth == 4, "one 16-byte record per spin");
+        U32x4 nbw[WIDE_ELL ? EPT : 1];
+        Real hpre[WIDE_ELL ? EPT : 1];
         uintptr_t ellp = (uintptr_t)a.ell;
+        uintptr_t ellh = (uintptr_t)a.ellh;
         if constexpr (WIDE_ELL) {
-            asm volatile("" : "+s"(ellp));
+            asm volatile("" : "+s"(ellp), "+s"(ellh));
             if (use_ell)
 #pragma unroll
-                for (int e = 0; e < ELL_AHEAD && e < EPT; ++e) nbw[e] = load_rec3(ellp, (size_t)e * B + tid);
+                for (int e = 0; e < ELL_AHEAD && e < EPT; ++e) {
+                    nbw[e] = ((const GlobalU32x4 *)(ellp + (size_t)e * LB * 16))[tid];
+                    hpre[e] = ((const GlobalF32 *)(ellh + (size_t)e * LB * 4))[tid];
+                }
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             if constexpr (WIDE_ELL) {
-                if (use_ell && e + ELL_AHEAD < EPT)  // a uniform base per spin plus the lane's offset
-                    nbw[e + ELL_AHEAD] = load_rec3(ellp + (size_t)(e + ELL_AHEAD) * B * sizeof(Rec3), tid);
+                if (use_ell && e + ELL_AHEAD < EPT) {  // a uniform base per spin plus the lane's offset
+                    nbw[e + ELL_AHEAD] = ((const GlobalU32x4 *)(ellp + (size_t)(e + ELL_AHEAD) * LB * 16))[tid];
+                    hpre[e + ELL_AHEAD] = ((const GlobalF32 *)(ellh + (size_t)(e + ELL_AHEAD) * LB * 4))[tid];
+                }
             }
             if constexpr (WIDE_ELL) {
-                // positions e B .. e B + B - 1: a scalar test first (all in range for every e but
+                // positions e LB .. e LB + LB - 1: a scalar test first (all in range for every e but
                 // the last ones), the per-lane test only where the range ends; the limit is made
                 // opaque per step so that the per-lane masks are not all kept across the step loop
-                int lim = n - e * B;
+                int lim = n - e * LB;
                 asm volatile("" : "+s"(lim));
-                if (lim < B && tid >= lim) continue;
+                if (lim < LB && tid >= lim) continue;
             } else {
                 if (e * B + tid >= n) continue;
             }
             // (the fixed-width-row form needs no spin index: its rows and vertex are by position)
-            const int i = WIDE_ELL ? e * B + tid : local_index<EPT>(spin_of(e));
+            const int i = WIDE_ELL ? e * LB + tid : local_index<EPT>(spin_of(e));
             Real y[RG];
             if constexpr (is_pms(CK)) {
                 coupling<Real, CK, RG>(a, i, sc, y, img, prow_r[e], pcnt_r[e]);
             } else if constexpr (WIDE_ELL) {
-                // one replica per workgroup: a byte per spin and copy (the vertex or its complement)
-                read_nb(e);
-                const uint32_t cnt = nb8[e][0] + nb8[e][1] + nb8[e][2] + nb8[e][3];
-                // y = w (deg - 2 count) + h = base - 2 w count (exact for integer w and h).  (The
-                // base word is copied out of the vector first: a bit cast applied to a vector
-                // element directly has been compiled as a cast of element 0.)
-                const uint32_t base_bits = nbase[e];
+                // one replica per workgroup: the neighbours' terms sgn(J) s as signed bytes, read
+                // at immediate offsets of the read parity's buffer; y = w sum + h
+                const uint32_t sb = twb + RPc * TWS;
+                const int sum = (int)*(LdsI8 *)(size_t)(sb + nbw[e][0]) + (int)*(LdsI8 *)(size_t)(sb + nbw[e][1]) +
+                                (int)*(LdsI8 *)(size_t)(sb + nbw[e][2]) + (int)*(LdsI8 *)(size_t)(sb + nbw[e][3]);
 #pragma unroll
-                for (int r = 0; r < RG; ++r)
-                    y[r] = dfma((Real)(-2.0 * a.w), (Real)(int)cnt, (Real)__builtin_bit_cast(float, base_bits));
+                for (int r = 0; r < RG; ++r) y[r] = dfma((Real)a.w, (Real)sum, hpre[e]);
             } else {
                 coupling<Real, CK, RG>(a, i, sc, y);
             }
@@ -724,11 +775,9 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 Real x = 0, c;
                 Real sg;
                 if constexpr (WIDE_ELL) {
-                    // the fixed-width-row form: the vertex sign is bit k of cur (read through an
-                    // opaque copy, so that no spin's sign is computed ahead of its update);
-                    // cos(theta) drives the update, sin(theta) only the loss (LOSS)
-                    const uint32_t cb = cur;
-                    sg = (Real)__builtin_bit_cast(float, 0x3f800000u | ((cb << (31 - k)) & 0x80000000u));
+                    // the fixed-width-row form: the vertex sign is the lane's own byte of the read
+                    // parity; cos(theta) drives the update, sin(theta) only the loss (LOSS)
+                    sg = (Real)(int)*(LdsI8 *)(size_t)tw_pos(RPc, e);
                     c = wrapped_cos(th[k]);
                     if constexpr (LOSS) {
                         Real cunused;
@@ -764,11 +813,23 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 Real xn = x;  // a stopped replica keeps its angle, moments and vertex
                 bool xneg = WIDE_ELL ? sg < 0 : x < 0;
                 if (!decltype(check)::value || !((done >> r) & 1u)) {
-                    const Real tn = WIDE_ELL ? angle_step_scaled(th[k], mo[k], ve[k], c * tt, adam, b1, b2, sa1, lr, sa2, eps)
-                                             : angle_step(th[k], mo[k], ve[k], c * tt, adam, b1, omb1, b2, omb2, lib1, lr,
-                                                          ib2, eps);
+                    Real tn;
+                    if constexpr (WIDE_ELL) {
+                        tn = angle_step_scaled(th[k], mo[k], ve[k], c * tt, adam, b1, b2, sa1, lr, sa2, eps);
+                        // the wrap changes no angle below 3 in magnitude: it runs when some lane of
+                        // the wavefront has a larger one (a uniform branch), else the sign is tn's
+                        xneg = tn < (Real)0;
+                        if (__builtin_amdgcn_ballot_w64((tn < (Real)0 ? -tn : tn) >= (Real)3)) {
+                            tn = wrap_angle(tn);
+                            xneg = wrapped_sin_neg(tn);
+                        }
+                    } else {
+                        tn = angle_step(th[k], mo[k], ve[k], c * tt, adam, b1, omb1, b2, omb2, lib1, lr, ib2, eps);
+                    }
                     th[k] = tn;
-                    if (KEEP) {
+                    if constexpr (WIDE_ELL) {
+                        // (its sign is set above)
+                    } else if (KEEP) {
                         Real cn;
                         dsincos(tn, &xn, &cn);
                         xs[k] = xn;
@@ -782,11 +843,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     }
                 }
                 if constexpr (WIDE_ELL) {
-                    const uint32_t xb = xneg ? 1u : 0u;
-                    // nxt |= xb << k as one shift-or with the shift as an immediate (the compiler's
-                    // select of 0 / 1 << k keeps every such constant in a register)
-                    asm("v_lshl_or_b32 %0, %1, %2, %0" : "+v"(nxt) : "v"(xb), "i"(k));
-                    word = (SW)xb;
+                    word = xneg ? (SW)1 : (SW)0;
                 } else if (xneg) {
                     nxt |= 1u << k;
                     word |= (SW)(1u << SWd::shift(r));
@@ -802,7 +859,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 if (done) replicas(Flag<true>{});
                 else replicas(Flag<false>{});
             }
-            put(t & 1, e, word);
+            put(RPc >= 0 ? 1 - RPc : (t & 1), e, word);
             // keep the scheduler from interleaving elements: bounds live ranges
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -821,7 +878,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
             }
         }
         __syncthreads();
-        const uint32_t f = flg[(t - 1) & 1];
+        const uint32_t f = TWIN ? 0u : flg[(t - 1) & 1];
         if (f) {
 #pragma unroll
             for (int r = 0; r < RG; ++r) {
@@ -835,13 +892,30 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         }
         prv = cur;
         cur = nxt;
-        if (wave == 0) {
+        if (TWIN || wave == 0) {
             bool imp = false;
             if (lane < RG) {
                 Real Es = 0, Ls = 0;
-                for (int w = 0; w < NW; ++w) {
-                    Es += ep[((t & 1) * NW + w) * RG + lane];
-                    Ls += lp[((t & 1) * NW + w) * RG + lane];
+                if constexpr (TWIN) {
+                    // a fixed number of wavefronts (one replica): the partials load together, then
+                    // add in wavefront order as below
+                    constexpr int NWc = LB / 64;
+                    Real pe[NWc], pl[NWc];
+#pragma unroll
+                    for (int w = 0; w < NWc; ++w) {
+                        pe[w] = ep[(t & 1) * NWc + w];
+                        if constexpr (LOSS) pl[w] = lp[(t & 1) * NWc + w];
+                    }
+#pragma unroll
+                    for (int w = 0; w < NWc; ++w) {
+                        Es += pe[w];
+                        if constexpr (LOSS) Ls += pl[w];
+                    }
+                } else {
+                    for (int w = 0; w < NW; ++w) {
+                        Es += ep[((t & 1) * NW + w) * RG + lane];
+                        Ls += lp[((t & 1) * NW + w) * RG + lane];
+                    }
                 }
                 const double E = (double)Es, L = (double)Ls;
                 imp = E < ebest && !((done >> lane) & 1u);  // a stopped replica is no longer scored
@@ -849,11 +923,14 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                     ebest = E;
                     bstep = a.t0 + t;
                 }
-                if (a.etrace) a.etrace[(size_t)(t - 1) * a.R + r0 + lane] = E;
-                if (a.ltrace) a.ltrace[(size_t)(t - 1) * a.R + r0 + lane] = L;
+                if (wave == 0) {
+                    if (a.etrace) a.etrace[(size_t)(t - 1) * a.R + r0 + lane] = E;
+                    if (trace_l) a.ltrace[(size_t)(t - 1) * a.R + r0 + lane] = L;
+                }
             }
             const uint64_t bal = __ballot(imp);
-            if (lane == 0) flg[t & 1] = (uint32_t)bal;
+            if constexpr (TWIN) twimp = bal != 0;  // one replica per workgroup
+            else if (lane == 0) flg[t & 1] = (uint32_t)bal;
         }
         if (conv) {
             // every wavefront replays the test on the same loss (same order of summation as
@@ -880,9 +957,21 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
             done |= (uint32_t)__ballot(now);
             if (done == (1u << RG) - 1u) {  // every replica of this workgroup has stopped
                 tlast = t;
-                break;
+                return true;
             }
         }
+        return false;
+    };
+    if constexpr (TWIN) {
+        // two steps per iteration, each with its parity as a compile-time constant
+        for (int t = 1; t <= a.steps; t += 2) {
+            if (step(IntC<0>{}, t)) break;
+            if (t + 1 > a.steps) break;
+            if (step(IntC<1>{}, t + 1)) break;
+        }
+    } else {
+        for (int t = 1; t <= a.steps; ++t)
+            if (step(IntC<-1>{}, t)) break;
     }
     __syncthreads();
     if (a.conv_step && wave == 0 && lane < RG) a.conv_step[r0 + lane] = conv_t;
@@ -890,7 +979,10 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         Real *cs = (Real *)a.conv_state + (size_t)(r0 + lane) * (kConvWindowMax + 1);
         for (int q = 0; q <= kConvWindowMax; ++q) cs[q] = cring[q * RG + lane];
     }
-    if (tlast > 0) {
+    if constexpr (TWIN) {
+        // the vertex scored in the last step, s^(tlast-1), is in parity (tlast - 1) & 1
+        if (tlast > 0 && twimp) tw_keep((tlast - 1) & 1);
+    } else if (tlast > 0) {
         const uint32_t f = flg[tlast & 1];
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
@@ -1323,35 +1415,21 @@ __global__ void k_format(DevProblem p, int packed, uint32_t *pm, Real *val_out, 
     }
 }
 
-// Fixed-width neighbour rows for the wide engine, one 12-byte record per position q = e * block + t
-// (spin q): words 0 and 1 hold the entries 2 col + (J < 0) of its (at most four) neighbours, two
-// 16-bit entries per word (the neighbour's vertex byte or its complement; pads 2 n, a zero byte),
-// and word 2 the float base = w deg + h, so that y = w (deg - 2 count) + h = base - 2 w count is one
-// FMA (exact for integer w and h).  A field that is not an integer below 2^23 in magnitude sets
-// *bad (such rows must not be used).
-__global__ void k_ell_format(DevProblem p, const uint32_t *pm, const float *hf, double w, int ept, int block,
-                             uint32_t *ell, int32_t *bad) {
+// Fixed-width neighbour rows for the wide engine, one 16-byte record per position q = e * block + t
+// (spin q): its (at most four) entries 2 col + (J < 0), the byte of the neighbour's term sgn(J) s in
+// the vertex buffer; unused entries 2 ept block, the zero pair.  hrow[q]: the spin's field in FP32
+// (0 without one, and for q >= n).
+__global__ void k_ell_format(DevProblem p, const uint32_t *pm, const float *hf, int ept, int block, uint32_t *ell,
+                             float *hrow) {
     const int total = ept * block;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
         const int e = q / block, t = q % block;
         const int rs = q < p.n ? p.row_ptr[q] : 0, deg = q < p.n ? p.row_ptr[q + 1] - rs : 0;
-        double hk = 0.0;
-        if (hf && q < p.n) {
-            const float hv = hf[q];
-            if (!(hv == rintf(hv) && fabsf(hv) < 8388608.f)) {
-                atomicOr(bad, 1);
-            } else {
-                hk = (double)hv;
-            }
-        }
-        uint32_t ent[kEllWidth];
+        uint32_t *o = ell + ((size_t)e * block + t) * kEllWidth;
 #pragma unroll
         for (int j = 0; j < kEllWidth; ++j)
-            ent[j] = j < deg ? 2u * (pm[rs + j] & 0x7fffffffu) + (pm[rs + j] >> 31) : 2u * (uint32_t)p.n;
-        uint32_t *o = ell + ((size_t)e * block + t) * kEllWords;
-        o[0] = ent[0] | (ent[1] << 16);
-        o[1] = ent[2] | (ent[3] << 16);
-        o[2] = __float_as_uint((float)(w * (double)deg + hk));
+            o[j] = j < deg ? 2u * (pm[rs + j] & 0x7fffffffu) + (pm[rs + j] >> 31) : 2u * (uint32_t)total;
+        hrow[(size_t)e * block + t] = hf && q < p.n ? hf[q] : 0.f;
     }
 }
 
@@ -1675,14 +1753,12 @@ int32_t ds_max_n(bool fp64) {
     return 48 * 1024;
 }
 
-hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, double w, int ept,
-                             int block, uint32_t *ell, int32_t *bad, hipStream_t s) {
-    // entries 2 col + 1 < 2^16 in 16 bits
-    if (p.format != ISING_CSR || ept <= 0 || block <= 0 || (int64_t)ept * block < p.n || !bad || p.n >= 32768)
+hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, int ept, int block,
+                             uint32_t *ell, float *hrow, hipStream_t s) {
+    if (p.format != ISING_CSR || ept <= 0 || block != launch_bound(ept) || (int64_t)ept * block < p.n)
         return hipErrorInvalidValue;
     const int total = ept * block;
-    hipLaunchKernelGGL(k_ell_format, dim3((total + 255) / 256), dim3(256), 0, s, p, pm, hf, w, ept, block, ell,
-                       bad);
+    hipLaunchKernelGGL(k_ell_format, dim3((total + 255) / 256), dim3(256), 0, s, p, pm, hf, ept, block, ell, hrow);
     return hipGetLastError();
 }
 
@@ -1710,6 +1786,8 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s, std::str
     if (l.block % 64 || l.block < 64 || l.block > ds_block_limit(l.ept) || (l.ept > 0 && (int64_t)l.ept * l.block < a.n) ||
         a.R % l.rg)
         return hipErrorInvalidValue;
+    if (ck == CK_PME && (l.block != launch_bound(l.ept) || !a.ellh))  // its positions assume B = launch_bound
+        return hipErrorInvalidValue;
     if (l.coupling == CK_PMS && a.pms_rb != pms_region_bytes(l)) return hipErrorInvalidValue;
     if ((a.loss == ISING_LOSS_RELAXED) != l.relaxed || (l.relaxed && l.ept <= 0))
         return hipErrorInvalidValue;
@@ -1729,7 +1807,8 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s, std::str
         }
     }
     const size_t lds = ds_lds_bytes(l, a.n, a.pimg_groups, ck == CK_PME);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const size_t lds_static = ck == CK_PME ? (size_t)2 * twin_stride(l.ept, l.block) : 0;
+    if (lds + lds_static > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -1821,7 +1900,8 @@ size_t ds_lds_bytes(const DSLaunch &l, int n, int pimg_groups, bool twin) {
     const int nw = l.block / 64;
     size_t sbytes;
     if (l.coupling == CK_PMS) sbytes = (size_t)4 * pms_region_bytes(l);
-    else sbytes = l.ept > 0 ? (size_t)2 * (l.ept * l.block + 1) * sw * (twin ? 2 : 1) : (size_t)3 * n * sw;
+    else if (twin) sbytes = 0;  // static: twin_lds, 2 twin_stride(ept, block) bytes
+    else sbytes = l.ept > 0 ? (size_t)2 * (l.ept * l.block + 1) * sw : (size_t)3 * n * sw;
     size_t lds = ((sbytes + 15) & ~(size_t)15) + 2 * 2 * nw * l.rg * real + 8;
     if (l.coupling == CK_PMS) lds = ((lds + 15) & ~(size_t)15) + (size_t)8 * pimg_groups;
     if (l.relaxed) {
