@@ -470,9 +470,9 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
         if (form == DF_BF16X2) HIP_TRY(ctx, pool.get("dn.Jlo", mk * 2, &Jlo));
     }
     if (p.h) HIP_TRY(ctx, pool.get("dn.h", (size_t)n * 4, &hf));
-    HIP_TRY(ctx, pool.get("dn.S", (size_t)2 * R * d.Kp * (form == DF_FP32 ? 4 : form == DF_FP8 ? 1 : 2), &S));
-    HIP_TRY(ctx, pool.get("dn.Ep", (size_t)(d.Mp / 128) * R * 4, &Ep));
-    HIP_TRY(ctx, pool.get("dn.Lp", (size_t)(d.Mp / 128) * R * 4, &Lp));
+    HIP_TRY(ctx, pool.get("dn.S", (size_t)kDenseVertexBufs * R * d.Kp * (form == DF_FP32 ? 4 : form == DF_FP8 ? 1 : 2), &S));
+    HIP_TRY(ctx, pool.get("dn.Ep", (size_t)2 * (d.Mp / 128) * R * 4, &Ep));
+    HIP_TRY(ctx, pool.get("dn.Lp", (size_t)2 * (d.Mp / 128) * R * 4, &Lp));
     HIP_TRY(ctx, launch_dense_prepare(to_dev(p), form, d.Mp, d.Kp, Jhi, Jlo, Jf, (float *)hf, s));
     d.Jhi = Jhi;
     d.Jlo = Jlo;

@@ -200,6 +200,9 @@ hipError_t launch_gather_row(const int8_t *block, int32_t n, const int32_t *best
 // ---- domain selection for dense couplings on MFMA (kernels_dense.hip) --------
 enum DenseForm { DF_FP32 = 0, DF_BF16X2 = 1, DF_BF16 = 2, DF_FP8 = 3 };
 
+// Vertex buffers of the matrix-core engine: step t reads buffer (t - 1) % 3 and writes t % 3, so
+// the vertex scored in step t - 1 stays intact while step t's tiles keep its best-vertex record.
+constexpr int kDenseVertexBufs = 3;
 struct DenseRun {
     int n = 0, R = 0, Mp = 0, Kp = 0, form = DF_BF16X2, opt = ISING_OPT_ADAM, t0 = 0, steps = 0, init_mode = 2;
     int reinit = 1;
@@ -209,9 +212,9 @@ struct DenseRun {
     const void *Jhi = nullptr, *Jlo = nullptr, *Jf = nullptr;
     const float *h = nullptr;
     const void *uniform = nullptr;
-    void *S = nullptr;  // two vertex buffers [R][Kp] (BF16 bits or FP32)
+    void *S = nullptr;  // kDenseVertexBufs vertex buffers [R][Kp] (FP32, BF16 bits or FP8 bytes)
     float *theta = nullptr, *m = nullptr, *v = nullptr;
-    float *Epart = nullptr, *Lpart = nullptr;  // [Mp / 128][R]
+    float *Epart = nullptr, *Lpart = nullptr;  // [2][Mp / 128][R], by step parity
     double *e_best = nullptr;
     int32_t *best_step = nullptr;
     int8_t *s_best = nullptr;
@@ -223,11 +226,12 @@ hipError_t launch_dense_prepare(const DevProblem &p, int form, int Mp, int Kp, v
                                 float *hf, hipStream_t s);
 // State initialisation (t0 = 0) or vertex re-derivation (t0 > 0) before a chunk.
 hipError_t launch_dense_init(const DenseRun &d, hipStream_t s);
-// Advance `count` problems of the same form by `steps` steps: two launches per
-// step for the whole group.  scratch: dense_group_scratch_bytes() of device memory.
+// Advance `count` problems of the same form by `steps` steps: one launch per step for the whole
+// group (each step's tiles also keep the previous step's best vertices) and one for the last
+// step's best vertices.  scratch: dense_group_scratch_bytes() of device memory.
 hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps, void *scratch, hipStream_t s);
 // The same in two parts, for callers that capture the kernels in a graph: the upload of the
-// group's descriptors and work lists to scratch (host-synchronous), and the 2 * steps kernel
+// group's descriptors and work lists to scratch (host-synchronous), and the steps + 1 kernel
 // launches alone (no copies or fills), which read everything per-problem from scratch.
 struct DenseGroupShape {
     int form = DF_BF16X2, descs = 0, tiles = 0, quads = 0;

@@ -6,9 +6,10 @@
 //   E_r partial += s (y + h),  L_r partial += sin(theta) (y - mu s + h),
 //   GD / ADAM update of theta, wrap, next vertex S~' = sgn(sin theta') written
 //   as the next step's B operand.
-// A small second kernel combines the per-row-tile energy partials in a fixed
-// order, keeps each replica's best energy and copies the vertex of an
-// improvement.
+// The per-row-tile energy partials of a step are combined in a fixed order, each
+// replica's best energy kept and the vertex of an improvement copied by the next
+// step's tiles (after their own epilogue; partials double-buffered by step parity,
+// vertices in three buffers), and for the last step by a small second kernel.
 //
 // Forms of the coupling product (the iterates are FP32 in all of them):
 //   DF_FP32   J and S~ in FP32, v_mfma_f32_32x32x2_f32
@@ -19,7 +20,8 @@
 //   DF_FP8    couplings of one integer magnitude w: J / w = -1, 0, +1 and the vertex
 //             exact in FP8 (E4M3), v_mfma_f32_32x32x64_f8f6f4, y = w (J / w) S~ exact
 // Tile: 128 spins x 128 replicas per workgroup of four wavefronts (2 x 2, each
-// 64 x 64 = 2 x 2 MFMA blocks of 32 x 32), K staged through LDS in chunks of 32.
+// 64 x 64 = 2 x 2 MFMA blocks of 32 x 32); the split form 128 x 256 on eight (2 x 4).
+// K staged through LDS in chunks of 64 BF16 / 128 FP8 values (32 FP32).
 // Operand layouts: J padded row-major [Mp][Kp]; S~ replica-major [R][Kp]
 // (each replica's spins contiguous), so both MFMA operands are K-contiguous.
 // State theta, m, v, s_best: replica-major [R][n].
@@ -46,6 +48,22 @@ constexpr int GEMM_LDS_BF16 = (BM + BN) * AST * 2;  // J hi (or J lo) and vertex
 constexpr int GEMM_LDS_FP32 = (BM + BN) * FST * 4;
 constexpr int EPI_LDS = 64 * TST * 4;
 constexpr int cmax(int x, int y) { return x > y ? x : y; }
+
+// Tile of one workgroup: BM spins by BN replicas on NT threads, wavefronts WM x WN of 64 x 64
+// each.  The split form moves twice the operand bytes of J per product, so its tiles are twice
+// as wide (256 replicas, 8 wavefronts, LDS double-buffered: one workgroup per CU): each staged
+// chunk of J then serves twice the replicas, which cuts the L2-to-CU operand traffic per product
+// by a third.
+template <int FORM>
+struct TileShape {
+    static constexpr bool WIDE = FORM == DF_BF16X2;
+    static constexpr int BN = WIDE ? 256 : 128;
+    static constexpr int NT = WIDE ? 512 : 256;
+    static constexpr int WN = BN / 64, WM = BM / 64;
+    static_assert(WM * WN * 64 == NT, "one 64 x 64 block per wavefront");
+};
+__host__ __device__ constexpr int tile_bn(int form) { return form == DF_BF16X2 ? 256 : 128; }
+__host__ __device__ constexpr int tile_threads(int form) { return form == DF_BF16X2 ? 512 : 256; }
 
 // sum of each 16-lane row of a wavefront (quads, then half rows, then rows), result in every lane
 __device__ inline float row_sum16(float v) {
@@ -149,8 +167,8 @@ __global__ void k_dense_split(DevProblem p, int Mp, int Kp, int form, unsigned s
 
 // theta_0 = asin(U), m = v = 0, S~_1 = sgn(sin theta_0) (padding zero), e_best = +inf
 __global__ void k_dense_init(int n, int R, int Kp, int form, int init_mode, uint64_t seed, const float *uniform,
-                             float *theta, float *m, float *v, void *S, void *S_other, double *e_best,
-                             int32_t *best_step, int8_t *s_best) {
+                             float *theta, float *m, float *v, void *S, void *S_other, void *S_third,
+                             double *e_best, int32_t *best_step, int8_t *s_best) {
     const int64_t total = (int64_t)R * Kp;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * blockDim.x) {
@@ -181,13 +199,16 @@ __global__ void k_dense_init(int n, int R, int Kp, int form, int init_mode, uint
         }
         if (form == DF_FP32) {
             ((float *)S)[q] = s;
-            ((float *)S_other)[q] = 0.f;  // the other buffer's padding must be zero too
+            ((float *)S_other)[q] = 0.f;  // the other buffers' padding must be zero too
+            ((float *)S_third)[q] = 0.f;
         } else if (form == DF_FP8) {
             ((unsigned char *)S)[q] = fp8_of(s);
             ((unsigned char *)S_other)[q] = 0;
+            ((unsigned char *)S_third)[q] = 0;
         } else {
             ((unsigned short *)S)[q] = bf16_bits(s);
             ((unsigned short *)S_other)[q] = 0;
+            ((unsigned short *)S_third)[q] = 0;
         }
     }
     if (init_mode != 0) {
@@ -220,9 +241,11 @@ struct DenseDescT {
     Ptr<const unsigned short> Jhi, Jlo;
     Ptr<const float> Jf;
     Ptr<const float> h;
-    Ptr<char> S0, S1;        // vertex buffers: S0 holds the chunk's first vertex
+    // vertex buffers: step tloc reads S[(tloc - 1) % 3] and writes S[tloc % 3] (S0 holds the
+    // chunk's first vertex), so the vertex scored in step tloc - 1 is intact through step tloc
+    Ptr<char> S0, S1, S2;
     Ptr<float> theta, m, v;
-    Ptr<float> Epart, Lpart;  // [mtiles][R]
+    Ptr<float> Epart, Lpart;  // [2][mtiles][R]: step tloc writes part tloc & 1
     Ptr<double> e_best;
     Ptr<int32_t> best_step;
     Ptr<int8_t> s_best;
@@ -233,12 +256,15 @@ using DenseDesc = DenseDescT<plain_ptr>;
 using DenseDescG = DenseDescT<global_ptr>;
 static_assert(sizeof(DenseDesc) == sizeof(DenseDescG), "descriptor layouts must agree");
 
-// One K chunk (64) of the BF16 operands held in registers: rows tid / 8 + 32 p (p = 0..3)
-// of the J tile (hi, and lo for the split form) and of the vertex tile, 8 bf16 at 16-byte
-// unit tid % 8.  Eight lanes read one row's 128-byte line of the chunk: the loads use whole
-// cache lines (half lines with a chunk of 32 limit the misses a CU's vector cache holds).
+// One K chunk (64) of the BF16 operands held in registers: rows tid / 8 + (NT / 8) p of the J
+// tile (hi, and lo for the split form; BM rows) and of the vertex tile (BN rows), 8 bf16 at
+// 16-byte unit tid % 8.  Eight lanes read one row's 128-byte line of the chunk: the loads use
+// whole cache lines (half lines with a chunk of 32 limit the misses a CU's vector cache holds).
+template <int FORM>
 struct BfStage {
-    u16x8 ah[4], al[4], b[4];
+    static constexpr int RS = TileShape<FORM>::NT / 8;  // rows per pass
+    static constexpr int NA = BM / RS, NB = TileShape<FORM>::BN / RS;
+    u16x8 ah[NA], al[NA], b[NB];
 };
 // Element offset of 16-byte unit u (8 bf16, u = 0..7) of row r in an LDS chunk.  The unit
 // index is XORed with (r ^ (r >> 3)) & 7, so that the MFMA fragment reads (one row per
@@ -246,50 +272,135 @@ struct BfStage {
 __device__ __forceinline__ int swz(int r, int u) { return r * AST + ((u ^ r ^ (r >> 3)) & 7) * 8; }
 
 template <int FORM>
-__device__ __forceinline__ BfStage bf_gload(const DenseDescG &a, const void *S_in, int row0, int col0, int k0, int tid) {
-    BfStage s;
+__device__ __forceinline__ BfStage<FORM> bf_gload(const DenseDescG &a, const void *S_in, int row0, int col0, int k0,
+                                                  int tid) {
+    using St = BfStage<FORM>;
+    St s;
     const int rr = tid >> 3, c8 = (tid & 7) * 8;
     const size_t kpu = FORM == DF_FP8 ? a.Kp >> 1 : a.Kp;  // row length in 2-byte units
     const unsigned short *Sb = (const unsigned short *)S_in;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const size_t ja = (size_t)(row0 + rr + 32 * p) * kpu + k0 + c8;
+    for (int p = 0; p < St::NA; ++p) {
+        const size_t ja = (size_t)(row0 + rr + St::RS * p) * kpu + k0 + c8;
         s.ah[p] = *(const u16x8 *)(a.Jhi + ja);
         s.al[p] = FORM == DF_BF16X2 ? *(const u16x8 *)(a.Jlo + ja) : u16x8{};
-        // replica rows past R read row R - 1 (no branch around the load); the stage store
-        // writes zeros for them
-        s.b[p] = *(const u16x8 *)(Sb + (size_t)min(col0 + rr + 32 * p, a.R - 1) * kpu + k0 + c8);
     }
+#pragma unroll
+    for (int p = 0; p < St::NB; ++p)  // replica rows past R read row R - 1 (no branch around the
+                                      // load); the stage store writes zeros for them
+        s.b[p] = *(const u16x8 *)(Sb + (size_t)min(col0 + rr + St::RS * p, a.R - 1) * kpu + k0 + c8);
     return s;
 }
 // the J part goes to Ah (hi) and Al (lo), the vertex part to Bs
 template <int FORM>
 __device__ __forceinline__ void bf_stage_store(unsigned short *Ah, unsigned short *Al, unsigned short *Bs,
-                                               const BfStage &s, int tid, int col0, int R) {
+                                               const BfStage<FORM> &s, int tid, int col0, int R) {
+    using St = BfStage<FORM>;
     const int rr = tid >> 3, u = tid & 7;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int o = swz(rr + 32 * p, u);
+    for (int p = 0; p < St::NA; ++p) {
+        const int o = swz(rr + St::RS * p, u);
         *(u16x8 *)(Ah + o) = s.ah[p];
         if (FORM == DF_BF16X2) *(u16x8 *)(Al + o) = s.al[p];
-        *(u16x8 *)(Bs + o) = col0 + rr + 32 * p < R ? s.b[p] : u16x8{};
+    }
+#pragma unroll
+    for (int p = 0; p < St::NB; ++p)
+        *(u16x8 *)(Bs + swz(rr + St::RS * p, u)) = col0 + rr + St::RS * p < R ? s.b[p] : u16x8{};
+}
+
+// vertex buffer k (0..2); the buffer addresses are selected as values (a select of the fields
+// themselves makes the compiler keep the whole descriptor in scratch memory)
+__device__ __forceinline__ char *vbuf(const DenseDescG &a, int k) {
+    const uintptr_t p0 = (uintptr_t)(char *)a.S0, p1 = (uintptr_t)(char *)a.S1, p2 = (uintptr_t)(char *)a.S2;
+    return (char *)(k == 0 ? p0 : k == 1 ? p1 : p2);
+}
+
+// Step tloc's energy of replica r from the row-tile partials (ascending tile order) and its
+// best-vertex update; one wavefront (lane = 0..63).
+__device__ __forceinline__ void best_of(const DenseDescG &a, const int tloc, const int r, const int lane, const int form) {
+    const size_t ppar = (size_t)(tloc & 1) * a.mtiles * a.R;
+    const void *S_t = (const void *)vbuf(a, (tloc - 1) % 3);
+    // row-tile partials loaded by the lanes together, summed in ascending tile order
+    float E = 0.f, L = 0.f;
+    for (int t0 = 0; t0 < a.mtiles; t0 += 64) {
+        const int t = t0 + lane;
+        const float ev = t < a.mtiles ? a.Epart[ppar + (size_t)t * a.R + r] : 0.f;
+        const float lv = (a.ltrace && t < a.mtiles) ? a.Lpart[ppar + (size_t)t * a.R + r] : 0.f;
+        const int m = min(64, a.mtiles - t0);
+        for (int j = 0; j < m; ++j) {
+            E += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, ev), j));
+            L += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lv), j));
+        }
+    }
+    const bool imp = (double)E < a.e_best[r];
+    if (imp) {
+        const size_t src = (size_t)r * a.Kp, dst = (size_t)r * a.n;
+        if ((a.n & 7) == 0) {
+            // 8 spins per lane and iteration: 16 (BF16) or 32 (FP32) bytes in, 8 bytes out
+            for (int i = 8 * lane; i < a.n; i += 512) {
+                float sv[8];
+                if (form == DF_FP32) {
+                    const float4 p0 = *(const float4 *)((const float *)S_t + src + i);
+                    const float4 p1 = *(const float4 *)((const float *)S_t + src + i + 4);
+                    sv[0] = p0.x; sv[1] = p0.y; sv[2] = p0.z; sv[3] = p0.w;
+                    sv[4] = p1.x; sv[5] = p1.y; sv[6] = p1.z; sv[7] = p1.w;
+                } else if (form == DF_FP8) {
+                    // the sign bit of an FP8 value is its top bit
+                    const uint2 p8 = *(const uint2 *)((const unsigned char *)S_t + src + i);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        sv[u] = (p8.x >> (8 * u + 7)) & 1 ? -1.f : 1.f;
+                        sv[u + 4] = (p8.y >> (8 * u + 7)) & 1 ? -1.f : 1.f;
+                    }
+                } else {
+                    const u16x8 p8 = *(const u16x8 *)((const unsigned short *)S_t + src + i);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) sv[u] = bf16_to_f(p8[u]);
+                }
+                uint32_t lo = 0, hi = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    lo |= (uint32_t)(uint8_t)(sv[u] < 0.f ? -1 : 1) << (8 * u);
+                    hi |= (uint32_t)(uint8_t)(sv[u + 4] < 0.f ? -1 : 1) << (8 * u);
+                }
+                *(uint2 *)(a.s_best + dst + i) = make_uint2(lo, hi);
+            }
+        } else {
+            for (int i = lane; i < a.n; i += 64) {
+                const float sv = form == DF_FP32  ? ((const float *)S_t)[src + i]
+                                 : form == DF_FP8 ? (((const unsigned char *)S_t)[src + i] & 0x80 ? -1.f : 1.f)
+                                                  : bf16_to_f(((const unsigned short *)S_t)[src + i]);
+                a.s_best[dst + i] = sv < 0.f ? (int8_t)-1 : (int8_t)1;
+            }
+        }
+    }
+    if (lane == 0) {
+        if (imp) {
+            a.e_best[r] = (double)E;
+            a.best_step[r] = a.t0 + tloc;
+        }
+        if (a.etrace) a.etrace[(size_t)(tloc - 1) * a.R + r] = (double)E;
+        if (a.ltrace) a.ltrace[(size_t)(tloc - 1) * a.R + r] = (double)L;
     }
 }
 
 template <int FORM>
 __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int tloc, const int mt, const int nt) {
+    using TS = TileShape<FORM>;
+    constexpr int TBN = TS::BN, NTH = TS::NT;
+    // split form: two buffers of J hi, vertex and J lo rows
     __shared__ __align__(16) unsigned char lds[cmax(FORM == DF_FP32    ? 2 * GEMM_LDS_FP32
-                                                    : FORM == DF_BF16X2 ? GEMM_LDS_BF16 + BM * AST * 2
+                                                    : FORM == DF_BF16X2 ? 2 * (2 * BM + TBN) * AST * 2
                                                                         : 2 * GEMM_LDS_BF16,
                                                     EPI_LDS)];
-    __shared__ float red_e[1][BN], red_l[1][BN];
+    __shared__ float red_e[1][TBN], red_l[1][TBN];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const void *S_in = (const void *)(((tloc - 1) & 1) ? a.S1 : a.S0);
-    void *S_out = (void *)(((tloc - 1) & 1) ? a.S0 : a.S1);
+    const int wm = wave / TS::WN, wn = wave % TS::WN;
+    const void *S_in = (const void *)vbuf(a, (tloc - 1) % 3);
+    void *S_out = (void *)vbuf(a, tloc % 3);
     const float ib1 = a.opt == ISING_OPT_ADAM ? a.bias[2 * (tloc - 1)] : 1.f;
     const float ib2 = a.opt == ISING_OPT_ADAM ? a.bias[2 * (tloc - 1) + 1] : 1.f;
-    const int row0 = mt * BM, col0 = nt * BN;
+    const int row0 = mt * BM, col0 = nt * TBN;
     f32x16 acc[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -343,24 +454,29 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
         }
     } else {
         // NST chunks in flight in registers (stages refilled in turn, NST chunks ahead), one
-        // LDS-only barrier per chunk with two LDS buffers (the BF16 form), or two barriers
-        // per chunk with one buffer (the split form, whose J hi and lo chunks leave no room
-        // for a second buffer at two workgroups per CU).  The global loads are issued
-        // unconditionally (the last chunk is re-read past the end) so that the wait for the
-        // oldest stage is a fixed count of outstanding loads.
-        constexpr int NST = FORM == DF_BF16 ? 3 : 2;  // register budget: two workgroups per CU
-        constexpr int NBUF = FORM == DF_BF16X2 ? 1 : 2;
-        constexpr int BUF = FORM == DF_BF16X2 ? (2 * BM + BN) * AST : (BM + BN) * AST;  // bf16 elements
+        // LDS-only barrier per chunk with two LDS buffers.  The global loads are issued
+        // unconditionally (the last chunk is re-read) so that the wait for the oldest stage is
+        // a fixed count of outstanding loads.
+        constexpr int NST = 2;  // register budget: two workgroups per CU (one for the split form's wide tile)
+        constexpr int BUF = FORM == DF_BF16X2 ? (2 * BM + TBN) * AST : (BM + TBN) * AST;  // bf16 elements
         // chunks of 128 bytes per row: 64 BF16 or 128 FP8 values of k
         const int nch = (FORM == DF_FP8 ? a.Kp >> 1 : a.Kp) / KCB, last = nch - 1;
-        BfStage s0 = bf_gload<FORM>(a, S_in, row0, col0, 0, tid);
-        BfStage s1 = bf_gload<FORM>(a, S_in, row0, col0, min(1, last) * KCB, tid);
-        BfStage s2;
+        BfStage<FORM> s0 = bf_gload<FORM>(a, S_in, row0, col0, 0, tid);
+        BfStage<FORM> s1 = bf_gload<FORM>(a, S_in, row0, col0, min(1, last) * KCB, tid);
+        BfStage<FORM> s2;
         if (NST == 3) s2 = bf_gload<FORM>(a, S_in, row0, col0, min(2, last) * KCB, tid);
-        auto mfma_chunk = [&](int c) {
-            const unsigned short *Ah = (const unsigned short *)lds + (NBUF == 2 ? (c & 1) * BUF : 0);
+        // Chunk c's products from LDS buffer c & 1.  The stage holding chunk c + 1 is written to
+        // the other buffer among the products (that buffer was last read by chunk c - 1, before
+        // the previous barrier; after the last chunk it is written with a re-read chunk that no
+        // one reads), so the LDS stores overlap the matrix cores instead of standing between two
+        // barriers.  BF16 forms: the fragments of k-step ks + 1 are read while the products of
+        // k-step ks run, and the scheduler is asked to interleave the stores with the products.
+        auto chunk = [&](const int c, BfStage<FORM> &next) {
+            const unsigned short *Ah = (const unsigned short *)lds + (c & 1) * BUF;
             const unsigned short *Bs = Ah + BM * AST;
-            const unsigned short *Al = Bs + BN * AST;
+            const unsigned short *Al = Bs + TBN * AST;
+            unsigned short *Nh = (unsigned short *)lds + ((c + 1) & 1) * BUF;
+            auto store = [&]() { bf_stage_store<FORM>(Nh, Nh + (BM + TBN) * AST, Nh + BM * AST, next, tid, col0, a.R); };
             if constexpr (FORM == DF_FP8) {
                 // 32 bytes (k 64 ks + 32 (l / 32) .. + 31) per lane and operand; both operands put
                 // the same k in the same lane slot, so the k order inside the instruction is immaterial
@@ -388,58 +504,85 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                         for (int bj = 0; bj < 2; ++bj)
                             acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[bi], bf[bj], acc[bi][bj],
                                                                                          0, 0, 0, 0, 0, 0);
+                    if (ks == 0) store();
                 }
             } else {
-#pragma unroll
-                for (int ks = 0; ks < KCB / 16; ++ks) {
-                    const int u = 2 * ks + (lane >> 5);
+                struct Frag {
                     bf16x8 ah[2], al[2], bv[2];
+                };
+                auto read = [&](int ks) {
+                    Frag f;
+                    const int u = 2 * ks + (lane >> 5);
 #pragma unroll
                     for (int bi = 0; bi < 2; ++bi) {
                         const int o = swz(wm * 64 + bi * 32 + (lane & 31), u);
-                        ah[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Ah + o));
-                        if (FORM == DF_BF16X2) al[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Al + o));
+                        f.ah[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Ah + o));
+                        if (FORM == DF_BF16X2) f.al[bi] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Al + o));
                     }
 #pragma unroll
                     for (int bj = 0; bj < 2; ++bj)
-                        bv[bj] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Bs + swz(wn * 64 + bj * 32 + (lane & 31), u)));
+                        f.bv[bj] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(Bs + swz(wn * 64 + bj * 32 + (lane & 31), u)));
+                    return f;
+                };
+                auto mfma = [&](const Frag &f) {
 #pragma unroll
                     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
                         for (int bj = 0; bj < 2; ++bj) {
                             if (FORM == DF_BF16X2)
-                                acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bv[bj], acc[bi][bj], 0, 0, 0);
-                            acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+                                acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.al[bi], f.bv[bj], acc[bi][bj], 0, 0, 0);
+                            acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[bi], f.bv[bj], acc[bi][bj], 0, 0, 0);
                         }
+                };
+                static_assert(KCB / 16 == 4, "four k-steps per chunk");
+                constexpr int NMF = FORM == DF_BF16X2 ? 8 : 4;  // products per k-step
+                constexpr int NWR = BfStage<FORM>::NA * (FORM == DF_BF16X2 ? 2 : 1) + BfStage<FORM>::NB;  // stores
+                Frag f0 = read(0);
+                Frag f1 = read(1);
+                store();
+                mfma(f0);
+                f0 = read(2);
+                mfma(f1);
+                f1 = read(3);
+                mfma(f0);
+                mfma(f1);
+                // order: the stores spread over the first two k-steps' products, each k-step's
+                // fragment reads ahead of its products
+#pragma unroll
+                for (int q = 0; q < 2 * NMF; ++q) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one product
+                    if (q < NWR) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // one LDS store
                 }
             }
         };
+        bf_stage_store<FORM>((unsigned short *)lds, (unsigned short *)lds + (BM + TBN) * AST,
+                             (unsigned short *)lds + BM * AST, s0, tid, col0, a.R);
+        s0 = bf_gload<FORM>(a, S_in, row0, col0, min(NST, last) * KCB, tid);
+        lds_barrier();
+        // iteration c stores the stage of chunk c + 1 and refills it with chunk c + 1 + NST
 #define DENSE_BF_CHUNK(C, ST)                                                                          \
     {                                                                                                  \
         const int c_ = (C);                                                                            \
-        unsigned short *Ah_ = (unsigned short *)lds + (NBUF == 2 ? (c_ & 1) * BUF : 0);              \
-        if (NBUF == 1 && c_ > 0) lds_barrier();                                                        \
-        bf_stage_store<FORM>(Ah_, Ah_ + (BM + BN) * AST, Ah_ + BM * AST, ST, tid, col0, a.R);          \
+        chunk(c_, ST);                                                                                 \
         __builtin_amdgcn_sched_barrier(0);                                                             \
-        ST = bf_gload<FORM>(a, S_in, row0, col0, min(c_ + NST, last) * KCB, tid);                     \
+        ST = bf_gload<FORM>(a, S_in, row0, col0, min(c_ + 1 + NST, last) * KCB, tid);                 \
         lds_barrier();                                                                                 \
-        mfma_chunk(c_);                                                                                \
     }
         int c = 0;
         if constexpr (NST == 3) {
             for (; c + 3 <= nch; c += 3) {
-                DENSE_BF_CHUNK(c, s0);
-                DENSE_BF_CHUNK(c + 1, s1);
-                DENSE_BF_CHUNK(c + 2, s2);
+                DENSE_BF_CHUNK(c, s1);
+                DENSE_BF_CHUNK(c + 1, s2);
+                DENSE_BF_CHUNK(c + 2, s0);
             }
-            if (c < nch) DENSE_BF_CHUNK(c, s0);
-            if (c + 1 < nch) DENSE_BF_CHUNK(c + 1, s1);
+            if (c < nch) DENSE_BF_CHUNK(c, s1);
+            if (c + 1 < nch) DENSE_BF_CHUNK(c + 1, s2);
         } else {
             for (; c + 2 <= nch; c += 2) {
-                DENSE_BF_CHUNK(c, s0);
-                DENSE_BF_CHUNK(c + 1, s1);
+                DENSE_BF_CHUNK(c, s1);
+                DENSE_BF_CHUNK(c + 1, s0);
             }
-            if (c < nch) DENSE_BF_CHUNK(c, s0);
+            if (c < nch) DENSE_BF_CHUNK(c, s1);
         }
 #undef DENSE_BF_CHUNK
     }
@@ -447,7 +590,7 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
 
     // ---- fused epilogue.  The accumulators (C block (bi, bj), lane l, element q hold
     // row 64 wm + 32 bi + 8 (q / 4) + 4 (l / 32) + q % 4, column 64 wn + 32 bj + l % 32) are
-    // transposed through LDS, one half of the replica columns at a time, so that each
+    // transposed through LDS, 64 replica columns (one wavefront column) at a time, so that each
     // thread then owns 4 consecutive spins of a replica: the state streams as float4
     // with 32 lanes covering 128 consecutive spins of one replica.
     const bool adam = a.opt == ISING_OPT_ADAM;
@@ -459,14 +602,21 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
     float h4[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) h4[u] = (a.h && i0 + u < a.n) ? a.h[i0 + u] : 0.f;
-    // The state of all 8 replicas a thread updates in one half is loaded at the start of
-    // that half (before the accumulators are transposed), so that its loads are in flight
-    // together: the epilogue is bound by this traffic.
-    float sth[8][4], smo[8][4], sve[8][4];
+    // The state of all KR replicas a thread updates in one part is loaded together (before the
+    // accumulators are transposed), so that its loads are in flight together: the epilogue is
+    // bound by this traffic.  Thread tid takes replicas tid / 32 + RSTEP k.  With 512 threads (KR
+    // = 4) the next part's state is loaded while the current part is updated, two buffers, so
+    // that as many loads stay in flight as with two 256-thread workgroups per CU.
+    constexpr int RSTEP = NTH / 32, KR = 64 / RSTEP;
+    constexpr int NSB = KR <= 4 ? 2 : 1;  // state buffers
+    float sth_[NSB][KR][4], smo_[NSB][KR][4], sve_[NSB][KR][4];
     auto load_half = [&](int half) {
+        float(&sth)[KR][4] = sth_[half % NSB];
+        float(&smo)[KR][4] = smo_[half % NSB];
+        float(&sve)[KR][4] = sve_[half % NSB];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int r = col0 + half * 64 + (tid >> 5) + 8 * k;
+        for (int k = 0; k < KR; ++k) {
+            const int r = col0 + half * 64 + (tid >> 5) + RSTEP * k;
 #pragma unroll
             for (int u = 0; u < 4; ++u) sth[k][u] = smo[k][u] = sve[k][u] = 0.f;
             if (r < a.R && i0 < a.n) {
@@ -492,9 +642,14 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             }
         }
     };
+    if (NSB == 2) load_half(0);
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        load_half(half);
+    for (int half = 0; half < TS::WN; ++half) {
+        if (NSB == 1) load_half(half);
+        else if (half + 1 < TS::WN) load_half(half + 1);
+        float(&sth)[KR][4] = sth_[half % NSB];
+        float(&smo)[KR][4] = smo_[half % NSB];
+        float(&sve)[KR][4] = sve_[half % NSB];
         if (wn == half) {
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj)
@@ -509,8 +664,8 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
         }
         lds_barrier();
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int rl = (tid >> 5) + 8 * k;        // replica within this half
+        for (int k = 0; k < KR; ++k) {
+            const int rl = (tid >> 5) + RSTEP * k;    // replica within this part
             const int r = col0 + half * 64 + rl;
             float th[4], mo[4], ve[4];
 #pragma unroll
@@ -601,7 +756,7 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             const float l_hi = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Lp), 47)) +
                                __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Lp), 63));
             if (lane == 0) {
-                const int rw = half * 64 + (wave * 2) + 8 * k;  // replica of lanes 0-31 (tid >> 5 = 2 wave)
+                const int rw = half * 64 + (wave * 2) + RSTEP * k;  // replica of lanes 0-31 (tid >> 5 = 2 wave)
                 red_e[0][rw] = e_lo;
                 red_e[0][rw + 1] = e_hi;
                 red_l[0][rw] = l_lo;
@@ -610,91 +765,38 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
         }
         lds_barrier();
     }
-    if (tid < BN && col0 + tid < a.R) {
-        a.Epart[(size_t)mt * a.R + col0 + tid] = red_e[0][tid];
-        if (a.Lpart) a.Lpart[(size_t)mt * a.R + col0 + tid] = red_l[0][tid];
+    const size_t ppar = (size_t)(tloc & 1) * a.mtiles * a.R;
+    if (tid < TBN && col0 + tid < a.R) {
+        a.Epart[ppar + (size_t)mt * a.R + col0 + tid] = red_e[0][tid];
+        if (a.Lpart) a.Lpart[ppar + (size_t)mt * a.R + col0 + tid] = red_l[0][tid];
+    }
+    // The previous step's best-vertex bookkeeping for this tile's share of its replica columns
+    // (its partials are complete: written by the previous launch), one wavefront per replica.
+    if (tloc > 1) {
+        const int share = (TBN + a.mtiles - 1) / a.mtiles;
+        const int rb = col0 + mt * share, re = min(min(col0 + TBN, a.R), rb + share);
+        for (int r = rb + wave; r < re; r += NTH / 64) best_of(a, tloc - 1, r, lane, FORM);
     }
 }
 
+// (two workgroups per CU for the 256-thread tiles: at most 256 registers per lane)
 template <int FORM>
-__global__ __launch_bounds__(256) void k_dense_step(const DenseDesc *__restrict__ descs,
+__global__ __launch_bounds__(TileShape<FORM>::NT, TileShape<FORM>::WIDE ? 1 : 2) void k_dense_step(
+    const DenseDesc *__restrict__ descs,
                                                     const int4 *__restrict__ tiles, int tloc) {
     const int4 t = tiles[blockIdx.x];  // (problem, row tile, replica tile)
     const DenseDescG a = ((const DenseDescG *)descs)[t.x];
     dense_step_body<FORM>(a, tloc, t.y, t.z);
 }
 
-// one wavefront per replica: E_t from the row-tile partials (ascending), best-vertex update
+// one wavefront per replica: the last step of a chunk (earlier steps are kept by the next step's
+// tiles)
 __global__ __launch_bounds__(256) void k_dense_best(const DenseDesc *__restrict__ descs,
                                                     const int2 *__restrict__ quads, int tloc, int form) {
     const int2 qd = quads[blockIdx.x];  // (problem, group of four replicas)
     const DenseDescG a = ((const DenseDescG *)descs)[qd.x];
-    const int lane = threadIdx.x & 63;
     const int r = qd.y * 4 + (threadIdx.x >> 6);
-    if (r >= a.R) return;
-    const void *S_t = (const void *)(((tloc - 1) & 1) ? a.S1 : a.S0);
-    // row-tile partials loaded by the lanes together, summed in ascending tile order
-    float E = 0.f, L = 0.f;
-    for (int t0 = 0; t0 < a.mtiles; t0 += 64) {
-        const int t = t0 + lane;
-        const float ev = t < a.mtiles ? a.Epart[(size_t)t * a.R + r] : 0.f;
-        const float lv = (a.ltrace && t < a.mtiles) ? a.Lpart[(size_t)t * a.R + r] : 0.f;
-        const int m = min(64, a.mtiles - t0);
-        for (int j = 0; j < m; ++j) {
-            E += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, ev), j));
-            L += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lv), j));
-        }
-    }
-    const bool imp = (double)E < a.e_best[r];
-    if (imp) {
-        const size_t src = (size_t)r * a.Kp, dst = (size_t)r * a.n;
-        if ((a.n & 7) == 0) {
-            // 8 spins per lane and iteration: 16 (BF16) or 32 (FP32) bytes in, 8 bytes out
-            for (int i = 8 * lane; i < a.n; i += 512) {
-                float sv[8];
-                if (form == DF_FP32) {
-                    const float4 p0 = *(const float4 *)((const float *)S_t + src + i);
-                    const float4 p1 = *(const float4 *)((const float *)S_t + src + i + 4);
-                    sv[0] = p0.x; sv[1] = p0.y; sv[2] = p0.z; sv[3] = p0.w;
-                    sv[4] = p1.x; sv[5] = p1.y; sv[6] = p1.z; sv[7] = p1.w;
-                } else if (form == DF_FP8) {
-                    // the sign bit of an FP8 value is its top bit
-                    const uint2 p8 = *(const uint2 *)((const unsigned char *)S_t + src + i);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        sv[u] = (p8.x >> (8 * u + 7)) & 1 ? -1.f : 1.f;
-                        sv[u + 4] = (p8.y >> (8 * u + 7)) & 1 ? -1.f : 1.f;
-                    }
-                } else {
-                    const u16x8 p8 = *(const u16x8 *)((const unsigned short *)S_t + src + i);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) sv[u] = bf16_to_f(p8[u]);
-                }
-                uint32_t lo = 0, hi = 0;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    lo |= (uint32_t)(uint8_t)(sv[u] < 0.f ? -1 : 1) << (8 * u);
-                    hi |= (uint32_t)(uint8_t)(sv[u + 4] < 0.f ? -1 : 1) << (8 * u);
-                }
-                *(uint2 *)(a.s_best + dst + i) = make_uint2(lo, hi);
-            }
-        } else {
-            for (int i = lane; i < a.n; i += 64) {
-                const float sv = form == DF_FP32  ? ((const float *)S_t)[src + i]
-                                 : form == DF_FP8 ? (((const unsigned char *)S_t)[src + i] & 0x80 ? -1.f : 1.f)
-                                                  : bf16_to_f(((const unsigned short *)S_t)[src + i]);
-                a.s_best[dst + i] = sv < 0.f ? (int8_t)-1 : (int8_t)1;
-            }
-        }
-    }
-    if (lane == 0) {
-        if (imp) {
-            a.e_best[r] = (double)E;
-            a.best_step[r] = a.t0 + tloc;
-        }
-        if (a.etrace) a.etrace[(size_t)(tloc - 1) * a.R + r] = (double)E;
-        if (a.ltrace) a.ltrace[(size_t)(tloc - 1) * a.R + r] = (double)L;
-    }
+    if (r < a.R) best_of(a, tloc, r, threadIdx.x & 63, form);
 }
 
 }  // namespace
@@ -741,6 +843,7 @@ static DenseDesc make_desc(const DenseRun &d) {
     a.jscale = d.form == DF_FP8 ? d.jscale : 1.f;
     a.S0 = (char *)d.S;
     a.S1 = (char *)d.S + (size_t)d.R * d.Kp * sbytes;
+    a.S2 = (char *)d.S + (size_t)2 * d.R * d.Kp * sbytes;
     a.theta = d.theta;
     a.m = d.m;
     a.v = d.v;
@@ -759,7 +862,7 @@ static size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 size_t dense_group_scratch_bytes(const DenseRun *const *runs, int count) {
     size_t tiles = 0, quads = 0;
     for (int k = 0; k < count; ++k) {
-        tiles += (size_t)(runs[k]->Mp / BM) * ((runs[k]->R + BN - 1) / BN);
+        tiles += (size_t)(runs[k]->Mp / BM) * ((runs[k]->R + tile_bn(runs[k]->form) - 1) / tile_bn(runs[k]->form));
         quads += (size_t)(runs[k]->R + 3) / 4;
     }
     return align16(count * sizeof(DenseDesc)) + tiles * sizeof(int4) + quads * sizeof(int2) + 64;
@@ -785,7 +888,7 @@ hipError_t dense_group_upload(const DenseRun *const *runs, int count, void *scra
             return hipErrorInvalidValue;
         if (d.opt == ISING_OPT_ADAM && !d.bias) return hipErrorInvalidValue;
         descs.push_back(make_desc(d));
-        const int MT = d.Mp / BM, NT = (d.R + BN - 1) / BN;
+        const int MT = d.Mp / BM, NT = (d.R + tile_bn(form) - 1) / tile_bn(form);
         for (int nt = 0; nt < NT; ++nt)
             for (int mt = 0; mt < MT; ++mt) {
                 const int x = (mt * kRowGroups / MT) * kColGroups + nt * kColGroups / NT;
@@ -830,12 +933,14 @@ hipError_t dense_group_launch(const DenseGroupShape &shape, void *scratch, int s
     const int4 *dt = (const int4 *)(p + align16((size_t)shape.descs * sizeof(DenseDesc)));
     const int2 *dq = (const int2 *)((const char *)dt + (size_t)shape.tiles * sizeof(int4));
     for (int t = 1; t <= steps; ++t) {
-        if (shape.form == DF_FP32) hipLaunchKernelGGL(k_dense_step<DF_FP32>, dim3(shape.tiles), dim3(256), 0, s, dd, dt, t);
-        else if (shape.form == DF_BF16X2) hipLaunchKernelGGL(k_dense_step<DF_BF16X2>, dim3(shape.tiles), dim3(256), 0, s, dd, dt, t);
-        else if (shape.form == DF_FP8) hipLaunchKernelGGL(k_dense_step<DF_FP8>, dim3(shape.tiles), dim3(256), 0, s, dd, dt, t);
-        else hipLaunchKernelGGL(k_dense_step<DF_BF16>, dim3(shape.tiles), dim3(256), 0, s, dd, dt, t);
-        hipLaunchKernelGGL(k_dense_best, dim3(shape.quads), dim3(256), 0, s, dd, dq, t, shape.form);
+        const dim3 blk(tile_threads(shape.form));
+        if (shape.form == DF_FP32) hipLaunchKernelGGL(k_dense_step<DF_FP32>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
+        else if (shape.form == DF_BF16X2) hipLaunchKernelGGL(k_dense_step<DF_BF16X2>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
+        else if (shape.form == DF_FP8) hipLaunchKernelGGL(k_dense_step<DF_FP8>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
+        else hipLaunchKernelGGL(k_dense_step<DF_BF16>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
     }
+    // the last step's best-vertex bookkeeping (earlier steps are kept inside the next step)
+    if (steps > 0) hipLaunchKernelGGL(k_dense_best, dim3(shape.quads), dim3(256), 0, s, dd, dq, steps, shape.form);
     return hipGetLastError();
 }
 
@@ -852,11 +957,12 @@ hipError_t launch_dense_init(const DenseRun &d, hipStream_t s) {
     const size_t sbytes = d.form == DF_FP32 ? 4 : d.form == DF_FP8 ? 1 : 2;
     char *S0 = (char *)d.S;
     char *S1 = S0 + (size_t)d.R * d.Kp * sbytes;
+    char *S2 = S1 + (size_t)d.R * d.Kp * sbytes;
     const int64_t total = (int64_t)d.R * d.Kp;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
     hipLaunchKernelGGL(k_dense_init, dim3(blocks), dim3(256), 0, s, d.n, d.R, d.Kp, d.form,
                        d.t0 == 0 ? d.init_mode : 0, d.seed, (const float *)d.uniform, d.theta, d.m, d.v,
-                       (void *)S0, (void *)S1, d.e_best, d.best_step, d.s_best);
+                       (void *)S0, (void *)S1, (void *)S2, d.e_best, d.best_step, d.s_best);
     return hipGetLastError();
 }
 

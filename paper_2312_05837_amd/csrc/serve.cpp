@@ -124,8 +124,8 @@ size_t footprint(const Request &q) {
         const size_t Mp = (n + 127) / 128 * 128, Kp = (n + 63) / 64 * 64;
         b += n * n * vs;                 // J
         b += Mp * Kp * 4;                // split or FP32 operand
-        b += 2 * R * Kp * 4;             // vertex buffers
-        b += (Mp / 128) * R * 8;         // energy partials
+        b += kDenseVertexBufs * R * Kp * 4;  // vertex buffers
+        b += 2 * (Mp / 128) * R * 8;     // energy partials, by step parity
     } else {
         b += (n + 1) * 4 + q.hp.nnz * (4 + vs);   // CSR
         b += q.hp.nnz * 8 + n * 24;               // device formats
