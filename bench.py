@@ -736,7 +736,8 @@ def main():
         if prec == "fp32" and inst.integer and len(np.unique(np.abs(inst.J[inst.J != 0]))) <= 1 \
                 and np.abs(inst.J).max() * nG < 2 ** 24:
             form = "fp8"
-        # one launch pair per step.  Matrix cores: 2 n^2 R flops.  HBM, algorithmic bytes: the
+        # one launch per step (each also keeps the previous step's best vertices; one more launch
+        # after the last step), timed together.  Matrix cores: 2 n^2 R flops.  HBM, algorithmic bytes: the
         # optimizer state read and written once (theta, m, v: 24 B; GD theta only: 8 B), the
         # vertex operand written once and read once, the stored couplings read once.
         # The bound is the one with the longer ideal time; the other is given beside it.
@@ -747,7 +748,8 @@ def main():
         mfma_frac = flops / per_step / MFMA_PEAK[form]
         hbm_frac = hbm_bytes / per_step / HBM_PEAK
         common = {"traffic": recorded_traffic("k_dense_step", args.workload),
-                  "kernel": "k_dense_step (MFMA product + fused update) and k_dense_best, per step",
+                  "kernel": "k_dense_step (MFMA product + fused update + the previous step's best vertices), "
+                            "per step, with the chunk's closing k_dense_best",
                   "kernel_ms": k_ms, "launch_us": per_step * 1e6, "flops_per_launch": flops,
                   "algorithmic_bytes_per_launch": hbm_bytes, "mfma_frac": mfma_frac, "hbm_frac": hbm_frac,
                   "mfma_peak_tflops": MFMA_PEAK[form] / 1e12, "form": form}
