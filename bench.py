@@ -155,6 +155,34 @@ def measured_copy_rate():
     return 2.0 * COPY_CALIBRATION_BYTES / (best * 1e-3)
 
 
+def measured_mfma_rate(form):
+    """FLOP/s of a plain library GEMM (torch.matmul: hipBLASLt / rocBLAS) with random operands of
+    the form's input type and FP32 accumulation, 8192^3, sustained over about half a second of
+    back-to-back products: the matrix cores' measured rate under load beside the nominal peak
+    (the clock drops under toggling operands).  None for forms torch has no plain GEMM for."""
+    import torch
+    dt = {"bf16x2": torch.bfloat16, "bf16": torch.bfloat16, "fp32": torch.float32}.get(form)
+    if dt is None:
+        return None
+    n = 8192
+    g = torch.Generator(device="cuda").manual_seed(0)
+    a = (torch.randn(n, n, device="cuda", generator=g) / n ** 0.5).to(dt)
+    b = torch.randn(n, n, device="cuda", generator=g).to(dt)
+    c = torch.matmul(a, b)
+    torch.cuda.synchronize()
+    reps = 300 if dt == torch.bfloat16 else 30
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.matmul(a, b, out=c)
+    e1.record()
+    e1.synchronize()
+    rate = 2.0 * n ** 3 * reps / (e0.elapsed_time(e1) * 1e-3)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return rate
+
+
 PROBLEM = {}  # problem-level reading of the returned energy, filled by make_instance for front-end kinds
 
 
@@ -775,6 +803,14 @@ def main():
         peaks["hbm_copy_GBps"] = copy_rate / 1e9
         if roof["bound"] == "hbm":
             roof["frac_of_measured_copy"] = roof["achieved"] * 1e9 / copy_rate
+        if dense_mfma:
+            mrate = measured_mfma_rate(roof["form"])
+            if mrate:
+                peaks[f"mfma_{roof['form']}_library_gemm_TFLOPs"] = mrate / 1e12
+                peaks["mfma_nominal_TFLOPs"] = roof["mfma_peak_tflops"]
+                # the products executed per step (the split form runs two) against the library GEMM's rate
+                executed = roof["flops_per_launch"] * (2 if roof["form"] == "bf16x2" else 1)
+                roof["mfma_frac_of_measured_gemm"] = executed / (roof["launch_us"] * 1e-6) / mrate
     e_final = float(E.item())
     t_ds = float(np.mean([s["t_ds_ms"] for s in stats]))
     out = {

@@ -1025,9 +1025,12 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
 //      (as the engine does) and puts them in LDS;
 //   B: all 1024 threads update (position, replica) items j = k 1024 + thread, each thread
 //      always the same replica (j mod 4), so the updates spread evenly over 16 wavefronts.
-// Every item runs the engine's own operations (angle_step, dsincos), the vertex bytes are
-// written where the engine writes its words, and the energy sums are exact integers in any
-// order: the results are the engine's bit for bit.
+// The vertex bytes are written where the engine writes its words and the energy sums are exact
+// integers in any order.  No loss is computed here, so an item's update is that of the
+// fixed-width-row form without the loss: cos(theta) alone (wrapped_cos), the sign of the vertex
+// kept as +-1, scaled moments, and the wrap only where some lane of the wavefront needs it; its
+// rounding differs from the engine's (which evaluates sin and cos together), and both are
+// compared with the oracle.
 constexpr int kSplitBlock = 1024, kSplitItems = 4;
 
 size_t split_lds_bytes(int pms_rb, int pimg_groups, int bimg) {
@@ -1074,14 +1077,16 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
     }
     float *gth = (float *)a.theta, *gm = (float *)a.m, *gv = (float *)a.v;
     constexpr bool adam = ADAM;
-    float th[KI], mo[KI], ve[KI], xs[KI], cs[KI];
+    // per item: the angle, the moments scaled as in the fixed-width-row form (mo = m / (1 - b1),
+    // ve = v / (1 - b2)) and the current vertex sign s as +-1
+    float th[KI], mo[KI], ve[KI], sgn[KI];
     int spin[KI];
     uint32_t cur = 0, prv = 0, best = 0;
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
         const int j = k * kSplitBlock + tid;
-        th[k] = mo[k] = ve[k] = xs[k] = 0.f;
-        cs[k] = 1.f;
+        th[k] = mo[k] = ve[k] = 0.f;
+        sgn[k] = 1.f;
         spin[k] = 0;
         if (j >= 4 * n) continue;
         const int q = j >> 2, i = a.pperm[q];
@@ -1090,13 +1095,13 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
         float t;
         if (a.init_mode == 0) {
             t = gth[idx];
-            if (t > 3.5f || t < -3.5f) {  // as the engine: angles it wrote are within pi
+            if (t > 3.15f || t < -3.15f) {  // angles the engines write are within pi_f
                 const float qw = drint(t * Consts<float>::inv_twopi);
                 t = t - qw * Consts<float>::twopi_hi;
                 t = t - qw * Consts<float>::twopi_lo;
             }
-            if (gm) mo[k] = gm[idx];
-            if (gv) ve[k] = gv[idx];
+            if (gm) mo[k] = gm[idx] / (float)(1.0 - a.b1);
+            if (gv) ve[k] = gv[idx] / (float)(1.0 - a.b2);
             if (a.s_best[idx] < 0) best |= 1u << k;
         } else {
             const float u = a.init_mode == 1 ? ((const float *)a.uniform)[idx] : draw_uniform<float>(a.seed, r0 + rr, i);
@@ -1105,8 +1110,7 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
         th[k] = t;
         float x, c;
         dsincos(t, &x, &c);
-        xs[k] = x;
-        cs[k] = c;
+        sgn[k] = x < 0 ? -1.f : 1.f;
         if (x < 0) cur |= 1u << k;
         put_byte(0, q, rr, x < 0);
     }
@@ -1125,7 +1129,7 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
     for (int t = 1; t <= a.steps; ++t) {
         const uint32_t *sc = vbuf((t - 1) & 1);
         const float ib1 = adam ? bct[2 * (t - 1)] : 1.f, ib2 = adam ? bct[2 * (t - 1) + 1] : 1.f;
-        const float lib1 = lr * ib1;
+        const float sa1 = lr * ib1 * omb1, sa2 = ib2 * omb2;  // the scaled-moment form's factors
         // A: the coupling product of position tid for the four replicas
         if (tid < n) {
             float y[RG];
@@ -1141,20 +1145,25 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
             const int j = k * kSplitBlock + tid;
             if (j >= 4 * n) continue;
             const int q = j >> 2;
-            const float x = xs[k], c = cs[k];
-            const float sg = x < 0 ? -1.f : 1.f;
-            // no field: the engine's y + 0 is y here (y = w (deg - 2 count) with w > 0 is never -0)
-            const float yh = yb[j];
+            // cos(theta) alone drives the update (no loss is computed here); the sign of the
+            // vertex is kept as +-1
+            const float c = wrapped_cos(th[k]);
+            const float sg = sgn[k];
+            const float yh = yb[j];  // no field
             Ep = dfma(sg, yh, Ep);
             const float tt = dfma(-mu, sg, yh);
-            const float tn = angle_step(th[k], mo[k], ve[k], c * tt, adam, b1, omb1, b2, omb2, lib1, lr, ib2, eps);
+            float tn = angle_step_scaled(th[k], mo[k], ve[k], c * tt, adam, b1, b2, sa1, lr, sa2, eps);
+            // the wrap changes no angle below 3 in magnitude: it runs when some lane of the
+            // wavefront has a larger one (a uniform branch), else the sign is tn's
+            bool neg = tn < 0.f;
+            if (__builtin_amdgcn_ballot_w64(__builtin_fabsf(tn) >= 3.f)) {
+                tn = wrap_angle(tn);
+                neg = wrapped_sin_neg(tn);
+            }
             th[k] = tn;
-            float xn, cn;
-            dsincos(tn, &xn, &cn);
-            xs[k] = xn;
-            cs[k] = cn;
-            if (xn < 0) nxt |= 1u << k;
-            put_byte(t & 1, q, rr, xn < 0);
+            sgn[k] = neg ? -1.f : 1.f;
+            if (neg) nxt |= 1u << k;
+            put_byte(t & 1, q, rr, neg);
         }
         // per-replica sums (exact integers: any order): the four lanes of a replica in each row of
         // 16 lanes by two DPP rotations, then across the four rows by two lane exchanges
@@ -1191,8 +1200,8 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
         if (j >= 4 * n) continue;
         const size_t idx = (size_t)(r0 + rr) * n + spin[k];
         gth[idx] = th[k];
-        if (gm) gm[idx] = mo[k];
-        if (gv) gv[idx] = ve[k];
+        if (gm) gm[idx] = mo[k] * (float)(1.0 - a.b1);
+        if (gv) gv[idx] = ve[k] * (float)(1.0 - a.b2);
         a.s_best[idx] = ((best >> k) & 1u) ? (int8_t)-1 : (int8_t)1;
     }
     if (wave == 0 && lane < RG) {
