@@ -447,7 +447,10 @@ __device__ __forceinline__ int local_index(int i) {
 // convergence test), whose update then evaluates cos(theta) alone and takes the vertex sign
 // from the bit it already holds; true computes sin(theta) as well, for the loss.  Both run
 // the same update of the angles, so their trajectories are identical.
-template <typename Real, int CK, int RG, int EPT, int OPT = -1, bool LOSS = true>
+// PLAIN (fixed-width-row form without the loss only): unit couplings (w = 1) and no field, so the
+// product is the integer sum itself and no per-position field is loaded; the same results as
+// the general form (y = fma(1, sum, 0) = sum exactly).
+template <typename Real, int CK, int RG, int EPT, int OPT = -1, bool LOSS = true, bool PLAIN = false>
 __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     using SWd = SpinWord<RG>;
     using SW = typename SWd::T;
@@ -709,7 +712,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         // ahead of it); the field (or 0) of each position in a separate array, loaded with it
         static_assert(kEllWidth == 4, "one 16-byte record per spin");
         U32x4 nbw[WIDE_ELL ? EPT : 1];
-        Real hpre[WIDE_ELL ? EPT : 1];
+        Real hpre[WIDE_ELL && !PLAIN ? EPT : 1];
         uintptr_t ellp = (uintptr_t)a.ell;
         uintptr_t ellh = (uintptr_t)a.ellh;
         if constexpr (WIDE_ELL) {
@@ -718,7 +721,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
 #pragma unroll
                 for (int e = 0; e < ELL_AHEAD && e < EPT; ++e) {
                     nbw[e] = ((const GlobalU32x4 *)(ellp + (size_t)e * LB * 16))[tid];
-                    hpre[e] = ((const GlobalF32 *)(ellh + (size_t)e * LB * 4))[tid];
+                    if constexpr (!PLAIN) hpre[e] = ((const GlobalF32 *)(ellh + (size_t)e * LB * 4))[tid];
                 }
         }
 #pragma unroll
@@ -726,7 +729,8 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
             if constexpr (WIDE_ELL) {
                 if (use_ell && e + ELL_AHEAD < EPT) {  // a uniform base per spin plus the lane's offset
                     nbw[e + ELL_AHEAD] = ((const GlobalU32x4 *)(ellp + (size_t)(e + ELL_AHEAD) * LB * 16))[tid];
-                    hpre[e + ELL_AHEAD] = ((const GlobalF32 *)(ellh + (size_t)(e + ELL_AHEAD) * LB * 4))[tid];
+                    if constexpr (!PLAIN)
+                        hpre[e + ELL_AHEAD] = ((const GlobalF32 *)(ellh + (size_t)(e + ELL_AHEAD) * LB * 4))[tid];
                 }
             }
             if constexpr (WIDE_ELL) {
@@ -751,7 +755,10 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 const int sum = (int)*(LdsI8 *)(size_t)(sb + nbw[e][0]) + (int)*(LdsI8 *)(size_t)(sb + nbw[e][1]) +
                                 (int)*(LdsI8 *)(size_t)(sb + nbw[e][2]) + (int)*(LdsI8 *)(size_t)(sb + nbw[e][3]);
 #pragma unroll
-                for (int r = 0; r < RG; ++r) y[r] = dfma((Real)a.w, (Real)sum, hpre[e]);
+                for (int r = 0; r < RG; ++r) {
+                    if constexpr (PLAIN) y[r] = (Real)sum;
+                    else y[r] = dfma((Real)a.w, (Real)sum, hpre[e]);
+                }
             } else {
                 coupling<Real, CK, RG>(a, i, sc, y);
             }
@@ -1210,9 +1217,9 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
     }
 }
 
-template <typename Real, int CK, int RG, int EPT, int OPT = -1, bool LOSS = true>
+template <typename Real, int CK, int RG, int EPT, int OPT = -1, bool LOSS = true, bool PLAIN = false>
 __global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
-    ds_body<Real, CK, RG, EPT, OPT, LOSS>(a, blockIdx.x * RG);
+    ds_body<Real, CK, RG, EPT, OPT, LOSS, PLAIN>(a, blockIdx.x * RG);
 }
 
 // Batched form for serving: workgroup b runs replica group map[b].y of problem
@@ -1725,7 +1732,7 @@ KFn pick_rg(int rg, int ept) {
 }
 
 template <typename Real>
-KFn pick(int ck, int rg, int ept, bool adam, bool loss) {
+KFn pick(int ck, int rg, int ept, bool adam, bool loss, bool plain) {
     switch (ck) {
         case CK_PM: return pick_rg<Real, CK_PM>(rg, ept);
         case CK_PMS: return ept > 0 ? pick_rg<Real, CK_PMS>(rg, ept) : nullptr;
@@ -1733,12 +1740,14 @@ KFn pick(int ck, int rg, int ept, bool adam, bool loss) {
         case CK_PME:
             if constexpr (sizeof(Real) == 4) {
                 if (rg != 1) return nullptr;
-                // the optimizer compiled in (these kernels run the longest per launch)
-                // and whether the loss is needed (a trace or the convergence test)
-#define ISING_PME(E)                                                                                 \
-    if (ept == E)                                                                                    \
-        return loss ? (adam ? k_ds<Real, CK_PME, 1, E, 1, true> : k_ds<Real, CK_PME, 1, E, 0, true>) \
-                    : (adam ? k_ds<Real, CK_PME, 1, E, 1, false> : k_ds<Real, CK_PME, 1, E, 0, false>);
+                // the optimizer compiled in (these kernels run the longest per launch), whether the
+                // loss is needed (a trace or the convergence test), and unit couplings without a field
+#define ISING_PME(E)                                                                                      \
+    if (ept == E) {                                                                                       \
+        if (loss) return adam ? k_ds<Real, CK_PME, 1, E, 1, true> : k_ds<Real, CK_PME, 1, E, 0, true>;      \
+        if (plain) return adam ? k_ds<Real, CK_PME, 1, E, 1, false, true> : k_ds<Real, CK_PME, 1, E, 0, false, true>; \
+        return adam ? k_ds<Real, CK_PME, 1, E, 1, false> : k_ds<Real, CK_PME, 1, E, 0, false>;              \
+    }
                 ISING_PME(8)
                 ISING_PME(16)
                 ISING_PME(28)
@@ -1790,7 +1799,9 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s, std::str
                                                                           : l.coupling;
     const bool adam = a.opt == ISING_OPT_ADAM;
     const bool need_loss = a.ltrace != nullptr || a.conv_tol > 0;
-    KFn fn = l.fp64 ? pick<double>(ck, l.rg, l.ept, adam, need_loss) : pick<float>(ck, l.rg, l.ept, adam, need_loss);
+    const bool plain = ck == CK_PME && !need_loss && a.h == nullptr && a.w == 1.0;
+    KFn fn = l.fp64 ? pick<double>(ck, l.rg, l.ept, adam, need_loss, plain)
+                    : pick<float>(ck, l.rg, l.ept, adam, need_loss, plain);
     if (!fn) return hipErrorInvalidValue;
     if (l.block % 64 || l.block < 64 || l.block > ds_block_limit(l.ept) || (l.ept > 0 && (int64_t)l.ept * l.block < a.n) ||
         a.R % l.rg)
@@ -1828,7 +1839,7 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s, std::str
         const char *ckn = ck >= 0 && ck < (int)(sizeof(cks) / sizeof(cks[0])) ? cks[ck] : "?";
         *kernel = std::string(l.ept > 0 ? "k_ds<" : "k_ds_stream<") + (l.fp64 ? "double" : "float") + ", " + ckn +
                   ", rg=" + std::to_string(l.rg) + ", ept=" + std::to_string(l.ept) +
-                  (ck == CK_PME ? (need_loss ? ", loss" : ", no loss") : "") + ">";
+                  (ck == CK_PME ? (need_loss ? ", loss" : plain ? ", no loss, unit" : ", no loss") : "") + ">";
     }
     return hipGetLastError();
 }
