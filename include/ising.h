@@ -172,11 +172,12 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
                              ising_stats *stats_out, void *stream);
 
 /* Name of the domain-selection kernel form launched by the last ising_ds_dev,
- * ising_ds_dense_dev or ising_solve(_dev) call on ctx, e.g. "k_ds_split<adam>" or
- * "k_ds<float, PME, rg=1, ept=28>" ("" before the first launch).  A diagnostic: the
- * engine picks its form from the problem and the requested outputs (traces, the
- * convergence test) and every form gives the same results; tests use it to know
- * which one they checked.  Valid until the next call on ctx. */
+ * ising_ds_dense_dev or ising_solve(_dev) call on ctx, e.g. "k_ds_split<adam>",
+ * "k_ds<float, PME, rg=1, ept=28, no loss, unit>" or "k_dense_step<bf16x2>" ("" before the
+ * first launch).  A diagnostic: the engine picks its form from the problem and the requested
+ * outputs (traces, the convergence test); the forms compute the same method and agree with
+ * each other to rounding (the loss-free forms evaluate cos(theta) alone), and tests use the
+ * name to know which one they checked.  Valid until the next call on ctx. */
 const char *ising_last_kernel(const ising_ctx *ctx);
 
 /* ---- exact energy (scalar energy form, Sec. II) ------------------------- */
