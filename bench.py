@@ -57,6 +57,10 @@ WORKLOADS = {
     "reg3_20000": ("random 3-regular N=20000 +-1 weights, CSR", "reg3", 256, 10000, "fp32"),
     "sk2000_bf16x2": ("dense SK N=2000 J~N(0,1/N), J split hi/lo BF16 on MFMA", "sk2000g", 4096, 2000, "bf16x2"),
     "sk2000_bf16": ("dense SK N=2000 J~N(0,1/N), J in BF16 on MFMA", "sk2000g", 4096, 2000, "bf16"),
+    "sk2000_i8x3": ("dense SK N=2000 J~N(0,1/N), J as 2^e times three INT8 digits on MFMA (exact int32 products)",
+                    "sk2000g", 4096, 2000, "i8x3"),
+    "sk2000_i8x2": ("dense SK N=2000 J~N(0,1/N), J as 2^e times two INT8 digits on MFMA (exact int32 products)",
+                    "sk2000g", 4096, 2000, "i8x2"),
     "sk2000_fp32": ("dense SK N=2000 J~N(0,1/N), FP32 MFMA", "sk2000g", 4096, 2000, "fp32"),
     "sk2000pm1_fp8": ("dense SK N=2000 J=+-1, J and the vertex in FP8 on MFMA (exact)", "sk2000pm1", 4096, 2000, "fp8"),
     "sk2000pm1_bf16": ("dense SK N=2000 J=+-1, J and the vertex in BF16 on MFMA (exact)", "sk2000pm1", 4096, 2000,
@@ -73,11 +77,13 @@ WORKLOADS = {
 }
 DEFAULT_WORKLOAD = "torus20000"
 # peak rates of the matrix cores (dense, no sparsity), per precision of the coupling product
-MFMA_PEAK = {"bf16x2": 2.5e15, "bf16": 2.5e15, "fp8": 5.0e15, "fp32": 157.3e12}
+MFMA_PEAK = {"bf16x2": 2.5e15, "bf16": 2.5e15, "fp8": 5.0e15, "fp32": 157.3e12, "i8x3": 5.0e15, "i8x2": 5.0e15}
+# products the matrix cores execute per step, in units of one J S~ product
+DENSE_PRODUCTS = {"bf16x2": 2, "i8x3": 3, "i8x2": 2}
 HBM_PEAK = 8.0e12  # bytes/s
 # bytes per element of the vertex operand and of the stored couplings, per dense form
-DENSE_SB = {"fp32": 4, "bf16": 2, "bf16x2": 2, "fp8": 1}
-DENSE_JB = {"fp32": 4, "bf16": 2, "bf16x2": 4, "fp8": 1}
+DENSE_SB = {"fp32": 4, "bf16": 2, "bf16x2": 2, "fp8": 1, "i8x3": 1, "i8x2": 1}
+DENSE_JB = {"fp32": 4, "bf16": 2, "bf16x2": 4, "fp8": 1, "i8x3": 3, "i8x2": 2}
 
 # Sources of each dominant kernel: a recorded HBM traffic figure is used only
 # while these files are unchanged since the counters were taken.
@@ -408,11 +414,14 @@ def ttt_known_bench(args):
 
 
 def ttt_bench(args):
-    """Time to the plain FP32 form's target energy on the SK-2000 Gaussian instance (R = 4096):
-    the FP32 form's best energy after 2000 steps is the target; each reduced-precision form is
-    solved with the same seed for increasing step counts (a shorter run is a prefix of a longer
-    one), and its time to target is the wall time of the first count whose returned vector,
-    re-evaluated exactly in FP64, reaches the target."""
+    """Time to the plain FP32 form's target energy on the SK-2000 Gaussian instance (R = 4096,
+    ADAM lr 6).  The best energy of 4096 replicas after T steps is a random outcome of chaotic
+    trajectories (any change of rounding gives another sample), so each figure is taken over
+    five seeds: the target is the median over the seeds of the FP32 form's best energy after
+    T = 2000 steps; each other form is solved with the same seeds for increasing step counts (a
+    shorter run is a prefix of a longer one, up to 2T), and its time to target is the median
+    wall time of the first count whose median best energy (the returned vectors re-evaluated
+    in FP64) reaches the target."""
     import numpy as np
     import torch
     import paper_2312_05837_amd as P
@@ -420,36 +429,41 @@ def ttt_bench(args):
     prob = to_device(inst)
     ctx = P.ising_create(0)
     R, T = 4096, 2000
+    seeds = (1234, 1235, 1236, 1237, 1238)
     spins = torch.empty(inst.n, dtype=torch.int8, device="cuda")
     E = torch.empty(1, dtype=torch.float64, device="cuda")
 
-    def solve(prec, steps):
-        prm = P.params(replicas=R, steps=steps, optimizer="adam", precision=prec, lr=6.0, mu=0.5, seed=1234,
+    def solve(prec, steps, seed):
+        prm = P.params(replicas=R, steps=steps, optimizer="adam", precision=prec, lr=6.0, mu=0.5, seed=seed,
                        prune=True)
-        P.ising_solve_dev(ctx, prob, prm, spins, E, None)  # warm-up of this shape
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         P.ising_solve_dev(ctx, prob, prm, spins, E, None)
         torch.cuda.synchronize()
         return float(E.item()), time.perf_counter() - t0
 
-    e_target, t_fp32 = solve("fp32", T)
-    forms = {"fp32": {"steps": T, "time_s": t_fp32, "energy": e_target}}
-    for prec in ("bf16x2", "bf16"):
-        forms[prec] = {"steps": None, "time_s": None, "energy_at_T": None}
-        for steps in (125, 250, 500, 1000, 2000):
-            e, t = solve(prec, steps)
-            if steps == T:
-                forms[prec]["energy_at_T"] = e
-            if e <= e_target:
-                forms[prec].update(steps=steps, time_s=t, energy=e, speedup_vs_fp32=t_fp32 / t)
+    def over_seeds(prec, steps):
+        solve(prec, steps, seeds[0])  # warm-up of this shape
+        r = [solve(prec, steps, sd) for sd in seeds]
+        return [x[0] for x in r], float(np.median([x[1] for x in r]))
+
+    e32, t_fp32 = over_seeds("fp32", T)
+    e_target = float(np.median(e32))
+    forms = {"fp32": {"steps": T, "time_s": t_fp32, "energies": e32, "median_energy": e_target}}
+    for prec in ("bf16x2", "bf16", "i8x3", "i8x2"):
+        forms[prec] = {"steps": None, "time_s": None}
+        for steps in (125, 250, 500, 1000, 2000, 4000):
+            es, t = over_seeds(prec, steps)
+            forms[prec].update(last_steps=steps, energies=es, median_energy=float(np.median(es)))
+            if np.median(es) <= e_target:
+                forms[prec].update(steps=steps, time_s=t, speedup_vs_fp32=t_fp32 / t)
                 break
-        if forms[prec]["energy_at_T"] is None:
-            forms[prec]["energy_at_T"] = solve(prec, T)[0]
     P.ising_destroy(ctx)
     print(json.dumps({"metric": "time-to-target energy", "unit": "s", "higher_is_better": False, "n_gpus": 1,
                       "data": "synthetic", "config": {"workload": "SK N=2000, J~N(0,1/N), R=4096, ADAM lr 6",
-                                                      "target": "best energy of the FP32 form after 2000 steps"},
+                                                      "seeds": list(seeds),
+                                                      "target": "median over the seeds of the FP32 form's best "
+                                                                "energy after 2000 steps"},
                       "target_energy": e_target, "forms": forms}))
 
 
@@ -756,7 +770,7 @@ def main():
     nnzG = int(inst.nnz)
     if stats[-1]["eta"] != 0.0:  # the engine ran on the reduced problem: its stored entries
         nnzG = int(P.ising_pruned_info(P.ising_prune_dev(ctx, prob))["nnz_G"])
-    dense_mfma = inst.is_dense and (prec in ("bf16x2", "bf16", "fp8") or (prec == "fp32" and nG > 256))
+    dense_mfma = inst.is_dense and (prec in ("bf16x2", "bf16", "fp8", "i8x3", "i8x2") or (prec == "fp32" and nG > 256))
     if dense_mfma:
         # the coupling product J S~ on the matrix cores: 2 n_G^2 R flops per step; integer
         # couplings of one magnitude run the (exact) FP8 form even when FP32 is asked
@@ -809,7 +823,7 @@ def main():
                 peaks[f"mfma_{roof['form']}_library_gemm_TFLOPs"] = mrate / 1e12
                 peaks["mfma_nominal_TFLOPs"] = roof["mfma_peak_tflops"]
                 # the products executed per step (the split form runs two) against the library GEMM's rate
-                executed = roof["flops_per_launch"] * (2 if roof["form"] == "bf16x2" else 1)
+                executed = roof["flops_per_launch"] * DENSE_PRODUCTS.get(roof["form"], 1)
                 roof["mfma_frac_of_measured_gemm"] = executed / (roof["launch_us"] * 1e-6) / mrate
     e_final = float(E.item())
     t_ds = float(np.mean([s["t_ds_ms"] for s in stats]))
@@ -824,7 +838,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x2": "bf16x2/f32", "bf16": "bf16/f32", "fp8": "fp8/f32"}[prec],
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x2": "bf16x2/f32", "bf16": "bf16/f32", "fp8": "fp8/f32",
+                  "i8x3": "i8x3/f32", "i8x2": "i8x2/f32"}[prec],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n": inst.n, "n_G": nG, "nnz": int(inst.nnz),
                    "replicas": R, "ds_steps": T, "mean_steps_run": T_eff, "optimizer": args.optimizer, "lr": lr,

@@ -79,9 +79,25 @@ enum { ISING_LOSS_VERTEX = 0, ISING_LOSS_RELAXED = 1 };
  * ENOTSUP otherwise): J / w and the vertex exact in FP8 (E4M3) on the matrix
  * cores, FP32 accumulation, FP32 iterates; every product and sum is exact, so
  * the results equal the FP32 form's bit for bit, and an FP32 request on such
- * couplings runs this form.  The energy of the returned vector is always
+ * couplings runs this form.  I8X3 and I8X2 (dense couplings, n <= 65536;
+ * ENOTSUP otherwise): J held as 2^e Jq, one power-of-two scale for the whole
+ * matrix and Jq an integer of three (two) balanced INT8 digits, the vertex +-1
+ * in INT8; the product Jq S~ is exact in int32 on the matrix cores and y =
+ * 2^e float(Jq S~) is rounded once.  e is the smallest exponent with
+ * max|J_ij| <= 2^e qmax (qmax = 8355711 for three digits, 32639 for two) and
+ * max_i sum_j |J_ij| + 2^e 257 n <= 2^e (2^31 - 1), so each entry carries an
+ * absolute error of at most 2^(e-1) (none when J / 2^e is an integer, e.g.
+ * +-1 couplings); FP32 iterates.  The energy of the returned vector is always
  * recomputed in FP64 (or exactly for integer J). */
-enum { ISING_PREC_FP64 = 0, ISING_PREC_FP32 = 1, ISING_PREC_BF16X2 = 2, ISING_PREC_BF16 = 3, ISING_PREC_FP8 = 4 };
+enum {
+    ISING_PREC_FP64 = 0,
+    ISING_PREC_FP32 = 1,
+    ISING_PREC_BF16X2 = 2,
+    ISING_PREC_BF16 = 3,
+    ISING_PREC_FP8 = 4,
+    ISING_PREC_I8X3 = 5,
+    ISING_PREC_I8X2 = 6
+};
 
 typedef struct ising_problem {
     int32_t n;           /* spin count, > 0 */
@@ -100,7 +116,7 @@ typedef struct ising_params {
     int32_t replicas;    /* R >= 1 independent trajectories */
     int32_t steps;       /* T >= 0 iterations */
     int32_t optimizer;   /* ISING_OPT_GD or ISING_OPT_ADAM */
-    int32_t precision;   /* ISING_PREC_* (BF16X2, BF16 and FP8: dense couplings only) */
+    int32_t precision;   /* ISING_PREC_* (BF16X2, BF16, FP8, I8X3, I8X2: dense couplings only) */
     double lr;           /* learning rate (the paper uses 6.0 with ADAM) */
     double mu;           /* augmented-Lagrangian weight mu > 0 of the L1-norm form */
     double beta1, beta2, eps;  /* ADAM constants (Kingma-Ba defaults 0.9, 0.999, 1e-8) */

@@ -31,6 +31,7 @@ ISING_I32, ISING_F32, ISING_F64 = 0, 1, 2
 ISING_OPT_GD, ISING_OPT_ADAM = 0, 1
 ISING_LOSS_VERTEX, ISING_LOSS_RELAXED = 0, 1
 ISING_PREC_FP64, ISING_PREC_FP32, ISING_PREC_BF16X2, ISING_PREC_BF16, ISING_PREC_FP8 = 0, 1, 2, 3, 4
+ISING_PREC_I8X3, ISING_PREC_I8X2 = 5, 6
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EBUSY", 5: "ETIMEDOUT",
                 6: "ECANCELED", 7: "ENOTSUP"}
@@ -211,7 +212,8 @@ def params(replicas=32, steps=100, optimizer="adam", precision="fp32", lr=6.0, m
            conv_window=5) -> ising_params:
     opt = {"gd": ISING_OPT_GD, "adam": ISING_OPT_ADAM}[optimizer] if isinstance(optimizer, str) else optimizer
     prec = {"fp64": ISING_PREC_FP64, "fp32": ISING_PREC_FP32, "bf16x2": ISING_PREC_BF16X2,
-            "bf16": ISING_PREC_BF16, "fp8": ISING_PREC_FP8}[precision] if isinstance(precision, str) \
+            "bf16": ISING_PREC_BF16, "fp8": ISING_PREC_FP8, "i8x3": ISING_PREC_I8X3,
+            "i8x2": ISING_PREC_I8X2}[precision] if isinstance(precision, str) \
         else precision
     lo = {"vertex": ISING_LOSS_VERTEX, "relaxed": ISING_LOSS_RELAXED}[loss] if isinstance(loss, str) else loss
     return ising_params(replicas, steps, opt, prec, lr, mu, beta1, beta2, eps, seed, 1 if prune else 0, lo,

@@ -425,6 +425,8 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
     return ISING_OK;
 }
 
+constexpr int kDenseInt8MaxN = 65536;
+
 ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, Pool &pool,
                            hipStream_t s, DenseRun &d, double unit) {
     if (p.format != ISING_DENSE) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine needs dense couplings");
@@ -441,7 +443,12 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
     else if (prm.precision == ISING_PREC_FP8 && unit > 0) form = DF_FP8;
     else if (prm.precision == ISING_PREC_FP8)
         return fail(ctx, ISING_ENOTSUP, "the FP8 form needs couplings of one integer magnitude w with n w < 2^24");
-    else return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs FP32, BF16X2, BF16 or FP8");
+    else if (prm.precision == ISING_PREC_I8X3) form = DF_I8X3;
+    else if (prm.precision == ISING_PREC_I8X2) form = DF_I8X2;
+    else return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs FP32, BF16X2, BF16, FP8, I8X3 or I8X2");
+    // INT8 forms: every partial sum stays below 2^31 only while 257 n is well below it
+    if ((form == DF_I8X3 || form == DF_I8X2) && p.n > kDenseInt8MaxN)
+        return fail(ctx, ISING_ENOTSUP, "the INT8 forms take n <= 65536");
     if (prm.replicas <= 0) return fail(ctx, ISING_EINVAL, "bad replicas");
     if (prm.optimizer != ISING_OPT_GD && prm.optimizer != ISING_OPT_ADAM)
         return fail(ctx, ISING_EINVAL, "unknown optimizer");
@@ -450,8 +457,9 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
     d.n = n;
     d.R = R;
     d.Mp = (n + 127) / 128 * 128;
-    // the K loops read 128 bytes of each row per chunk: 64 BF16 or 128 FP8 values
-    d.Kp = form == DF_FP8 ? (n + 127) / 128 * 128 : (n + 63) / 64 * 64;
+    // the K loops read 128 bytes of each row per chunk: 64 BF16 or 128 FP8 / INT8 values
+    const bool bytes = form == DF_FP8 || form == DF_I8X3 || form == DF_I8X2;
+    d.Kp = bytes ? (n + 127) / 128 * 128 : (n + 63) / 64 * 64;
     d.jscale = form == DF_FP8 ? (float)unit : 1.f;
     d.form = form;
     d.opt = prm.optimizer;
@@ -462,18 +470,23 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
     d.b2 = prm.beta2;
     d.eps = prm.eps;
     void *Jhi = nullptr, *Jlo = nullptr, *Jf = nullptr, *hf = nullptr, *S = nullptr, *Ep = nullptr, *Lp = nullptr;
+    void *jsc = nullptr;
     const size_t mk = (size_t)d.Mp * d.Kp;
     if (form == DF_FP32) {
         HIP_TRY(ctx, pool.get("dn.Jf", mk * 4, &Jf));
+    } else if (form == DF_BF16X2) {
+        HIP_TRY(ctx, pool.get("dn.Jhi", mk * 2, &Jhi));
+        HIP_TRY(ctx, pool.get("dn.Jlo", mk * 2, &Jlo));
     } else {
-        HIP_TRY(ctx, pool.get("dn.Jhi", mk * (form == DF_FP8 ? 1 : 2), &Jhi));
-        if (form == DF_BF16X2) HIP_TRY(ctx, pool.get("dn.Jlo", mk * 2, &Jlo));
+        HIP_TRY(ctx, pool.get("dn.Jhi", mk * dense_j_bytes(form), &Jhi));  // (INT8: the digit planes)
     }
+    if (form == DF_I8X3 || form == DF_I8X2) HIP_TRY(ctx, pool.get("dn.jsc", kDenseScaleBytes, &jsc));
     if (p.h) HIP_TRY(ctx, pool.get("dn.h", (size_t)n * 4, &hf));
-    HIP_TRY(ctx, pool.get("dn.S", (size_t)kDenseVertexBufs * R * d.Kp * (form == DF_FP32 ? 4 : form == DF_FP8 ? 1 : 2), &S));
+    HIP_TRY(ctx, pool.get("dn.S", (size_t)kDenseVertexBufs * R * d.Kp * dense_vertex_bytes(form), &S));
     HIP_TRY(ctx, pool.get("dn.Ep", (size_t)2 * (d.Mp / 128) * R * 4, &Ep));
     HIP_TRY(ctx, pool.get("dn.Lp", (size_t)2 * (d.Mp / 128) * R * 4, &Lp));
-    HIP_TRY(ctx, launch_dense_prepare(to_dev(p), form, d.Mp, d.Kp, Jhi, Jlo, Jf, (float *)hf, s));
+    HIP_TRY(ctx, launch_dense_prepare(to_dev(p), form, d.Mp, d.Kp, Jhi, Jlo, Jf, (float *)hf, jsc, s));
+    d.jsc = jsc;
     d.Jhi = Jhi;
     d.Jlo = Jlo;
     d.Jf = Jf;
@@ -516,7 +529,7 @@ ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_param
     HIP_TRY(ctx, pool.get("dn.group", dense_group_scratch_bytes(&one, 1), &scratch));
     if (kbeg) HIP_TRY(ctx, hipEventRecord(kbeg, s));
     hipError_t e = launch_dense_run(d, scratch, s);
-    static const char *const forms[] = {"fp32", "bf16x2", "bf16", "fp8"};
+    static const char *const forms[] = {"fp32", "bf16x2", "bf16", "fp8", "i8x3", "i8x2"};
     ctx->last_kernel = std::string("k_dense_step<") + forms[d.form] + ">";
     if (e != hipSuccess)
         return fail(ctx, e == hipErrorInvalidValue ? ISING_ENOTSUP : ISING_EDEVICE,
@@ -530,7 +543,8 @@ constexpr int kDenseMfmaMinN = 256;  // n above which dense FP32 problems use MF
 
 bool use_dense_engine(const ising_problem &p, const ising_params &prm) {
     if (p.format != ISING_DENSE || prm.loss != ISING_LOSS_VERTEX || prm.conv_tol > 0) return false;
-    if (prm.precision == ISING_PREC_BF16X2 || prm.precision == ISING_PREC_BF16 || prm.precision == ISING_PREC_FP8)
+    if (prm.precision == ISING_PREC_BF16X2 || prm.precision == ISING_PREC_BF16 || prm.precision == ISING_PREC_FP8 ||
+        prm.precision == ISING_PREC_I8X3 || prm.precision == ISING_PREC_I8X2)
         return true;
     return prm.precision == ISING_PREC_FP32 && p.n > kDenseMfmaMinN;
 }
@@ -909,8 +923,9 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
     const int R = params->replicas;
     const bool dense_engine = use_dense_engine(*red, *params);
     if (!dense_engine && (params->precision == ISING_PREC_BF16X2 || params->precision == ISING_PREC_BF16 ||
-                          params->precision == ISING_PREC_FP8))
-        return fail(ctx, ISING_ENOTSUP, "BF16 and FP8 forms need dense couplings");
+                          params->precision == ISING_PREC_FP8 || params->precision == ISING_PREC_I8X3 ||
+                          params->precision == ISING_PREC_I8X2))
+        return fail(ctx, ISING_ENOTSUP, "BF16, FP8 and INT8 forms need dense couplings");
     const size_t real = params->precision == ISING_PREC_FP64 ? 8 : 4;
     int32_t *bestdev = nullptr;
     int8_t *sG = nullptr;

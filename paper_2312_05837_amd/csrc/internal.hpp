@@ -198,7 +198,7 @@ hipError_t launch_gather_row(const int8_t *block, int32_t n, const int32_t *best
                              hipStream_t s);
 
 // ---- domain selection for dense couplings on MFMA (kernels_dense.hip) --------
-enum DenseForm { DF_FP32 = 0, DF_BF16X2 = 1, DF_BF16 = 2, DF_FP8 = 3 };
+enum DenseForm { DF_FP32 = 0, DF_BF16X2 = 1, DF_BF16 = 2, DF_FP8 = 3, DF_I8X3 = 4, DF_I8X2 = 5 };
 
 // Vertex buffers of the matrix-core engine: step t reads buffer (t - 1) % 3 and writes t % 3, so
 // the vertex scored in step t - 1 stays intact while step t's tiles keep its best-vertex record.
@@ -209,10 +209,13 @@ struct DenseRun {
     uint64_t seed = 0;
     double lr = 6.0, mu = 0.5, b1 = 0.9, b2 = 0.999, eps = 1e-8;
     float jscale = 1.f;  // FP8 form: the common magnitude w of the couplings (operand J / w)
+    // INT8 forms: the matrix's scale, device memory written by launch_dense_prepare (float 2^e at
+    // byte 16, the exponent e as int32 at byte 20 of kDenseScaleBytes)
+    const void *jsc = nullptr;
     const void *Jhi = nullptr, *Jlo = nullptr, *Jf = nullptr;
     const float *h = nullptr;
     const void *uniform = nullptr;
-    void *S = nullptr;  // kDenseVertexBufs vertex buffers [R][Kp] (FP32, BF16 bits or FP8 bytes)
+    void *S = nullptr;  // kDenseVertexBufs vertex buffers [R][Kp] (FP32, BF16 bits, FP8 or INT8 bytes)
     float *theta = nullptr, *m = nullptr, *v = nullptr;
     float *Epart = nullptr, *Lpart = nullptr;  // [2][Mp / 128][R], by step parity
     double *e_best = nullptr;
@@ -221,9 +224,20 @@ struct DenseRun {
     double *etrace = nullptr, *ltrace = nullptr;
     const float *bias = nullptr;  // ADAM bias corrections of steps t0+1.. (2 floats per step)
 };
-// Pad and split J (and convert h to float into hf when both are non-null).
+// Pad and split J (and convert h to float into hf when both are non-null).  INT8 forms: Jhi
+// holds the digit planes [D][Mp][Kp] and jsc (kDenseScaleBytes of device memory) receives the
+// scale, found on the device.
+constexpr size_t kDenseScaleBytes = 32;
 hipError_t launch_dense_prepare(const DevProblem &p, int form, int Mp, int Kp, void *Jhi, void *Jlo, void *Jf,
-                                float *hf, hipStream_t s);
+                                float *hf, void *jsc, hipStream_t s);
+// vertex operand bytes per element of a form
+constexpr size_t dense_vertex_bytes(int form) {
+    return form == DF_FP32 ? 4 : (form == DF_BF16X2 || form == DF_BF16) ? 2 : 1;
+}
+// J operand bytes per padded element of a form (all planes)
+constexpr size_t dense_j_bytes(int form) {
+    return form == DF_FP32 ? 4 : form == DF_BF16X2 ? 4 : form == DF_BF16 ? 2 : form == DF_I8X3 ? 3 : form == DF_I8X2 ? 2 : 1;
+}
 // State initialisation (t0 = 0) or vertex re-derivation (t0 > 0) before a chunk.
 hipError_t launch_dense_init(const DenseRun &d, hipStream_t s);
 // Advance `count` problems of the same form by `steps` steps: one launch per step for the whole

@@ -19,9 +19,18 @@
 //   DF_BF16   J_hi only
 //   DF_FP8    couplings of one integer magnitude w: J / w = -1, 0, +1 and the vertex
 //             exact in FP8 (E4M3), v_mfma_f32_32x32x64_f8f6f4, y = w (J / w) S~ exact
+//   DF_I8X3   J = 2^e Jq with Jq an integer of three balanced INT8 digits (Jq = 65536 a +
+//   DF_I8X2   256 b + c; two digits for I8X2) and one power-of-two scale for the whole
+//             matrix; the vertex +-1 in INT8; v_mfma_i32_32x32x32_i8 digit plane by digit
+//             plane with the accumulators multiplied by 256 between planes (Horner), so
+//             Jq S~ is exact in int32 and y = 2^e float(Jq S~) rounds once.  e is the
+//             smallest exponent with max|J| <= 2^e qmax (qmax = 127 (256^D - 1) / 255)
+//             and max_i sum_j |J_ij| + 2^e 257 n <= 2^e (2^31 - 1), which bounds every
+//             partial sum of every plane (any order) below 2^31.
 // Tile: 128 spins x 128 replicas per workgroup of four wavefronts (2 x 2, each
 // 64 x 64 = 2 x 2 MFMA blocks of 32 x 32); the split form 128 x 256 on eight (2 x 4).
-// K staged through LDS in chunks of 64 BF16 / 128 FP8 values (32 FP32).
+// K staged through LDS in chunks of 64 BF16 / 128 FP8 or INT8 values (32 FP32); the INT8
+// forms run their digit planes one after another through the same K loop.
 // Operand layouts: J padded row-major [Mp][Kp]; S~ replica-major [R][Kp]
 // (each replica's spins contiguous), so both MFMA operands are K-contiguous.
 // State theta, m, v, s_best: replica-major [R][n].
@@ -38,13 +47,20 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+
+// forms with one-byte operands (FP8, INT8) and the digit planes of J per product
+__host__ __device__ constexpr bool byte_form(int f) { return f == DF_FP8 || f == DF_I8X3 || f == DF_I8X2; }
+__host__ __device__ constexpr bool int8_form(int f) { return f == DF_I8X3 || f == DF_I8X2; }
+__host__ __device__ constexpr int jdigits(int f) { return f == DF_I8X3 ? 3 : f == DF_I8X2 ? 2 : 1; }
+// largest |Jq| of D balanced INT8 digits: 127 (256^D - 1) / 255
+__host__ __device__ constexpr double jq_max(int D) { return D == 3 ? 8355711.0 : 32639.0; }
 
 constexpr int BM = 128, BN = 128, KC = 32;
 constexpr int KCB = 64;       // K chunk of the BF16 forms: one 128-byte line per row and chunk
 constexpr int AST = KCB;      // LDS row stride (bf16 elements) of the BF16 chunks (16-byte units swizzled)
 constexpr int FST = KC + 1;   // LDS row stride (floats) for the FP32 form
 constexpr int TST = BM + 4;   // LDS row stride (floats) of the transposed accumulator tile
-constexpr int GEMM_LDS_BF16 = (BM + BN) * AST * 2;  // J hi (or J lo) and vertex rows of one chunk
 constexpr int GEMM_LDS_FP32 = (BM + BN) * FST * 4;
 constexpr int EPI_LDS = 64 * TST * 4;
 constexpr int cmax(int x, int y) { return x > y ? x : y; }
@@ -54,16 +70,17 @@ constexpr int cmax(int x, int y) { return x > y ? x : y; }
 // as wide (256 replicas, 8 wavefronts, LDS double-buffered: one workgroup per CU): each staged
 // chunk of J then serves twice the replicas, which cuts the L2-to-CU operand traffic per product
 // by a third.
+__host__ __device__ constexpr bool wide_form(int f) { return f == DF_BF16X2 || int8_form(f); }
 template <int FORM>
 struct TileShape {
-    static constexpr bool WIDE = FORM == DF_BF16X2;
+    static constexpr bool WIDE = wide_form(FORM);
     static constexpr int BN = WIDE ? 256 : 128;
     static constexpr int NT = WIDE ? 512 : 256;
     static constexpr int WN = BN / 64, WM = BM / 64;
     static_assert(WM * WN * 64 == NT, "one 64 x 64 block per wavefront");
 };
-__host__ __device__ constexpr int tile_bn(int form) { return form == DF_BF16X2 ? 256 : 128; }
-__host__ __device__ constexpr int tile_threads(int form) { return form == DF_BF16X2 ? 512 : 256; }
+__host__ __device__ constexpr int tile_bn(int form) { return wide_form(form) ? 256 : 128; }
+__host__ __device__ constexpr int tile_threads(int form) { return wide_form(form) ? 512 : 256; }
 
 // sum of each 16-lane row of a wavefront (quads, then half rows, then rows), result in every lane
 __device__ inline float row_sum16(float v) {
@@ -142,7 +159,8 @@ __device__ inline uint64_t splitmix64(uint64_t seed, uint64_t c) {
 
 template <typename V>
 __global__ void k_dense_split(DevProblem p, int Mp, int Kp, int form, unsigned short *Jhi, unsigned short *Jlo,
-                              float *Jf, float *hf) {
+                              float *Jf, float *hf, const int32_t *jexp) {
+    const int e = int8_form(form) ? *jexp : 0;
     if (hf && p.h)
         for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += gridDim.x * blockDim.x)
             hf[i] = (float)((const V *)p.h)[i];
@@ -156,6 +174,16 @@ __global__ void k_dense_split(DevProblem p, int Mp, int Kp, int form, unsigned s
         } else if (form == DF_FP8) {
             // J / w is -1, 0 or +1 (the caller checked one integer magnitude w)
             ((unsigned char *)Jhi)[q] = fp8_of(v == 0.0 ? 0.f : (v < 0.0 ? -1.f : 1.f));
+        } else if (int8_form(form)) {
+            // Jq = rint(J / 2^e) (the scaling is exact) as balanced base-256 digits, most
+            // significant digit in plane 0; |Jq| <= qmax, so the top digit is within [-128, 127]
+            int64_t jq = (int64_t)rint(ldexp(v, -e));
+            const int D = jdigits(form);
+            for (int d = D - 1; d >= 0; --d) {
+                const int64_t c = ((jq + 128) & 255) - 128;
+                ((signed char *)Jhi)[(size_t)d * total + q] = (signed char)c;
+                jq = (jq - c) / 256;
+            }
         } else {
             const float vf = (float)v;
             const unsigned short hi = bf16_bits(vf);
@@ -163,6 +191,57 @@ __global__ void k_dense_split(DevProblem p, int Mp, int Kp, int form, unsigned s
             if (form == DF_BF16X2) Jlo[q] = bf16_bits((float)(v - (double)bf16_to_f(hi)));
         }
     }
+}
+
+// INT8 forms: the largest |J_ij| and the largest row sum of |J_ij| (FP64), as the bit patterns of
+// non-negative doubles, which order like unsigned integers, into mx[0] and mx[1] (zeroed before).
+template <typename V>
+__global__ __launch_bounds__(256) void k_dense_absmax(DevProblem p, unsigned long long *mx) {
+    __shared__ double ss[4], sm[4];
+    for (int i = blockIdx.x; i < p.n; i += gridDim.x) {
+        double sum = 0.0, big = 0.0;
+        for (int j = threadIdx.x; j < p.n; j += 256) {
+            const double a = fabs((double)((const V *)p.J)[(size_t)i * p.n + j]);
+            sum += a;
+            big = fmax(big, a);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            sum += __shfl_xor(sum, o);
+            big = fmax(big, __shfl_xor(big, o));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            ss[threadIdx.x >> 6] = sum;
+            sm[threadIdx.x >> 6] = big;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double rs = (ss[0] + ss[1]) + (ss[2] + ss[3]);
+            const double rm = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+            atomicMax(mx + 0, (unsigned long long)__double_as_longlong(rm));
+            atomicMax(mx + 1, (unsigned long long)__double_as_longlong(rs));
+        }
+        __syncthreads();
+    }
+}
+
+// The scale exponent e of the INT8 forms (one thread): the smallest e with max|J| <= 2^e qmax and
+// max row sum + 2^e 257 n <= 2^e (2^31 - 1), within [-126, 127] so that 2^e is a normal float.
+// Writes 2^e (float) at byte 16 and e at byte 20 of the scale buffer.
+__global__ void k_dense_exponent(int n, int digits, unsigned long long *mx) {
+    const double big = __longlong_as_double((long long)mx[0]), rsum = __longlong_as_double((long long)mx[1]);
+    const double qmax = jq_max(digits), lim = 2147483647.0;
+    auto fits = [&](int e) { return big <= ldexp(qmax, e) && rsum + ldexp(257.0 * n, e) <= ldexp(lim, e); };
+    int e = -126;
+    if (big > 0.0) {
+        int k;
+        frexp(big / qmax, &k);
+        e = max(-126, k - 2);
+        while (e < 127 && !fits(e)) ++e;
+        while (e > -126 && fits(e - 1)) --e;
+    }
+    float *f = (float *)((char *)mx + 16);
+    *f = ldexpf(1.f, e);
+    *(int32_t *)((char *)mx + 20) = e;
 }
 
 // theta_0 = asin(U), m = v = 0, S~_1 = sgn(sin theta_0) (padding zero), e_best = +inf
@@ -201,8 +280,8 @@ __global__ void k_dense_init(int n, int R, int Kp, int form, int init_mode, uint
             ((float *)S)[q] = s;
             ((float *)S_other)[q] = 0.f;  // the other buffers' padding must be zero too
             ((float *)S_third)[q] = 0.f;
-        } else if (form == DF_FP8) {
-            ((unsigned char *)S)[q] = fp8_of(s);
+        } else if (byte_form(form)) {
+            ((unsigned char *)S)[q] = form == DF_FP8 ? fp8_of(s) : (unsigned char)(signed char)s;
             ((unsigned char *)S_other)[q] = 0;
             ((unsigned char *)S_third)[q] = 0;
         } else {
@@ -237,6 +316,7 @@ struct DenseDescT {
     float lr, mu, b1, b2, eps, omb1, omb2;
     int t0;                  // global step before the chunk
     float jscale;            // y = jscale * (J S~) of the stored operand (w for the FP8 form, else 1)
+    Ptr<const float> jpow;   // INT8 forms: y = 2^e float(Jq S~), 2^e in device memory
     Ptr<const float> bias;   // 1/(1-b1^t), 1/(1-b2^t) of the chunk's steps, at 2 (tloc - 1)
     Ptr<const unsigned short> Jhi, Jlo;
     Ptr<const float> Jf;
@@ -271,17 +351,18 @@ struct BfStage {
 // lane, one unit) touch distinct banks.
 __device__ __forceinline__ int swz(int r, int u) { return r * AST + ((u ^ r ^ (r >> 3)) & 7) * 8; }
 
+// J rows start at plane offset joff (2-byte units; INT8 digit planes), the vertex rows at 0.
 template <int FORM>
 __device__ __forceinline__ BfStage<FORM> bf_gload(const DenseDescG &a, const void *S_in, int row0, int col0, int k0,
-                                                  int tid) {
+                                                  int tid, size_t joff = 0) {
     using St = BfStage<FORM>;
     St s;
     const int rr = tid >> 3, c8 = (tid & 7) * 8;
-    const size_t kpu = FORM == DF_FP8 ? a.Kp >> 1 : a.Kp;  // row length in 2-byte units
+    const size_t kpu = byte_form(FORM) ? a.Kp >> 1 : a.Kp;  // row length in 2-byte units
     const unsigned short *Sb = (const unsigned short *)S_in;
 #pragma unroll
     for (int p = 0; p < St::NA; ++p) {
-        const size_t ja = (size_t)(row0 + rr + St::RS * p) * kpu + k0 + c8;
+        const size_t ja = joff + (size_t)(row0 + rr + St::RS * p) * kpu + k0 + c8;
         s.ah[p] = *(const u16x8 *)(a.Jhi + ja);
         s.al[p] = FORM == DF_BF16X2 ? *(const u16x8 *)(a.Jlo + ja) : u16x8{};
     }
@@ -344,8 +425,8 @@ __device__ __forceinline__ void best_of(const DenseDescG &a, const int tloc, con
                     const float4 p1 = *(const float4 *)((const float *)S_t + src + i + 4);
                     sv[0] = p0.x; sv[1] = p0.y; sv[2] = p0.z; sv[3] = p0.w;
                     sv[4] = p1.x; sv[5] = p1.y; sv[6] = p1.z; sv[7] = p1.w;
-                } else if (form == DF_FP8) {
-                    // the sign bit of an FP8 value is its top bit
+                } else if (byte_form(form)) {
+                    // the sign bit of an FP8 or INT8 value is its top bit
                     const uint2 p8 = *(const uint2 *)((const unsigned char *)S_t + src + i);
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -368,7 +449,7 @@ __device__ __forceinline__ void best_of(const DenseDescG &a, const int tloc, con
         } else {
             for (int i = lane; i < a.n; i += 64) {
                 const float sv = form == DF_FP32  ? ((const float *)S_t)[src + i]
-                                 : form == DF_FP8 ? (((const unsigned char *)S_t)[src + i] & 0x80 ? -1.f : 1.f)
+                                 : byte_form(form) ? (((const unsigned char *)S_t)[src + i] & 0x80 ? -1.f : 1.f)
                                                   : bf16_to_f(((const unsigned short *)S_t)[src + i]);
                 a.s_best[dst + i] = sv < 0.f ? (int8_t)-1 : (int8_t)1;
             }
@@ -391,7 +472,7 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
     // split form: two buffers of J hi, vertex and J lo rows
     __shared__ __align__(16) unsigned char lds[cmax(FORM == DF_FP32    ? 2 * GEMM_LDS_FP32
                                                     : FORM == DF_BF16X2 ? 2 * (2 * BM + TBN) * AST * 2
-                                                                        : 2 * GEMM_LDS_BF16,
+                                                                        : 2 * (BM + TBN) * AST * 2,
                                                     EPI_LDS)];
     __shared__ float red_e[1][TBN], red_l[1][TBN];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -459,12 +540,18 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
         // a fixed count of outstanding loads.
         constexpr int NST = 2;  // register budget: two workgroups per CU (one for the split form's wide tile)
         constexpr int BUF = FORM == DF_BF16X2 ? (2 * BM + TBN) * AST : (BM + TBN) * AST;  // bf16 elements
-        // chunks of 128 bytes per row: 64 BF16 or 128 FP8 values of k
-        const int nch = (FORM == DF_FP8 ? a.Kp >> 1 : a.Kp) / KCB, last = nch - 1;
-        BfStage<FORM> s0 = bf_gload<FORM>(a, S_in, row0, col0, 0, tid);
-        BfStage<FORM> s1 = bf_gload<FORM>(a, S_in, row0, col0, min(1, last) * KCB, tid);
+        // chunks of 128 bytes per row: 64 BF16 or 128 FP8 / INT8 values of k; the INT8 forms run
+        // nch chunks per digit plane, planes in turn (chunk g: plane g / nch)
+        const int nch = (byte_form(FORM) ? a.Kp >> 1 : a.Kp) / KCB, ntot = jdigits(FORM) * nch, last = ntot - 1;
+        const size_t plane = (size_t)a.Mp * (a.Kp >> 1);  // 2-byte units per INT8 digit plane
+        auto gl = [&](int g) {
+            const int p = jdigits(FORM) == 1 ? 0 : (g >= nch) + (jdigits(FORM) == 3 && g >= 2 * nch);
+            return bf_gload<FORM>(a, S_in, row0, col0, (g - p * nch) * KCB, tid, p * plane);
+        };
+        BfStage<FORM> s0 = gl(0);
+        BfStage<FORM> s1 = gl(min(1, last));
         BfStage<FORM> s2;
-        if (NST == 3) s2 = bf_gload<FORM>(a, S_in, row0, col0, min(2, last) * KCB, tid);
+        if (NST == 3) s2 = gl(min(2, last));
         // Chunk c's products from LDS buffer c & 1.  The stage holding chunk c + 1 is written to
         // the other buffer among the products (that buffer was last read by chunk c - 1, before
         // the previous barrier; after the last chunk it is written with a re-read chunk that no
@@ -477,9 +564,10 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
             const unsigned short *Al = Bs + TBN * AST;
             unsigned short *Nh = (unsigned short *)lds + ((c + 1) & 1) * BUF;
             auto store = [&]() { bf_stage_store<FORM>(Nh, Nh + (BM + TBN) * AST, Nh + BM * AST, next, tid, col0, a.R); };
-            if constexpr (FORM == DF_FP8) {
+            if constexpr (byte_form(FORM)) {
                 // 32 bytes (k 64 ks + 32 (l / 32) .. + 31) per lane and operand; both operands put
-                // the same k in the same lane slot, so the k order inside the instruction is immaterial
+                // the same k in the same lane slot, so the k order inside the instruction is
+                // immaterial (INT8: the first and second 16 bytes feed two 32-k products)
 #pragma unroll
                 for (int ks = 0; ks < 2; ++ks) {
                     const int u = 4 * ks + 2 * (lane >> 5);
@@ -501,9 +589,21 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
 #pragma unroll
                     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                        for (int bj = 0; bj < 2; ++bj)
-                            acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[bi], bf[bj], acc[bi][bj],
-                                                                                         0, 0, 0, 0, 0, 0);
+                        for (int bj = 0; bj < 2; ++bj) {
+                            if constexpr (FORM == DF_FP8) {
+                                acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                    af[bi], bf[bj], acc[bi][bj], 0, 0, 0, 0, 0, 0);
+                            } else {
+                                const i32x4 a0 = {af[bi][0], af[bi][1], af[bi][2], af[bi][3]};
+                                const i32x4 a1 = {af[bi][4], af[bi][5], af[bi][6], af[bi][7]};
+                                const i32x4 b0 = {bf[bj][0], bf[bj][1], bf[bj][2], bf[bj][3]};
+                                const i32x4 b1 = {bf[bj][4], bf[bj][5], bf[bj][6], bf[bj][7]};
+                                i32x16 c = __builtin_bit_cast(i32x16, acc[bi][bj]);
+                                c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, c, 0, 0, 0);
+                                c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, c, 0, 0, 0);
+                                acc[bi][bj] = __builtin_bit_cast(f32x16, c);
+                            }
+                        }
                     if (ks == 0) store();
                 }
             } else {
@@ -557,32 +657,43 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
         };
         bf_stage_store<FORM>((unsigned short *)lds, (unsigned short *)lds + (BM + TBN) * AST,
                              (unsigned short *)lds + BM * AST, s0, tid, col0, a.R);
-        s0 = bf_gload<FORM>(a, S_in, row0, col0, min(NST, last) * KCB, tid);
+        s0 = gl(min(NST, last));
         lds_barrier();
+        // INT8 forms, first chunk of a digit plane after the first: the accumulators hold the
+        // higher digits' sum, which the next digit's terms join at 256 times its weight
+        auto horner = [&](int g) {
+            if (int8_form(FORM) && (g == nch || g == 2 * nch))
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj)
+                        acc[bi][bj] = __builtin_bit_cast(f32x16, __builtin_bit_cast(i32x16, acc[bi][bj]) << 8);
+        };
         // iteration c stores the stage of chunk c + 1 and refills it with chunk c + 1 + NST
 #define DENSE_BF_CHUNK(C, ST)                                                                          \
     {                                                                                                  \
         const int c_ = (C);                                                                            \
+        horner(c_);                                                                                    \
         chunk(c_, ST);                                                                                 \
         __builtin_amdgcn_sched_barrier(0);                                                             \
-        ST = bf_gload<FORM>(a, S_in, row0, col0, min(c_ + 1 + NST, last) * KCB, tid);                 \
+        ST = gl(min(c_ + 1 + NST, last));                                                              \
         lds_barrier();                                                                                 \
     }
         int c = 0;
         if constexpr (NST == 3) {
-            for (; c + 3 <= nch; c += 3) {
+            for (; c + 3 <= ntot; c += 3) {
                 DENSE_BF_CHUNK(c, s1);
                 DENSE_BF_CHUNK(c + 1, s2);
                 DENSE_BF_CHUNK(c + 2, s0);
             }
-            if (c < nch) DENSE_BF_CHUNK(c, s1);
-            if (c + 1 < nch) DENSE_BF_CHUNK(c + 1, s2);
+            if (c < ntot) DENSE_BF_CHUNK(c, s1);
+            if (c + 1 < ntot) DENSE_BF_CHUNK(c + 1, s2);
         } else {
-            for (; c + 2 <= nch; c += 2) {
+            for (; c + 2 <= ntot; c += 2) {
                 DENSE_BF_CHUNK(c, s1);
                 DENSE_BF_CHUNK(c + 1, s0);
             }
-            if (c < nch) DENSE_BF_CHUNK(c, s1);
+            if (c < ntot) DENSE_BF_CHUNK(c, s1);
         }
 #undef DENSE_BF_CHUNK
     }
@@ -594,7 +705,9 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
     // thread then owns 4 consecutive spins of a replica: the state streams as float4
     // with 32 lanes covering 128 consecutive spins of one replica.
     const bool adam = a.opt == ISING_OPT_ADAM;
-    const unsigned char f8p = FORM == DF_FP8 ? fp8_of(1.f) : 0, f8m = FORM == DF_FP8 ? fp8_of(-1.f) : 0;
+    // the vertex bytes of +1 and -1 (FP8 or INT8)
+    const unsigned char f8p = FORM == DF_FP8 ? fp8_of(1.f) : 1, f8m = FORM == DF_FP8 ? fp8_of(-1.f) : 0xff;
+    const float jp = int8_form(FORM) ? *a.jpow : 1.f;  // 2^e
     float *T = (float *)lds;  // [64 replicas][TST]
     const int g = tid & 31;   // spin group: rows 4g .. 4g+3 of the tile
     const int i0 = row0 + 4 * g;
@@ -681,6 +794,9 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                 if constexpr (FORM == DF_FP8)
 #pragma unroll
                     for (int u = 0; u < 4; ++u) yv[u] *= a.jscale;  // exact: integers below 2^24
+                if constexpr (int8_form(FORM))
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) yv[u] = (float)__builtin_bit_cast(int, yv[u]) * jp;  // one rounding
                 const size_t base = (size_t)r * a.n + i0;
                 unsigned short sb[4];
                 float sf[4];
@@ -732,7 +848,7 @@ __device__ __forceinline__ void dense_step_body(const DenseDescG &a, const int t
                 const size_t sbase = (size_t)r * a.Kp + i0;  // Kp % 64 == 0, i0 % 4 == 0: aligned
                 if (FORM == DF_FP32) {
                     *(float4 *)((float *)S_out + sbase) = make_float4(sf[0], sf[1], sf[2], sf[3]);
-                } else if (FORM == DF_FP8) {
+                } else if (byte_form(FORM)) {
                     uint32_t w = 0;
 #pragma unroll
                     for (int u = 0; u < 4; ++u) w |= (uint32_t)(sf[u] == 0.f ? 0 : sf[u] < 0.f ? f8m : f8p) << (8 * u);
@@ -802,18 +918,32 @@ __global__ __launch_bounds__(256) void k_dense_best(const DenseDesc *__restrict_
 }  // namespace
 
 hipError_t launch_dense_prepare(const DevProblem &p, int form, int Mp, int Kp, void *Jhi, void *Jlo, void *Jf,
-                                float *hf, hipStream_t s) {
+                                float *hf, void *jsc, hipStream_t s) {
     const int64_t total = (int64_t)Mp * Kp;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
+    const int32_t *jexp = nullptr;
+    if (int8_form(form)) {
+        if (!jsc) return hipErrorInvalidValue;
+        // a fill kernel would do as well; this runs before any captured launch sequence
+        hipError_t e = hipMemsetAsync(jsc, 0, 16, s);
+        if (e != hipSuccess) return e;
+        const int rb = std::min(p.n, 4096);
+        unsigned long long *mx = (unsigned long long *)jsc;
+        if (p.vtype == ISING_I32) hipLaunchKernelGGL(k_dense_absmax<int32_t>, dim3(rb), dim3(256), 0, s, p, mx);
+        else if (p.vtype == ISING_F32) hipLaunchKernelGGL(k_dense_absmax<float>, dim3(rb), dim3(256), 0, s, p, mx);
+        else hipLaunchKernelGGL(k_dense_absmax<double>, dim3(rb), dim3(256), 0, s, p, mx);
+        hipLaunchKernelGGL(k_dense_exponent, dim3(1), dim3(1), 0, s, p.n, jdigits(form), mx);
+        jexp = (const int32_t *)((const char *)jsc + 20);
+    }
     if (p.vtype == ISING_I32)
         hipLaunchKernelGGL(k_dense_split<int32_t>, dim3(blocks), dim3(256), 0, s, p, Mp, Kp, form,
-                           (unsigned short *)Jhi, (unsigned short *)Jlo, (float *)Jf, hf);
+                           (unsigned short *)Jhi, (unsigned short *)Jlo, (float *)Jf, hf, jexp);
     else if (p.vtype == ISING_F32)
         hipLaunchKernelGGL(k_dense_split<float>, dim3(blocks), dim3(256), 0, s, p, Mp, Kp, form,
-                           (unsigned short *)Jhi, (unsigned short *)Jlo, (float *)Jf, hf);
+                           (unsigned short *)Jhi, (unsigned short *)Jlo, (float *)Jf, hf, jexp);
     else
         hipLaunchKernelGGL(k_dense_split<double>, dim3(blocks), dim3(256), 0, s, p, Mp, Kp, form,
-                           (unsigned short *)Jhi, (unsigned short *)Jlo, (float *)Jf, hf);
+                           (unsigned short *)Jhi, (unsigned short *)Jlo, (float *)Jf, hf, jexp);
     return hipGetLastError();
 }
 
@@ -839,8 +969,9 @@ static DenseDesc make_desc(const DenseRun &d) {
     a.Jlo = (const unsigned short *)d.Jlo;
     a.Jf = (const float *)d.Jf;
     a.h = d.h;
-    const size_t sbytes = d.form == DF_FP32 ? 4 : d.form == DF_FP8 ? 1 : 2;
+    const size_t sbytes = dense_vertex_bytes(d.form);
     a.jscale = d.form == DF_FP8 ? d.jscale : 1.f;
+    a.jpow = int8_form(d.form) ? (const float *)((const char *)d.jsc + 16) : nullptr;
     a.S0 = (char *)d.S;
     a.S1 = (char *)d.S + (size_t)d.R * d.Kp * sbytes;
     a.S2 = (char *)d.S + (size_t)2 * d.R * d.Kp * sbytes;
@@ -884,8 +1015,9 @@ hipError_t dense_group_upload(const DenseRun *const *runs, int count, void *scra
     std::vector<int4> per_xcd[kXcds];
     for (int k = 0; k < count; ++k) {
         const DenseRun &d = *runs[k];
-        if (d.form != form || d.Mp % BM || d.Kp % (d.form == DF_FP8 ? 2 * KCB : KCB) || d.Mp < d.n || d.Kp < d.n)
+        if (d.form != form || d.Mp % BM || d.Kp % (byte_form(d.form) ? 2 * KCB : KCB) || d.Mp < d.n || d.Kp < d.n)
             return hipErrorInvalidValue;
+        if (int8_form(d.form) && !d.jsc) return hipErrorInvalidValue;
         if (d.opt == ISING_OPT_ADAM && !d.bias) return hipErrorInvalidValue;
         descs.push_back(make_desc(d));
         const int MT = d.Mp / BM, NT = (d.R + tile_bn(form) - 1) / tile_bn(form);
@@ -937,6 +1069,8 @@ hipError_t dense_group_launch(const DenseGroupShape &shape, void *scratch, int s
         if (shape.form == DF_FP32) hipLaunchKernelGGL(k_dense_step<DF_FP32>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
         else if (shape.form == DF_BF16X2) hipLaunchKernelGGL(k_dense_step<DF_BF16X2>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
         else if (shape.form == DF_FP8) hipLaunchKernelGGL(k_dense_step<DF_FP8>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
+        else if (shape.form == DF_I8X3) hipLaunchKernelGGL(k_dense_step<DF_I8X3>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
+        else if (shape.form == DF_I8X2) hipLaunchKernelGGL(k_dense_step<DF_I8X2>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
         else hipLaunchKernelGGL(k_dense_step<DF_BF16>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
     }
     // the last step's best-vertex bookkeeping (earlier steps are kept inside the next step)
@@ -954,7 +1088,7 @@ hipError_t launch_dense_group(const DenseRun *const *runs, int count, int steps,
 
 hipError_t launch_dense_init(const DenseRun &d, hipStream_t s) {
     // (re)derive the vertex buffer from theta at every chunk; initialise the state at t0 = 0
-    const size_t sbytes = d.form == DF_FP32 ? 4 : d.form == DF_FP8 ? 1 : 2;
+    const size_t sbytes = dense_vertex_bytes(d.form);
     char *S0 = (char *)d.S;
     char *S1 = S0 + (size_t)d.R * d.Kp * sbytes;
     char *S2 = S1 + (size_t)d.R * d.Kp * sbytes;

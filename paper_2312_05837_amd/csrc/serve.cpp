@@ -121,9 +121,11 @@ size_t footprint(const Request &q) {
     const size_t vs = vsize(q.hp.value_type);
     size_t b = 0;
     if (q.hp.format == ISING_DENSE) {
-        const size_t Mp = (n + 127) / 128 * 128, Kp = (n + 63) / 64 * 64;
+        // (K padded to 128 covers every form's padding; 4 bytes per element covers every
+        // form's J and vertex operands)
+        const size_t Mp = (n + 127) / 128 * 128, Kp = (n + 127) / 128 * 128;
         b += n * n * vs;                 // J
-        b += Mp * Kp * 4;                // split or FP32 operand
+        b += Mp * Kp * 4 + kDenseScaleBytes;  // split, digit planes or FP32 operand
         b += kDenseVertexBufs * R * Kp * 4;  // vertex buffers
         b += 2 * (Mp / 128) * R * 8;     // energy partials, by step parity
     } else {

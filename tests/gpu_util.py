@@ -31,6 +31,29 @@ def as_float32_instance(inst):
     return out
 
 
+def int8_represented(inst, digits):
+    """The couplings the INT8 matrix-core forms compute with: J = 2^e Jq, Jq = rint(J / 2^e), e the
+    smallest exponent in [-126, 127] with max|J| <= 2^e qmax and max_i sum_j |J_ij| + 2^e 257 n <=
+    2^e (2^31 - 1) (qmax = 8355711 for three INT8 digits, 32639 for two), as the library documents
+    the form; returns (instance with those couplings, e)."""
+    qmax = {3: 8355711.0, 2: 32639.0}[digits]
+    J = inst.J
+    big = float(np.abs(J).max())
+    rsum = float(np.abs(J).sum(axis=1).max())
+    lim = 2.0 ** 31 - 1
+
+    def fits(e):
+        return big <= np.ldexp(qmax, e) and rsum + np.ldexp(257.0 * inst.n, e) <= np.ldexp(lim, e)
+
+    e = -126
+    while e < 127 and not fits(e):
+        e += 1
+    Jq = np.rint(np.ldexp(J, -e))
+    assert np.abs(Jq).max() <= qmax
+    rep = I.Instance(inst.n, f"{inst.name}/i8x{digits}", inst.h.copy(), np.ldexp(Jq, e), integer=inst.integer)
+    return rep, e
+
+
 def energy_bound(inst):
     """gamma_{n+1} (sum|J| + sum|h|): summation error bound of an FP64 energy in any order."""
     u = 2.0 ** -53

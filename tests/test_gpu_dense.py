@@ -16,7 +16,7 @@ import pytest
 
 import instances as I
 import oracle
-from gpu_util import to_problem, iterate_error, compare_trajectories
+from gpu_util import to_problem, iterate_error, compare_trajectories, int8_represented
 
 pytestmark = pytest.mark.gpu
 
@@ -123,7 +123,7 @@ def test_solve_dense_engine_energy_recomputed_fp64(ctx):
     import torch
     import paper_2312_05837_amd as P
     inst = I.sk_gauss(400, 9)
-    for prec in ("fp32", "bf16x2", "bf16"):
+    for prec in ("fp32", "bf16x2", "bf16", "i8x3", "i8x2"):
         s, E, Ei, st = P.ising_solve_dev(ctx, to_problem(inst), P.params(replicas=256, steps=200, precision=prec,
                                                                            optimizer="adam", lr=6.0, mu=0.5))
         torch.cuda.synchronize()
@@ -190,19 +190,69 @@ def test_solve_fp8_form_integer_energy(ctx):
     assert np.array_equal(res["fp8"][0], res["fp32"][0]) and np.array_equal(res["fp8"][0], res["bf16"][0])
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x2", 2e-4)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x2", 2e-4), ("i8x3", 1e-5)])
 def test_full_size_sk2000(ctx, prec, tol):
     # the precision-form workload at its own size: dense SK N = 2000, J ~ N(0, 1/N), R = 256
     # replicas (the oracle on the first and last 64), GD lr 0.01 over 100 steps in 10 calls.
     # FP32: the FP32 matrix-core form at the FP32 bar.  BF16X2: J as hi + lo BF16 parts
-    # (relative error <= 2^-16 per entry) at the BF16X2 bar.
+    # (relative error <= 2^-16 per entry) at the BF16X2 bar.  I8X3: the oracle on the couplings
+    # it represents (2^e Jq) at the FP32 bar.
     import paper_2312_05837_amd as P
     inst = I.sk_gauss(2000, 0)
+    ref_inst = int8_represented(inst, 3)[0] if prec == "i8x3" else inst
     R = 256
     U = I.uniform_draws(5, R, inst.n)
     got = _run(ctx, inst, R, 100, "gd", 0.01, prec, 10, U)
     assert P.ising_last_kernel(ctx) == f"k_dense_step<{prec}>", P.ising_last_kernel(ctx)
     got["loss_trace"] = np.zeros_like(got["energy_trace"])
-    worst, excl = compare_trajectories(inst, got, U, 100, "gd", 0.01, 10, TOL=tol, check_loss=False,
+    worst, excl = compare_trajectories(ref_inst, got, U, 100, "gd", 0.01, 10, TOL=tol, check_loss=False,
                                        max_excluded=8)
     print(f"sk2000 {prec}: worst iterate error vs FP64 oracle {worst:.2e}, excluded {excl}/128")
+
+
+# ---- INT8 forms: J = 2^e Jq, Jq of three (two) balanced INT8 digits, exact int32 products ------
+
+def test_int8_forms_exact_on_integer_couplings(ctx):
+    # J = +-3 with integer fields (n = 300: K padding and a ragged spin tile; R = 130: a ragged
+    # replica tile): J / 2^e is an integer, so the products are exact and I8X3 and I8X2 requests
+    # give the FP8 form's iterates, energies and best vertices bit for bit
+    import paper_2312_05837_amd as P
+    pm = I.sk_pm1(300, 11)
+    h = np.random.default_rng(12).integers(-4, 5, size=300)
+    inst = I.Instance(300, "sk_pm3_field_300", h, pm.J * 3, integer=True)
+    U = I.uniform_draws(13, 130, inst.n)
+    a = _run(ctx, inst, 130, 60, "adam", 6.0, "fp8", 2, U)
+    for prec in ("i8x3", "i8x2"):
+        b = _run(ctx, inst, 130, 60, "adam", 6.0, prec, 2, U)
+        assert P.ising_last_kernel(ctx) == f"k_dense_step<{prec}>", P.ising_last_kernel(ctx)
+        for k in ("theta", "m", "v", "s_best", "e_best", "best_step", "energy_trace"):
+            assert np.array_equal(a[k], b[k]), (prec, k)
+
+
+@pytest.mark.parametrize("prec,digits", [("i8x3", 3), ("i8x2", 2)])
+@pytest.mark.parametrize("opt,lr,steps", [("gd", 0.01, 100), ("adam", 0.02, 30)])
+def test_int8_forms_gaussian_iterates(ctx, prec, digits, opt, lr, steps):
+    # Gaussian couplings with a field, n = 300: the FP64 oracle run on the couplings the form
+    # represents (2^e Jq) at the FP32 bar; its product is exact in int32 and y is rounded once,
+    # so only the FP32 iterate arithmetic differs.  For two digits 2^e is about 2^-16 of max|J|,
+    # so a wrong exponent or digit would show at this bar; three digits are compared the same way.
+    base = I.sk_gauss(300, 21)
+    inst = I.Instance(300, "g300h", np.random.default_rng(22).normal(size=300), base.J, integer=False)
+    rep, e = int8_represented(inst, digits)
+    U = I.uniform_draws(23, 96, inst.n)
+    chunks = 10 if steps == 100 else 3
+    got = _run(ctx, inst, 96, steps, opt, lr, prec, chunks, U)
+    got["loss_trace"] = np.zeros_like(got["energy_trace"])
+    worst, excl = compare_trajectories(rep, got, U, steps, opt, lr, chunks, check_loss=False)
+    rel = np.abs(rep.J - inst.J).max() / np.abs(inst.J).max()
+    print(f"{prec} {opt}: e = {e}, max |J - 2^e Jq| / max|J| = {rel:.1e}, "
+          f"worst iterate error vs FP64 oracle on 2^e Jq {worst:.2e}, excluded {excl}/96")
+
+
+def test_int8_forms_rejected_for_sparse(ctx):
+    import paper_2312_05837_amd as P
+    inst = I.torus(10, 10, 1, "pm1")
+    for prec in ("i8x3", "i8x2"):
+        with pytest.raises(P.IsingError) as e:
+            P.ising_solve_dev(ctx, to_problem(inst), P.params(replicas=64, steps=10, precision=prec))
+        assert e.value.status == P.ISING_ENOTSUP
