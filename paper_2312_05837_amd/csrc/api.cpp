@@ -291,7 +291,7 @@ ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params 
 }
 
 ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
-                        Pool &pool, hipStream_t s, DSArgs &a, DSPlan &plan, bool register_only) {
+                        Pool &pool, hipStream_t s, DSArgs &a, DSPlan &plan, bool register_only, bool batched) {
     if (prm.replicas <= 0) return fail(ctx, ISING_EINVAL, "bad replicas");
     if (prm.optimizer != ISING_OPT_GD && prm.optimizer != ISING_OPT_ADAM)
         return fail(ctx, ISING_EINVAL, "unknown optimizer");
@@ -320,7 +320,19 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
     a.loss = prm.loss;
     a.conv_tol = prm.conv_tol > 0 ? prm.conv_tol : 0.0;
     a.conv_window = prm.conv_window;
-    if ((plan.packed || plan.mult) && plan.l.ept > 0 && plan.l.ept <= 8) {
+    // Small problems with +-w couplings of degree <= 4 (tori, 3-regular graphs): the fixed-width-row
+    // form with one replica per workgroup of four wavefronts and 4 or 8 spins per thread, instead
+    // of the staged image (which puts four replicas in a workgroup and gathers through LDS)
+    bool small_rows = false;
+    if (plan.packed && !batched && !fp64 && !plan.l.relaxed && ing.maxdeg() <= kEllWidth && pme_small_ept(p.n) > 0 &&
+        plan.l.ept > 0) {
+        small_rows = true;
+        plan.l.coupling = CK_PM;
+        plan.l.rg = 1;
+        plan.l.ept = pme_small_ept(p.n);
+        plan.l.block = kPmeSmallBlock;
+    }
+    if (!small_rows && (plan.packed || plan.mult) && plan.l.ept > 0 && plan.l.ept <= 8) {
         const double wunit = plan.packed ? ing.w : 1.0;
         // stage the +-w couplings in LDS when the image fits next to the vertex buffers (and,
         // for the relaxed loss, next to sin(theta) and its negation)
@@ -356,9 +368,9 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
     // wide packed engine (one replica per workgroup, 8+ spins per thread): fixed-width neighbour
     // rows and a per-position field, loaded ahead of each spin's update, when every degree fits
     // them; the workgroup is then the launch bound of its spins per thread
-    if (plan.packed && plan.l.coupling == CK_PM && plan.l.ept >= 8 && plan.l.rg == 1 && !plan.l.relaxed &&
+    if (plan.packed && plan.l.coupling == CK_PM && (plan.l.ept >= 8 || small_rows) && plan.l.rg == 1 && !plan.l.relaxed &&
         ing.maxdeg() <= kEllWidth && (int64_t)plan.l.ept * ds_block_limit(plan.l.ept) < 32768) {
-        plan.l.block = ds_block_limit(plan.l.ept);
+        if (!small_rows) plan.l.block = ds_block_limit(plan.l.ept);
         void *ell = nullptr, *hrow = nullptr;
         const size_t pos = (size_t)plan.l.ept * plan.l.block;
         HIP_TRY(ctx, pool.get("ds.ell", pos * kEllWidth * 4, &ell));

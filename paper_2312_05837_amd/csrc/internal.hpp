@@ -162,9 +162,14 @@ hipError_t launch_bias_table(double b1, double b2, int t0, int steps, bool fp64,
 int32_t ds_max_n(bool fp64);
 // largest workgroup of the persistent engine with `ept` spins per thread (0: streaming)
 int ds_block_limit(int ept);
+// The fixed-width-row form for small problems: one replica per workgroup of kPmeSmallBlock
+// threads with pme_small_ept(n) spins per thread (4 up to n = 1024, 8 up to 2048; 0 above).
+constexpr int kPmeSmallBlock = 256;
+int pme_small_ept(int n);
 // Fixed-width neighbour rows (DSArgs::ell, DSArgs::ellh) from the sign-packed CSR; every
-// degree <= kEllWidth, block = ds_block_limit(ept), ept * block < 32768.  hf: the field in FP32
-// (nullable).  ell: ept * block * kEllWidth words; hrow: ept * block floats.
+// degree <= kEllWidth, block = ds_block_limit(ept) (or kPmeSmallBlock with pme_small_ept(n)),
+// ept * block < 32768.  hf: the field in FP32 (nullable).  ell: ept * block * kEllWidth words;
+// hrow: ept * block floats.
 hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, int ept, int block,
                              uint32_t *ell, float *hrow, hipStream_t s);
 // Build the CK_PMS image; writes the total group count to *total_groups (host,

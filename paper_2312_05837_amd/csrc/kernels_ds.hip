@@ -450,7 +450,9 @@ __device__ __forceinline__ int local_index(int i) {
 // PLAIN (fixed-width-row form without the loss only): unit couplings (w = 1) and no field, so the
 // product is the integer sum itself and no per-position field is loaded; the same results as
 // the general form (y = fma(1, sum, 0) = sum exactly).
-template <typename Real, int CK, int RG, int EPT, int OPT = -1, bool LOSS = true, bool PLAIN = false>
+// LBX (fixed-width-row form only): the workgroup size when it is not launch_bound(EPT): small
+// problems run one replica per workgroup of one or two wavefronts (pme_small_block).
+template <typename Real, int CK, int RG, int EPT, int OPT = -1, bool LOSS = true, bool PLAIN = false, int LBX = 0>
 __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     using SWd = SpinWord<RG>;
     using SW = typename SWd::T;
@@ -475,7 +477,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     // The fixed-width-row form runs with B = launch_bound(EPT) (checked at launch), so its
     // positions e LB + tid and the parity stride of its vertex buffer are compile-time constants
     // and its LDS reads and writes take them as immediate offsets.
-    constexpr int LB = launch_bound(EPT);
+    constexpr int LB = LBX > 0 ? LBX : launch_bound(EPT);
     constexpr int TWS = twin_stride(EPT, LB);
     const int npad = EPT * B + 1;
     // (the fixed-width-row form's vertex buffers are static, outside the dynamic LDS)
@@ -1217,9 +1219,9 @@ __global__ __launch_bounds__(kSplitBlock) void k_ds_split(const DSArgs a, int bi
     }
 }
 
-template <typename Real, int CK, int RG, int EPT, int OPT = -1, bool LOSS = true, bool PLAIN = false>
-__global__ __launch_bounds__(launch_bound(EPT)) void k_ds(const DSArgs a) {
-    ds_body<Real, CK, RG, EPT, OPT, LOSS, PLAIN>(a, blockIdx.x * RG);
+template <typename Real, int CK, int RG, int EPT, int OPT = -1, bool LOSS = true, bool PLAIN = false, int LBX = 0>
+__global__ __launch_bounds__(LBX > 0 ? LBX : launch_bound(EPT)) void k_ds(const DSArgs a) {
+    ds_body<Real, CK, RG, EPT, OPT, LOSS, PLAIN, LBX>(a, blockIdx.x * RG);
 }
 
 // Batched form for serving: workgroup b runs replica group map[b].y of problem
@@ -1731,8 +1733,13 @@ KFn pick_rg(int rg, int ept) {
     }
 }
 
+// workgroup sizes of the fixed-width-row form: launch_bound(ept), or the small-problem blocks
+bool pme_block_ok(int ept, int block) {
+    return block == launch_bound(ept) || (block == kPmeSmallBlock && (ept == 4 || ept == 8));
+}
+
 template <typename Real>
-KFn pick(int ck, int rg, int ept, bool adam, bool loss, bool plain) {
+KFn pick(int ck, int rg, int ept, bool adam, bool loss, bool plain, int block) {
     switch (ck) {
         case CK_PM: return pick_rg<Real, CK_PM>(rg, ept);
         case CK_PMS: return ept > 0 ? pick_rg<Real, CK_PMS>(rg, ept) : nullptr;
@@ -1742,16 +1749,18 @@ KFn pick(int ck, int rg, int ept, bool adam, bool loss, bool plain) {
                 if (rg != 1) return nullptr;
                 // the optimizer compiled in (these kernels run the longest per launch), whether the
                 // loss is needed (a trace or the convergence test), and unit couplings without a field
-#define ISING_PME(E)                                                                                      \
-    if (ept == E) {                                                                                       \
-        if (loss) return adam ? k_ds<Real, CK_PME, 1, E, 1, true> : k_ds<Real, CK_PME, 1, E, 0, true>;      \
-        if (plain) return adam ? k_ds<Real, CK_PME, 1, E, 1, false, true> : k_ds<Real, CK_PME, 1, E, 0, false, true>; \
-        return adam ? k_ds<Real, CK_PME, 1, E, 1, false> : k_ds<Real, CK_PME, 1, E, 0, false>;              \
+#define ISING_PME(E, LBX)                                                                                 \
+    if (ept == E && block == (LBX > 0 ? LBX : launch_bound(E))) {                                          \
+        if (loss) return adam ? k_ds<Real, CK_PME, 1, E, 1, true, false, LBX> : k_ds<Real, CK_PME, 1, E, 0, true, false, LBX>; \
+        if (plain) return adam ? k_ds<Real, CK_PME, 1, E, 1, false, true, LBX> : k_ds<Real, CK_PME, 1, E, 0, false, true, LBX>; \
+        return adam ? k_ds<Real, CK_PME, 1, E, 1, false, false, LBX> : k_ds<Real, CK_PME, 1, E, 0, false, false, LBX>; \
     }
-                ISING_PME(8)
-                ISING_PME(16)
-                ISING_PME(28)
-                ISING_PME(32)
+                ISING_PME(8, 0)
+                ISING_PME(16, 0)
+                ISING_PME(28, 0)
+                ISING_PME(32, 0)
+                ISING_PME(4, kPmeSmallBlock)
+                ISING_PME(8, kPmeSmallBlock)
 #undef ISING_PME
             }
             return nullptr;
@@ -1765,6 +1774,8 @@ KFn pick(int ck, int rg, int ept, bool adam, bool loss, bool plain) {
 
 int ds_block_limit(int ept) { return ept > 0 ? launch_bound(ept) : 1024; }
 
+int pme_small_ept(int n) { return n <= 4 * kPmeSmallBlock ? 4 : n <= 8 * kPmeSmallBlock ? 8 : 0; }
+
 int32_t ds_max_n(bool fp64) {
     // streaming engine, one replica per workgroup: three byte-per-spin LDS buffers
     (void)fp64;
@@ -1773,7 +1784,7 @@ int32_t ds_max_n(bool fp64) {
 
 hipError_t launch_ell_format(const DevProblem &p, const uint32_t *pm, const float *hf, int ept, int block,
                              uint32_t *ell, float *hrow, hipStream_t s) {
-    if (p.format != ISING_CSR || ept <= 0 || block != launch_bound(ept) || (int64_t)ept * block < p.n)
+    if (p.format != ISING_CSR || ept <= 0 || !pme_block_ok(ept, block) || (int64_t)ept * block < p.n)
         return hipErrorInvalidValue;
     const int total = ept * block;
     hipLaunchKernelGGL(k_ell_format, dim3((total + 255) / 256), dim3(256), 0, s, p, pm, hf, ept, block, ell, hrow);
@@ -1800,13 +1811,13 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s, std::str
     const bool adam = a.opt == ISING_OPT_ADAM;
     const bool need_loss = a.ltrace != nullptr || a.conv_tol > 0;
     const bool plain = ck == CK_PME && !need_loss && a.h == nullptr && a.w == 1.0;
-    KFn fn = l.fp64 ? pick<double>(ck, l.rg, l.ept, adam, need_loss, plain)
-                    : pick<float>(ck, l.rg, l.ept, adam, need_loss, plain);
+    KFn fn = l.fp64 ? pick<double>(ck, l.rg, l.ept, adam, need_loss, plain, l.block)
+                    : pick<float>(ck, l.rg, l.ept, adam, need_loss, plain, l.block);
     if (!fn) return hipErrorInvalidValue;
     if (l.block % 64 || l.block < 64 || l.block > ds_block_limit(l.ept) || (l.ept > 0 && (int64_t)l.ept * l.block < a.n) ||
         a.R % l.rg)
         return hipErrorInvalidValue;
-    if (ck == CK_PME && (l.block != launch_bound(l.ept) || !a.ellh))  // its positions assume B = launch_bound
+    if (ck == CK_PME && (!pme_block_ok(l.ept, l.block) || !a.ellh))  // its positions assume B = its block
         return hipErrorInvalidValue;
     if (l.coupling == CK_PMS && a.pms_rb != pms_region_bytes(l)) return hipErrorInvalidValue;
     if ((a.loss == ISING_LOSS_RELAXED) != l.relaxed || (l.relaxed && l.ept <= 0))
@@ -1839,6 +1850,7 @@ hipError_t launch_ds(const DSArgs &a, const DSLaunch &l, hipStream_t s, std::str
         const char *ckn = ck >= 0 && ck < (int)(sizeof(cks) / sizeof(cks[0])) ? cks[ck] : "?";
         *kernel = std::string(l.ept > 0 ? "k_ds<" : "k_ds_stream<") + (l.fp64 ? "double" : "float") + ", " + ckn +
                   ", rg=" + std::to_string(l.rg) + ", ept=" + std::to_string(l.ept) +
+                  (ck == CK_PME && l.block != launch_bound(l.ept) ? ", block=" + std::to_string(l.block) : "") +
                   (ck == CK_PME ? (need_loss ? ", loss" : plain ? ", no loss, unit" : ", no loss") : "") + ">";
     }
     return hipGetLastError();

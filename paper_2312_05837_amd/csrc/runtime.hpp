@@ -127,8 +127,10 @@ struct DSPlan {
 ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
                      DSPlan &plan, bool register_only = false);
 // Device formats and the problem/hyper-parameter fields of a DSArgs (state, steps left to the caller).
+// batched: the plan is for the batched (serving) launches, which take at most 4 spins per thread.
 ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
-                        Pool &pool, hipStream_t s, DSArgs &a, DSPlan &plan, bool register_only = false);
+                        Pool &pool, hipStream_t s, DSArgs &a, DSPlan &plan, bool register_only = false,
+                        bool batched = false);
 ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
                     const void *uniform, int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool,
                     hipStream_t s, hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr);

@@ -219,7 +219,8 @@ ising_status admit(Server &S, Request &q) {
             d.bias = (const float *)bias;
         }
     } else {
-        ST_TRY(prepare_ds(ctx, *q.red, q.prm, q.ing, pool, s, q.args, q.plan, /*register_only=*/true));
+        ST_TRY(prepare_ds(ctx, *q.red, q.prm, q.ing, pool, s, q.args, q.plan, /*register_only=*/true,
+                          /*batched=*/true));
         if (q.plan.l.ept > 4)  // the batched launches hold at most 4 spins per thread
             return fail(ctx, ISING_ENOTSUP, "served sparse problems need at most 4096 spins after pruning");
         q.args.theta = q.st.theta;

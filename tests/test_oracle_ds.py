@@ -309,6 +309,7 @@ def _lowered_cases():
     import test_gpu_dense as TD
     multi = {c[0]: c for c in T.MULTI}
     relaxed = {c[0]: c for c in T.RELAXED}
+    rows = {c[0]: c for c in T.ROWS_ORACLE}
     pm = I.sk_pm1(300, 11)
     pm3 = I.Instance(300, "sk_pm3_field_300", np.random.default_rng(12).integers(-4, 5, size=300), pm.J * 3,
                      integer=True)
@@ -317,6 +318,7 @@ def _lowered_cases():
         ("er_int3_mult_rg4", multi["er_int3_mult_rg4"][1], 1024, 11, "gd", 0.01, 100, "vertex"),
         ("er3000_rg2_ept4", multi["er3000_rg2_ept4"][1], 512, 11, "gd", 0.01, 100, "vertex"),
         ("split_er_int3", multi["er_int3_mult_rg4"][1], 1024, 43, "gd", 0.005, 100, "vertex"),
+        ("rows_reg3_1500_field5", rows["reg3_1500_field5_block256_ept8"][1], 256, 43, "gd", 0.01, 100, "vertex"),
         ("torus100x200_field63", lambda: I.random_integer_field(I.torus(100, 200, 26, "pm1"), 26, 63), 4, 11,
          "gd", 0.001, 100, "vertex"),
         ("dense_sk_pm1_300", TD.CASES[0][1], 200, 5, "gd", 0.01, 100, "vertex"),
@@ -335,7 +337,8 @@ def _lowered_cases():
     ]
 
 
-_LOWERED_IDS = ["er_int3_mult_rg4", "er3000_rg2_ept4", "split_er_int3", "torus100x200_field63", "dense_sk_pm1_300",
+_LOWERED_IDS = ["er_int3_mult_rg4", "er3000_rg2_ept4", "split_er_int3", "rows_reg3_1500_field5", "torus100x200_field63",
+                "dense_sk_pm1_300",
                 "dense_bf16_pm1_300", "dense_fp8_pm3_field_300", "relaxed_sk64_dense",
                 "relaxed_er800_pm1_packed_rg4", "relaxed_t1_uniform_real_csr_ept2", "paper_gd_sk64",
                 "paper_gd_er800", "paper_gd_sk2000_gauss", "paper_adam_sk64"]
