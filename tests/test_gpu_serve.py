@@ -258,3 +258,51 @@ def test_convergence_test_in_serving(ctx):
         assert np.array_equal(s.cpu().numpy(), spins), inst.name
         assert float(E.item()) == energy == oracle.energy(inst, spins)
         assert stats["converged"] == st["converged"] and stats["mean_steps_run"] == st["mean_steps_run"]
+
+
+def test_reduced_precision_dense_forms_in_serving(ctx):
+    # Gaussian dense requests in the BF16X2, I8X3 and I8X2 forms (float64 couplings; pruning keeps
+    # them whole) served together with integer sparse requests: each served result equals the same
+    # request served alone and the plain solve bit for bit, and its energy is the FP64 energy of
+    # its vector.
+    import torch
+    import paper_2312_05837_amd as P
+    from gpu_util import to_problem
+    dense = [(I.sk_gauss(300, 61), 128, 1, "bf16x2"), (I.sk_gauss(257, 62), 64, 2, "i8x3"),
+             (I.sk_gauss(500, 63), 256, 3, "i8x2"), (I.sk_gauss(300, 64), 128, 4, "i8x3")]
+    sparse = [(inst, R, seed, "fp32") for inst, R, seed in _requests(4, 9)]
+    reqs = dense + sparse
+
+    def serve(batch):
+        P.ising_serve_start(ctx, chunk_steps=50)
+        keep, tickets = [], []
+        for inst, R, seed, prec in batch:
+            if inst.is_dense and not inst.integer:
+                st, k = P.host_problem(inst.n, J=inst.J.astype(np.float64))
+            else:
+                st, k = _host(inst)
+            keep.append(k)
+            tickets.append(P.ising_submit(ctx, st, P.params(replicas=R, steps=200, optimizer="adam", lr=6.0,
+                                                             mu=0.5, seed=seed, precision=prec)))
+        res = [P.ising_wait(ctx, t, inst.n) for t, (inst, _, _, _) in zip(tickets, batch)]
+        P.ising_serve_stop(ctx)
+        return res
+
+    mix = serve(reqs)
+    for k, (inst, R, seed, prec) in enumerate(reqs):
+        status, spins, energy, _ = mix[k]
+        assert status == P.ISING_OK, (k, prec)
+        if inst.integer:
+            assert energy == oracle.energy(inst, spins)
+        else:
+            assert abs(energy - oracle.energy(inst, spins)) <= 1e-9 * np.abs(inst.J).sum()
+    for k in range(len(dense)):
+        inst, R, seed, prec = reqs[k]
+        alone = serve([reqs[k]])[0]
+        assert np.array_equal(alone[1], mix[k][1]) and alone[2] == mix[k][2], (k, prec)
+        s, E, Ei, st = P.ising_solve_dev(ctx, to_problem(inst), P.params(replicas=R, steps=200, optimizer="adam",
+                                                                          lr=6.0, mu=0.5, seed=seed,
+                                                                          precision=prec))
+        torch.cuda.synchronize()
+        assert np.array_equal(s.cpu().numpy(), mix[k][1]), (k, prec)
+        assert float(E.item()) == mix[k][2], (k, prec)
