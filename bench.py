@@ -415,13 +415,15 @@ def ttt_known_bench(args):
 
 def ttt_bench(args):
     """Time to the plain FP32 form's target energy on the SK-2000 Gaussian instance (R = 4096,
-    ADAM lr 6).  The best energy of 4096 replicas after T steps is a random outcome of chaotic
-    trajectories (any change of rounding gives another sample), so each figure is taken over
-    five seeds: the target is the median over the seeds of the FP32 form's best energy after
-    T = 2000 steps; each other form is solved with the same seeds for increasing step counts (a
-    shorter run is a prefix of a longer one, up to 2T), and its time to target is the median
-    wall time of the first count whose median best energy (the returned vectors re-evaluated
-    in FP64) reaches the target."""
+    ADAM lr 6), two ways.
+    - Single seed: the target is the FP32 form's best energy after T = 2000 steps with seed 1234;
+      each other form is solved with the same seed for increasing step counts (a shorter run is a
+      prefix of a longer one, up to 2T), and its time to target is the wall time of the first count
+      whose returned vector, re-evaluated exactly in FP64, reaches the target.
+    - Median over five seeds: the best energy of 4096 replicas is a random outcome of chaotic
+      trajectories (any change of rounding draws another sample), so the same is done with the
+      median over seeds 1234..1238 of the best energies as the target and as each form's figure,
+      and the median solve time."""
     import numpy as np
     import torch
     import paper_2312_05837_amd as P
@@ -445,26 +447,36 @@ def ttt_bench(args):
     def over_seeds(prec, steps):
         solve(prec, steps, seeds[0])  # warm-up of this shape
         r = [solve(prec, steps, sd) for sd in seeds]
-        return [x[0] for x in r], float(np.median([x[1] for x in r]))
+        return [x[0] for x in r], [x[1] for x in r]
 
-    e32, t_fp32 = over_seeds("fp32", T)
-    e_target = float(np.median(e32))
-    forms = {"fp32": {"steps": T, "time_s": t_fp32, "energies": e32, "median_energy": e_target}}
+    e32, t32 = over_seeds("fp32", T)
+    target1, t1_fp32 = e32[0], t32[0]
+    target5, t5_fp32 = float(np.median(e32)), float(np.median(t32))
+    forms = {"fp32": {"steps": T, "energies": e32, "times_s": t32,
+                      "seed_1234": {"steps": T, "time_s": t1_fp32, "energy": target1},
+                      "median_5_seeds": {"steps": T, "time_s": t5_fp32, "energy": target5}}}
     for prec in ("bf16x2", "bf16", "i8x3", "i8x2"):
-        forms[prec] = {"steps": None, "time_s": None}
+        f = {"seed_1234": {"steps": None, "time_s": None}, "median_5_seeds": {"steps": None, "time_s": None},
+             "energies_by_steps": {}}
         for steps in (125, 250, 500, 1000, 2000, 4000):
-            es, t = over_seeds(prec, steps)
-            forms[prec].update(last_steps=steps, energies=es, median_energy=float(np.median(es)))
-            if np.median(es) <= e_target:
-                forms[prec].update(steps=steps, time_s=t, speedup_vs_fp32=t_fp32 / t)
+            es, ts = over_seeds(prec, steps)
+            f["energies_by_steps"][steps] = es
+            if f["seed_1234"]["steps"] is None and es[0] <= target1:
+                f["seed_1234"] = {"steps": steps, "time_s": ts[0], "energy": es[0], "speedup_vs_fp32": t1_fp32 / ts[0]}
+            if f["median_5_seeds"]["steps"] is None and np.median(es) <= target5:
+                tm = float(np.median(ts))
+                f["median_5_seeds"] = {"steps": steps, "time_s": tm, "energy": float(np.median(es)),
+                                       "speedup_vs_fp32": t5_fp32 / tm}
+            if f["seed_1234"]["steps"] is not None and f["median_5_seeds"]["steps"] is not None:
                 break
+        forms[prec] = f
     P.ising_destroy(ctx)
     print(json.dumps({"metric": "time-to-target energy", "unit": "s", "higher_is_better": False, "n_gpus": 1,
                       "data": "synthetic", "config": {"workload": "SK N=2000, J~N(0,1/N), R=4096, ADAM lr 6",
                                                       "seeds": list(seeds),
-                                                      "target": "median over the seeds of the FP32 form's best "
-                                                                "energy after 2000 steps"},
-                      "target_energy": e_target, "forms": forms}))
+                                                      "target": "the FP32 form's best energy after 2000 steps "
+                                                                "(seed 1234; and the median over the seeds)"},
+                      "target_energy": target1, "target_energy_median": target5, "forms": forms}))
 
 
 def serve_bench(args):
@@ -830,6 +842,7 @@ def main():
     out = {
         "metric": "replica-spin updates/s",
         "value": value,
+        "value_with_n": inst.n * R * T_eff / (ms_per_step * 1e-3),  # the same rate counted over all n spins
         "unit": "replica-spin updates/s",
         "n_gpus": 1,
         "steps": args.steps,
