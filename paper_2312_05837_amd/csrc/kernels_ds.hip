@@ -685,6 +685,18 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         for (int e = 0; e < EPT; ++e) b |= (*(LdsI8 *)(size_t)tw_pos(par, e) < 0 ? 1u : 0u) << e;
         best = b;
     };
+    // The small-problem fixed-width-row form (a few spins per thread) keeps its records and fields
+    // in registers for the whole run; the large one loads them ahead of each spin in every step.
+    constexpr bool ELL_RES = CK == CK_PME && LBX > 0;
+    U32x4 nbw_res[ELL_RES ? EPT : 1];
+    Real hres[ELL_RES && !PLAIN ? EPT : 1];
+    if constexpr (ELL_RES) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            nbw_res[e] = ((const GlobalU32x4 *)((uintptr_t)a.ell + (size_t)e * LB * 16))[tid];
+            if constexpr (!PLAIN) hres[e] = ((const GlobalF32 *)((uintptr_t)a.ellh + (size_t)e * LB * 4))[tid];
+        }
+    }
     // One step t (read parity (t - 1) & 1); returns true when every replica has stopped.
     auto step = [&](auto PC, const int t) __attribute__((always_inline)) -> bool {
         // read parity: compile-time for the fixed-width-row form (RP = 0 at odd t, 1 at even t)
@@ -707,7 +719,7 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
         // stay inside the step instead of being hoisted for every spin)
         constexpr bool WIDE_ELL = CK == CK_PME;
         constexpr int ELL_AHEAD = EPT >= 28 ? 2 : 4;  // the widest variants leave little register room
-        constexpr bool use_ell = WIDE_ELL;
+        constexpr bool use_ell = WIDE_ELL && !ELL_RES;
         // a spin's record is contiguous: its four entries in one 16-byte load per lane, coalesced
         // over the wave (every word used: a record with an unused word let that word's register be
         // reused while its load was in flight, which made every spin wait for the load issued
@@ -754,12 +766,13 @@ __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
                 // one replica per workgroup: the neighbours' terms sgn(J) s as signed bytes, read
                 // at immediate offsets of the read parity's buffer; y = w sum + h
                 const uint32_t sb = twb + RPc * TWS;
-                const int sum = (int)*(LdsI8 *)(size_t)(sb + nbw[e][0]) + (int)*(LdsI8 *)(size_t)(sb + nbw[e][1]) +
-                                (int)*(LdsI8 *)(size_t)(sb + nbw[e][2]) + (int)*(LdsI8 *)(size_t)(sb + nbw[e][3]);
+                const U32x4 rec = ELL_RES ? nbw_res[e] : nbw[e];
+                const int sum = (int)*(LdsI8 *)(size_t)(sb + rec[0]) + (int)*(LdsI8 *)(size_t)(sb + rec[1]) +
+                                (int)*(LdsI8 *)(size_t)(sb + rec[2]) + (int)*(LdsI8 *)(size_t)(sb + rec[3]);
 #pragma unroll
                 for (int r = 0; r < RG; ++r) {
                     if constexpr (PLAIN) y[r] = (Real)sum;
-                    else y[r] = dfma((Real)a.w, (Real)sum, hpre[e]);
+                    else y[r] = dfma((Real)a.w, (Real)sum, ELL_RES ? hres[e] : hpre[e]);
                 }
             } else {
                 coupling<Real, CK, RG>(a, i, sc, y);
