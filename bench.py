@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # the FP32 vector rate in lane operations (157.3 TFLOP/s counts an FMA as two): twice the figure
-# above, reached with packed FP32, which this build does not use; reported beside it
+# above, reached with packed FP32, which these kernels are compiled without; reported beside it
 FP32_VECTOR_LANE_OPS = 157.3e12 / 2
 # Algorithmic operations of one (spin, replica) update besides the coupling
 # product, counted from the step's formulas (sin, cos, sign, y+h, energy and
