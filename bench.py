@@ -65,6 +65,8 @@ WORKLOADS = {
     "sk2000pm1_fp8": ("dense SK N=2000 J=+-1, J and the vertex in FP8 on MFMA (exact)", "sk2000pm1", 4096, 2000, "fp8"),
     "sk2000pm1_bf16": ("dense SK N=2000 J=+-1, J and the vertex in BF16 on MFMA (exact)", "sk2000pm1", 4096, 2000,
                        "bf16"),
+    "sk2000int3_fp32": ("dense SK N=2000, integer J of magnitudes 1..3, FP32 request (runs one INT8 digit: exact)",
+                        "sk2000int3", 4096, 2000, "fp32"),
     "er800_relaxed": ("sparse Erdos-Renyi N=800 p=0.06 +-1 weights, CSR, relaxed-vertex loss (s~* = sin theta)",
                       "er", 1024, 5000, "fp32", {"loss": "relaxed"}),
     "maxcut3_1000": ("MaxCut-3 shape (Sec. IV-D): 3-regular N=1000, unit weights, through ising_from_maxcut",
@@ -77,13 +79,14 @@ WORKLOADS = {
 }
 DEFAULT_WORKLOAD = "torus20000"
 # peak rates of the matrix cores (dense, no sparsity), per precision of the coupling product
-MFMA_PEAK = {"bf16x2": 2.5e15, "bf16": 2.5e15, "fp8": 5.0e15, "fp32": 157.3e12, "i8x3": 5.0e15, "i8x2": 5.0e15}
+MFMA_PEAK = {"bf16x2": 2.5e15, "bf16": 2.5e15, "fp8": 5.0e15, "fp32": 157.3e12, "i8x3": 5.0e15, "i8x2": 5.0e15,
+             "i8x1": 5.0e15}
 # products the matrix cores execute per step, in units of one J S~ product
 DENSE_PRODUCTS = {"bf16x2": 2, "i8x3": 3, "i8x2": 2}
 HBM_PEAK = 8.0e12  # bytes/s
 # bytes per element of the vertex operand and of the stored couplings, per dense form
-DENSE_SB = {"fp32": 4, "bf16": 2, "bf16x2": 2, "fp8": 1, "i8x3": 1, "i8x2": 1}
-DENSE_JB = {"fp32": 4, "bf16": 2, "bf16x2": 4, "fp8": 1, "i8x3": 3, "i8x2": 2}
+DENSE_SB = {"fp32": 4, "bf16": 2, "bf16x2": 2, "fp8": 1, "i8x3": 1, "i8x2": 1, "i8x1": 1}
+DENSE_JB = {"fp32": 4, "bf16": 2, "bf16x2": 4, "fp8": 1, "i8x3": 3, "i8x2": 2, "i8x1": 1}
 
 # Sources of each dominant kernel: a recorded HBM traffic figure is used only
 # while these files are unchanged since the counters were taken.
@@ -240,6 +243,11 @@ def make_instance(kind, frontend="library"):
         return I.sk_gauss(2000, 0)
     if kind == "sk2000pm1":
         return I.sk_pm1(2000, 0)
+    if kind == "sk2000int3":  # the SK sign pattern with integer magnitudes 1..3
+        pm = I.sk_pm1(2000, 0)
+        mag = np.random.default_rng(1).integers(1, 4, size=(2000, 2000))
+        mag = np.triu(mag, 1) + np.triu(mag, 1).T
+        return I.Instance(2000, "sk2000_int3", np.zeros(2000, dtype=np.int64), pm.J * mag, integer=True)
     if kind == "t1binary":
         return I.table1_regular(1000, 6, "binary_int", 0)
     raise ValueError(kind)
@@ -785,11 +793,14 @@ def main():
     dense_mfma = inst.is_dense and (prec in ("bf16x2", "bf16", "fp8", "i8x3", "i8x2") or (prec == "fp32" and nG > 256))
     if dense_mfma:
         # the coupling product J S~ on the matrix cores: 2 n_G^2 R flops per step; integer
-        # couplings of one magnitude run the (exact) FP8 form even when FP32 is asked
+        # couplings of one magnitude run the (exact) FP8 form even when FP32 is asked, integer
+        # couplings up to 127 of several magnitudes the (exact) one-digit INT8 form
         form = prec
-        if prec == "fp32" and inst.integer and len(np.unique(np.abs(inst.J[inst.J != 0]))) <= 1 \
-                and np.abs(inst.J).max() * nG < 2 ** 24:
-            form = "fp8"
+        if prec == "fp32" and inst.integer and np.abs(inst.J).max() * nG < 2 ** 24:
+            if len(np.unique(np.abs(inst.J[inst.J != 0]))) <= 1:
+                form = "fp8"
+            elif np.abs(inst.J).max() <= 127:
+                form = "i8x1"
         # one launch per step (each also keeps the previous step's best vertices; one more launch
         # after the last step), timed together.  Matrix cores: 2 n^2 R flops.  HBM, algorithmic bytes: the
         # optimizer state read and written once (theta, m, v: 24 B; GD theta only: 8 B), the

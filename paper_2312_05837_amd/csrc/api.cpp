@@ -440,7 +440,8 @@ ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &
 constexpr int kDenseInt8MaxN = 65536;
 
 ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, Pool &pool,
-                           hipStream_t s, DenseRun &d, double unit) {
+                           hipStream_t s, DenseRun &d, const DenseExact &ex) {
+    const double unit = ex.unit;
     if (p.format != ISING_DENSE) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine needs dense couplings");
     if (prm.loss != ISING_LOSS_VERTEX) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs the vertex loss");
     if (prm.conv_tol > 0) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs fixed step counts");
@@ -448,7 +449,10 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
     // couplings of one integer magnitude w: J / w and the vertex are exact in FP8 and every
     // product and partial sum is an integer below 2^24, so the FP8 form gives the FP32
     // form's results bit for bit
+    // couplings that are integers up to 127 of several magnitudes: one INT8 digit holds them and
+    // every sum is an integer below 2^24, so that form gives the FP32 form's results too
     if (prm.precision == ISING_PREC_FP32 && unit > 0) form = DF_FP8;
+    else if (prm.precision == ISING_PREC_FP32 && ex.imax > 0) form = DF_I8X1;
     else if (prm.precision == ISING_PREC_FP32) form = DF_FP32;
     else if (prm.precision == ISING_PREC_BF16X2) form = DF_BF16X2;
     else if (prm.precision == ISING_PREC_BF16) form = DF_BF16;
@@ -459,7 +463,7 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
     else if (prm.precision == ISING_PREC_I8X2) form = DF_I8X2;
     else return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs FP32, BF16X2, BF16, FP8, I8X3 or I8X2");
     // INT8 forms: every partial sum stays below 2^31 only while 257 n is well below it
-    if ((form == DF_I8X3 || form == DF_I8X2) && p.n > kDenseInt8MaxN)
+    if ((form == DF_I8X3 || form == DF_I8X2 || form == DF_I8X1) && p.n > kDenseInt8MaxN)
         return fail(ctx, ISING_ENOTSUP, "the INT8 forms take n <= 65536");
     if (prm.replicas <= 0) return fail(ctx, ISING_EINVAL, "bad replicas");
     if (prm.optimizer != ISING_OPT_GD && prm.optimizer != ISING_OPT_ADAM)
@@ -470,7 +474,7 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
     d.R = R;
     d.Mp = (n + 127) / 128 * 128;
     // the K loops read 128 bytes of each row per chunk: 64 BF16 or 128 FP8 / INT8 values
-    const bool bytes = form == DF_FP8 || form == DF_I8X3 || form == DF_I8X2;
+    const bool bytes = form == DF_FP8 || form == DF_I8X3 || form == DF_I8X2 || form == DF_I8X1;
     d.Kp = bytes ? (n + 127) / 128 * 128 : (n + 63) / 64 * 64;
     d.jscale = form == DF_FP8 ? (float)unit : 1.f;
     d.form = form;
@@ -492,7 +496,7 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
     } else {
         HIP_TRY(ctx, pool.get("dn.Jhi", mk * dense_j_bytes(form), &Jhi));  // (INT8: the digit planes)
     }
-    if (form == DF_I8X3 || form == DF_I8X2) HIP_TRY(ctx, pool.get("dn.jsc", kDenseScaleBytes, &jsc));
+    if (form == DF_I8X3 || form == DF_I8X2 || form == DF_I8X1) HIP_TRY(ctx, pool.get("dn.jsc", kDenseScaleBytes, &jsc));
     if (p.h) HIP_TRY(ctx, pool.get("dn.h", (size_t)n * 4, &hf));
     HIP_TRY(ctx, pool.get("dn.S", (size_t)kDenseVertexBufs * R * d.Kp * dense_vertex_bytes(form), &S));
     HIP_TRY(ctx, pool.get("dn.Ep", (size_t)2 * (d.Mp / 128) * R * 4, &Ep));
@@ -510,14 +514,14 @@ ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_p
 }
 
 ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const void *uniform,
-                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s, double unit,
-                       hipEvent_t kbeg, hipEvent_t kend) {
+                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s,
+                       const DenseExact &ex, hipEvent_t kbeg, hipEvent_t kend) {
     if (steps < 0 || t0 < 0) return fail(ctx, ISING_EINVAL, "bad steps/t0");
     if (!st || !st->theta || !st->s_best || !st->e_best || !st->best_step)
         return fail(ctx, ISING_EINVAL, "state buffers missing");
     if (prm.optimizer == ISING_OPT_ADAM && (!st->m || !st->v)) return fail(ctx, ISING_EINVAL, "ADAM needs m and v");
     DenseRun d;
-    ST_TRY(prepare_dense(ctx, p, prm, pool, s, d, unit));
+    ST_TRY(prepare_dense(ctx, p, prm, pool, s, d, ex));
     d.t0 = t0;
     d.steps = steps;
     d.init_mode = t0 > 0 ? 0 : (uniform ? 1 : 2);
@@ -541,7 +545,7 @@ ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_param
     HIP_TRY(ctx, pool.get("dn.group", dense_group_scratch_bytes(&one, 1), &scratch));
     if (kbeg) HIP_TRY(ctx, hipEventRecord(kbeg, s));
     hipError_t e = launch_dense_run(d, scratch, s);
-    static const char *const forms[] = {"fp32", "bf16x2", "bf16", "fp8", "i8x3", "i8x2"};
+    static const char *const forms[] = {"fp32", "bf16x2", "bf16", "fp8", "i8x3", "i8x2", "i8x1"};
     ctx->last_kernel = std::string("k_dense_step<") + forms[d.form] + ">";
     if (e != hipSuccess)
         return fail(ctx, e == hipErrorInvalidValue ? ISING_ENOTSUP : ISING_EDEVICE,
@@ -561,8 +565,12 @@ bool use_dense_engine(const ising_problem &p, const ising_params &prm) {
     return prm.precision == ISING_PREC_FP32 && p.n > kDenseMfmaMinN;
 }
 
-double exact_unit(const Ingest &ing, int n) {
-    return ing.integer() && ing.uniform_mag() && (double)n * ing.w < 16777216.0 ? ing.w : 0.0;
+DenseExact dense_exact(const Ingest &ing, int n) {
+    DenseExact ex;
+    ex.unit = ing.integer() && ing.uniform_mag() && (double)n * ing.w < 16777216.0 ? ing.w : 0.0;
+    const int m = ing.integer() ? ing.max_abs_int() : 0;
+    ex.imax = m >= 1 && m <= 127 && (double)n * m < 16777216.0 ? m : 0;
+    return ex;
 }
 
 double ms_between(hipEvent_t a, hipEvent_t b) {
@@ -880,7 +888,7 @@ ising_status ising_ds_dense_dev(ising_ctx *ctx, const ising_problem *problem, co
     hipStream_t s = (hipStream_t)stream;
     Ingest ing;
     ST_TRY(ingest(ctx, to_dev(*problem), ctx->pool, ing, s));
-    return run_dense(ctx, *problem, *params, uniform, t0, steps, state, ctx->pool, s, exact_unit(ing, problem->n));
+    return run_dense(ctx, *problem, *params, uniform, t0, steps, state, ctx->pool, s, dense_exact(ing, problem->n));
 }
 
 ising_status ising_select_dev(ising_ctx *ctx, const double *e_best, int32_t replicas, int32_t *best,
@@ -957,7 +965,7 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
         HIP_TRY(ctx, pool.get("solve.bstep", (size_t)R * 4, (void **)&st.best_step));
         if (params->conv_tol > 0) HIP_TRY(ctx, pool.get("solve.conv", (size_t)R * 4, (void **)&st.conv_step));
         if (dense_engine)
-            ST_TRY(run_dense(ctx, *red, *params, nullptr, 0, params->steps, &st, pool, s, exact_unit(ing, red->n),
+            ST_TRY(run_dense(ctx, *red, *params, nullptr, 0, params->steps, &st, pool, s, dense_exact(ing, red->n),
                              ev[5], ev[6]));
         else ST_TRY(run_ds(ctx, *red, *params, ing, nullptr, 0, params->steps, &st, pool, s, ev[5], ev[6]));
         HIP_TRY(ctx, hipEventRecord(ev[3], s));

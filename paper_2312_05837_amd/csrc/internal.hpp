@@ -203,7 +203,7 @@ hipError_t launch_gather_row(const int8_t *block, int32_t n, const int32_t *best
                              hipStream_t s);
 
 // ---- domain selection for dense couplings on MFMA (kernels_dense.hip) --------
-enum DenseForm { DF_FP32 = 0, DF_BF16X2 = 1, DF_BF16 = 2, DF_FP8 = 3, DF_I8X3 = 4, DF_I8X2 = 5 };
+enum DenseForm { DF_FP32 = 0, DF_BF16X2 = 1, DF_BF16 = 2, DF_FP8 = 3, DF_I8X3 = 4, DF_I8X2 = 5, DF_I8X1 = 6 };
 
 // Vertex buffers of the matrix-core engine: step t reads buffer (t - 1) % 3 and writes t % 3, so
 // the vertex scored in step t - 1 stays intact while step t's tiles keep its best-vertex record.
@@ -241,7 +241,7 @@ constexpr size_t dense_vertex_bytes(int form) {
 }
 // J operand bytes per padded element of a form (all planes)
 constexpr size_t dense_j_bytes(int form) {
-    return form == DF_FP32 ? 4 : form == DF_BF16X2 ? 4 : form == DF_BF16 ? 2 : form == DF_I8X3 ? 3 : form == DF_I8X2 ? 2 : 1;
+    return form == DF_FP32 ? 4 : form == DF_BF16X2 ? 4 : form == DF_BF16 ? 2 : form == DF_I8X3 ? 3 : form == DF_I8X2 ? 2 : 1;  // FP8, I8X1
 }
 // State initialisation (t0 = 0) or vertex re-derivation (t0 > 0) before a chunk.
 hipError_t launch_dense_init(const DenseRun &d, hipStream_t s);

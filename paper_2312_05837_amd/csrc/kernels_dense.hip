@@ -20,7 +20,8 @@
 //   DF_FP8    couplings of one integer magnitude w: J / w = -1, 0, +1 and the vertex
 //             exact in FP8 (E4M3), v_mfma_f32_32x32x64_f8f6f4, y = w (J / w) S~ exact
 //   DF_I8X3   J = 2^e Jq with Jq an integer of three balanced INT8 digits (Jq = 65536 a +
-//   DF_I8X2   256 b + c; two digits for I8X2) and one power-of-two scale for the whole
+//   DF_I8X2   256 b + c; two digits for I8X2, one for I8X1, which FP32 requests on integer
+//   DF_I8X1   couplings up to 127 run: exact there) and one power-of-two scale for the whole
 //             matrix; the vertex +-1 in INT8; v_mfma_i32_32x32x32_i8 digit plane by digit
 //             plane with the accumulators multiplied by 256 between planes (Horner), so
 //             Jq S~ is exact in int32 and y = 2^e float(Jq S~) rounds once.  e is the
@@ -50,11 +51,11 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 
 // forms with one-byte operands (FP8, INT8) and the digit planes of J per product
-__host__ __device__ constexpr bool byte_form(int f) { return f == DF_FP8 || f == DF_I8X3 || f == DF_I8X2; }
-__host__ __device__ constexpr bool int8_form(int f) { return f == DF_I8X3 || f == DF_I8X2; }
+__host__ __device__ constexpr bool int8_form(int f) { return f == DF_I8X3 || f == DF_I8X2 || f == DF_I8X1; }
+__host__ __device__ constexpr bool byte_form(int f) { return f == DF_FP8 || int8_form(f); }
 __host__ __device__ constexpr int jdigits(int f) { return f == DF_I8X3 ? 3 : f == DF_I8X2 ? 2 : 1; }
 // largest |Jq| of D balanced INT8 digits: 127 (256^D - 1) / 255
-__host__ __device__ constexpr double jq_max(int D) { return D == 3 ? 8355711.0 : 32639.0; }
+__host__ __device__ constexpr double jq_max(int D) { return D == 3 ? 8355711.0 : D == 2 ? 32639.0 : 127.0; }
 
 constexpr int BM = 128, BN = 128, KC = 32;
 constexpr int KCB = 64;       // K chunk of the BF16 forms: one 128-byte line per row and chunk
@@ -70,7 +71,8 @@ constexpr int cmax(int x, int y) { return x > y ? x : y; }
 // as wide (256 replicas, 8 wavefronts, LDS double-buffered: one workgroup per CU): each staged
 // chunk of J then serves twice the replicas, which cuts the L2-to-CU operand traffic per product
 // by a third.
-__host__ __device__ constexpr bool wide_form(int f) { return f == DF_BF16X2 || int8_form(f); }
+// (one plane of one-byte operands, FP8 or INT8, runs faster on the 128 x 128 tiles)
+__host__ __device__ constexpr bool wide_form(int f) { return f == DF_BF16X2 || f == DF_I8X3 || f == DF_I8X2; }
 template <int FORM>
 struct TileShape {
     static constexpr bool WIDE = wide_form(FORM);
@@ -1071,6 +1073,7 @@ hipError_t dense_group_launch(const DenseGroupShape &shape, void *scratch, int s
         else if (shape.form == DF_FP8) hipLaunchKernelGGL(k_dense_step<DF_FP8>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
         else if (shape.form == DF_I8X3) hipLaunchKernelGGL(k_dense_step<DF_I8X3>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
         else if (shape.form == DF_I8X2) hipLaunchKernelGGL(k_dense_step<DF_I8X2>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
+        else if (shape.form == DF_I8X1) hipLaunchKernelGGL(k_dense_step<DF_I8X1>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
         else hipLaunchKernelGGL(k_dense_step<DF_BF16>, dim3(shape.tiles), blk, 0, s, dd, dt, t);
     }
     // the last step's best-vertex bookkeeping (earlier steps are kept inside the next step)

@@ -134,18 +134,24 @@ ising_status prepare_ds(ising_ctx *ctx, const ising_problem &p, const ising_para
 ising_status run_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
                     const void *uniform, int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool,
                     hipStream_t s, hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr);
-// Operands of the matrix-core engine (split J) and the problem fields of a DenseRun.
-// unit: the common magnitude w of exact integer couplings (see exact_unit), else 0; an
-// FP32 request on such couplings runs the FP8 form, which is exact there.
+// Integer couplings that a one-byte matrix-core form holds exactly.  unit: w when all nonzero
+// couplings are integers of one magnitude w and n w < 2^24 (every product of J / w with a vertex,
+// and every partial sum, is then exact in FP8 x FP8 with FP32 accumulation), else 0.  imax: the
+// largest |J| when the couplings are integers with |J| <= 127 and n |J| < 2^24 (one INT8 digit
+// holds them; every sum is an integer below 2^24), else 0.
+struct DenseExact {
+    double unit = 0.0;
+    int imax = 0;
+};
+DenseExact dense_exact(const Ingest &ing, int n);
+// Operands of the matrix-core engine (split J) and the problem fields of a DenseRun.  An FP32
+// request on exact integer couplings runs the FP8 form (one magnitude) or the INT8 form with
+// one digit (several magnitudes up to 127): exact there, with the FP32 form's results.
 ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, Pool &pool,
-                           hipStream_t s, DenseRun &d, double unit);
+                           hipStream_t s, DenseRun &d, const DenseExact &ex);
 ising_status run_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const void *uniform,
-                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s, double unit,
-                       hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr);
-// w when all nonzero couplings are integers of one magnitude w and n w < 2^24 (every
-// product of J / w with a vertex, and every partial sum, is then exact in FP8 x FP8 with
-// FP32 accumulation), else 0.
-double exact_unit(const Ingest &ing, int n);
+                       int32_t t0, int32_t steps, ising_ds_state *st, Pool &pool, hipStream_t s,
+                       const DenseExact &ex, hipEvent_t kbeg = nullptr, hipEvent_t kend = nullptr);
 bool use_dense_engine(const ising_problem &p, const ising_params &prm);
 double ms_between(hipEvent_t a, hipEvent_t b);
 

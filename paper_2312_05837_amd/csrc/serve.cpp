@@ -199,7 +199,7 @@ ising_status admit(Server &S, Request &q) {
     HIP_TRY(ctx, pool.get("ebest", (size_t)R * 8, (void **)&q.st.e_best));
     HIP_TRY(ctx, pool.get("bstep", (size_t)R * 4, (void **)&q.st.best_step));
     if (q.dense) {
-        ST_TRY(prepare_dense(ctx, *q.red, q.prm, pool, s, q.drun, exact_unit(q.ing, q.red->n)));
+        ST_TRY(prepare_dense(ctx, *q.red, q.prm, pool, s, q.drun, dense_exact(q.ing, q.red->n)));
         DenseRun &d = q.drun;
         d.lr = q.prm.lr;
         d.mu = q.prm.mu;

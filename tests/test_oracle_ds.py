@@ -324,6 +324,7 @@ def _lowered_cases():
         ("dense_sk_pm1_300", TD.CASES[0][1], 200, 5, "gd", 0.01, 100, "vertex"),
         ("dense_bf16_pm1_300", lambda: I.sk_pm1(300, 4), 64, 9, "gd", 0.01, 100, "vertex"),
         ("dense_fp8_pm3_field_300", lambda: pm3, 64, 14, "gd", 0.01, 100, "vertex"),
+        ("dense_i8x1_int3_field_300", TD.int3_field_300, 64, 75, "gd", 0.01, 100, "vertex"),
         ("relaxed_sk64_dense", relaxed["sk64_dense"][1], 32, 13, "gd", 0.01, 100, "relaxed"),
         ("relaxed_er800_pm1_packed_rg4", relaxed["er800_pm1_packed_rg4"][1], 1024, 13, "gd", 0.01, 100,
          "relaxed"),
@@ -339,7 +340,7 @@ def _lowered_cases():
 
 _LOWERED_IDS = ["er_int3_mult_rg4", "er3000_rg2_ept4", "split_er_int3", "rows_reg3_1500_field5", "torus100x200_field63",
                 "dense_sk_pm1_300",
-                "dense_bf16_pm1_300", "dense_fp8_pm3_field_300", "relaxed_sk64_dense",
+                "dense_bf16_pm1_300", "dense_fp8_pm3_field_300", "dense_i8x1_int3_field_300", "relaxed_sk64_dense",
                 "relaxed_er800_pm1_packed_rg4", "relaxed_t1_uniform_real_csr_ept2", "paper_gd_sk64",
                 "paper_gd_er800", "paper_gd_sk2000_gauss", "paper_adam_sk64"]
 
