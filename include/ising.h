@@ -87,10 +87,10 @@ enum { ISING_LOSS_VERTEX = 0, ISING_LOSS_RELAXED = 1 };
  * max|J_ij| <= 2^e qmax (qmax = 8355711 for three digits, 32639 for two) and
  * max_i sum_j |J_ij| + 2^e 257 n <= 2^e (2^31 - 1), so each entry carries an
  * absolute error of at most 2^(e-1) (none when J / 2^e is an integer, e.g.
- * +-1 couplings); FP32 iterates.  An FP32 request on dense integer couplings
- * with |J| <= 127 of several magnitudes (and n max|J| < 2^24) runs the same
- * form with one digit: exact, with the FP32 form's results.  The energy of the
- * returned vector is always
+ * +-1 couplings); FP32 iterates.  An FP32 request that runs on the matrix
+ * cores (dense, n > 256) with integer couplings |J| <= 127 of several
+ * magnitudes (and n max|J| < 2^24) runs the same form with one digit: exact,
+ * with the FP32 form's results.  The energy of the returned vector is always
  * recomputed in FP64 (or exactly for integer J). */
 enum {
     ISING_PREC_FP64 = 0,
