@@ -190,16 +190,16 @@ def test_solve_fp8_form_integer_energy(ctx):
     assert np.array_equal(res["fp8"][0], res["fp32"][0]) and np.array_equal(res["fp8"][0], res["bf16"][0])
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x2", 2e-4), ("i8x3", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x2", 2e-4), ("i8x3", 1e-5), ("i8x2", 1e-5)])
 def test_full_size_sk2000(ctx, prec, tol):
     # the precision-form workload at its own size: dense SK N = 2000, J ~ N(0, 1/N), R = 256
     # replicas (the oracle on the first and last 64), GD lr 0.01 over 100 steps in 10 calls.
     # FP32: the FP32 matrix-core form at the FP32 bar.  BF16X2: J as hi + lo BF16 parts
-    # (relative error <= 2^-16 per entry) at the BF16X2 bar.  I8X3: the oracle on the couplings
-    # it represents (2^e Jq) at the FP32 bar.
+    # (relative error <= 2^-16 per entry) at the BF16X2 bar.  I8X3 and I8X2: the oracle on the
+    # couplings they represent (2^e Jq) at the FP32 bar.
     import paper_2312_05837_amd as P
     inst = I.sk_gauss(2000, 0)
-    ref_inst = int8_represented(inst, 3)[0] if prec == "i8x3" else inst
+    ref_inst = int8_represented(inst, {"i8x3": 3, "i8x2": 2}[prec])[0] if prec.startswith("i8") else inst
     R = 256
     U = I.uniform_draws(5, R, inst.n)
     got = _run(ctx, inst, R, 100, "gd", 0.01, prec, 10, U)
@@ -289,3 +289,4 @@ def test_fp32_requests_on_integer_couplings_run_one_int8_digit(ctx):
     got["loss_trace"] = np.zeros_like(got["energy_trace"])
     worst, excl = compare_trajectories(inst, got, U2, 100, "gd", 0.002, 10, check_loss=False)
     print(f"one INT8 digit: worst iterate error vs FP64 oracle {worst:.2e}, excluded {excl}/64")
+
