@@ -29,7 +29,8 @@
 //             and max_i sum_j |J_ij| + 2^e 257 n <= 2^e (2^31 - 1), which bounds every
 //             partial sum of every plane (any order) below 2^31.
 // Tile: 128 spins x 128 replicas per workgroup of four wavefronts (2 x 2, each
-// 64 x 64 = 2 x 2 MFMA blocks of 32 x 32); the split form 128 x 256 on eight (2 x 4).
+// 64 x 64 = 2 x 2 MFMA blocks of 32 x 32); the split form and the INT8 forms of two and
+// three digits 128 x 256 on eight (2 x 4).
 // K staged through LDS in chunks of 64 BF16 / 128 FP8 or INT8 values (32 FP32); the INT8
 // forms run their digit planes one after another through the same K loop.
 // Operand layouts: J padded row-major [Mp][Kp]; S~ replica-major [R][Kp]
@@ -179,8 +180,10 @@ __global__ void k_dense_split(DevProblem p, int Mp, int Kp, int form, unsigned s
         } else if (int8_form(form)) {
             // Jq = rint(J / 2^e) (the scaling is exact) as balanced base-256 digits, most
             // significant digit in plane 0; |Jq| <= qmax, so the top digit is within [-128, 127]
-            int64_t jq = (int64_t)rint(ldexp(v, -e));
+            // (|J| above qmax 2^127, where no exponent fits, saturates at qmax)
             const int D = jdigits(form);
+            const double qm = jq_max(D);
+            int64_t jq = (int64_t)fmin(fmax(rint(ldexp(v, -e)), -qm), qm);
             for (int d = D - 1; d >= 0; --d) {
                 const int64_t c = ((jq + 128) & 255) - 128;
                 ((signed char *)Jhi)[(size_t)d * total + q] = (signed char)c;
