@@ -346,6 +346,9 @@ CONV = [
     ("t1_binary_int_pms", lambda: I.table1_regular(1000, 6, "binary_int", 3), 32, "fp32"),
     ("gauss_dense200", lambda: I.sk_gauss(200, 4), 16, "fp32"),
     ("er_field_fp64", lambda: I.random_integer_field(I.erdos_renyi(300, 0.05, 4, "pm1"), 4, 3), 8, "fp64"),
+    # the fixed-width-row forms with the loss: small problems (four wavefronts per replica) and large
+    ("torus20x40_field3_rows", lambda: I.random_integer_field(I.torus(20, 40, 5, "pm1"), 5, 3), 32, "fp32"),
+    ("torus100x200_rows_ept28", lambda: I.torus(100, 200, 7, "pm1"), 8, "fp32"),
 ]
 
 
@@ -372,27 +375,24 @@ def test_convergence_stops_replicas(ctx, name, mk, R, prec):
     L = st["loss_trace"].cpu().numpy()
     for r in range(R):
         assert conv[r] == oracle.convergence_step(L[:, r], 5, 0.005), r
-    # state and best vertex of a stopped replica: those of the same run without the test after that step
-    cmax = int(conv.max())
-    free = P.ds_state(inst.n, R, prec, steps_trace=0)
+    # state and best vertex of a stopped replica: those of the same run without the test after that
+    # step, run as one launch of that many steps (the fixed-width-row forms resume ADAM moments
+    # rounded once more at a call boundary, so the reference is never split across calls)
     prm_free = P.params(replicas=R, steps=T, optimizer="adam", lr=6.0, mu=0.5, precision=prec)
-    thetas, energies = [], []
-    for c in range(cmax):
-        f2 = dict(free)
-        f2["energy_trace"] = torch.zeros((1, R), dtype=torch.float64, device="cuda")
-        P.ising_ds_dev(ctx, prob, prm_free, f2, t0=c, steps=1, uniform=U if c == 0 else None)
-        torch.cuda.synchronize()
-        thetas.append(free["theta"].cpu().numpy().copy())
-        energies.append(f2["energy_trace"].cpu().numpy()[0])
-    energies = np.array(energies)
     th = st["theta"].cpu().numpy()
     eb = st["e_best"].cpu().numpy()
     bs = st["best_step"].cpu().numpy()
-    for r in np.nonzero(conv)[0]:
-        c = conv[r]
-        assert np.array_equal(th[r], thetas[c - 1][r]), r
-        assert eb[r] == energies[:c, r].min(), r
-        assert bs[r] == int(np.argmin(energies[:c, r])) + 1, r
+    for c in sorted(set(int(x) for x in conv if x > 0)):
+        free = P.ds_state(inst.n, R, prec, steps_trace=0)
+        free["energy_trace"] = torch.zeros((c, R), dtype=torch.float64, device="cuda")
+        P.ising_ds_dev(ctx, prob, prm_free, free, t0=0, steps=c, uniform=U)
+        torch.cuda.synchronize()
+        th_c = free["theta"].cpu().numpy()
+        energies = free["energy_trace"].cpu().numpy()
+        for r in np.nonzero(conv == c)[0]:
+            assert np.array_equal(th[r], th_c[r]), (c, r)
+            assert eb[r] == energies[:, r].min(), (c, r)
+            assert bs[r] == int(np.argmin(energies[:, r])) + 1, (c, r)
 
 
 def test_convergence_in_solve_stats(ctx):
@@ -411,7 +411,12 @@ def test_convergence_in_solve_stats(ctx):
     assert e.value.status == P.ISING_EINVAL
 
 
-@pytest.mark.parametrize("name,mk,R,prec", CONV, ids=[c[0] for c in CONV])
+# (the fixed-width-row forms keep ADAM's moments scaled in registers and store them unscaled, so a
+# continued call resumes from moments rounded once more than one launch holds: not these cases)
+CONV_CONTINUED = [c for c in CONV if not c[0].endswith(("_rows", "_rows_ept28"))]
+
+
+@pytest.mark.parametrize("name,mk,R,prec", CONV_CONTINUED, ids=[c[0] for c in CONV_CONTINUED])
 def test_convergence_across_calls_equals_one_launch(ctx, name, mk, R, prec):
     # the test's window and stop steps carried through the state: four calls of 100 steps give
     # the one-launch run's angles, moments, stop steps and best vertices bit for bit
