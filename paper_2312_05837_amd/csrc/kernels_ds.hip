@@ -32,11 +32,13 @@
 //            group-major (group k of its 64 lanes contiguous), and each row's
 //            neighbours are ordered so that at every read the lanes of a
 //            wavefront tend to hit distinct LDS banks.
-//   CK_PME   +-w couplings of degree <= 4 with one replica per workgroup and 8+
-//            spins per thread: fixed-width rows in global memory, a spin's four
-//            entries 2 col + (J < 0) in one 16-byte word loaded a few spins ahead,
-//            into a vertex buffer holding each spin's byte and its complement;
-//            an integer field rides in the rows' spare bits.
+//   CK_PME   +-w couplings of degree <= 4 with one replica per workgroup: 8 or more
+//            spins per thread on 768-1024 threads for large problems, 4 or 8 on 256
+//            threads for n <= 2048; fixed-width rows in global memory, a spin's four
+//            entries 2 col + (J < 0) in one 16-byte word loaded a few spins ahead
+//            (kept in registers for the whole run in the small form), into a vertex
+//            buffer holding each spin's byte and its complement; the field (FP32,
+//            per position) loaded with the rows.
 //   CK_CSRV  CSR values in the state precision.
 //   CK_DENSE dense rows in the state precision (small problems).
 #include "internal.hpp"
@@ -451,7 +453,8 @@ __device__ __forceinline__ int local_index(int i) {
 // product is the integer sum itself and no per-position field is loaded; the same results as
 // the general form (y = fma(1, sum, 0) = sum exactly).
 // LBX (fixed-width-row form only): the workgroup size when it is not launch_bound(EPT): small
-// problems run one replica per workgroup of one or two wavefronts (pme_small_block).
+// problems run one replica per workgroup of kPmeSmallBlock threads (pme_small_ept spins each),
+// whose few records and fields per thread stay in registers for the whole run.
 template <typename Real, int CK, int RG, int EPT, int OPT = -1, bool LOSS = true, bool PLAIN = false, int LBX = 0>
 __device__ __forceinline__ void ds_body(const DSArgs &a, const int r0) {
     using SWd = SpinWord<RG>;
