@@ -290,3 +290,20 @@ def test_fp32_requests_on_integer_couplings_run_one_int8_digit(ctx):
     worst, excl = compare_trajectories(inst, got, U2, 100, "gd", 0.002, 10, check_loss=False)
     print(f"one INT8 digit: worst iterate error vs FP64 oracle {worst:.2e}, excluded {excl}/64")
 
+
+
+@pytest.mark.parametrize("prec,digits,shift", [("i8x3", 3, 102), ("i8x2", 2, 110)])
+def test_int8_forms_at_the_exponent_floor(ctx, prec, digits, shift):
+    # Gaussian couplings scaled by 2^-shift (n = 300): the smallest fitting exponent lies below
+    # -126, so the scale is held at 2^-126 (a normal float) and the couplings are represented
+    # more coarsely; the FP64 oracle on the couplings the form represents (built by the documented
+    # rule, which holds the exponent at -126 too) at the FP32 bar, GD over 30 steps
+    base = I.sk_gauss(300, 81)
+    inst = I.Instance(300, "g300_tiny", np.zeros(300), np.ldexp(base.J, -shift), integer=False)
+    rep, e = int8_represented(inst, digits)
+    assert e == -126
+    U = I.uniform_draws(82, 64, inst.n)
+    got = _run(ctx, inst, 64, 30, "gd", 0.01, prec, 3, U)
+    got["loss_trace"] = np.zeros_like(got["energy_trace"])
+    worst, excl = compare_trajectories(rep, got, U, 30, "gd", 0.01, 3, check_loss=False)
+    print(f"{prec} at 2^-{shift}: e = {e}, worst iterate error vs FP64 oracle on 2^e Jq {worst:.2e}, excluded {excl}/64")
