@@ -722,8 +722,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; replicas are independent, so a multi-GPU run "
-                                   "would split them across devices (see the design notes) but is not built",
+        print(json.dumps({"error": "the benchmark runs on one GPU; replicas are independent, so a run on "
+                                   "several GPUs would split them across devices, which is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
