@@ -164,12 +164,40 @@ def measured_copy_rate():
     return 2.0 * COPY_CALIBRATION_BYTES / (best * 1e-3)
 
 
+def measured_int8_rate():
+    """Integer operations/s of a plain library INT8 GEMM (torch._int_mm, int32 accumulation) with
+    uniform random operands, 8192^3, over about half a second; None where torch has none."""
+    import torch
+    try:
+        n = 8192
+        g = torch.Generator(device="cuda").manual_seed(0)
+        a = torch.randint(-128, 128, (n, n), device="cuda", dtype=torch.int8, generator=g)
+        b = torch.randint(-128, 128, (n, n), device="cuda", dtype=torch.int8, generator=g)
+        c = torch._int_mm(a, b)
+        torch.cuda.synchronize()
+        reps = 300
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            torch._int_mm(a, b, out=c)
+        e1.record()
+        e1.synchronize()
+        rate = 2.0 * n ** 3 * reps / (e0.elapsed_time(e1) * 1e-3)
+        del a, b, c
+        torch.cuda.empty_cache()
+        return rate
+    except Exception:
+        return None
+
+
 def measured_mfma_rate(form):
     """FLOP/s of a plain library GEMM (torch.matmul: hipBLASLt / rocBLAS) with random operands of
     the form's input type and FP32 accumulation, 8192^3, sustained over about half a second of
     back-to-back products: the matrix cores' measured rate under load beside the nominal peak
     (the clock drops under toggling operands).  None for forms torch has no plain GEMM for."""
     import torch
+    if form in ("i8x3", "i8x2", "i8x1"):
+        return measured_int8_rate()
     dt = {"bf16x2": torch.bfloat16, "bf16": torch.bfloat16, "fp32": torch.float32}.get(form)
     if dt is None:
         return None
@@ -843,7 +871,8 @@ def main():
         if dense_mfma:
             mrate = measured_mfma_rate(roof["form"])
             if mrate:
-                peaks[f"mfma_{roof['form']}_library_gemm_TFLOPs"] = mrate / 1e12
+                unit = "TOPs" if roof["form"].startswith("i8") else "TFLOPs"  # INT8: integer operations
+                peaks[f"mfma_{roof['form']}_library_gemm_{unit}"] = mrate / 1e12
                 peaks["mfma_nominal_TFLOPs"] = roof["mfma_peak_tflops"]
                 # the products executed per step (the split form runs two) against the library GEMM's rate
                 executed = roof["flops_per_launch"] * DENSE_PRODUCTS.get(roof["form"], 1)
