@@ -262,14 +262,17 @@ def test_convergence_test_in_serving(ctx):
 
 def test_reduced_precision_dense_forms_in_serving(ctx):
     # Gaussian dense requests in the BF16X2, I8X3 and I8X2 forms (float64 couplings; pruning keeps
-    # them whole) served together with integer sparse requests: each served result equals the same
-    # request served alone and the plain solve bit for bit, and its energy is the FP64 energy of
-    # its vector.
+    # them whole) and an FP32 request on integer dense couplings of several magnitudes (one INT8
+    # digit) served together with integer sparse requests: each served result equals the same
+    # request served alone and the plain solve bit for bit, and its energy is the exact (integer)
+    # or FP64 energy of its vector.
     import torch
     import paper_2312_05837_amd as P
     from gpu_util import to_problem
+    import test_gpu_dense as TD
     dense = [(I.sk_gauss(300, 61), 128, 1, "bf16x2"), (I.sk_gauss(257, 62), 64, 2, "i8x3"),
-             (I.sk_gauss(500, 63), 256, 3, "i8x2"), (I.sk_gauss(300, 64), 128, 4, "i8x3")]
+             (I.sk_gauss(500, 63), 256, 3, "i8x2"), (I.sk_gauss(300, 64), 128, 4, "i8x3"),
+             (TD.int3_field_300(), 96, 5, "fp32")]  # integer magnitudes 1..3: one INT8 digit
     sparse = [(inst, R, seed, "fp32") for inst, R, seed in _requests(4, 9)]
     reqs = dense + sparse
 
