@@ -352,14 +352,19 @@ ising_status ising_ds_dev(ising_ctx *ctx, const ising_problem *problem, const is
 int32_t ising_ds_max_n(int32_t precision);
 
 /* The same steps for a dense problem on the matrix cores: each step is one
- * launch computing Y = J S~ for a 128-spin x 128-replica tile with MFMA
- * (precision FP32: v_mfma_f32_32x32x2_f32; BF16X2 / BF16: v_mfma_f32_32x32x16_bf16
- * on J_hi (+ J_lo); FP8, and FP32 on couplings of one integer magnitude:
- * v_mfma_f32_32x32x64_f8f6f4 on J / w), with the elementwise update fused into the tile epilogue,
- * plus a small launch that keeps each replica's best energy.  State arrays are
- * float (theta, m, v), traces and e_best double; energies tracked during the
- * run are those of the chosen form (FP32 accumulation).  Any R >= 1; n up to
- * the device memory.  Errors: ENOTSUP for FP64 precision or a CSR problem. */
+ * launch computing Y = J S~ in tiles of 128 spins x 128 replicas (x 256 replicas
+ * for BF16X2, I8X3 and I8X2) with MFMA (precision FP32: v_mfma_f32_32x32x2_f32;
+ * BF16X2 / BF16: v_mfma_f32_32x32x16_bf16 on J_hi (+ J_lo); FP8, and FP32 on
+ * couplings of one integer magnitude: v_mfma_f32_32x32x64_f8f6f4 on J / w;
+ * I8X3 / I8X2, and FP32 on integer couplings of several magnitudes up to 127:
+ * v_mfma_i32_32x32x32_i8 on each digit plane of Jq), with the elementwise update
+ * fused into the tile epilogue; each launch also keeps the previous step's best
+ * energies, and a small launch after the last step keeps the final one's.
+ * State arrays are float (theta, m, v), traces and e_best double; energies
+ * tracked during the run are those of the chosen form (FP32 accumulation, int32
+ * for the INT8 digit planes).  Any R >= 1; n up to the device memory (65536 for
+ * the INT8 forms).  Errors: ENOTSUP for FP64 precision, a CSR problem, or the
+ * conditions the precision states. */
 ising_status ising_ds_dense_dev(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
                                 const void *uniform, int32_t t0, int32_t steps, ising_ds_state *state,
                                 void *stream);
