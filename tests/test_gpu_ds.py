@@ -504,6 +504,8 @@ SPLIT_ORACLE = [
     ("er700_ragged", lambda: I.erdos_renyi(700, 0.05, 33, "pm1")),
     ("er1000_all16", lambda: I.erdos_renyi(1000, 0.01, 34, "pm1")),  # positions on all 16 wavefronts
     ("er1000_int3", lambda: _er_int3()),  # integer couplings up to 3: the image with repeated entries
+    ("er1024_full", lambda: I.erdos_renyi(1024, 0.03, 35, "pm1")),  # one spin on every thread
+    ("er65_two_waves", lambda: I.erdos_renyi(65, 0.2, 36, "pm1")),  # a 128-slot image, one lane in the second
 ]
 # GD on couplings up to 3 with these draws: the formulas evaluated in float32 already depart from
 # the float64 oracle by more than the bar at lr 0.005 (1.35e-5; pinned as split_er_int3 in
