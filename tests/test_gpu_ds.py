@@ -583,6 +583,14 @@ ROWS_ORACLE = [  # name, maker, replicas, kernel form expected
      "k_ds<float, PME, rg=1, ept=4, block=256,"),
     ("reg3_1500_field5_block256_ept8", lambda: I.random_integer_field(I.random_regular(1500, 3, 54, "pm1"), 54, 5),
      256, "k_ds<float, PME, rg=1, ept=8, block=256,"),
+    # the small form's limits: every slot of 4 (8) spins per thread filled, and a problem on a
+    # fraction of one element
+    ("reg4_1024_block256_ept4", lambda: I.random_regular(1024, 4, 55, "pm1"), 256,
+     "k_ds<float, PME, rg=1, ept=4, block=256,"),
+    ("reg3_2048_block256_ept8", lambda: I.random_regular(2048, 3, 56, "pm1"), 256,
+     "k_ds<float, PME, rg=1, ept=8, block=256,"),
+    ("reg3_70_block256_ept4", lambda: I.random_regular(70, 3, 57, "pm1"), 256,
+     "k_ds<float, PME, rg=1, ept=4, block=256,"),
 ]
 # GD on the 3-regular N = 1500 graph with fields up to 5 and these draws: the formulas evaluated in
 # float32 already depart from the float64 oracle by 1.1e-5 at lr 0.01 (pinned as
