@@ -67,7 +67,11 @@ CASES = [  # name, maker, replicas, (GD lr, ADAM lr): the standard 0.01 / 0.02 u
     ("sk_pm1_300", lambda: I.sk_pm1(300, 1), 200, (0.002, 0.02)),
     ("gauss_300", lambda: I.sk_gauss(300, 2), 200, (0.01, 0.02)),
     ("gauss_field_130", lambda: I.Instance(130, "g130", np.random.default_rng(3).normal(size=130),
-                                           I.sk_gauss(130, 3).J, integer=False), 70, (0.01, 0.02))]
+                                           I.sk_gauss(130, 3).J, integer=False), 70, (0.01, 0.02)),
+    # tile edges: one spin past the first 128-spin tile with a single replica, and whole tiles
+    # with no padding in either dimension
+    ("gauss_129_R1", lambda: I.sk_gauss(129, 4), 1, (0.01, 0.02)),
+    ("gauss_256_R256", lambda: I.sk_gauss(256, 6), 256, (0.01, 0.02))]
 
 
 @pytest.mark.parametrize("opt,steps", [("gd", 100), ("adam", 30)])
@@ -229,24 +233,27 @@ def test_int8_forms_exact_on_integer_couplings(ctx):
             assert np.array_equal(a[k], b[k]), (prec, k)
 
 
+@pytest.mark.parametrize("n,R", [(300, 96), (129, 1), (256, 512)])
 @pytest.mark.parametrize("prec,digits", [("i8x3", 3), ("i8x2", 2)])
 @pytest.mark.parametrize("opt,lr,steps", [("gd", 0.01, 100), ("adam", 0.02, 30)])
-def test_int8_forms_gaussian_iterates(ctx, prec, digits, opt, lr, steps):
-    # Gaussian couplings with a field, n = 300: the FP64 oracle run on the couplings the form
-    # represents (2^e Jq) at the FP32 bar; its product is exact in int32 and y is rounded once,
-    # so only the FP32 iterate arithmetic differs.  For two digits 2^e is about 2^-16 of max|J|,
-    # so a wrong exponent or digit would show at this bar; three digits are compared the same way.
-    base = I.sk_gauss(300, 21)
-    inst = I.Instance(300, "g300h", np.random.default_rng(22).normal(size=300), base.J, integer=False)
+def test_int8_forms_gaussian_iterates(ctx, prec, digits, opt, lr, steps, n, R):
+    # Gaussian couplings with a field: the FP64 oracle run on the couplings the form represents
+    # (2^e Jq) at the FP32 bar; its product is exact in int32 and y is rounded once, so only the
+    # FP32 iterate arithmetic differs.  For two digits 2^e is about 2^-16 of max|J|, so a wrong
+    # exponent or digit would show at this bar; three digits are compared the same way.  Shapes:
+    # n = 300 with R = 96 (K padding, ragged tiles in both dimensions), one spin past the first
+    # 128-spin tile with a single replica, and whole 128 x 256 tiles with no padding.
+    base = I.sk_gauss(n, 21)
+    inst = I.Instance(n, f"g{n}h", np.random.default_rng(22).normal(size=n), base.J, integer=False)
     rep, e = int8_represented(inst, digits)
-    U = I.uniform_draws(23, 96, inst.n)
+    U = I.uniform_draws(23, R, inst.n)
     chunks = 10 if steps == 100 else 3
-    got = _run(ctx, inst, 96, steps, opt, lr, prec, chunks, U)
+    got = _run(ctx, inst, R, steps, opt, lr, prec, chunks, U)
     got["loss_trace"] = np.zeros_like(got["energy_trace"])
     worst, excl = compare_trajectories(rep, got, U, steps, opt, lr, chunks, check_loss=False)
     rel = np.abs(rep.J - inst.J).max() / np.abs(inst.J).max()
-    print(f"{prec} {opt}: e = {e}, max |J - 2^e Jq| / max|J| = {rel:.1e}, "
-          f"worst iterate error vs FP64 oracle on 2^e Jq {worst:.2e}, excluded {excl}/96")
+    print(f"{prec} {opt} n={n} R={R}: e = {e}, max |J - 2^e Jq| / max|J| = {rel:.1e}, "
+          f"worst iterate error vs FP64 oracle on 2^e Jq {worst:.2e}, excluded {excl}/{R}")
 
 
 def test_int8_forms_rejected_for_sparse(ctx):
