@@ -107,6 +107,21 @@ def test_bf16_forms_exact_on_pm1(ctx):
     compare_trajectories(pm, got, U2, 100, "gd", 0.002, 10, check_loss=False)
 
 
+@pytest.mark.parametrize("n,R", [(129, 1), (256, 512), (384, 257)])
+def test_bf16_forms_exact_on_pm1_at_tile_edges(ctx, n, R):
+    # the same bitwise identity of the FP32, BF16X2 and BF16 forms on +-1/2 couplings at tile
+    # edges: one spin past the first 128-spin tile with one replica, whole tiles with no padding
+    # (BF16X2 on 128 x 256 tiles, the others on 128 x 128), and one replica past a whole tile
+    pm = I.sk_pm1(n, 40 + n)
+    inst = I.Instance(n, f"sk_half_{n}", np.zeros(n), pm.J * 0.5, integer=False)
+    U = I.uniform_draws(41, R, n)
+    a = _run(ctx, inst, R, 40, "adam", 6.0, "fp32", 1, U)
+    for prec in ("bf16x2", "bf16"):
+        b = _run(ctx, inst, R, 40, "adam", 6.0, prec, 1, U)
+        for k in ("theta", "m", "v", "s_best", "e_best", "best_step", "energy_trace"):
+            assert np.array_equal(a[k], b[k]), (prec, k)
+
+
 @pytest.mark.parametrize("prec,tol,steps", [("bf16x2", 2e-4, 100), ("bf16", 5e-2, 20)])
 def test_bf16_forms_gaussian_error_bound(ctx, prec, tol, steps):
     # a vertex may legitimately differ where the oracle's |sin theta| is below the form's
