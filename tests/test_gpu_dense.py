@@ -174,6 +174,22 @@ def test_fp8_form_exact_on_uniform_integer_couplings(ctx):
     print(f"FP8 form: worst iterate error vs FP64 oracle {worst:.2e}, excluded {excl}/64")
 
 
+@pytest.mark.parametrize("n,R", [(129, 1), (256, 256), (384, 257)])
+def test_integer_forms_agree_at_tile_edges(ctx, n, R):
+    # J = +-3 with integer fields at tile edges: the FP8 form (one magnitude), three INT8 digits
+    # and BF16 give the same iterates, energies and best vertices bit for bit (each product and
+    # sum is an exact integer in every form), and so does an FP32 request, which runs FP8
+    pm = I.sk_pm1(n, 60 + n)
+    h = np.random.default_rng(61).integers(-4, 5, size=n)
+    inst = I.Instance(n, f"sk_pm3_field_{n}", h, pm.J * 3, integer=True)
+    U = I.uniform_draws(62, R, n)
+    a = _run(ctx, inst, R, 40, "adam", 6.0, "fp8", 2, U)
+    for prec in ("i8x3", "bf16", "fp32"):
+        b = _run(ctx, inst, R, 40, "adam", 6.0, prec, 2, U)
+        for k in ("theta", "m", "v", "s_best", "e_best", "best_step", "energy_trace"):
+            assert np.array_equal(a[k], b[k]), (prec, k)
+
+
 def test_fp8_form_rejected_for_other_couplings(ctx):
     import torch
     import paper_2312_05837_amd as P
