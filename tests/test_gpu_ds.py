@@ -141,6 +141,7 @@ MULTI = [
     ("reg3_12000_field100_csr_ept16", lambda: I.random_integer_field(I.random_regular(12000, 3, 25, "pm1"), 25, 100),
      4),
     ("torus150x200_stream", lambda: I.torus(150, 200, 22, "pm1"), 4),
+    ("reg3_49152_stream_max", lambda: I.random_regular(48 * 1024, 3, 27, "pm1"), 4),  # the engine's largest n
 ]
 
 
@@ -328,6 +329,21 @@ def test_relaxed_loss_iterates(ctx, name, mk, R, prec, opt, lr, steps):
                    uniform=torch.tensor(U, dtype=dt, device="cuda"), loss="relaxed")
     worst, excl = _compare(inst, got, U, steps, opt, lr, chunks, loss="relaxed")
     print(f"relaxed {name} {prec} {opt} lr={lr}: worst iterate error {worst:.2e}, excluded {excl}/{R}")
+
+
+def test_beyond_the_largest_n_rejected(ctx):
+    # one spin past ising_ds_max_n: ENOTSUP before any work is enqueued, state untouched
+    import torch
+    import paper_2312_05837_amd as P
+    n = P.ising_ds_max_n(P.ISING_PREC_FP32) + 1
+    inst = I.random_regular(n, 4, 28, "pm1")
+    state = P.ds_state(n, 4)
+    state["theta"].fill_(0.25)
+    with pytest.raises(P.IsingError) as e:
+        P.ising_ds_dev(ctx, to_problem(inst), P.params(replicas=4, steps=5), state)
+    assert e.value.status == P.ISING_ENOTSUP
+    torch.cuda.synchronize()
+    assert bool((state["theta"] == 0.25).all())
 
 
 def test_relaxed_loss_rejected_where_not_built(ctx):
