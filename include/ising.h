@@ -117,7 +117,8 @@ typedef struct ising_problem {
 
 typedef struct ising_params {
     int32_t replicas;    /* R >= 1 independent trajectories */
-    int32_t steps;       /* T >= 0 iterations */
+    int32_t steps;       /* T >= 0 iterations (T = 0 scores no vertex: every best record keeps
+                            its start, +1 on every spin, and replica 0 is selected) */
     int32_t optimizer;   /* ISING_OPT_GD or ISING_OPT_ADAM */
     int32_t precision;   /* ISING_PREC_* (BF16X2, BF16, FP8, I8X3, I8X2: dense couplings only) */
     double lr;           /* learning rate (the paper uses 6.0 with ADAM) */

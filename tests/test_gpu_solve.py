@@ -101,6 +101,29 @@ def test_solve_matches_oracle_solution_non_chaotic(ctx):
     assert np.array_equal(s, ref["spins"])
 
 
+@pytest.mark.parametrize("name,mk,prec", [
+    ("forest_fields", lambda: I.random_forest_plus_cycles(300, 41, n_extra=40, hmax=2), "fp32"),
+    ("forest_fields", lambda: I.random_forest_plus_cycles(300, 41, n_extra=40, hmax=2), "fp64"),
+    ("sk_gauss_300_dense", lambda: I.sk_gauss(300, 42), "fp32"),
+    ("sk_gauss_300_dense", lambda: I.sk_gauss(300, 42), "bf16x2"),
+    ("sk_gauss_300_dense", lambda: I.sk_gauss(300, 42), "i8x3")])
+def test_zero_steps(ctx, name, mk, prec):
+    # T = 0: no vertex is scored, so every replica keeps the vertex its best record starts from
+    # (+1 on every spin of the reduced problem), replica 0 is selected (all best energies +inf,
+    # lowest index) and the returned vector is that vertex retrieved through the pruning record,
+    # with its exact energy
+    inst = mk()
+    pr = oracle.prune(inst)
+    s, E, Ei, st = _solve(ctx, inst, replicas=8, steps=0, optimizer="adam", precision=prec, lr=6.0, mu=0.5)
+    want = oracle.unprune(pr, np.ones(pr.G.size, dtype=np.int64))
+    assert np.array_equal(s, want)
+    assert st["best_replica"] == 0
+    if inst.integer:
+        assert Ei == oracle.energy(inst, s)
+    else:
+        assert abs(E - oracle.energy(inst, s)) <= 2 * energy_bound(inst)
+
+
 def test_solve_host_buffers(ctx):
     import ctypes as C
     import paper_2312_05837_amd as P
