@@ -75,6 +75,9 @@ CASES = [
     ("t1_uniform_real_csr", lambda: I.table1_regular(500, 6, "uniform", 6), 8),
     ("torus50x100_ept8", lambda: I.torus(50, 100, 7, "pm1"), 8),
     ("ragged_n65_r6", lambda: I.random_integer_field(I.erdos_renyi(65, 0.2, 8, "pm1"), 8, 2), 6),
+    # replica counts that no replica group divides: odd, and one
+    ("er800_odd_R3", lambda: I.erdos_renyi(800, 0.06, 9, "pm1"), 3),
+    ("torus20x40_single_R1", lambda: I.torus(20, 40, 10, "pm1"), 1),
 ]
 
 # Several spins per thread (the register engine beyond 1024 spins): two replicas per
