@@ -242,6 +242,24 @@ ising_status admit(Server &S, Request &q) {
             q.args.bias = bias;
         }
     }
+    if (q.prm.steps == 0) {
+        // no step to run: the state is initialised as a call of zero steps initialises it (angles
+        // from the draws, best energies +inf with the all +1 vertex), so that the harvest reads
+        // the same records as the plain solve
+        if (q.dense) {
+            DenseRun d0 = q.drun;
+            d0.t0 = 0;
+            d0.steps = 0;
+            d0.init_mode = 2;
+            HIP_TRY(ctx, launch_dense_init(d0, s));
+        } else {
+            DSArgs a0 = q.args;
+            a0.t0 = 0;
+            a0.steps = 0;
+            a0.init_mode = 2;
+            HIP_TRY(ctx, launch_ds(a0, q.plan.l, s));
+        }
+    }
     HIP_TRY(ctx, hipStreamSynchronize(s));
     return ISING_OK;
 }

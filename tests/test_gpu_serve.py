@@ -88,6 +88,29 @@ def test_alone_equals_mix_and_plain_solve(ctx):
         assert stats["t_total_ms"] >= stats["t_ds_ms"] >= 0
 
 
+def test_zero_step_requests(ctx):
+    # T = 0 (no step to run): each request, dense or sparse, returns what the plain solve returns,
+    # the all +1 reduced vertex retrieved through its pruning record, with its exact energy
+    import torch
+    import paper_2312_05837_amd as P
+    from gpu_util import to_problem
+    reqs = _requests(8, 13)
+    assert any(inst.is_dense and inst.n > 256 for inst, _, _ in reqs) and any(not inst.is_dense for inst, _, _ in reqs)
+    res, info = _serve(ctx, reqs, steps=0, chunk=50, max_resident=8)
+    assert info["completed"] == len(reqs) and info["failed"] == 0
+    for (inst, R, seed), (status, spins, energy, stats) in zip(reqs, res):
+        assert status == P.ISING_OK
+        pr = oracle.prune(inst)
+        assert np.array_equal(spins, oracle.unprune(pr, np.ones(pr.G.size, dtype=np.int64)))
+        assert energy == oracle.energy(inst, spins)
+        s, E, Ei, st = P.ising_solve_dev(ctx, to_problem(inst), P.params(replicas=R, steps=0, optimizer="adam",
+                                                                          lr=6.0, mu=0.5, seed=seed,
+                                                                          precision="fp32"))
+        torch.cuda.synchronize()
+        assert np.array_equal(s.cpu().numpy(), spins)
+        assert float(E.item()) == energy
+
+
 def test_requests_arriving_while_others_run_are_admitted(ctx):
     import paper_2312_05837_amd as P
     reqs = _requests(12, 7)
