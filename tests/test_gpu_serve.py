@@ -111,6 +111,31 @@ def test_zero_step_requests(ctx):
         assert float(E.item()) == energy
 
 
+def test_unpruned_requests_equal_plain_solve(ctx):
+    # prune = 0 in serving: the request runs on the whole instance and returns what the plain
+    # solve with prune = 0 returns, bit for bit (sparse and dense requests, some with fields)
+    import torch
+    import paper_2312_05837_amd as P
+    from gpu_util import to_problem
+    reqs = _requests(6, 17)
+    P.ising_serve_start(ctx, chunk_steps=50, max_resident=8)
+    keep, tickets = [], []
+    for inst, R, seed in reqs:
+        st, kp = _host(inst)
+        keep.append(kp)
+        tickets.append(P.ising_submit(ctx, st, P.params(replicas=R, steps=150, seed=seed, prune=False)))
+    res = [P.ising_wait(ctx, t, inst.n) for t, (inst, _, _) in zip(tickets, reqs)]
+    P.ising_serve_stop(ctx)
+    for (inst, R, seed), (status, spins, energy, stats) in zip(reqs, res):
+        assert status == P.ISING_OK
+        assert stats["n_G"] == inst.n
+        s, E, Ei, st = P.ising_solve_dev(ctx, to_problem(inst), P.params(replicas=R, steps=150, seed=seed,
+                                                                          prune=False))
+        torch.cuda.synchronize()
+        assert np.array_equal(s.cpu().numpy(), spins)
+        assert float(E.item()) == energy == oracle.energy(inst, spins)
+
+
 def test_requests_arriving_while_others_run_are_admitted(ctx):
     import paper_2312_05837_amd as P
     reqs = _requests(12, 7)

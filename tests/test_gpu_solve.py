@@ -124,6 +124,24 @@ def test_zero_steps(ctx, name, mk, prec):
         assert abs(E - oracle.energy(inst, s)) <= 2 * energy_bound(inst)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_without_pruning_matches_oracle(ctx, prec):
+    # prune = 0: domain selection runs on the whole instance (n_G = n, C = 0) and the selected
+    # vector is returned as it is; GD at a small step, so GPU and oracle follow the same
+    # trajectories and select the same replica and vertex
+    import paper_2312_05837_amd as P
+    inst = I.random_forest_plus_cycles(400, 9, n_extra=60, hmax=2)
+    R, T = 16, 200
+    s, E, Ei, st = _solve(ctx, inst, replicas=R, steps=T, optimizer="gd", precision=prec, lr=0.01, mu=0.5,
+                          seed=23, prune=False)
+    U = I.uniform_draws(23, R, inst.n)
+    ref = oracle.solve(inst, U, T, opt="gd", lr=0.01, mu=0.5, do_prune=False)
+    assert st["n_G"] == inst.n and st["constant_C"] == 0 and st["rounds"] == 0
+    assert Ei == ref["energy"] == oracle.energy(inst, s)
+    assert st["best_replica"] == ref["replica"]
+    assert np.array_equal(s, ref["spins"])
+
+
 def test_solve_host_buffers(ctx):
     import ctypes as C
     import paper_2312_05837_amd as P
