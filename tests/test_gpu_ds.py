@@ -373,6 +373,20 @@ CONV = [
 
 @pytest.mark.parametrize("name,mk,R,prec", CONV, ids=[c[0] for c in CONV])
 def test_convergence_stops_replicas(ctx, name, mk, R, prec):
+    _convergence_stops(ctx, mk, R, prec, 5)
+
+
+@pytest.mark.parametrize("W", [1, 8])
+@pytest.mark.parametrize("name,mk,R,prec", [CONV[0], CONV[3]], ids=[CONV[0][0], CONV[3][0]])
+def test_convergence_window_limits(ctx, name, mk, R, prec, W):
+    # the window's limits: one loss (its spread is 0, so every replica stops at step 1) and the
+    # largest window the kernels hold (8 losses in the ring)
+    conv = _convergence_stops(ctx, mk, R, prec, W)
+    if W == 1:
+        assert np.all(conv == 1)
+
+
+def _convergence_stops(ctx, mk, R, prec, W):
     import torch
     import paper_2312_05837_amd as P
     from gpu_util import to_problem
@@ -382,7 +396,7 @@ def test_convergence_stops_replicas(ctx, name, mk, R, prec):
     U = torch.tensor(I.uniform_draws(15, R, inst.n), dtype=dt, device="cuda")
     prob = to_problem(inst)
     prm = P.params(replicas=R, steps=T, optimizer="adam", lr=6.0, mu=0.5, precision=prec, conv_tol=0.005,
-                   conv_window=5)
+                   conv_window=W)
     st = P.ds_state(inst.n, R, prec, steps_trace=T)
     st["conv_step"] = torch.zeros(R, dtype=torch.int32, device="cuda")
     P.ising_ds_dev(ctx, prob, prm, st, t0=0, steps=T, uniform=U)
@@ -393,7 +407,7 @@ def test_convergence_stops_replicas(ctx, name, mk, R, prec):
     # the kernel's decision is the test replayed on its own (recorded) losses
     L = st["loss_trace"].cpu().numpy()
     for r in range(R):
-        assert conv[r] == oracle.convergence_step(L[:, r], 5, 0.005), r
+        assert conv[r] == oracle.convergence_step(L[:, r], W, 0.005), r
     # state and best vertex of a stopped replica: those of the same run without the test after that
     # step, run as one launch of that many steps (the fixed-width-row forms resume ADAM moments
     # rounded once more at a call boundary, so the reference is never split across calls)
@@ -412,6 +426,7 @@ def test_convergence_stops_replicas(ctx, name, mk, R, prec):
             assert np.array_equal(th[r], th_c[r]), (c, r)
             assert eb[r] == energies[:, r].min(), (c, r)
             assert bs[r] == int(np.argmin(energies[:, r])) + 1, (c, r)
+    return conv
 
 
 def test_convergence_in_solve_stats(ctx):
