@@ -386,6 +386,27 @@ def test_convergence_window_limits(ctx, name, mk, R, prec, W):
         assert np.all(conv == 1)
 
 
+@pytest.mark.parametrize("W", [0, 9])
+def test_convergence_window_out_of_range_rejected(ctx, W):
+    # windows the kernels do not hold: EINVAL before any domain-selection work is enqueued, in the
+    # plain solve and in the engine call (whose state stays untouched)
+    import torch
+    import paper_2312_05837_amd as P
+    from gpu_util import to_problem
+    inst = I.torus(20, 40, 5, "pm1")
+    prm = P.params(replicas=8, steps=20, conv_tol=0.005, conv_window=W)
+    with pytest.raises(P.IsingError) as e:
+        P.ising_solve_dev(ctx, to_problem(inst), prm)
+    assert e.value.status == P.ISING_EINVAL
+    st = P.ds_state(inst.n, 8)
+    st["theta"].fill_(0.5)
+    with pytest.raises(P.IsingError) as e:
+        P.ising_ds_dev(ctx, to_problem(inst), prm, st)
+    assert e.value.status == P.ISING_EINVAL
+    torch.cuda.synchronize()
+    assert bool((st["theta"] == 0.5).all())
+
+
 def _convergence_stops(ctx, mk, R, prec, W):
     import torch
     import paper_2312_05837_amd as P
