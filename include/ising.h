@@ -121,9 +121,11 @@ typedef struct ising_params {
                             its start, +1 on every spin, and replica 0 is selected) */
     int32_t optimizer;   /* ISING_OPT_GD or ISING_OPT_ADAM */
     int32_t precision;   /* ISING_PREC_* (BF16X2, BF16, FP8, I8X3, I8X2: dense couplings only) */
-    double lr;           /* learning rate (the paper uses 6.0 with ADAM) */
-    double mu;           /* augmented-Lagrangian weight mu > 0 of the L1-norm form */
-    double beta1, beta2, eps;  /* ADAM constants (Kingma-Ba defaults 0.9, 0.999, 1e-8) */
+    double lr;           /* learning rate, finite and > 0 (the paper uses 6.0 with ADAM) */
+    double mu;           /* augmented-Lagrangian weight of the L1-norm form, finite and > 0 */
+    double beta1, beta2, eps;  /* ADAM constants (Kingma-Ba defaults 0.9, 0.999, 1e-8): 0 <= beta < 1,
+                                  eps finite and > 0.  lr, mu or (ADAM) these outside their
+                                  ranges: ISING_EINVAL before any work */
     uint64_t seed;       /* key of the counter-based initial draws */
     int32_t prune;       /* nonzero: run Algorithm 1 before domain selection */
     int32_t loss;        /* ISING_LOSS_VERTEX (0) or ISING_LOSS_RELAXED */

@@ -44,6 +44,15 @@ ising_status check_problem_shape(ising_ctx *ctx, const ising_problem *p) {
     return ISING_OK;
 }
 
+ising_status check_params(ising_ctx *ctx, const ising_params &prm) {
+    if (!std::isfinite(prm.lr) || prm.lr <= 0) return fail(ctx, ISING_EINVAL, "lr must be finite and > 0");
+    if (!std::isfinite(prm.mu) || prm.mu <= 0) return fail(ctx, ISING_EINVAL, "mu must be finite and > 0");
+    if (prm.optimizer == ISING_OPT_ADAM && (!(prm.beta1 >= 0 && prm.beta1 < 1) || !(prm.beta2 >= 0 && prm.beta2 < 1) ||
+                                            !std::isfinite(prm.eps) || prm.eps <= 0))
+        return fail(ctx, ISING_EINVAL, "ADAM needs 0 <= beta1, beta2 < 1 and a finite eps > 0");
+    return ISING_OK;
+}
+
 ising_status upload_problem(ising_ctx *ctx, const ising_problem &host, Pool &pool, const std::string &prefix,
                             ising_problem &d, hipStream_t s) {
     const int n = host.n;
@@ -212,6 +221,7 @@ ising_status prune_core(ising_ctx *ctx, const DevProblem &p, ising_pruned &pr, h
 
 ising_status plan_ds(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, const Ingest &ing,
                      DSPlan &plan, bool register_only) {
+    ST_TRY(check_params(ctx, prm));
     const bool fp64 = prm.precision == ISING_PREC_FP64;
     if (prm.precision != ISING_PREC_FP64 && prm.precision != ISING_PREC_FP32)
         return fail(ctx, ISING_ENOTSUP, "precision not supported by the persistent engine");
@@ -442,6 +452,7 @@ constexpr int kDenseInt8MaxN = 65536;
 ising_status prepare_dense(ising_ctx *ctx, const ising_problem &p, const ising_params &prm, Pool &pool,
                            hipStream_t s, DenseRun &d, const DenseExact &ex) {
     const double unit = ex.unit;
+    ST_TRY(check_params(ctx, prm));
     if (p.format != ISING_DENSE) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine needs dense couplings");
     if (prm.loss != ISING_LOSS_VERTEX) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs the vertex loss");
     if (prm.conv_tol > 0) return fail(ctx, ISING_ENOTSUP, "the matrix-core engine runs fixed step counts");
@@ -906,6 +917,7 @@ ising_status ising_solve_dev(ising_ctx *ctx, const ising_problem *problem, const
     if (!ctx || !params || !spins_out) return ISING_EINVAL;
     ST_TRY(check_problem_shape(ctx, problem));
     if (params->replicas <= 0 || params->steps < 0) return fail(ctx, ISING_EINVAL, "bad replicas/steps");
+    ST_TRY(check_params(ctx, *params));
     if (energy_int_out && problem->value_type != ISING_I32)
         return fail(ctx, ISING_EINVAL, "integer energies need an ISING_I32 problem");
     HIP_TRY(ctx, hipSetDevice(ctx->device));

@@ -99,6 +99,10 @@ ising_status fail(ising_ctx *ctx, ising_status st, const std::string &msg);
     } while (0)
 
 ising_status check_problem_shape(ising_ctx *ctx, const ising_problem *p);
+// Step size, weight of the L1 term and ADAM constants: lr and mu finite and > 0; for ADAM
+// 0 <= beta1, beta2 < 1 and eps finite and > 0 (every bias correction and step denominator
+// finite).  ctx may be NULL (no message).
+ising_status check_params(ising_ctx *ctx, const ising_params &prm);
 // Copy a host-buffer problem into device buffers of `pool` (keys prefixed by `prefix`) on
 // stream s; *dev receives the same problem with device pointers.  Not synchronised.
 ising_status upload_problem(ising_ctx *ctx, const ising_problem &host, Pool &pool, const std::string &prefix,

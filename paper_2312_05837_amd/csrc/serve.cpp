@@ -626,6 +626,7 @@ ising_status ising_submit(ising_ctx *ctx, const ising_problem *problem, const is
         if (!problem || problem->n <= 0 || params->replicas <= 0 || params->steps < 0) return ISING_EINVAL;
     }
     if (problem->value_type < ISING_I32 || problem->value_type > ISING_F64) return ISING_EINVAL;
+    if (check_params(nullptr, *params) != ISING_OK) return ISING_EINVAL;
     // the batched launches run the vertex loss (fixed step counts, or until the convergence test)
     if (params->loss != ISING_LOSS_VERTEX) return ISING_ENOTSUP;
     auto q = std::make_unique<Request>();

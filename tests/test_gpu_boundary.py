@@ -117,3 +117,42 @@ def test_host_calls_reject_bad_input(ctx):
     with pytest.raises(P.IsingError) as e:
         P.ising_unprune(P.Pruned(None), np.zeros(1, np.int8))
     assert e.value.status == P.ISING_EINVAL
+
+
+@pytest.mark.parametrize("bad", [dict(lr=0.0), dict(lr=float("nan")), dict(mu=0.0), dict(mu=float("inf")),
+                                 dict(beta1=1.0), dict(beta2=-0.1), dict(eps=0.0)])
+def test_bad_step_parameters_rejected(ctx, bad):
+    # step size, L1 weight and ADAM constants outside their ranges: EINVAL from the plain solve,
+    # both engine calls and submission, before any work (the engine state stays untouched)
+    import torch
+    import paper_2312_05837_amd as P
+    from gpu_util import to_problem
+    kw = dict(replicas=8, steps=10, optimizer="adam", lr=6.0, mu=0.5)
+    kw.update(bad)
+    prm = P.params(**kw)
+    sparse, dense = I.torus(20, 40, 5, "pm1"), I.sk_pm1(300, 5)
+    for inst in (sparse, dense):
+        with pytest.raises(P.IsingError) as e:
+            P.ising_solve_dev(ctx, to_problem(inst), prm)
+        assert e.value.status == P.ISING_EINVAL, bad
+    for call, inst in ((P.ising_ds_dev, sparse), (P.ising_ds_dense_dev, dense)):
+        st = P.ds_state(inst.n, 8)
+        st["theta"].fill_(0.5)
+        with pytest.raises(P.IsingError) as e:
+            call(ctx, to_problem(inst), prm, st)
+        assert e.value.status == P.ISING_EINVAL, (bad, call.__name__)
+        torch.cuda.synchronize()
+        assert bool((st["theta"] == 0.5).all())
+    P.ising_serve_start(ctx)
+    try:
+        hp, keep = P.host_problem(sparse.n, row_ptr=sparse.row_ptr, col=sparse.col, val=sparse.val.astype(np.int32))
+        with pytest.raises(P.IsingError) as e:
+            P.ising_submit(ctx, hp, prm)
+        assert e.value.status == P.ISING_EINVAL
+    finally:
+        P.ising_serve_stop(ctx)
+    # the ADAM constants do not constrain GD
+    if "beta1" in bad or "beta2" in bad or "eps" in bad:
+        kw["optimizer"] = "gd"
+        kw["lr"] = 0.01
+        P.ising_solve_dev(ctx, to_problem(sparse), P.params(**kw))
