@@ -197,6 +197,11 @@ def test_failures_forced_from_the_host(ctx):
     st, keep1 = P.host_problem(2, J=J)
     t_bad = P.ising_submit(ctx, st, P.params(replicas=8, steps=10))
     assert P.ising_wait(ctx, t_bad, 2)[0] == P.ISING_EINVAL
+    # a convergence window the kernels do not hold: rejected at admission
+    tor = I.torus(8, 8, 3, "pm1")
+    st0, keep0 = _host(tor)
+    t_win = P.ising_submit(ctx, st0, P.params(replicas=8, steps=10, conv_tol=0.005, conv_window=9))
+    assert P.ising_wait(ctx, t_win, tor.n)[0] == P.ISING_EINVAL
     # larger than the whole budget: refused with ENOMEM
     big = I.sk_pm1(1200, 1)
     st2, keep2 = _host(big)
@@ -217,7 +222,7 @@ def test_failures_forced_from_the_host(ctx):
     assert status == P.ISING_OK and energy == oracle.energy(small, spins)
     info = P.ising_serve_query(ctx)
     P.ising_serve_stop(ctx)
-    assert info["failed"] == 2 and info["canceled"] == 1 and info["completed"] == 1
+    assert info["failed"] == 3 and info["canceled"] == 1 and info["completed"] == 1
 
 
 def test_large_sparse_and_grouped_dense_requests(ctx):
