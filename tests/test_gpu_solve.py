@@ -56,6 +56,9 @@ CASES = [
     ("t1_binary_int_1000", lambda: I.table1_regular(1000, 6, "binary_int", 7)),
     ("torus_20x40", lambda: I.torus(20, 40, 8, "pm1")),
     ("all_pruned", lambda: I.from_edges(4, [(0, 1, 1), (2, 3, -1)], np.array([5, 0, 0, 1]))),
+    # dense couplings: FP32 on the matrix cores (FP8 for the +-1 instance), FP64 on the persistent engine
+    ("sk_gauss_600_dense", lambda: I.sk_gauss(600, 9)),
+    ("sk_pm1_400_dense_field", lambda: I.random_integer_field(I.sk_pm1(400, 10), 10, 2)),
     # no couplings: the spins with a field are determined, the others reach domain selection with
     # an empty coupling matrix (every vertex optimal); and the same with no field at all
     ("isolated_spins", lambda: I.from_edges(70, [], np.r_[np.zeros(40), np.arange(1, 31) * (-1) ** np.arange(30)])),
@@ -79,7 +82,7 @@ def test_solve_consistent_with_oracle(ctx, name, mk, prec):
     if inst.integer:
         assert Ei == oracle.energy(inst, s)
         assert st["constant_C"] == pr.C
-        if inst.col.size == 0:  # no couplings: the minimum is -sum |h|, reached by any vertex of G
+        if not inst.is_dense and inst.col.size == 0:  # no couplings: the minimum is -sum |h|, reached by any vertex of G
             assert Ei == -np.abs(inst.h).sum()
     else:
         assert abs(E - oracle.energy(inst, s)) <= 2 * energy_bound(inst)
