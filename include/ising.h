@@ -413,7 +413,10 @@ typedef struct ising_serve_info {
 
 /* Start the scheduler of ctx (one per context).  cfg nullable (defaults). */
 ising_status ising_serve_start(ising_ctx *ctx, const ising_serve_config *cfg);
-/* Finish every queued and resident request, then stop the scheduler. */
+/* Finish every queued and resident request, then stop the scheduler.  ising_wait
+ * calls blocked on requests when it is called return their results before the
+ * server is released; no other call on the context may run concurrently with it,
+ * and results not collected before it returns are discarded. */
 ising_status ising_serve_stop(ising_ctx *ctx);
 /* Queue a solve.  problem: host buffers, copied before the call returns.
  * params as for ising_solve; sparse requests run in FP32.  *ticket identifies

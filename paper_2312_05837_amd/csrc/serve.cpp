@@ -88,6 +88,7 @@ struct Server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     bool stop = false;
+    int waiters = 0;  // ising_wait calls inside the server (stop releases it only when none is)
     uint64_t next_ticket = 1;
     std::deque<Request *> queue;
     std::vector<Request *> resident;
@@ -604,6 +605,11 @@ ising_status ising_serve_stop(ising_ctx *ctx) {
     }
     S->cv_work.notify_all();
     if (S->thr.joinable()) S->thr.join();
+    {
+        // every request is finished now; waits blocked on them return before the server goes
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv_done.wait(lk, [&] { return S->waiters == 0; });
+    }
     (void)hipSetDevice(ctx->device);
     (void)hipStreamDestroy(S->main);
     for (auto &g : S->graphs)
@@ -667,6 +673,15 @@ ising_status ising_wait(ising_ctx *ctx, uint64_t ticket, int32_t timeout_ms, int
     if (!ctx || !ctx->server) return ISING_EINVAL;
     Server *S = ctx->server;
     std::unique_lock<std::mutex> lk(S->mu);
+    // counted while inside (the guard is released before lk, so with the mutex held)
+    struct Inside {
+        Server *S;
+        ~Inside() {
+            --S->waiters;
+            S->cv_done.notify_all();
+        }
+    } inside{S};
+    ++S->waiters;
     auto it = S->all.find(ticket);
     if (it == S->all.end()) return ISING_EINVAL;
     Request *q = it->second.get();

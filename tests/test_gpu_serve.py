@@ -136,6 +136,27 @@ def test_unpruned_requests_equal_plain_solve(ctx):
         assert float(E.item()) == energy == oracle.energy(inst, spins)
 
 
+def test_stop_while_a_wait_is_blocked(ctx):
+    # a wait blocked on a running request when the server is stopped returns that request's
+    # result (stop finishes it first and releases the server only after the wait has returned)
+    import threading
+    import paper_2312_05837_amd as P
+    inst = I.erdos_renyi(300, 0.03, 21, "pm1")
+    P.ising_serve_start(ctx, chunk_steps=100)
+    st, keep = _host(inst)
+    t = P.ising_submit(ctx, st, P.params(replicas=64, steps=1000000, seed=3))
+    out = {}
+    waiter = threading.Thread(target=lambda: out.setdefault("r", P.ising_wait(ctx, t, inst.n)))
+    waiter.start()
+    time.sleep(0.3)  # the wait is inside the library, blocked on the running request
+    assert waiter.is_alive()
+    assert P.ising_serve_stop(ctx) is None
+    waiter.join(timeout=120)
+    assert not waiter.is_alive()
+    status, spins, energy, stats = out["r"]
+    assert status == P.ISING_OK and energy == oracle.energy(inst, spins) and stats["steps"] == 1000000
+
+
 def test_requests_arriving_while_others_run_are_admitted(ctx):
     import paper_2312_05837_amd as P
     reqs = _requests(12, 7)
