@@ -429,7 +429,8 @@ ising_status ising_submit(ising_ctx *ctx, const ising_problem *problem, const is
                           uint64_t *ticket);
 /* Wait up to timeout_ms (negative: forever) for a request and copy its result
  * (spins_out: n int8, energy_out, stats_out; each nullable).  A wait that
- * returns anything but ETIMEDOUT consumes the ticket.  For served requests the
+ * returns anything but ETIMEDOUT consumes the ticket: of two waits on one
+ * ticket, one returns the result and the other EINVAL.  For served requests the
  * stats hold: t_upload_ms = time queued, t_prune_ms = admission (upload,
  * checks, pruning, formats), t_ds_ms = time resident, t_total_ms = submit to
  * completion.  Returns the request's status: OK, EINVAL / ENOTSUP (rejected at

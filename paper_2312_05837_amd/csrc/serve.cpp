@@ -682,12 +682,17 @@ ising_status ising_wait(ising_ctx *ctx, uint64_t ticket, int32_t timeout_ms, int
         }
     } inside{S};
     ++S->waiters;
-    auto it = S->all.find(ticket);
-    if (it == S->all.end()) return ISING_EINVAL;
-    Request *q = it->second.get();
-    auto ready = [&] { return q->state == Q_DONE; };
+    if (S->all.find(ticket) == S->all.end()) return ISING_EINVAL;
+    // the ticket is looked up again at every wake-up: another wait on it may have consumed it
+    auto ready = [&] {
+        auto i = S->all.find(ticket);
+        return i == S->all.end() || i->second->state == Q_DONE;
+    };
     if (timeout_ms < 0) S->cv_done.wait(lk, ready);
     else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) return ISING_ETIMEDOUT;
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return ISING_EINVAL;  // consumed by another wait meanwhile
+    Request *q = it->second.get();
     const ising_status st = q->result;
     if (st == ISING_OK) {
         if (spins_out) std::memcpy(spins_out, q->spins.data(), q->spins.size());

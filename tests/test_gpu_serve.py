@@ -157,6 +157,27 @@ def test_stop_while_a_wait_is_blocked(ctx):
     assert status == P.ISING_OK and energy == oracle.energy(inst, spins) and stats["steps"] == 1000000
 
 
+def test_two_waits_on_one_ticket(ctx):
+    # one of them returns the result and consumes the ticket; the other returns EINVAL
+    import threading
+    import paper_2312_05837_amd as P
+    inst = I.erdos_renyi(300, 0.03, 22, "pm1")
+    P.ising_serve_start(ctx, chunk_steps=100)
+    st, keep = _host(inst)
+    t = P.ising_submit(ctx, st, P.params(replicas=64, steps=300000, seed=4))
+    outs = []
+    threads = [threading.Thread(target=lambda: outs.append(P.ising_wait(ctx, t, inst.n))) for _ in range(2)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=120)
+    P.ising_serve_stop(ctx)
+    statuses = sorted(o[0] for o in outs)
+    assert statuses == [P.ISING_OK, P.ISING_EINVAL]
+    status, spins, energy, _ = next(o for o in outs if o[0] == P.ISING_OK)
+    assert energy == oracle.energy(inst, spins)
+
+
 def test_requests_arriving_while_others_run_are_admitted(ctx):
     import paper_2312_05837_amd as P
     reqs = _requests(12, 7)
