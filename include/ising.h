@@ -168,7 +168,9 @@ typedef struct ising_pruned ising_pruned;
 ising_status ising_create(int device, ising_ctx **out);
 /* Destroy a context; waits for its outstanding work.  NULL is allowed. */
 ising_status ising_destroy(ising_ctx *ctx);
-/* Message of the last failed call on ctx ("" if none).  Valid until the next call. */
+/* Message of the last failed call on ctx ("" if none; with serving, also the last
+ * failure of a served request collected by ising_wait).  A copy owned by the
+ * calling thread, valid until that thread calls ising_last_error again. */
 const char *ising_last_error(const ising_ctx *ctx);
 
 /* ---- whole solve (host buffers) ---------------------------------------- */

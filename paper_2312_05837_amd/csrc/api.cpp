@@ -23,8 +23,20 @@ using namespace ising::rt;
 namespace ising {
 namespace rt {
 
+void set_error(ising_ctx *ctx, const std::string &msg) {
+    if (!ctx) return;
+    std::lock_guard<std::mutex> lk(ctx->err_mu);
+    ctx->err = msg;
+}
+
+std::string error_copy(ising_ctx *ctx) {
+    if (!ctx) return std::string();
+    std::lock_guard<std::mutex> lk(ctx->err_mu);
+    return ctx->err;
+}
+
 ising_status fail(ising_ctx *ctx, ising_status st, const std::string &msg) {
-    if (ctx) ctx->err = msg;
+    set_error(ctx, msg);
     return st;
 }
 
@@ -631,7 +643,13 @@ ising_status ising_destroy(ising_ctx *ctx) {
     return ISING_OK;
 }
 
-const char *ising_last_error(const ising_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+const char *ising_last_error(const ising_ctx *ctx) {
+    // a copy per calling thread, valid until that thread's next call of this function
+    thread_local std::string copy;
+    if (!ctx) return "no context";
+    copy = error_copy(const_cast<ising_ctx *>(ctx));
+    return copy.c_str();
+}
 
 const char *ising_last_kernel(const ising_ctx *ctx) { return ctx ? ctx->last_kernel.c_str() : ""; }
 

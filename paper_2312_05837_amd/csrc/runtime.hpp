@@ -58,7 +58,8 @@ struct Server;
 struct ising_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    std::string err;
+    std::string err;           // written through set_error / read through error_copy only
+    std::mutex err_mu;         // the scheduler thread of serving and waiting threads write it too
     std::string last_kernel;  // domain-selection kernel form of the last launch on this context
     ising::rt::Pool pool;
     std::mutex mu;
@@ -83,6 +84,9 @@ namespace ising {
 namespace rt {
 
 ising_status fail(ising_ctx *ctx, ising_status st, const std::string &msg);
+// The context's last failure message, set and copied under its lock (ctx may be NULL).
+void set_error(ising_ctx *ctx, const std::string &msg);
+std::string error_copy(ising_ctx *ctx);
 
 #define HIP_TRY(ctx, expr)                                                                     \
     do {                                                                                       \

@@ -519,7 +519,7 @@ void loop(Server *Sp) {
             std::lock_guard<std::mutex> lk(S.mu);
             if (st != ISING_OK) {
                 q->result = st;
-                q->error = S.ctx->err;
+                q->error = error_copy(S.ctx);
                 q->state = Q_DONE;
                 q->t_done = now_ms();
                 release(S, *q);
@@ -549,7 +549,7 @@ void loop(Server *Sp) {
             if (st == ISING_OK) st = finish(S, *q);
             std::lock_guard<std::mutex> lk(S.mu);
             q->result = st;
-            if (st != ISING_OK && q->error.empty()) q->error = S.ctx->err;
+            if (st != ISING_OK && q->error.empty()) q->error = error_copy(S.ctx);
             q->t_done = now_ms();
             q->state = Q_DONE;
             S.resident.erase(std::find(S.resident.begin(), S.resident.end(), q));
@@ -705,7 +705,7 @@ ising_status ising_wait(ising_ctx *ctx, uint64_t ticket, int32_t timeout_ms, int
             stats_out->t_total_ms = q->t_done - q->t_submit;                                  // latency
         }
     } else if (!q->error.empty()) {
-        ctx->err = q->error;
+        set_error(ctx, q->error);
     }
     S->all.erase(it);  // a ticket is consumed by its successful wait
     return st;
