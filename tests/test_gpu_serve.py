@@ -178,6 +178,40 @@ def test_two_waits_on_one_ticket(ctx):
     assert energy == oracle.energy(inst, spins)
 
 
+def test_submit_and_wait_from_several_threads(ctx):
+    # submission and waiting are thread-safe: four threads each submit and collect their own
+    # requests; every result equals the same request served alone from one thread
+    import threading
+    import paper_2312_05837_amd as P
+    reqs = _requests(12, 19)
+    P.ising_serve_start(ctx, chunk_steps=50, max_resident=8)
+    results = [None] * len(reqs)
+    keep = []
+    lock = threading.Lock()
+
+    def worker(ids):
+        for k in ids:
+            inst, R, seed = reqs[k]
+            st, kp = _host(inst)
+            with lock:
+                keep.append(kp)
+            t = P.ising_submit(ctx, st, P.params(replicas=R, steps=200, optimizer="adam", lr=6.0, mu=0.5,
+                                                 seed=seed, precision="fp32"))
+            results[k] = P.ising_wait(ctx, t, inst.n)
+
+    threads = [threading.Thread(target=worker, args=(list(range(w, len(reqs), 4)),)) for w in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=300)
+    P.ising_serve_stop(ctx)
+    alone, _ = _serve(ctx, reqs, chunk=50, max_resident=8)
+    for k, (inst, _, _) in enumerate(reqs):
+        assert results[k][0] == P.ISING_OK, k
+        assert np.array_equal(results[k][1], alone[k][1]) and results[k][2] == alone[k][2], k
+        assert results[k][2] == oracle.energy(inst, results[k][1])
+
+
 def test_requests_arriving_while_others_run_are_admitted(ctx):
     import paper_2312_05837_amd as P
     reqs = _requests(12, 7)
