@@ -425,8 +425,9 @@ ising_status ising_serve_stop(ising_ctx *ctx);
  * the request.  Thread-safe.  With the convergence test on, a request runs on the
  * persistent engine in FP32 and finishes at the end of the chunk in which its last
  * replica stopped (its result as from ising_solve with the same params).  Errors:
- * EINVAL (no server, malformed shape), ENOTSUP (params->loss other than
- * ISING_LOSS_VERTEX; the convergence test with a precision other than FP32). */
+ * EINVAL (no server, malformed shape, step parameters out of range), ENOTSUP
+ * (params->loss other than ISING_LOSS_VERTEX; the convergence test with a
+ * precision other than FP32), EBUSY (the server is stopping). */
 ising_status ising_submit(ising_ctx *ctx, const ising_problem *problem, const ising_params *params,
                           uint64_t *ticket);
 /* Wait up to timeout_ms (negative: forever) for a request and copy its result

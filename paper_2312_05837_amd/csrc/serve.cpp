@@ -659,6 +659,7 @@ ising_status ising_submit(ising_ctx *ctx, const ising_problem *problem, const is
     q->hp.h = problem->h ? (const void *)1 : nullptr;  // marks "has a field"; the data is in q->h
     q->t_submit = now_ms();
     std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return ISING_EBUSY;  // stopping: a request queued now would never run
     q->ticket = S->next_ticket++;
     *ticket = q->ticket;
     S->queue.push_back(q.get());

@@ -157,6 +157,26 @@ def test_stop_while_a_wait_is_blocked(ctx):
     assert status == P.ISING_OK and energy == oracle.energy(inst, spins) and stats["steps"] == 1000000
 
 
+def test_submit_while_stopping_refused(ctx):
+    # once stop has begun (it is finishing a long request), a new submission is refused with
+    # EBUSY instead of being queued behind a scheduler that is about to exit
+    import threading
+    import paper_2312_05837_amd as P
+    inst = I.erdos_renyi(300, 0.03, 23, "pm1")
+    P.ising_serve_start(ctx, chunk_steps=100)
+    st, keep = _host(inst)
+    P.ising_submit(ctx, st, P.params(replicas=64, steps=1000000, seed=5))
+    stopper = threading.Thread(target=lambda: P.ising_serve_stop(ctx))
+    stopper.start()
+    time.sleep(0.3)
+    assert stopper.is_alive()
+    with pytest.raises(P.IsingError) as e:
+        P.ising_submit(ctx, st, P.params(replicas=64, steps=10, seed=6))
+    assert e.value.status == P.ISING_EBUSY
+    stopper.join(timeout=120)
+    assert not stopper.is_alive()
+
+
 def test_two_waits_on_one_ticket(ctx):
     # one of them returns the result and consumes the ticket; the other returns EINVAL
     import threading
